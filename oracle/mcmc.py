@@ -1,0 +1,238 @@
+"""DINO-mMALA in reduced coordinates: Alg. 1 first stage + Prop. 4.2 (oracle; test infrastructure).
+
+State of a chain: reduced whitened KLE coordinates x in R^r and the complement
+coordinates z_perp in R^(d_m - r) (prior N(0, I) in both). Everything the MH
+decision depends on lives in R^r (Sec. 5.4: the first stage runs entirely in the
+reduced coefficient space); the complement follows the pCN move of Prop. 4.2.
+
+Readings of the paper taken here (listed with reasons in the design notes):
+* Observable basis: the network outputs physical observables and each problem has
+  its own diagonal noise covariance Gamma = diag(noise_var); the whitened quantities
+  are V^* y -> Gamma^-1/2 y and V^* G~ -> Gamma^-1/2 f (equivalent to V = Gamma^1/2).
+  A problem observes the first d_y outputs of the network.
+* Reduced ppg sign (Sec. 5.1, eq. surrogate_rppg): the ppg of the misfit is
+  J^T Gamma^-1 (f - y), as in eq. ppg; the printed form has the opposite sign.
+* The determinant factor of the reduced RN derivative (Sec. 5.4) multiplies the
+  exponential, prod_j (d_j + 1)^(1/2), as in eq. mmala_trr; the printed form adds it.
+* The complement move is the pCN move of Prop. 4.2 (item 1), z_perp <- s z_perp + beta zeta.
+* The noise of the reduced proposal (eq. reduced_space_sampling) is mapped through the
+  Cholesky factor L of I + H (L L^T = I + H) instead of P (d+1)^-1/2: the same law,
+  N(0, (1 - s^2)(I + H)^-1), with a unique factor, so both sides draw the same point.
+* The acceptance uses the surrogate misfit (the first-stage ratio eq. da_dino_trr_1);
+  accept iff log xi_1 <= log rho (Alg. 1 rejects iff alpha < xi_1, so ties accept).
+* A proposal whose misfit is not finite or whose I + H is not positive definite is
+  rejected and counted.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import network, philox
+
+
+@dataclass
+class Problem:
+    """One inverse problem: network, data y (d_y,), noise variances (d_y,), step size."""
+    layers: list
+    y: np.ndarray
+    noise_var: np.ndarray
+    dt: float
+    seed: int = 0
+    request_id: int = 0
+
+    @property
+    def d_y(self) -> int:
+        return len(self.y)
+
+    @property
+    def s(self) -> float:
+        """s = (4 - dt)/(4 + dt) (Sec. 2.6, eq. mmala)."""
+        return (4.0 - self.dt) / (4.0 + self.dt)
+
+    @property
+    def beta(self) -> float:
+        """sqrt(1 - s^2)."""
+        return math.sqrt(1.0 - self.s ** 2)
+
+
+@dataclass
+class Cache:
+    """What Alg. 1 keeps "known at m_j": misfit, reduced ppg, ppGNH and its factors."""
+    f: np.ndarray        # (C, d_y) network output at x
+    phi: np.ndarray      # (C,) surrogate reduced misfit
+    g: np.ndarray        # (C, r) reduced ppg
+    H: np.ndarray        # (C, r, r) reduced ppGNH
+    d: np.ndarray        # (C, r) eigenvalues of H (eq. surrogate_eigendecomposition)
+    P: np.ndarray        # (C, r, r) eigenvectors of H
+    L: np.ndarray        # (C, r, r) lower Cholesky factor of I + H
+    ok: np.ndarray       # (C,) finite misfit and positive definite I + H
+
+
+def geometry(prob: Problem, x: np.ndarray) -> Cache:
+    """Surrogate misfit, reduced ppg and reduced ppGNH at x (Sec. 5.1), plus the
+    eigendecomposition of H (Sec. 5.2) and the Cholesky factor of I + H."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    C, r = x.shape
+    f_full, _ = network.forward(prob.layers, x)
+    J_full = network.jacobian_reverse(prob.layers, x)
+    dy = prob.d_y
+    f = f_full[:, :dy]
+    J = J_full[:, :dy, :]
+    w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
+    Jw = J * w[None, :, None]                      # V^* J~_r : whitened reduced Jacobian
+    res = (prob.y[None, :] - f) * w[None, :]       # V^* y - f_NN (whitened)
+    phi = 0.5 * np.sum(res * res, axis=1)          # eq. (reduced data misfit)
+    g = -np.einsum("cir,ci->cr", Jw, res)          # J^T Gamma^-1 (f - y)  (sign reading)
+    H = np.einsum("cir,cis->crs", Jw, Jw)          # eq. surrogate_rppgnh
+    d = np.zeros((C, r))
+    P = np.zeros((C, r, r))
+    L = np.zeros((C, r, r))
+    ok = np.isfinite(phi) & np.all(np.isfinite(g), axis=1)
+    for c in range(C):
+        if not ok[c] or not np.all(np.isfinite(H[c])):
+            ok[c] = False
+            continue
+        d[c], P[c] = np.linalg.eigh(H[c])
+        try:
+            L[c] = np.linalg.cholesky(np.eye(r) + H[c])
+        except np.linalg.LinAlgError:
+            ok[c] = False
+    return Cache(f=f, phi=phi, g=g, H=H, d=d, P=P, L=L, ok=ok)
+
+
+def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:
+    """Reduced proposal of Prop. 4.2 item 2 (eq. reduced_space_sampling):
+
+        x+ = P diag((d+s)/(d+1)) P^T x - P diag((1-s)/(d+1)) P^T g + noise,
+
+    noise = sqrt(1 - s^2) L^-T xi (Cholesky reading of P diag((1-s^2)/(d+1))^1/2 xi)."""
+    s, beta = prob.s, prob.beta
+    C, r = x.shape
+    out = np.empty_like(x)
+    for c in range(C):
+        d, P = cache.d[c], cache.P[c]
+        mean = P @ (((d + s) / (d + 1.0)) * (P.T @ x[c])) - P @ (((1.0 - s) / (d + 1.0)) * (P.T @ cache.g[c]))
+        noise = beta * sla.solve_triangular(cache.L[c], xi[c], lower=True, trans="T")
+        out[c] = mean + noise
+    return out
+
+
+def log_rho0(prob: Problem, m1: np.ndarray, m2: np.ndarray, cache1: Cache) -> np.ndarray:
+    """log of the reduced RN derivative rho~_0,r(m1, m2) of the surrogate mMALA proposal
+    with respect to pCN (Sec. 5.4), evaluated with the geometry cached at m1:
+
+        -(dt/8) || D P^T m1 - P^T g ||^2_{(D+I)^-1} + (sqrt(dt)/2) mhat^T (H m1 - g)
+        - (1/2) ||mhat||^2_H + (1/2) sum_j log(d_j + 1),   mhat = (m2 - s m1)/sqrt(1 - s^2)."""
+    dt, s, beta = prob.dt, prob.s, prob.beta
+    C = m1.shape[0]
+    out = np.empty(C)
+    for c in range(C):
+        d, P, g, H = cache1.d[c], cache1.P[c], cache1.g[c], cache1.H[c]
+        a = d * (P.T @ m1[c]) - P.T @ g
+        t1 = -(dt / 8.0) * np.sum(a * a / (d + 1.0))
+        mhat = (m2[c] - s * m1[c]) / beta
+        t2 = (math.sqrt(dt) / 2.0) * (mhat @ (H @ m1[c] - g))
+        t3 = -0.5 * (mhat @ (H @ mhat))
+        t4 = 0.5 * np.sum(np.log(d + 1.0))
+        out[c] = t1 + t2 + t3 + t4
+    return out
+
+
+def log_rho1(prob: Problem, x: np.ndarray, cache_x: Cache, xp: np.ndarray, cache_p: Cache) -> np.ndarray:
+    """log of the first-stage transition-rate ratio rho^(1)_r(x, x+) (eq. da_dino_trr_1)."""
+    return (cache_x.phi - cache_p.phi
+            + log_rho0(prob, xp, x, cache_p) - log_rho0(prob, x, xp, cache_x))
+
+
+@dataclass
+class ChainState:
+    x: np.ndarray                 # (C, r)
+    z: np.ndarray | None          # (C, d_m - r) complement, or None when not tracked
+    cache: Cache
+    step: int = 0                 # global step counter of the stream layout
+    accepts: np.ndarray = None
+    failures: np.ndarray = None
+    chains: np.ndarray = None     # chain indices used in the stream counter
+
+    def __post_init__(self):
+        C = self.x.shape[0]
+        if self.accepts is None:
+            self.accepts = np.zeros(C, dtype=np.int64)
+        if self.failures is None:
+            self.failures = np.zeros(C, dtype=np.int64)
+        if self.chains is None:
+            self.chains = np.arange(C)
+
+
+def init_state(prob: Problem, x0: np.ndarray, z0: np.ndarray | None = None, chains=None) -> ChainState:
+    x0 = np.array(x0, dtype=np.float64)
+    return ChainState(x=x0, z=None if z0 is None else np.array(z0, dtype=np.float64),
+                      cache=geometry(prob, x0), chains=None if chains is None else np.asarray(chains))
+
+
+def _select(cache_a: Cache, cache_b: Cache, mask: np.ndarray) -> Cache:
+    def pick(a, b):
+        m = mask.reshape((-1,) + (1,) * (a.ndim - 1))
+        return np.where(m, b, a)
+    return Cache(**{k: pick(getattr(cache_a, k), getattr(cache_b, k)) for k in cache_a.__dataclass_fields__})
+
+
+@dataclass
+class StepRecord:
+    xp: np.ndarray
+    cache_p: Cache
+    log_rho: np.ndarray
+    log_u: np.ndarray
+    accept: np.ndarray
+
+
+def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> StepRecord:
+    """One Markov transition for every chain (Alg. 1 first stage, Prop. 4.2).
+
+    xi (C, r), u (C,) and zeta (C, d_m - r) default to the Philox streams at the
+    current step; pass them to evaluate the transition at given draws."""
+    C, r = st.x.shape
+    if xi is None:
+        xi = philox.normals(prob.seed, prob.request_id, philox.STREAM_XI, st.step, st.chains, r)
+    if u is None:
+        u = philox.uniforms(prob.seed, prob.request_id, st.step, st.chains)
+    # Alg. 1: reduced proposal sampling, surrogate evaluation at x+, first-stage ratio
+    xp = propose(prob, st.x, st.cache, xi)
+    cp = geometry(prob, xp)
+    lr = log_rho1(prob, st.x, st.cache, xp, cp)
+    lr = np.where(cp.ok & np.isfinite(lr), lr, -np.inf)
+    log_u = np.log(u)
+    acc = log_u <= lr
+    st.failures += (~cp.ok).astype(np.int64)
+    # Prop. 4.2 item 1: pCN move of the complement, realised on accepted moves only
+    if st.z is not None and np.any(acc):
+        idx = np.nonzero(acc)[0]
+        if zeta is None:
+            zeta_a = philox.normals(prob.seed, prob.request_id, philox.STREAM_COMPLEMENT, st.step,
+                                    st.chains[idx], st.z.shape[1])
+        else:
+            zeta_a = zeta[idx]
+        st.z[idx] = prob.s * st.z[idx] + prob.beta * zeta_a
+    st.x = np.where(acc[:, None], xp, st.x)
+    st.cache = _select(st.cache, cp, acc)
+    st.accepts += acc.astype(np.int64)
+    st.step += 1
+    return StepRecord(xp=xp, cache_p=cp, log_rho=lr, log_u=log_u, accept=acc)
+
+
+def run(prob: Problem, st: ChainState, n_steps: int, trace: bool = True):
+    """Advance every chain n_steps; returns the reduced trace (n_steps, C, r) and
+    the misfit trace (n_steps, C) of the states after each step."""
+    C, r = st.x.shape
+    xs = np.empty((n_steps, C, r)) if trace else None
+    phis = np.empty((n_steps, C)) if trace else None
+    for t in range(n_steps):
+        transition(prob, st)
+        if trace:
+            xs[t] = st.x
+            phis[t] = st.cache.phi
+    return xs, phis

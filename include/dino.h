@@ -1,0 +1,228 @@
+/*
+ * dino.h - C ABI of the MI355X (gfx950) hot path of DINO-accelerated geometric MCMC
+ * (Cao, O'Leary-Roseberry & Ghattas, arXiv 2403.08220).
+ *
+ * The library runs the first stage of Alg. 1 (surrogate-driven mMALA with the
+ * surrogate misfit deciding acceptance, eq. da_dino_trr_1) for many independent
+ * chains at once, together with the pCN move of the complement subspace
+ * (Prop. 4.2 item 1). Every step of the path runs in HIP kernels on the device:
+ * reduced proposal (eq. reduced_space_sampling), surrogate forward and reduced
+ * Jacobian (eq. rb_dino and the reduced Jacobian that follows it), surrogate
+ * misfit, reduced ppg and reduced ppGNH (Sec. 5.1), Cholesky factor of I + H,
+ * reduced RN derivative and first-stage ratio (Sec. 5.4), MH decision, complement
+ * update, trace and statistics.
+ *
+ * Conventions
+ *  - Every call returns a dino_status; nothing throws or aborts across the ABI.
+ *    On failure dino_last_error() returns a message for the calling thread.
+ *  - Host pointers are borrowed for the duration of the call and copied.
+ *    Pointers documented as "device" must address device memory of the
+ *    context's GPU that stays valid until the call's stream work completes.
+ *  - Matrices are row-major. Reduced coordinates are whitened KLE coordinates
+ *    (prior N(0, I)), so x in R^r and the complement z in R^(d_m - r).
+ *  - "stream" is a hipStream_t passed as void*; NULL means the null stream.
+ *    Work is enqueued asynchronously; dino_read_* calls synchronise the stream
+ *    they last ran on.
+ *  - No call allocates device memory in dino_step; setup calls (dino_load_*,
+ *    dino_problem_create without a caller workspace) allocate with hipMalloc.
+ */
+#ifndef DINO_H
+#define DINO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dino_status;
+#define DINO_OK 0
+#define DINO_EINVAL (-1)   /* bad argument (size, pointer, range) */
+#define DINO_ENOMEM (-2)   /* device allocation failed or workspace too small */
+#define DINO_EDEVICE (-3)  /* a HIP runtime call failed */
+#define DINO_ESTATE (-4)   /* call made in the wrong order (e.g. step before init) */
+#define DINO_ENUMERIC (-5) /* non-finite input data */
+
+typedef struct dino_ctx dino_ctx;
+typedef struct dino_problem dino_problem;
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char* dino_last_error(void);
+/* Library version string. */
+const char* dino_version(void);
+
+/* Context on one GPU. device: HIP device ordinal. Holds the prior/basis and the
+ * network. Destroying a context with live problems is an error (DINO_ESTATE). */
+dino_status dino_ctx_create(int device, dino_ctx** out);
+dino_status dino_ctx_destroy(dino_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Prior and KLE basis (Sec. 2.1 Assumption 2; Sec. 4.2 KLE reduced basis).
+ * Grid Matern prior C_pr = (gamma(-Lap_h) + delta I)^-2 on an n x n unit-square
+ * grid (h = 1/(n-1), node p = j*n + i with i the x-index) with the zero-flux
+ * 5-point Laplacian. The basis is the closed-form DCT-II eigenbasis ordered by
+ * decreasing eigenvalue with exact ties broken by (k1, k2) ascending (k1 the
+ * x-frequency); the first r modes are kept. n >= 2, 1 <= r <= n*n,
+ * gamma > 0, delta > 0. Replaces a previously loaded prior.
+ */
+dino_status dino_load_prior(dino_ctx* ctx, int n, double gamma, double delta, int r);
+
+/* Copies of the basis to host buffers (any may be NULL):
+ *   dec      d_m x r   decoder Psi_r (columns psi_j = sqrt(lambda_j) eta_j)
+ *   lam      r         eigenvalues lambda_j
+ *   var_perp d_m       pointwise prior variance of the complement,
+ *                      sum_{k >= r} lambda_k eta_k(p)^2
+ *   modes    r x 2     (k1, k2) of every kept mode */
+dino_status dino_read_basis(dino_ctx* ctx, double* dec, double* lam, double* var_perp, int32_t* modes);
+
+/* ---------------------------------------------------------------------------
+ * Surrogate network f_NN (eq. rb_dino): a chain of layers, W_k of shape
+ * fan_out x fan_in (row-major, host FP64), b_k of length fan_out (NULL = 0).
+ *   DINO_LAYER_LINEAR: h <- W h + b
+ *   DINO_LAYER_ACT:    h <- gelu(W h + b)
+ *   DINO_LAYER_RESID:  h <- h + gelu(W h + b)        (fan_in == fan_out)
+ * gelu is the exact GELU z Phi(z). The first layer's fan_in is the reduced
+ * dimension r (must equal the prior's r); the last layer must be LINEAR and its
+ * fan_out is the number of network outputs d_out. At most 16 layers, widths <= 1024.
+ * The library keeps FP64, FP32 and BF16 copies of the weights.
+ */
+#define DINO_LAYER_LINEAR 0
+#define DINO_LAYER_ACT 1
+#define DINO_LAYER_RESID 2
+dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds, const int32_t* fan_out,
+                              const int32_t* fan_in, const double* const* W, const double* const* b);
+
+/* ---------------------------------------------------------------------------
+ * Problem: one inverse problem (data y, noise, step size) with n_chains chains.
+ *
+ * precision:
+ *   DINO_PREC_F64   every stage in FP64 (the plain FP64 GPU path).
+ *   DINO_PREC_BF16  surrogate forward in FP32; reduced Jacobian and GN Hessian
+ *                   from BF16 MFMA products with FP32 accumulation; proposal,
+ *                   Cholesky, log-densities and MH ratio in FP64.
+ * d_y: observed outputs (the first d_y of the network's d_out outputs).
+ * noise_var: diagonal of Gamma (d_y values > 0; +inf means the output carries no
+ *   information). dt > 0 is the step size (s = (4-dt)/(4+dt), eq. mmala).
+ * seed, request_id: the Philox4x64-10 key. Draw k of stream S for chain c at
+ *   step t uses counter (k/4, S, t, c): S = 0 proposal normals, 1 complement
+ *   normals, 2 MH uniform, 3 initial x, 4 initial z.
+ * track_complement: keep the complement state z (n_chains x (d_m - r) FP32).
+ * trace_capacity: number of steps whose reduced states (FP32) and misfits are
+ *   recorded for diagnostics (0 = none).
+ */
+#define DINO_PREC_F64 0
+#define DINO_PREC_BF16 1
+typedef struct {
+    int32_t n_chains;
+    int32_t d_y;
+    int32_t precision;
+    int32_t track_complement;
+    int32_t trace_capacity;
+    int32_t reserved;
+    double dt;
+    uint64_t seed;
+    uint64_t request_id;
+} dino_problem_desc;
+
+/* Device bytes a problem needs (state, caches, scratch, trace). */
+dino_status dino_problem_workspace_bytes(const dino_ctx* ctx, const dino_problem_desc* desc, size_t* bytes);
+
+/* Create a problem. y and noise_var are host arrays of d_y values.
+ * dev_ws/ws_bytes: caller-owned device workspace of at least
+ * dino_problem_workspace_bytes() bytes, 256-byte aligned; NULL lets the library
+ * allocate (and free it at destroy). EINVAL for dt <= 0, d_y outside
+ * [1, d_out], non-positive noise variances; ENUMERIC for non-finite y. */
+dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, const double* y,
+                                const double* noise_var, void* dev_ws, size_t ws_bytes, dino_problem** out);
+dino_status dino_problem_destroy(dino_problem* p);
+
+/* Initial states: x0 (n_chains x r, host FP64) and z0 (n_chains x (d_m - r),
+ * host FP32); NULL draws them from the prior (streams 3 and 4). Evaluates the
+ * geometry cache at x0 (Alg. 1 "known at m_j") and resets the step counter,
+ * acceptance counts and trace. */
+dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0, void* stream);
+
+/* Advance every chain n_steps transitions (Alg. 1 first stage + Prop. 4.2).
+ * Asynchronous on stream. Per-chain numerical failures (non-finite misfit,
+ * I + H not positive definite) reject the proposal and are counted; they do
+ * not fail the call. */
+dino_status dino_step(dino_problem* p, int n_steps, void* stream);
+
+/* Host copies of the state (any pointer may be NULL). x: n_chains x r FP64;
+ * z: n_chains x (d_m - r) FP32 (ESTATE if not tracked). */
+dino_status dino_read_states(dino_problem* p, double* x, float* z);
+
+/* Host copies of the cache at the current states: misfit (n_chains), reduced
+ * ppg (n_chains x r) and the lower Cholesky factor of I + H (n_chains x r x r,
+ * upper triangle unspecified). Any pointer may be NULL. */
+dino_status dino_read_cache(dino_problem* p, double* phi, double* g, double* L);
+
+/* Per-chain accepted moves and numerical failures since init, and the number of
+ * steps taken. Any pointer may be NULL. */
+dino_status dino_read_diagnostics(dino_problem* p, int64_t* accepts, int64_t* failures, int64_t* steps);
+
+/* Recorded trace: x_trace (steps x n_chains x r FP32) and phi_trace
+ * (steps x n_chains FP64) for the min(steps, trace_capacity) first steps. */
+dino_status dino_read_trace(dino_problem* p, float* x_trace, double* phi_trace, int64_t* n_recorded);
+
+/* Posterior field mean and pointwise variance (d_m each, host FP64) from the
+ * recorded trace after discarding the first burn_in recorded steps: mean =
+ * Psi_r xbar and var = diag(Psi_r S Psi_r^T) + var_perp (the complement is
+ * prior distributed and independent of the reduced part, Lemma 4.1). Also the
+ * reduced mean xbar (r) and covariance S (r x r) if the pointers are non-NULL.
+ * Computed on the device. */
+dino_status dino_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S);
+
+/* Multichain ESS fraction (Sec. 6.2.2, eq. ess; rho_t with lag-t
+ * autocovariances, Geyer truncation on positive pair sums) of every reduced
+ * coordinate from the recorded trace after burn_in steps; ess: r values. */
+dino_status dino_ess(dino_problem* p, int burn_in, double* ess);
+
+/* ---------------------------------------------------------------------------
+ * Stage timing. With profiling enabled, dino_step records HIP events on its
+ * stream around every stage of every step and synchronises after each step
+ * (slower; meant for measurement passes). Stages: 0 proposal, 1 surrogate
+ * forward, 2 reduced Jacobian, 3 misfit and ppg, 4 GN Hessian, 5 Cholesky,
+ * 6 acceptance, 7 complement, 8 trace. stage_ms: total milliseconds per stage;
+ * launches: kernel launches per stage per step; steps: profiled steps.
+ */
+#define DINO_N_STAGES 9
+dino_status dino_set_profiling(dino_problem* p, int enable);
+dino_status dino_read_profile(dino_problem* p, double* stage_ms, int32_t* launches, int64_t* steps);
+const char* dino_stage_name(int stage);
+
+/* ---------------------------------------------------------------------------
+ * Stage entry points on explicit device buffers (used to check each stage).
+ * All pointers are device pointers; n <= n_chains of the problem; chain
+ * index k of the batch uses counters of chain k.
+ */
+
+/* Geometry at reduced points x (n x r): network output f (n x d_y), surrogate
+ * misfit phi (n), reduced ppg g (n x r), reduced ppGNH H (n x r x r, full),
+ * lower Cholesky factor L of I + H (n x r x r), logdet = sum log L_ii (n) and
+ * ok (n int32: 1 if finite and positive definite). H may be NULL. */
+dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* f, double* phi, double* g,
+                               double* H, double* L, double* logdet, int32_t* ok, void* stream);
+
+/* Reduced proposal (eq. reduced_space_sampling, noise mapped through L^-T) from
+ * states x with cache (g, L) and given normals xi (all n x r / n x r x r):
+ * xp = L^-T (L^-1 [L L^T x - (1-s) x - (1-s) g] + sqrt(1-s^2) xi). */
+dino_status dino_eval_propose(dino_problem* p, int n, const double* x, const double* g, const double* L,
+                              const double* xi, double* xp, void* stream);
+
+/* log of the first-stage ratio rho^(1)_r(x, xp) (eq. da_dino_trr_1) from the
+ * two states and their caches (phi, g, L, logdet). */
+dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                              const double* L_x, const double* logdet_x, const double* xp,
+                              const double* phi_p, const double* g_p, const double* L_p,
+                              const double* logdet_p, double* log_rho, void* stream);
+
+/* Philox4x64-10 normals of one stream for n chains at one step: out n x count. */
+dino_status dino_eval_normals(dino_problem* p, int n, int stream_id, int64_t step, int count, double* out,
+                              void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DINO_H */

@@ -1,0 +1,230 @@
+"""Python binding of the DINO-mMALA HIP library: argument marshalling over the C ABI.
+
+Every step of the path runs in the library's kernels; torch supplies device memory
+(problem workspaces, stage buffers) and streams.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+
+import numpy as np
+
+from . import _lib
+from ._lib import DinoError, ProblemDesc, check, dptr, fptr, i32ptr, i64ptr  # noqa: F401
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ct.c_void_p(stream.cuda_stream)
+
+
+def _tp(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One GPU: holds the prior/KLE basis and the surrogate network."""
+
+    def __init__(self, device: int = 0):
+        self.lib = _lib.load()
+        h = ct.c_void_p()
+        check(self.lib.dino_ctx_create(device, ct.byref(h)))
+        self.h = h
+        self.device = device
+        self.n = self.r = None
+        self.d_out = None
+
+    def close(self):
+        if self.h:
+            check(self.lib.dino_ctx_destroy(self.h))
+            self.h = None
+
+    def load_prior(self, n: int, gamma: float, delta: float, r: int):
+        check(self.lib.dino_load_prior(self.h, n, gamma, delta, r))
+        self.n, self.r = n, r
+
+    @property
+    def d_m(self):
+        return self.n * self.n
+
+    def read_basis(self):
+        dec = np.empty((self.d_m, self.r))
+        lam = np.empty(self.r)
+        vp = np.empty(self.d_m)
+        modes = np.empty((self.r, 2), dtype=np.int32)
+        check(self.lib.dino_read_basis(self.h, dptr(dec), dptr(lam), dptr(vp), i32ptr(modes)))
+        return dict(dec=dec, lam=lam, var_perp=vp, modes=modes)
+
+    def load_network(self, layers):
+        """layers: list of (kind, W (fan_out x fan_in), b) with kind in linear/act/resid."""
+        L = len(layers)
+        kinds = np.array([_lib.LAYER_KINDS[k] for k, _, _ in layers], dtype=np.int32)
+        Ws = [np.ascontiguousarray(W, dtype=np.float64) for _, W, _ in layers]
+        bs = [np.ascontiguousarray(b if b is not None else np.zeros(W.shape[0]), dtype=np.float64)
+              for (_, W, b) in layers]
+        fo = np.array([W.shape[0] for W in Ws], dtype=np.int32)
+        fi = np.array([W.shape[1] for W in Ws], dtype=np.int32)
+        Wp = (_lib._D * L)(*[dptr(W) for W in Ws])
+        bp = (_lib._D * L)(*[dptr(b) for b in bs])
+        check(self.lib.dino_load_network(self.h, L, i32ptr(kinds), i32ptr(fo), i32ptr(fi), Wp, bp))
+        self.d_out = int(fo[-1])
+        self._layers_keepalive = (Ws, bs)
+
+
+class Problem:
+    """n_chains chains of one inverse problem, resident on the device."""
+
+    def __init__(self, ctx: Context, n_chains: int, y, noise_var, dt: float, seed: int = 0, request_id: int = 0,
+                 precision: str = "f64", track_complement: bool = True, trace_capacity: int = 0,
+                 torch_workspace: bool = True):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        nv = np.ascontiguousarray(noise_var, dtype=np.float64)
+        self.desc = ProblemDesc(n_chains=n_chains, d_y=len(y), precision=_lib.PRECISIONS[precision],
+                                track_complement=1 if track_complement else 0, trace_capacity=trace_capacity,
+                                reserved=0, dt=dt, seed=seed, request_id=request_id)
+        self.h = None
+        nbytes = ct.c_size_t()
+        # the library validates the descriptor against the context's prior and network
+        check(self.lib.dino_problem_workspace_bytes(ctx.h, ct.byref(self.desc), ct.byref(nbytes)))
+        self.C, self.r, self.d_y = n_chains, ctx.r, len(y)
+        self.d_perp = ctx.d_m - ctx.r
+        self.track_complement = track_complement
+        self.trace_capacity = trace_capacity
+        self.dt = dt
+        self.ws = None
+        ws_ptr = None
+        if torch_workspace:
+            torch = _torch()
+            self.ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+            base = self.ws.data_ptr()
+            ws_ptr = ct.c_void_p((base + 255) & ~255)
+        h = ct.c_void_p()
+        check(self.lib.dino_problem_create(ctx.h, ct.byref(self.desc), dptr(y), dptr(nv), ws_ptr, nbytes.value,
+                                           ct.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(self.lib.dino_problem_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- chain control ---------------------------------------------------------------
+    def init(self, x0=None, z0=None, stream=None):
+        x0 = None if x0 is None else np.ascontiguousarray(x0, dtype=np.float64)
+        z0 = None if z0 is None else np.ascontiguousarray(z0, dtype=np.float32)
+        if x0 is not None:
+            assert x0.shape == (self.C, self.r)
+        if z0 is not None:
+            assert z0.shape == (self.C, self.d_perp)
+        check(self.lib.dino_chains_init(self.h, dptr(x0), fptr(z0), _stream_handle(stream)))
+
+    def step(self, n: int, stream=None):
+        check(self.lib.dino_step(self.h, n, _stream_handle(stream)))
+
+    def set_profiling(self, enable: bool):
+        check(self.lib.dino_set_profiling(self.h, 1 if enable else 0))
+
+    def profile(self):
+        """Per-stage device time (ms, summed over profiled steps), launches per step, steps."""
+        ms = np.zeros(_lib.N_STAGES)
+        launches = np.zeros(_lib.N_STAGES, dtype=np.int32)
+        steps = np.zeros(1, dtype=np.int64)
+        check(self.lib.dino_read_profile(self.h, dptr(ms), i32ptr(launches), i64ptr(steps)))
+        names = [self.lib.dino_stage_name(i).decode() for i in range(_lib.N_STAGES)]
+        return {n: dict(ms=float(ms[i]), launches=int(launches[i])) for i, n in enumerate(names)}, int(steps[0])
+
+    # --- reads -----------------------------------------------------------------------
+    def states(self):
+        x = np.empty((self.C, self.r))
+        z = np.empty((self.C, self.d_perp), dtype=np.float32) if self.track_complement else None
+        check(self.lib.dino_read_states(self.h, dptr(x), fptr(z)))
+        return x, z
+
+    def cache(self):
+        phi = np.empty(self.C)
+        g = np.empty((self.C, self.r))
+        L = np.empty((self.C, self.r, self.r))
+        check(self.lib.dino_read_cache(self.h, dptr(phi), dptr(g), dptr(L)))
+        return phi, g, np.tril(L)
+
+    def diagnostics(self):
+        a = np.empty(self.C, dtype=np.int64)
+        f = np.empty(self.C, dtype=np.int64)
+        s = np.empty(1, dtype=np.int64)
+        check(self.lib.dino_read_diagnostics(self.h, i64ptr(a), i64ptr(f), i64ptr(s)))
+        return a, f, int(s[0])
+
+    def trace(self):
+        n = np.empty(1, dtype=np.int64)
+        check(self.lib.dino_read_trace(self.h, None, None, i64ptr(n)))
+        k = int(n[0])
+        xt = np.empty((k, self.C, self.r), dtype=np.float32)
+        pt = np.empty((k, self.C))
+        if k:
+            check(self.lib.dino_read_trace(self.h, fptr(xt), dptr(pt), i64ptr(n)))
+        return xt, pt
+
+    def posterior(self, burn_in: int):
+        d_m = self.ctx.d_m
+        mean, var = np.empty(d_m), np.empty(d_m)
+        xbar, S = np.empty(self.r), np.empty((self.r, self.r))
+        check(self.lib.dino_posterior(self.h, burn_in, dptr(mean), dptr(var), dptr(xbar), dptr(S)))
+        return mean, var, xbar, S
+
+    def ess(self, burn_in: int):
+        e = np.empty(self.r)
+        check(self.lib.dino_ess(self.h, burn_in, dptr(e)))
+        return e
+
+    # --- stage entry points on device tensors ------------------------------------------
+    def eval_geometry(self, x, stream=None, want_H=True):
+        torch = _torch()
+        n = x.shape[0]
+        dev = x.device
+        f = torch.empty((n, self.d_y), dtype=torch.float64, device=dev)
+        phi = torch.empty(n, dtype=torch.float64, device=dev)
+        g = torch.empty((n, self.r), dtype=torch.float64, device=dev)
+        H = torch.empty((n, self.r, self.r), dtype=torch.float64, device=dev) if want_H else None
+        L = torch.zeros((n, self.r, self.r), dtype=torch.float64, device=dev)
+        logdet = torch.empty(n, dtype=torch.float64, device=dev)
+        ok = torch.empty(n, dtype=torch.int32, device=dev)
+        check(self.lib.dino_eval_geometry(self.h, n, _tp(x), _tp(f), _tp(phi), _tp(g), _tp(H), _tp(L), _tp(logdet),
+                                          _tp(ok), _stream_handle(stream)))
+        return dict(f=f, phi=phi, g=g, H=H, L=L, logdet=logdet, ok=ok)
+
+    def eval_propose(self, x, g, L, xi, stream=None):
+        torch = _torch()
+        xp = torch.empty_like(x)
+        check(self.lib.dino_eval_propose(self.h, x.shape[0], _tp(x), _tp(g), _tp(L), _tp(xi), _tp(xp),
+                                         _stream_handle(stream)))
+        return xp
+
+    def eval_log_rho(self, x, cx, xp, cp, stream=None):
+        torch = _torch()
+        out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        check(self.lib.dino_eval_log_rho(self.h, x.shape[0], _tp(x), _tp(cx["phi"]), _tp(cx["g"]), _tp(cx["L"]),
+                                         _tp(cx["logdet"]), _tp(xp), _tp(cp["phi"]), _tp(cp["g"]), _tp(cp["L"]),
+                                         _tp(cp["logdet"]), _tp(out), _stream_handle(stream)))
+        return out
+
+    def eval_normals(self, n: int, stream_id: int, step: int, count: int, stream=None):
+        torch = _torch()
+        out = torch.empty((n, count), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        check(self.lib.dino_eval_normals(self.h, n, stream_id, step, count, _tp(out), _stream_handle(stream)))
+        return out

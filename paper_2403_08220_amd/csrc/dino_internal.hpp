@@ -1,0 +1,234 @@
+// Internal declarations of the DINO-mMALA HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "dino.h"
+
+namespace dino {
+
+// ----------------------------------------------------------------------------------
+// Errors: every ABI call converts failures to a status and a thread-local message.
+struct Error {
+    dino_status code;
+    std::string msg;
+};
+
+void set_error(const std::string& msg);
+void clear_error();
+
+#define DINO_HIP(call)                                                                         \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            throw ::dino::Error{DINO_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define DINO_REQUIRE(cond, code, text)                                \
+    do {                                                              \
+        if (!(cond)) throw ::dino::Error{(code), std::string(text)}; \
+    } while (0)
+
+// ----------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon et al., SC'11). Counter (block, stream, step, chain),
+// key (seed, request id). Both the oracle and the kernels implement it from that
+// definition; streams: 0 proposal normals, 1 complement normals, 2 MH uniform,
+// 3 initial x, 4 initial z.
+enum : int { STREAM_XI = 0, STREAM_COMPLEMENT = 1, STREAM_UNIFORM = 2, STREAM_INIT_X = 3, STREAM_INIT_Z = 4 };
+
+constexpr uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t PHILOX_M1 = 0xCA5A826395121157ull;
+constexpr uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t PHILOX_W1 = 0xBB67AE8584CAA73Bull;
+
+__device__ __forceinline__ void philox4x64(uint64_t c[4], uint64_t k0, uint64_t k1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        if (i) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        const uint64_t hi0 = __umul64hi(PHILOX_M0, c[0]);
+        const uint64_t lo0 = PHILOX_M0 * c[0];
+        const uint64_t hi1 = __umul64hi(PHILOX_M1, c[2]);
+        const uint64_t lo1 = PHILOX_M1 * c[2];
+        const uint64_t n0 = hi1 ^ c[1] ^ k0;
+        const uint64_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// ((w >> 12) + 1/2) 2^-52: exact in double, strictly inside (0, 1).
+__device__ __forceinline__ double philox_u01(uint64_t w) { return ((double)(w >> 12) + 0.5) * 0x1p-52; }
+
+// Normals 4*block .. 4*block+3 of a stream (Box-Muller on word pairs (0,1), (2,3)).
+__device__ __forceinline__ void philox_normals4(uint64_t seed, uint64_t rid, uint64_t block, uint64_t stream,
+                                                uint64_t step, uint64_t chain, double out[4]) {
+    uint64_t c[4] = {block, stream, step, chain};
+    philox4x64(c, seed, rid);
+    const double u0 = philox_u01(c[0]), u1 = philox_u01(c[1]);
+    const double u2 = philox_u01(c[2]), u3 = philox_u01(c[3]);
+    const double R0 = sqrt(-2.0 * log(u0));
+    const double R2 = sqrt(-2.0 * log(u2));
+    double s1, c1, s3, c3;
+    sincos(2.0 * M_PI * u1, &s1, &c1);
+    sincos(2.0 * M_PI * u3, &s3, &c3);
+    out[0] = R0 * c1;
+    out[1] = R0 * s1;
+    out[2] = R2 * c3;
+    out[3] = R2 * s3;
+}
+
+__device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t rid, uint64_t step, uint64_t chain) {
+    uint64_t c[4] = {0, (uint64_t)STREAM_UNIFORM, step, chain};
+    philox4x64(c, seed, rid);
+    return philox_u01(c[0]);
+}
+
+// ----------------------------------------------------------------------------------
+// Host-side objects.
+struct Layer {
+    int kind;
+    int fan_out, fan_in;
+    double* W64 = nullptr;  // fan_out x fan_in
+    double* b64 = nullptr;
+    float* W32 = nullptr;
+    float* b32 = nullptr;
+    __hip_bfloat16* WtB = nullptr;  // bf16 copy in the layout of the reverse sweep
+    std::vector<double> hostW, hostb;
+};
+
+struct Basis {
+    int n = 0, r = 0, d_m = 0;
+    double gamma = 0, delta = 0;
+    std::vector<int32_t> k1, k2;   // kept modes
+    std::vector<double> lam;       // kept eigenvalues
+    double* dec = nullptr;         // d_m x r
+    double* var_perp = nullptr;    // d_m
+    double* lam_dev = nullptr;     // r
+};
+
+struct dino_ctx_impl;
+}  // namespace dino
+
+struct dino_ctx {
+    int device = 0;
+    dino::Basis basis;
+    std::vector<dino::Layer> layers;
+    int r_in = 0, d_out = 0, max_width = 0, n_act = 0;
+    int live_problems = 0;
+};
+
+namespace dino {
+
+// Device views used by launches.
+struct NetView {
+    int n_layers;
+    int kinds[16];
+    int fan_out[16];
+    int fan_in[16];
+    const double* W64[16];
+    const double* b64[16];
+    const float* W32[16];
+    const float* b32[16];
+};
+
+}  // namespace dino
+
+struct dino_problem {
+    dino_ctx* ctx = nullptr;
+    dino_problem_desc desc{};
+    int C = 0, r = 0, d_y = 0, d_m = 0, d_perp = 0, wmax = 0, n_act = 0;
+    double s = 0, beta = 0;
+    bool own_ws = false;
+    bool initialised = false;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    int64_t step = 0;
+    int64_t recorded = 0;
+    hipStream_t last_stream = nullptr;
+
+    // problem data
+    double* y = nullptr;      // d_y
+    double* winv = nullptr;   // d_y: Gamma^-1/2 diagonal
+    // chain state and its cache
+    double* x = nullptr;      // C x r
+    double* g = nullptr;      // C x r
+    double* phi = nullptr;    // C
+    double* logdet = nullptr; // C
+    double* Lbuf = nullptr;   // 2 x C x r x r (ping-pong)
+    int32_t* cur = nullptr;   // C: which half of Lbuf holds the state's factor
+    float* z = nullptr;       // C x d_perp
+    int64_t* accepts = nullptr;
+    int64_t* failures = nullptr;
+    // proposal scratch
+    double* xp = nullptr;
+    double* gp = nullptr;
+    double* phip = nullptr;
+    double* logdetp = nullptr;
+    int32_t* okp = nullptr;
+    double* lfwd = nullptr;   // log rho_0(x -> xp) per chain
+    int32_t* acc = nullptr;   // accept flag of the last step
+    double* f = nullptr;      // C x d_y (FP64)
+    double* h0 = nullptr;     // C x wmax activations (ping)
+    double* h1 = nullptr;     // C x wmax (pong)
+    double* dprime = nullptr; // n_act x C x wmax  gelu'(z) of every activated layer
+    double* lam0 = nullptr;   // C x d_y x wmax   reverse-sweep buffers (FP64 path)
+    double* lam1 = nullptr;
+    double* Bj = nullptr;     // C x d_y x r whitened reduced Jacobian Gamma^-1/2 J
+    // trace
+    float* xtrace = nullptr;  // capacity x C x r
+    double* phitrace = nullptr;
+    // stage profiling
+    bool profile = false;
+    hipEvent_t ev[DINO_N_STAGES + 1] = {};
+    double stage_ms[DINO_N_STAGES] = {};
+    int32_t stage_launches[DINO_N_STAGES] = {};
+    int64_t profiled_steps = 0;
+};
+
+namespace dino {
+
+// launch helpers (kernels_*.hip)
+void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipStream_t st);
+void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t st);
+void launch_misfit_grad(dino_problem* p, int n, const double* f, const double* B, double* phi, double* g,
+                        hipStream_t st);
+// A_c (slot-selected) = [I +] B_c^T B_c; lower tiles only unless full.
+void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,
+                            int slot_xor, long slot_stride, int add_identity, int full, hipStream_t st);
+// Matrices addressed per chain c as base + c*stride + (slot[c] ^ slot_xor) * slot_stride.
+void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                          long slot_stride, double* logdet, int32_t* ok, hipStream_t st);
+void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
+                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given,
+                         int64_t step, double* xp, double* lfwd, const double* logdet, hipStream_t st);
+void launch_accept(dino_problem* p, int64_t step, hipStream_t st);
+void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                    const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
+                    const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st);
+void launch_complement(dino_problem* p, int64_t step, hipStream_t st);
+void launch_trace(dino_problem* p, int64_t row, hipStream_t st);
+void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st);
+void launch_normals(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count, double* out,
+                    hipStream_t st);
+void launch_copy_rows(int n, int width, const double* src, double* dst, hipStream_t st);
+
+// basis
+void build_basis_device(Basis& b);
+void launch_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S,
+                      hipStream_t st);
+void launch_ess(dino_problem* p, int burn_in, double* ess, hipStream_t st);
+
+NetView net_view(const dino_ctx* ctx);
+
+}  // namespace dino

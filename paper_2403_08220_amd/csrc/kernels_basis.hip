@@ -1,0 +1,278 @@
+// KLE basis of the grid Matern prior (Sec. 4.2), Rao-Blackwellised posterior
+// moments (Lemma 4.1) and the multichain ESS fraction (Sec. 6.2.2, eq. ess).
+#include "dino_internal.hpp"
+
+namespace dino {
+
+// DCT-II mode k at node i of an n-point line: sqrt((2 - [k=0])/n) cos(pi k (i + 1/2)/n).
+__device__ __forceinline__ double dct_q(int n, int k, int i) {
+    const double scale = (k == 0) ? sqrt(1.0 / n) : sqrt(2.0 / n);
+    return scale * cos(M_PI * (double)k * ((double)i + 0.5) / (double)n);
+}
+
+// dec[p][j] = sqrt(lam_j) q_{k1_j}(i) q_{k2_j}(jy), p = jy*n + i.
+__global__ void basis_dec_kernel(int n, int r, const int32_t* __restrict__ k1, const int32_t* __restrict__ k2,
+                                 const double* __restrict__ lam, double* __restrict__ dec) {
+    const long total = (long)n * n * r;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int j = (int)(e % r);
+        const long p = e / r;
+        const int i = (int)(p % n), jy = (int)(p / n);
+        dec[e] = sqrt(lam[j]) * dct_q(n, k1[j], i) * dct_q(n, k2[j], jy);
+    }
+}
+
+// Q2[i][k] = q_k(i)^2.
+__global__ void q2_kernel(int n, double* __restrict__ Q2) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, k = e % n;
+    const double q = dct_q(n, k, i);
+    Q2[e] = q * q;
+}
+
+// T[i][k2] = sum_k1 Q2[i][k1] lamc[k1][k2]
+__global__ void vp_stage1_kernel(int n, const double* __restrict__ Q2, const double* __restrict__ lamc,
+                                 double* __restrict__ T) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int i = e / n, k2 = e % n;
+    double acc = 0.0;
+    for (int k1 = 0; k1 < n; ++k1) acc += Q2[i * n + k1] * lamc[k1 * n + k2];
+    T[e] = acc;
+}
+
+// var_perp[jy*n + i] = sum_k2 T[i][k2] Q2[jy][k2]
+__global__ void vp_stage2_kernel(int n, const double* __restrict__ Q2, const double* __restrict__ T,
+                                 double* __restrict__ vp) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    const int jy = e / n, i = e % n;
+    double acc = 0.0;
+    for (int k2 = 0; k2 < n; ++k2) acc += T[i * n + k2] * Q2[jy * n + k2];
+    vp[e] = acc;
+}
+
+void build_basis_device(Basis& b) {
+    const int n = b.n, r = b.r, d_m = n * n;
+    int32_t *k1d = nullptr, *k2d = nullptr;
+    double *Q2 = nullptr, *lamc = nullptr, *T = nullptr;
+    DINO_HIP(hipMalloc(&b.dec, sizeof(double) * (size_t)d_m * r));
+    DINO_HIP(hipMalloc(&b.var_perp, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&b.lam_dev, sizeof(double) * r));
+    DINO_HIP(hipMalloc(&k1d, sizeof(int32_t) * r));
+    DINO_HIP(hipMalloc(&k2d, sizeof(int32_t) * r));
+    DINO_HIP(hipMalloc(&Q2, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&lamc, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&T, sizeof(double) * d_m));
+    DINO_HIP(hipMemcpy(k1d, b.k1.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(k2d, b.k2.data(), sizeof(int32_t) * r, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(b.lam_dev, b.lam.data(), sizeof(double) * r, hipMemcpyHostToDevice));
+    // complement eigenvalue grid lamc[k1][k2] (kept modes zeroed), from the host ordering
+    {
+        const double h = 1.0 / (n - 1);
+        std::vector<double> mu(n), lg((size_t)d_m);
+        for (int k = 0; k < n; ++k) {
+            const double sn = std::sin(M_PI * k / (2.0 * n));
+            mu[k] = 4.0 * sn * sn;
+        }
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                const double s = mu[std::min(a, c)] + mu[std::max(a, c)];
+                const double av = b.gamma * s / (h * h) + b.delta;
+                lg[(size_t)a * n + c] = 1.0 / (av * av);
+            }
+        for (int j = 0; j < r; ++j) lg[(size_t)b.k1[j] * n + b.k2[j]] = 0.0;
+        DINO_HIP(hipMemcpy(lamc, lg.data(), sizeof(double) * d_m, hipMemcpyHostToDevice));
+    }
+    const long total = (long)d_m * r;
+    hipLaunchKernelGGL(basis_dec_kernel, dim3((int)std::min<long>((total + 255) / 256, 16384)), dim3(256), 0, 0, n,
+                       r, k1d, k2d, b.lam_dev, b.dec);
+    const int g = (d_m + 255) / 256;
+    hipLaunchKernelGGL(q2_kernel, dim3(g), dim3(256), 0, 0, n, Q2);
+    hipLaunchKernelGGL(vp_stage1_kernel, dim3(g), dim3(256), 0, 0, n, Q2, lamc, T);
+    hipLaunchKernelGGL(vp_stage2_kernel, dim3(g), dim3(256), 0, 0, n, Q2, T, b.var_perp);
+    DINO_HIP(hipGetLastError());
+    DINO_HIP(hipDeviceSynchronize());
+    hipFree(k1d);
+    hipFree(k2d);
+    hipFree(Q2);
+    hipFree(lamc);
+    hipFree(T);
+}
+
+// ---------------------------------------------------------------------------------
+// Posterior moments from the trace rows [b, N): xbar (r), S (r x r, divide by count).
+__global__ void trace_mean_kernel(long nsamp, int r, const float* __restrict__ X, double* __restrict__ xbar) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    for (long s = threadIdx.x; s < nsamp; s += blockDim.x) acc += (double)X[s * r + j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) xbar[j] = red[0] / (double)nsamp;
+}
+
+__global__ __launch_bounds__(256) void trace_cov_kernel(long nsamp, int r, const float* __restrict__ X,
+                                                        const double* __restrict__ xbar, double* __restrict__ S) {
+    __shared__ double Aj[32][33];
+    __shared__ double Ak[32][33];
+    const int j0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    double acc[2][2] = {{0, 0}, {0, 0}};
+    for (long s0 = 0; s0 < nsamp; s0 += 32) {
+        for (int e = tid; e < 32 * 32; e += 256) {
+            const int ss = e >> 5, jj = e & 31;
+            const long s = s0 + ss;
+            Aj[ss][jj] = (s < nsamp && j0 + jj < r) ? (double)X[s * r + j0 + jj] - xbar[j0 + jj] : 0.0;
+            Ak[ss][jj] = (s < nsamp && k0 + jj < r) ? (double)X[s * r + k0 + jj] - xbar[k0 + jj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int ss = 0; ss < 32; ++ss) {
+            const double a0 = Aj[ss][ty], a1 = Aj[ss][ty + 16], b0 = Ak[ss][tx], b1 = Ak[ss][tx + 16];
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
+        }
+        __syncthreads();
+    }
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + ty + 16 * a, k = k0 + tx + 16 * b;
+            if (j < r && k < r) S[(long)j * r + k] = acc[a][b] / (double)nsamp;
+        }
+}
+
+// mean_p = sum_j dec[p][j] xbar_j ; var_p = dec[p] S dec[p]^T + var_perp[p]
+__global__ void field_moments_kernel(int d_m, int r, const double* __restrict__ dec, const double* __restrict__ xbar,
+                                     const double* __restrict__ S, const double* __restrict__ vp,
+                                     double* __restrict__ mean, double* __restrict__ var) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d_m) return;
+    const double* dp = dec + (long)p * r;
+    double m = 0.0, v = 0.0;
+    for (int j = 0; j < r; ++j) {
+        m += dp[j] * xbar[j];
+        double t = 0.0;
+        for (int k = 0; k < r; ++k) t += S[(long)j * r + k] * dp[k];
+        v += dp[j] * t;
+    }
+    mean[p] = m;
+    var[p] = v + vp[p];
+}
+
+void launch_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S,
+                      hipStream_t st) {
+    const long rows = p->recorded - burn_in;
+    const long nsamp = rows * p->C;
+    const float* X = p->xtrace + (long)burn_in * p->C * p->r;
+    const int r = p->r;
+    hipLaunchKernelGGL(trace_mean_kernel, dim3(r), dim3(256), 0, st, nsamp, r, X, xbar);
+    const int t = (r + 31) / 32;
+    hipLaunchKernelGGL(trace_cov_kernel, dim3(t, t), dim3(256), 0, st, nsamp, r, X, xbar, S);
+    const Basis& b = p->ctx->basis;
+    hipLaunchKernelGGL(field_moments_kernel, dim3((b.d_m + 127) / 128), dim3(128), 0, st, b.d_m, r, b.dec, xbar, S,
+                       b.var_perp, mean, var);
+    DINO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------------
+// ESS fraction per coordinate (eq. ess reading). Y[j][c][i] holds centred samples
+// (chain means removed); one block per coordinate walks the lags in pairs.
+__global__ void ess_center_kernel(int n, int C, int r, const float* __restrict__ X, double* __restrict__ Y,
+                                  double* __restrict__ cmean) {
+    const int j = blockIdx.x, c = blockIdx.y;
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)X[((long)i * C + c) * r + j];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double m = red[0] / n;
+    if (threadIdx.x == 0) cmean[(long)j * C + c] = m;
+    double* y = Y + ((long)j * C + c) * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = (double)X[((long)i * C + c) * r + j] - m;
+}
+
+__device__ double block_reduce_256(double v, double* red) {
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// sum over chains of the biased lag-t autocovariance numerators: sum_c sum_i y_ci y_c(i+t)
+__device__ double lag_sum(const double* y, int C, int n, int t, double* red) {
+    double acc = 0.0;
+    const long m = n - t;
+    for (long e = threadIdx.x; e < (long)C * m; e += blockDim.x) {
+        const long c = e / m, i = e % m;
+        acc += y[c * n + i] * y[c * n + i + t];
+    }
+    return block_reduce_256(acc, red);
+}
+
+__global__ void ess_kernel(int n, int C, const double* __restrict__ Y, const double* __restrict__ cmean,
+                           double* __restrict__ ess) {
+    __shared__ double red[256];
+    const int j = blockIdx.x;
+    const double* y = Y + (long)j * C * n;
+    // w: mean within-chain variance (divide by n - 1); v: pooled variance
+    const double ss = lag_sum(y, C, n, 0, red);
+    const double w = ss / ((double)C * (n - 1));
+    double gm = 0.0;
+    for (int c = 0; c < C; ++c) gm += cmean[(long)j * C + c];
+    gm /= C;
+    double bsum = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const double d = cmean[(long)j * C + c] - gm;
+        bsum += d * d;
+    }
+    double v = (double)(n - 1) / n * w;
+    if (C > 1) v += (double)(C + 1) / ((double)C * (C - 1)) * bsum;
+    if (!(v > 0.0)) {
+        if (threadIdx.x == 0) ess[j] = NAN;
+        return;
+    }
+    auto rho = [&](int t) {
+        const double ac = lag_sum(y, C, n, t, red) / ((double)n * C);
+        return 1.0 - (w - ac) / v;
+    };
+    double total = 0.0;
+    for (int tp = 0; 2 * tp + 1 < n; ++tp) {
+        const double re = (tp == 0) ? 1.0 : rho(2 * tp);
+        const double ro = rho(2 * tp + 1);
+        if (re + ro <= 0.0) break;
+        total += (tp > 0 ? re : 0.0) + ro;
+    }
+    if (threadIdx.x == 0) ess[j] = 1.0 / (1.0 + 2.0 * total);
+}
+
+void launch_ess(dino_problem* p, int burn_in, double* ess, hipStream_t st) {
+    const int n = (int)(p->recorded - burn_in), C = p->C, r = p->r;
+    double *Y = nullptr, *cm = nullptr;
+    DINO_HIP(hipMalloc(&Y, sizeof(double) * (size_t)r * C * n));
+    DINO_HIP(hipMalloc(&cm, sizeof(double) * (size_t)r * C));
+    const float* X = p->xtrace + (long)burn_in * C * r;
+    hipLaunchKernelGGL(ess_center_kernel, dim3(r, C), dim3(256), 0, st, n, C, r, X, Y, cm);
+    hipLaunchKernelGGL(ess_kernel, dim3(r), dim3(256), 0, st, n, C, Y, cm, ess);
+    DINO_HIP(hipGetLastError());
+    DINO_HIP(hipStreamSynchronize(st));
+    hipFree(Y);
+    hipFree(cm);
+}
+
+}  // namespace dino

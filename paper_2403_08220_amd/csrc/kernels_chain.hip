@@ -1,0 +1,576 @@
+// Per-chain FP64 kernels of the reduced mMALA transition:
+//  * Cholesky factor of I + H (replaces the eigendecomposition of Sec. 5.2),
+//  * reduced proposal (Prop. 4.2 item 2, eq. reduced_space_sampling),
+//  * reduced RN derivative and first-stage ratio (Sec. 5.4, eq. da_dino_trr_1),
+//  * MH decision (Alg. 1: reject iff alpha < xi_1) and state swap,
+//  * pCN move of the complement (Prop. 4.2 item 1), trace rows, draws.
+#include "dino_internal.hpp"
+
+namespace dino {
+
+constexpr int TPB = 256;      // threads per block of the per-chain kernels
+constexpr int MAXR = 512;     // largest reduced dimension of the per-chain kernels
+constexpr int SB = 32;        // block size of the triangular solves
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum over the block of one value per thread; red must hold TPB/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int k = 0; k < TPB / 64; ++k) t += red[k];
+    return t;
+}
+
+// out_j = sum_{i >= j} L[i][j] v_i  (L^T v). Waves take rows i = wave (mod 4); lanes
+// read 64 consecutive columns of a row; partial sums reduced through part[4][MAXR].
+__device__ void lt_matvec(const double* __restrict__ L, int r, const double* v, double* out, double* part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int jb = 0; jb < r; jb += 64) {
+        const int j = jb + lane;
+        double acc = 0.0;
+        if (j < r)
+            for (int i = jb + ((wave - jb) & 3); i < r; i += 4)
+                if (i >= j) acc += L[(long)i * r + j] * v[i];
+        if (j < r) part[wave * MAXR + j] = acc;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < r; j += TPB)
+        out[j] = part[j] + part[MAXR + j] + part[2 * MAXR + j] + part[3 * MAXR + j];
+    __syncthreads();
+}
+
+// out_i = sum_{j <= i} L[i][j] v_j  (L v). Rows in passes of 16: 16 threads per row,
+// each reading 4 consecutive columns per 64-column step; shuffle-reduced per row.
+__device__ void l_matvec(const double* __restrict__ L, int r, const double* v, double* out) {
+    const int sub = threadIdx.x & 15, rloc = threadIdx.x >> 4;
+    for (int i0 = 0; i0 < r; i0 += 16) {
+        const int i = i0 + rloc;
+        double acc = 0.0;
+        if (i < r)
+            for (int j = 4 * sub; j <= i; j += 64)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q <= i) acc += L[(long)i * r + j + q] * v[j + q];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        if (i < r && sub == 0) out[i] = acc;
+    }
+    __syncthreads();
+}
+
+// Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
+// a block first subtract the already solved part (8 threads per row), then lanes
+// 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
+__device__ void l_solve(const double* __restrict__ L, int r, const double* b, double* w, double* acc_s) {
+    const int tid = threadIdx.x;
+    for (int b0 = 0; b0 < r; b0 += SB) {
+        const int nb = min(SB, r - b0);
+        {
+            const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
+            const int i = b0 + il;
+            double acc = 0.0;
+            if (il < nb)
+                for (int j = 4 * sub; j < b0; j += 32)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (j + q < b0) acc += L[(long)i * r + j + q] * w[j + q];
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (il < nb && sub == 0) acc_s[il] = b[i] - acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            double row[SB];
+            double a = 0.0;
+            if (lane < nb) {
+#pragma unroll
+                for (int jj = 0; jj < SB; ++jj) row[jj] = (jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+                a = acc_s[lane];
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < SB; ++jj) row[jj] = 0.0;
+            }
+            double sol = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj) {
+                if (jj < nb) {
+                    const double wj = __shfl(a / row[jj], jj);  // valid on lane jj
+                    if (lane == jj) sol = wj;
+                    if (lane > jj) a -= row[jj] * wj;
+                }
+            }
+            if (lane < nb) w[b0 + lane] = sol;
+        }
+        __syncthreads();
+    }
+}
+
+// Backward substitution L^T x = b. Blocks from the bottom: rows of the block subtract
+// the solved part below through column reads (32 consecutive columns per row), then
+// lanes 0..SB-1 of wave 0 finish the block's transposed triangle.
+__device__ void lt_solve(const double* __restrict__ L, int r, const double* b, double* x, double* part) {
+    const int tid = threadIdx.x;
+    const int nblk = (r + SB - 1) / SB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int b0 = bi * SB;
+        const int nb = min(SB, r - b0);
+        {
+            const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
+            double acc = 0.0;
+            if (il < nb)
+                for (int j = b0 + nb + grp; j < r; j += 8) acc += L[(long)j * r + b0 + il] * x[j];
+            part[grp * SB + il] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            double col[SB];
+            double a = 0.0;
+            if (lane < nb) {
+                double s = 0.0;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) s += part[g * SB + lane];
+                a = b[b0 + lane] - s;
+#pragma unroll
+                for (int jj = 0; jj < SB; ++jj)
+                    col[jj] = (jj >= lane && jj < nb) ? L[(long)(b0 + jj) * r + b0 + lane] : 0.0;
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < SB; ++jj) col[jj] = 0.0;
+            }
+            double sol = 0.0;
+#pragma unroll
+            for (int jj = SB - 1; jj >= 0; --jj) {
+                if (jj < nb) {
+                    const double xj = __shfl(a / col[jj], jj);
+                    if (lane == jj) sol = xj;
+                    if (lane < jj) a -= col[jj] * xj;
+                }
+            }
+            if (lane < nb) x[b0 + lane] = sol;
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ long slot_offset(const int32_t* slot, int slot_xor, long slot_stride, int c) {
+    return slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0;
+}
+
+// ---------------------------------------------------------------------------------
+// In-place Cholesky of A_c (r x r, lower triangle read and written): right-looking
+// with 32-column panels factored in LDS; trailing update in 4x4 register blocks.
+constexpr int CNB = 32;
+constexpr int CLDP = CNB + 1;
+
+__global__ __launch_bounds__(TPB) void cholesky_kernel(int r, double* A, long strideA, const int32_t* slot,
+                                                       int slot_xor, long slot_stride, double* logdet,
+                                                       int32_t* ok) {
+    extern __shared__ double P[];  // r x CLDP
+    __shared__ int fail;
+    __shared__ double ld_acc;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    double* a = A + (long)c * strideA + slot_offset(slot, slot_xor, slot_stride, c);
+    if (tid == 0) {
+        fail = 0;
+        ld_acc = 0.0;
+    }
+    for (int j0 = 0; j0 < r; j0 += CNB) {
+        const int jb = min(CNB, r - j0), rows = r - j0;
+        for (int e = tid; e < rows * CNB; e += TPB) {
+            const int i = e / CNB, jj = e % CNB;
+            if (jj < jb) P[i * CLDP + jj] = a[(long)(j0 + i) * r + j0 + jj];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < jb; ++jj) {
+            const double piv = P[jj * CLDP + jj];
+            const double dgl = sqrt(piv);
+            const double inv = 1.0 / dgl;
+            __syncthreads();
+            if (tid == 0) {
+                if (!(piv > 0.0)) fail = 1;
+                else ld_acc += log(dgl);
+                P[jj * CLDP + jj] = dgl;
+            }
+            for (int i = jj + 1 + tid; i < rows; i += TPB) P[i * CLDP + jj] *= inv;
+            __syncthreads();
+            const int ncol = jb - jj - 1;
+            if (ncol > 0) {
+                const int nrow = rows - jj - 1;
+                for (int e = tid; e < nrow * ncol; e += TPB) {
+                    const int i = jj + 1 + e / ncol, k = jj + 1 + e % ncol;
+                    if (k <= i) P[i * CLDP + k] -= P[i * CLDP + jj] * P[k * CLDP + jj];
+                }
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < rows * CNB; e += TPB) {
+            const int i = e / CNB, jj = e % CNB;
+            if (jj < jb && jj <= i) a[(long)(j0 + i) * r + j0 + jj] = P[i * CLDP + jj];
+        }
+        const int t0 = j0 + jb, T = r - t0;
+        if (T > 0) {
+            const int nbk = (T + 3) / 4;
+            const int nblocks = nbk * (nbk + 1) / 2;
+            for (int bidx = tid; bidx < nblocks; bidx += TPB) {
+                int bi = (int)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) * 0.5);
+                while ((bi + 1) * (bi + 2) / 2 <= bidx) ++bi;
+                while (bi * (bi + 1) / 2 > bidx) --bi;
+                const int bk = bidx - bi * (bi + 1) / 2;
+                double acc[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) acc[q][s] = 0.0;
+                for (int jj = 0; jj < jb; ++jj) {
+                    double pi[4], pk[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int li = 4 * bi + q, lk = 4 * bk + q;
+                        pi[q] = (li < T) ? P[(jb + li) * CLDP + jj] : 0.0;
+                        pk[q] = (lk < T) ? P[(jb + lk) * CLDP + jj] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) acc[q][s] += pi[q] * pk[s];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const int i = t0 + 4 * bi + q, k = t0 + 4 * bk + s;
+                        if (i < r && k <= i) a[(long)i * r + k] -= acc[q][s];
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (logdet) logdet[c] = ld_acc;
+        if (ok) ok[c] = fail ? 0 : 1;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi).
+// lfwd (optional) = log rho_0(x -> xp) = -|xi|^2/2 + |mhat|^2/2 + logdet_x, the
+// mMALA over pCN log-density ratio at the drawn point, mhat = (xp - s x)/beta.
+__global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double beta, uint64_t seed, uint64_t rid,
+                                                      int64_t step, const double* __restrict__ x,
+                                                      const double* __restrict__ g, const double* L, long strideL,
+                                                      const int32_t* slot, int slot_xor, long slot_stride,
+                                                      const double* __restrict__ xi_given,
+                                                      const double* __restrict__ logdet, double* __restrict__ xp,
+                                                      double* __restrict__ lfwd) {
+    __shared__ double xs[MAXR], gs[MAXR], u[MAXR], t[MAXR], w[MAXR], xi[MAXR];
+    __shared__ double part[4 * MAXR];
+    __shared__ double red[TPB / 64];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const double* Lc = L + (long)c * strideL + slot_offset(slot, slot_xor, slot_stride, c);
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        gs[j] = g[(long)c * r + j];
+    }
+    if (xi_given) {
+        for (int j = tid; j < r; j += TPB) xi[j] = xi_given[(long)c * r + j];
+    } else {
+        for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
+            double nv[4];
+            philox_normals4(seed, rid, (uint64_t)b4, STREAM_XI, (uint64_t)step, (uint64_t)c, nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * b4 + q < r) xi[4 * b4 + q] = nv[q];
+        }
+    }
+    __syncthreads();
+    lt_matvec(Lc, r, xs, u, part);
+    l_matvec(Lc, r, u, t);
+    for (int j = tid; j < r; j += TPB) t[j] -= (1.0 - s) * (xs[j] + gs[j]);
+    __syncthreads();
+    l_solve(Lc, r, t, w, part);
+    for (int j = tid; j < r; j += TPB) w[j] += beta * xi[j];
+    __syncthreads();
+    lt_solve(Lc, r, w, u, part);
+    double nxi = 0.0, nm = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        xp[(long)c * r + j] = u[j];
+        const double m = (u[j] - s * xs[j]) / beta;
+        nxi += xi[j] * xi[j];
+        nm += m * m;
+    }
+    if (lfwd) {
+        nxi = block_sum(nxi, red);
+        nm = block_sum(nm, red);
+        if (tid == 0) lfwd[c] = -0.5 * nxi + 0.5 * nm + logdet[c];
+    }
+}
+
+// log rho_0(a -> b) with the cache (g_a, L_a, logdet_a) of a, Sec. 5.4 with
+// I + H = L L^T:  -(dt/8)|L^-1 v|^2 + (sqrt(dt)/2) mhat.v - (|L^T mhat|^2 - |mhat|^2)/2
+// + logdet, v = H a - g = L L^T a - a - g, mhat = (b - s a)/beta.
+// Uses L^-1 v = L^T a - L^-1 (a + g) and mhat.v = (L^T mhat).(L^T a) - mhat.(a + g).
+__device__ double log_rho0_dev(const double* La, int r, double dt, double s, double beta, const double* a,
+                               const double* b, const double* ga, double logdet_a, double* u1, double* w2,
+                               double* m, double* u2, double* tmp, double* part, double* red) {
+    const int tid = threadIdx.x;
+    for (int j = tid; j < r; j += TPB) {
+        tmp[j] = a[j] + ga[j];
+        m[j] = (b[j] - s * a[j]) / beta;
+    }
+    __syncthreads();
+    lt_matvec(La, r, a, u1, part);
+    lt_matvec(La, r, m, u2, part);
+    l_solve(La, r, tmp, w2, part);
+    double q1 = 0.0, d1 = 0.0, d2 = 0.0, n2 = 0.0, n3 = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        const double lv = u1[j] - w2[j];
+        q1 += lv * lv;
+        d1 += u2[j] * u1[j];
+        d2 += m[j] * tmp[j];
+        n2 += u2[j] * u2[j];
+        n3 += m[j] * m[j];
+    }
+    q1 = block_sum(q1, red);
+    d1 = block_sum(d1, red);
+    d2 = block_sum(d2, red);
+    n2 = block_sum(n2, red);
+    n3 = block_sum(n3, red);
+    return -(dt / 8.0) * q1 + 0.5 * sqrt(dt) * (d1 - d2) - 0.5 * (n2 - n3) + logdet_a;
+}
+
+__global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s, double beta, const double* x,
+                                                      const double* phi_x, const double* g_x, const double* L_x,
+                                                      const double* logdet_x, const double* xp,
+                                                      const double* phi_p, const double* g_p, const double* L_p,
+                                                      const double* logdet_p, double* out) {
+    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR];
+    __shared__ double part[4 * MAXR];
+    __shared__ double red[TPB / 64];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const long rr = (long)r * r;
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        ps[j] = xp[(long)c * r + j];
+        ga[j] = g_x[(long)c * r + j];
+    }
+    __syncthreads();
+    const double fwd = log_rho0_dev(L_x + c * rr, r, dt, s, beta, xs, ps, ga, logdet_x[c], u1, w2, m, u2, tmp,
+                                    part, red);
+    for (int j = tid; j < r; j += TPB) ga[j] = g_p[(long)c * r + j];
+    __syncthreads();
+    const double rev = log_rho0_dev(L_p + c * rr, r, dt, s, beta, ps, xs, ga, logdet_p[c], u1, w2, m, u2, tmp,
+                                    part, red);
+    if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
+}
+
+// MH decision of the first stage and the swap of state and cache on acceptance.
+__global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s, double beta, uint64_t seed,
+                                                     uint64_t rid, int64_t step, double* x, double* g, double* phi,
+                                                     double* logdet, const double* Lbuf, long half,
+                                                     int32_t* cur, const double* xp, const double* gp,
+                                                     const double* phip, const double* logdetp,
+                                                     const int32_t* okp, const double* lfwd, int64_t* accepts,
+                                                     int64_t* failures, int32_t* accflag) {
+    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR];
+    __shared__ double part[4 * MAXR];
+    __shared__ double red[TPB / 64];
+    __shared__ int decision;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const long rr = (long)r * r;
+    const int other = cur[c] ^ 1;
+    const double* Lp = Lbuf + (long)other * half + c * rr;
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        ps[j] = xp[(long)c * r + j];
+        ga[j] = gp[(long)c * r + j];
+    }
+    __syncthreads();
+    const int okc = okp[c];
+    double rev = 0.0;
+    if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red);
+    if (tid == 0) {
+        const double lr = phi[c] - phip[c] + rev - lfwd[c];
+        const double u = philox_uniform(seed, rid, (uint64_t)step, (uint64_t)c);
+        const bool good = okc && isfinite(lr);
+        const bool accept = good && (log(u) <= lr);
+        decision = accept ? 1 : 0;
+        if (!good) failures[c] += 1;
+        if (accept) {
+            accepts[c] += 1;
+            phi[c] = phip[c];
+            logdet[c] = logdetp[c];
+            cur[c] = other;
+        }
+        accflag[c] = decision;
+    }
+    __syncthreads();
+    if (decision) {
+        for (int j = tid; j < r; j += TPB) {
+            x[(long)c * r + j] = ps[j];
+            g[(long)c * r + j] = ga[j];
+        }
+    }
+}
+
+// pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state).
+__global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta,
+                                                         uint64_t seed, uint64_t rid, int64_t step,
+                                                         const int32_t* __restrict__ accflag, float* z) {
+    const int c = blockIdx.y;
+    if (!accflag[c]) return;
+    const int b4 = blockIdx.x * TPB + threadIdx.x;
+    const int j0 = 4 * b4;
+    if (j0 >= d_perp) return;
+    double nv[4];
+    philox_normals4(seed, rid, (uint64_t)b4, STREAM_COMPLEMENT, (uint64_t)step, (uint64_t)c, nv);
+    float* zc = z + (long)c * ldz;
+    if (j0 + 3 < d_perp) {
+        float4 v = *reinterpret_cast<const float4*>(zc + j0);
+        v.x = (float)(s * (double)v.x + beta * nv[0]);
+        v.y = (float)(s * (double)v.y + beta * nv[1]);
+        v.z = (float)(s * (double)v.z + beta * nv[2]);
+        v.w = (float)(s * (double)v.w + beta * nv[3]);
+        *reinterpret_cast<float4*>(zc + j0) = v;
+    } else {
+        for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)(s * (double)zc[j0 + q] + beta * nv[q]);
+    }
+}
+
+__global__ void trace_kernel(int C, int r, const double* __restrict__ x, const double* __restrict__ phi,
+                             float* __restrict__ xrow, double* __restrict__ phirow) {
+    const long total = (long)C * r;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+        xrow[e] = (float)x[e];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) phirow[c] = phi[c];
+}
+
+// Normals of one stream for n chains at one step: out[c][k], k < count.
+__global__ void normals_kernel(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count,
+                               double* out, long ldo, int as_float, float* outf) {
+    const int c = blockIdx.y;
+    const int b4 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || 4 * b4 >= count) return;
+    double nv[4];
+    philox_normals4(seed, rid, (uint64_t)b4, (uint64_t)stream_id, (uint64_t)step, (uint64_t)c, nv);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = 4 * b4 + q;
+        if (k < count) {
+            if (as_float) outf[(long)c * ldo + k] = (float)nv[q];
+            else out[(long)c * ldo + k] = nv[q];
+        }
+    }
+}
+
+__global__ void copy_rows_kernel(int n, int width, const double* __restrict__ src, double* __restrict__ dst) {
+    const long total = (long)n * width;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
+// ---------------------------------------------------------------------------------
+static size_t chol_lds(int r) { return (size_t)r * CLDP * sizeof(double); }
+
+void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                          long slot_stride, double* logdet, int32_t* ok, hipStream_t st) {
+    const size_t lds = chol_lds(r);
+    static bool attr_set = false;
+    if (!attr_set) {
+        DINO_HIP(hipFuncSetAttribute((const void*)cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024 - 256));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), lds, st, r, A, strideA, slot, slot_xor, slot_stride,
+                       logdet, ok);
+    DINO_HIP(hipGetLastError());
+}
+
+
+void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
+                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given,
+                         int64_t step, double* xp, double* lfwd, const double* logdet, hipStream_t st) {
+    hipLaunchKernelGGL(propose_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->s, p->beta, p->desc.seed,
+                       p->desc.request_id, step, x, g, L, strideL, slot, slot_xor, slot_stride, xi_given, logdet,
+                       xp, lfwd);
+    DINO_HIP(hipGetLastError());
+}
+
+
+void launch_accept(dino_problem* p, int64_t step, hipStream_t st) {
+    const long half = (long)p->C * p->r * p->r;
+    hipLaunchKernelGGL(accept_kernel, dim3(p->C), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->desc.seed,
+                       p->desc.request_id, step, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp,
+                       p->gp, p->phip, p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                    const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
+                    const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st) {
+    hipLaunchKernelGGL(log_rho_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, x, phi_x, g_x,
+                       L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, out);
+    DINO_HIP(hipGetLastError());
+}
+
+static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
+
+void launch_complement(dino_problem* p, int64_t step, hipStream_t st) {
+    if (!p->z || p->d_perp == 0) return;
+    const int nb4 = (p->d_perp + 3) / 4;
+    dim3 grid((nb4 + TPB - 1) / TPB, p->C);
+    hipLaunchKernelGGL(complement_kernel, grid, dim3(TPB), 0, st, p->d_perp, ldz_of(p->d_perp), p->s, p->beta,
+                       p->desc.seed, p->desc.request_id, step, p->acc, p->z);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_trace(dino_problem* p, int64_t row, hipStream_t st) {
+    const long total = (long)p->C * p->r;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 2048);
+    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(256), 0, st, p->C, p->r, p->x, p->phi,
+                       p->xtrace + row * total, p->phitrace + row * p->C);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st) {
+    if (draw_x) {
+        dim3 grid(((p->r + 3) / 4 + 255) / 256, p->C);
+        hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, p->desc.seed, p->desc.request_id, p->C,
+                           (int)STREAM_INIT_X, (int64_t)0, p->r, p->x, (long)p->r, 0, (float*)nullptr);
+    }
+    if (draw_z && p->z) {
+        dim3 grid(((p->d_perp + 3) / 4 + 255) / 256, p->C);
+        hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, p->desc.seed, p->desc.request_id, p->C,
+                           (int)STREAM_INIT_Z, (int64_t)0, p->d_perp, (double*)nullptr, (long)ldz_of(p->d_perp),
+                           1, p->z);
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_normals(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count, double* out,
+                    hipStream_t st) {
+    dim3 grid(((count + 3) / 4 + 255) / 256, n);
+    hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, seed, rid, n, stream_id, step, count, out,
+                       (long)count, 0, (float*)nullptr);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_copy_rows(int n, int width, const double* src, double* dst, hipStream_t st) {
+    const long total = (long)n * width;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(copy_rows_kernel, dim3(blocks), dim3(256), 0, st, n, width, src, dst);
+    DINO_HIP(hipGetLastError());
+}
+
+}  // namespace dino

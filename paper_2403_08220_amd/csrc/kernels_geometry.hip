@@ -1,0 +1,324 @@
+// Surrogate forward, reduced Jacobian (reverse mode) and the reduced misfit,
+// ppg and Gauss-Newton Hessian (Sec. 4 eq. rb_dino and the reduced Jacobian;
+// Sec. 5.1 eqs. surrogate_rppg, surrogate_rppgnh) - FP64 path kernels.
+#include "dino_internal.hpp"
+
+namespace dino {
+
+template <typename T>
+__device__ __forceinline__ T gelu_t(T z);
+template <>
+__device__ __forceinline__ double gelu_t<double>(double z) {
+    return 0.5 * z * (1.0 + erf(z * 0.70710678118654752440));
+}
+template <>
+__device__ __forceinline__ float gelu_t<float>(float z) {
+    return 0.5f * z * (1.0f + erff(z * 0.70710678f));
+}
+template <typename T>
+__device__ __forceinline__ T gelu_prime_t(T z);
+template <>
+__device__ __forceinline__ double gelu_prime_t<double>(double z) {
+    return 0.5 * (1.0 + erf(z * 0.70710678118654752440)) + z * 0.39894228040143267794 * exp(-0.5 * z * z);
+}
+template <>
+__device__ __forceinline__ float gelu_prime_t<float>(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678f)) + z * 0.39894228f * expf(-0.5f * z * z);
+}
+
+// ---------------------------------------------------------------------------------
+// Forward layer: out[m][n] = epi(sum_k in[m][k] W[n][k] + b[n]).
+// Tile 64 (rows) x 64 (outputs) x 16 (k); 256 threads, 4x4 outputs each at
+// rows ty + 16 i, columns tx + 16 j.
+template <typename T>
+__global__ __launch_bounds__(256) void fwd_layer_kernel(int M, int K, int N, const T* __restrict__ in, int ldin,
+                                                        const T* __restrict__ W, const T* __restrict__ b,
+                                                        int kind, T* __restrict__ out, int ldout,
+                                                        T* __restrict__ dprime, int ldd) {
+    __shared__ T As[16][64 + 1];
+    __shared__ T Ws[16][64 + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = ty + 16 * q, k = k0 + tx;
+            As[tx][row] = (m0 + row < M && k < K) ? in[(long)(m0 + row) * ldin + k] : T(0);
+            Ws[tx][row] = (n0 + row < N && k < K) ? W[(long)(n0 + row) * K + k] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            T a[4], w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = Ws[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * w[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + ty + 16 * i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + tx + 16 * j;
+            if (n >= N) continue;
+            const T z = acc[i][j] + (b ? b[n] : T(0));
+            T o;
+            if (kind == DINO_LAYER_LINEAR) {
+                o = z;
+            } else {
+                o = gelu_t<T>(z);
+                if (kind == DINO_LAYER_RESID) o += in[(long)m * ldin + n];
+                if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<T>(z);
+            }
+            out[(long)m * ldout + n] = o;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Reverse sweep layer on rows R = (chain, output): out[R][n] = (resid ? lam[R][n] : 0)
+//   + sum_k lam[R][k] * (d ? d[R / dy][k] : 1) * W[k][n],  W of shape K x N (fan_out x fan_in).
+template <typename T>
+__global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int dy, const T* __restrict__ lam,
+                                                        int ldl, const T* __restrict__ d, int ldd,
+                                                        const T* __restrict__ W, int resid, T* __restrict__ out,
+                                                        int ldo) {
+    __shared__ T As[16][64 + 1];
+    __shared__ T Bs[16][64 + 1];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    T acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = ty + 16 * q, k = k0 + tx;
+            T v = T(0);
+            if (m0 + row < M && k < K) {
+                v = lam[(long)(m0 + row) * ldl + k];
+                if (d) v *= d[(long)((m0 + row) / dy) * ldd + k];
+            }
+            As[tx][row] = v;
+            // B tile: 16 k-rows x 64 n-columns, thread t -> k = t / 64 + 4 q, n = t % 64
+            const int kb = (tid >> 6) + 4 * q, nb = tid & 63;
+            Bs[kb][nb] = (k0 + kb < K && n0 + nb < N) ? W[(long)(k0 + kb) * N + n0 + nb] : T(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            T a[4], w[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) w[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * w[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int m = m0 + ty + 16 * i;
+        if (m >= M) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int n = n0 + tx + 16 * j;
+            if (n >= N) continue;
+            T o = acc[i][j];
+            if (resid) o += lam[(long)m * ldl + n];
+            out[(long)m * ldo + n] = o;
+        }
+    }
+}
+
+// Lambda_L = diag(winv) W_out[:dy, :] for every chain: rows (c, i).
+template <typename T>
+__global__ void rev_init_kernel(int n, int dy, int w, const T* __restrict__ Wout, const double* __restrict__ winv,
+                                T* __restrict__ lam, int ldl) {
+    const long total = (long)n * dy * w;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int k = (int)(e % w);
+        const long R = e / w;
+        const int i = (int)(R % dy);
+        lam[R * ldl + k] = (T)(winv[i]) * Wout[(long)i * w + k];
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Misfit and reduced ppg per chain: e = winv (f - y), phi = |e|^2 / 2, g = B^T e.
+__global__ __launch_bounds__(256) void misfit_grad_kernel(int n, int dy, int r, const double* __restrict__ f,
+                                                          const double* __restrict__ y,
+                                                          const double* __restrict__ winv,
+                                                          const double* __restrict__ B, double* __restrict__ phi,
+                                                          double* __restrict__ g) {
+    __shared__ double e[1024];
+    __shared__ double red[4];
+    const int c = blockIdx.x;
+    const int tid = threadIdx.x;
+    double part = 0.0;
+    for (int i = tid; i < dy; i += blockDim.x) {
+        const double w = winv[i];
+        const double v = (w == 0.0) ? 0.0 : (f[(long)c * dy + i] - y[i]) * w;
+        e[i] = v;
+        part += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) phi[c] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
+    const double* Bc = B + (long)c * dy * r;
+    for (int j = tid; j < r; j += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < dy; ++i) acc += Bc[(long)i * r + j] * e[i];
+        g[(long)c * r + j] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// A_c = I + B_c^T B_c (or B_c^T B_c): tile 32 x 32 of the r x r output per block.
+__global__ __launch_bounds__(256) void gn_hessian_kernel(int dy, int r, const double* __restrict__ B, double* A,
+                                                         long strideA, const int32_t* __restrict__ slot,
+                                                         int slot_xor, long slot_stride, int add_identity,
+                                                         int full) {
+    __shared__ double Bj[16][33];
+    __shared__ double Bk[16][33];
+    const int c = blockIdx.z;
+    const int j0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
+    if (!full && k0 > j0 + 31) return;  // upper tiles: not needed by the lower Cholesky
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const double* Bc = B + (long)c * dy * r;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int i0 = 0; i0 < dy; i0 += 16) {
+        for (int e = tid; e < 16 * 32; e += 256) {
+            const int ii = e >> 5, jj = e & 31;
+            const bool okr = i0 + ii < dy;
+            Bj[ii][jj] = (okr && j0 + jj < r) ? Bc[(long)(i0 + ii) * r + j0 + jj] : 0.0;
+            Bk[ii][jj] = (okr && k0 + jj < r) ? Bc[(long)(i0 + ii) * r + k0 + jj] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+            const double a0 = Bj[ii][ty], a1 = Bj[ii][ty + 16];
+            const double b0 = Bk[ii][tx], b1 = Bk[ii][tx + 16];
+            acc[0][0] += a0 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][0] += a1 * b0;
+            acc[1][1] += a1 * b1;
+        }
+        __syncthreads();
+    }
+    const long off = (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    double* Ac = A + off;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int j = j0 + ty + 16 * a, k = k0 + tx + 16 * b;
+            if (j < r && k < r) Ac[(long)j * r + k] = acc[a][b] + ((add_identity && j == k) ? 1.0 : 0.0);
+        }
+}
+
+// ---------------------------------------------------------------------------------
+// Host launchers.
+static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
+
+void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipStream_t st) {
+    const dino_ctx* ctx = p->ctx;
+    const int L = (int)ctx->layers.size();
+    const double* in = x;
+    int ldin = p->r;
+    int act = 0;
+    for (int l = 0; l < L; ++l) {
+        const Layer& ly = ctx->layers[l];
+        const bool last = (l == L - 1);
+        double* out;
+        int ldout;
+        if (last) {
+            // only the observed outputs are needed
+            out = f_out;
+            ldout = p->d_y;
+        } else {
+            out = (l % 2 == 0) ? p->h0 : p->h1;
+            ldout = p->wmax;
+        }
+        const int N = last ? p->d_y : ly.fan_out;
+        double* dp = nullptr;
+        if (ly.kind != DINO_LAYER_LINEAR) dp = p->dprime + (long)act * p->C * p->wmax;
+        hipLaunchKernelGGL(fwd_layer_kernel<double>, grid2(n, N), dim3(256), 0, st, n, ly.fan_in, N, in, ldin,
+                           ly.W64, ly.b64, ly.kind, out, ldout, dp, p->wmax);
+        if (ly.kind != DINO_LAYER_LINEAR) ++act;
+        in = out;
+        ldin = ldout;
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t st) {
+    const dino_ctx* ctx = p->ctx;
+    const int L = (int)ctx->layers.size();
+    const int dy = p->d_y;
+    const Layer& outl = ctx->layers[L - 1];
+    double* cur = p->lam0;
+    double* nxt = p->lam1;
+    const int ld = p->wmax;
+    {
+        const long total = (long)n * dy * outl.fan_in;
+        const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+        hipLaunchKernelGGL(rev_init_kernel<double>, dim3(blocks), dim3(256), 0, st, n, dy, outl.fan_in, outl.W64,
+                           p->winv, cur, ld);
+    }
+    int act = p->n_act;
+    const int M = n * dy;
+    for (int l = L - 2; l >= 0; --l) {
+        const Layer& ly = ctx->layers[l];
+        const double* d = nullptr;
+        if (ly.kind != DINO_LAYER_LINEAR) {
+            --act;
+            d = p->dprime + (long)act * p->C * p->wmax;
+        }
+        const bool first = (l == 0);
+        double* out = first ? B_out : nxt;
+        const int ldo = first ? p->r : ld;
+        hipLaunchKernelGGL(rev_layer_kernel<double>, grid2(M, ly.fan_in), dim3(256), 0, st, M, ly.fan_out,
+                           ly.fan_in, dy, cur, ld, d, p->wmax, ly.W64, ly.kind == DINO_LAYER_RESID ? 1 : 0, out,
+                           ldo);
+        if (!first) std::swap(cur, nxt);
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_misfit_grad(dino_problem* p, int n, const double* f, const double* B, double* phi, double* g,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(misfit_grad_kernel, dim3(n), dim3(256), 0, st, n, p->d_y, p->r, f, p->y, p->winv, B, phi,
+                       g);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, long strideA,
+                            const int32_t* slot, int slot_xor, long slot_stride, int add_identity, int full,
+                            hipStream_t st) {
+    const int t = (p->r + 31) / 32;
+    hipLaunchKernelGGL(gn_hessian_kernel, dim3(t, t, n), dim3(256), 0, st, p->d_y, p->r, B, A, strideA, slot,
+                       slot_xor, slot_stride, add_identity, full);
+    DINO_HIP(hipGetLastError());
+}
+
+}  // namespace dino

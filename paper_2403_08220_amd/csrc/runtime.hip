@@ -1,0 +1,653 @@
+// C ABI of the DINO-mMALA library: contexts, prior/basis, network, problems,
+// the step loop, reads and stage entry points. See include/dino.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <numeric>
+
+#include "dino_internal.hpp"
+
+namespace dino {
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+void clear_error() { g_error.clear(); }
+
+template <typename F>
+static dino_status guarded(F&& fn) {
+    try {
+        fn();
+        return DINO_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return DINO_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return DINO_EDEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return DINO_EDEVICE;
+    }
+}
+
+static void free_basis(Basis& b) {
+    if (b.dec) hipFree(b.dec);
+    if (b.var_perp) hipFree(b.var_perp);
+    if (b.lam_dev) hipFree(b.lam_dev);
+    b.dec = b.var_perp = b.lam_dev = nullptr;
+}
+
+static void free_layers(std::vector<Layer>& ls) {
+    for (auto& l : ls) {
+        if (l.W64) hipFree(l.W64);
+        if (l.b64) hipFree(l.b64);
+        if (l.W32) hipFree(l.W32);
+        if (l.b32) hipFree(l.b32);
+        if (l.WtB) hipFree(l.WtB);
+    }
+    ls.clear();
+}
+
+NetView net_view(const dino_ctx* ctx) {
+    NetView v{};
+    v.n_layers = (int)ctx->layers.size();
+    for (int l = 0; l < v.n_layers; ++l) {
+        const Layer& ly = ctx->layers[l];
+        v.kinds[l] = ly.kind;
+        v.fan_out[l] = ly.fan_out;
+        v.fan_in[l] = ly.fan_in;
+        v.W64[l] = ly.W64;
+        v.b64[l] = ly.b64;
+        v.W32[l] = ly.W32;
+        v.b32[l] = ly.b32;
+    }
+    return v;
+}
+
+// Carves 256-byte aligned sub-buffers out of one workspace; with base == nullptr
+// it only measures.
+struct Carver {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
+
+static void layout(dino_problem* p, Carver& cv) {
+    const size_t C = p->C, r = p->r, dy = p->d_y, w = p->wmax;
+    p->y = cv.take<double>(dy);
+    p->winv = cv.take<double>(dy);
+    p->x = cv.take<double>(C * r);
+    p->g = cv.take<double>(C * r);
+    p->phi = cv.take<double>(C);
+    p->logdet = cv.take<double>(C);
+    p->Lbuf = cv.take<double>(2 * C * r * r);
+    p->cur = cv.take<int32_t>(C);
+    p->z = p->desc.track_complement ? cv.take<float>(C * (size_t)ldz_of(p->d_perp)) : nullptr;
+    p->accepts = cv.take<int64_t>(C);
+    p->failures = cv.take<int64_t>(C);
+    p->xp = cv.take<double>(C * r);
+    p->gp = cv.take<double>(C * r);
+    p->phip = cv.take<double>(C);
+    p->logdetp = cv.take<double>(C);
+    p->okp = cv.take<int32_t>(C);
+    p->lfwd = cv.take<double>(C);
+    p->acc = cv.take<int32_t>(C);
+    p->f = cv.take<double>(C * dy);
+    p->h0 = cv.take<double>(C * w);
+    p->h1 = cv.take<double>(C * w);
+    p->dprime = cv.take<double>((size_t)std::max(p->n_act, 1) * C * w);
+    p->lam0 = cv.take<double>(C * dy * w);
+    p->lam1 = cv.take<double>(C * dy * w);
+    p->Bj = cv.take<double>(C * dy * r);
+    const size_t cap = (size_t)std::max(p->desc.trace_capacity, 0);
+    p->xtrace = cap ? cv.take<float>(cap * C * r) : nullptr;
+    p->phitrace = cap ? cv.take<double>(cap * C) : nullptr;
+}
+
+static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
+    DINO_REQUIRE(ctx && d, DINO_EINVAL, "null context or descriptor");
+    DINO_REQUIRE(ctx->basis.r > 0, DINO_ESTATE, "load the prior before creating a problem");
+    DINO_REQUIRE(!ctx->layers.empty(), DINO_ESTATE, "load the network before creating a problem");
+    DINO_REQUIRE(ctx->r_in == ctx->basis.r, DINO_EINVAL, "network input width differs from the reduced dimension");
+    DINO_REQUIRE(d->n_chains >= 1 && d->n_chains <= (1 << 20), DINO_EINVAL, "n_chains out of range");
+    DINO_REQUIRE(d->d_y >= 1 && d->d_y <= ctx->d_out && d->d_y <= 1024, DINO_EINVAL, "d_y out of range");
+    DINO_REQUIRE(d->dt > 0.0 && std::isfinite(d->dt), DINO_EINVAL, "dt must be positive");
+    DINO_REQUIRE(d->precision == DINO_PREC_F64 || d->precision == DINO_PREC_BF16, DINO_EINVAL,
+                 "unknown precision");
+    DINO_REQUIRE(d->trace_capacity >= 0, DINO_EINVAL, "negative trace capacity");
+    DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
+}
+
+static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d) {
+    p->ctx = ctx;
+    p->desc = *d;
+    p->C = d->n_chains;
+    p->r = ctx->basis.r;
+    p->d_y = d->d_y;
+    p->d_m = ctx->basis.d_m;
+    p->d_perp = p->d_m - p->r;
+    p->wmax = ctx->max_width;
+    p->n_act = ctx->n_act;
+    p->s = (4.0 - d->dt) / (4.0 + d->dt);
+    p->beta = std::sqrt(1.0 - p->s * p->s);
+}
+
+static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void geometry_at(dino_problem* p, int n, const double* x, double* f, double* phi, double* g, double* A,
+                        long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* logdet,
+                        int32_t* ok, hipStream_t st) {
+    launch_forward(p, n, x, f, st);
+    launch_reverse_jacobian(p, n, p->Bj, st);
+    launch_misfit_grad(p, n, f, p->Bj, phi, g, st);
+    launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
+    launch_cholesky_slot(n, p->r, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
+}
+
+}  // namespace dino
+
+using namespace dino;
+
+extern "C" {
+
+const char* dino_last_error(void) { return g_error.c_str(); }
+const char* dino_version(void) { return "dino-mi355x 0.1 (gfx950)"; }
+
+dino_status dino_ctx_create(int device, dino_ctx** out) {
+    return guarded([&] {
+        DINO_REQUIRE(out, DINO_EINVAL, "null output pointer");
+        int count = 0;
+        DINO_HIP(hipGetDeviceCount(&count));
+        DINO_REQUIRE(device >= 0 && device < count, DINO_EINVAL, "device ordinal out of range");
+        DINO_HIP(hipSetDevice(device));
+        auto* c = new dino_ctx();
+        c->device = device;
+        *out = c;
+    });
+}
+
+dino_status dino_ctx_destroy(dino_ctx* ctx) {
+    return guarded([&] {
+        if (!ctx) return;
+        DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "context still has live problems");
+        DINO_HIP(hipSetDevice(ctx->device));
+        free_basis(ctx->basis);
+        free_layers(ctx->layers);
+        delete ctx;
+    });
+}
+
+dino_status dino_load_prior(dino_ctx* ctx, int n, double gamma, double delta, int r) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx, DINO_EINVAL, "null context");
+        DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "cannot replace the prior under live problems");
+        DINO_REQUIRE(n >= 2 && n <= 1025, DINO_EINVAL, "grid size out of range");
+        DINO_REQUIRE(r >= 1 && r <= n * n && r <= 512, DINO_EINVAL, "reduced dimension out of range");
+        DINO_REQUIRE(gamma > 0 && delta > 0 && std::isfinite(gamma) && std::isfinite(delta), DINO_EINVAL,
+                     "gamma and delta must be positive");
+        DINO_HIP(hipSetDevice(ctx->device));
+        // KLE order: increasing mu_k1 + mu_k2 (decreasing lambda), ties by (k1, k2).
+        std::vector<double> mu(n);
+        for (int k = 0; k < n; ++k) {
+            const double sn = std::sin(M_PI * k / (2.0 * n));
+            mu[k] = 4.0 * sn * sn;
+        }
+        const int d_m = n * n;
+        std::vector<int> idx(d_m);
+        std::iota(idx.begin(), idx.end(), 0);
+        auto key = [&](int e) { int a = e / n, c = e % n; return mu[std::min(a, c)] + mu[std::max(a, c)]; };
+        std::sort(idx.begin(), idx.end(), [&](int a, int b) {
+            const double ka = key(a), kb = key(b);
+            if (ka != kb) return ka < kb;
+            return a < b;  // e = k1 * n + k2: (k1, k2) lexicographic
+        });
+        Basis nb;
+        nb.n = n;
+        nb.r = r;
+        nb.d_m = d_m;
+        nb.gamma = gamma;
+        nb.delta = delta;
+        const double h = 1.0 / (n - 1);
+        for (int j = 0; j < r; ++j) {
+            const int e = idx[j];
+            nb.k1.push_back(e / n);
+            nb.k2.push_back(e % n);
+            const double a = gamma * key(e) / (h * h) + delta;
+            nb.lam.push_back(1.0 / (a * a));
+        }
+        build_basis_device(nb);
+        free_basis(ctx->basis);
+        ctx->basis = nb;
+    });
+}
+
+dino_status dino_read_basis(dino_ctx* ctx, double* dec, double* lam, double* var_perp, int32_t* modes) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && ctx->basis.r > 0, DINO_ESTATE, "no prior loaded");
+        DINO_HIP(hipSetDevice(ctx->device));
+        const Basis& b = ctx->basis;
+        if (dec) DINO_HIP(hipMemcpy(dec, b.dec, sizeof(double) * (size_t)b.d_m * b.r, hipMemcpyDeviceToHost));
+        if (lam) std::memcpy(lam, b.lam.data(), sizeof(double) * b.r);
+        if (var_perp) DINO_HIP(hipMemcpy(var_perp, b.var_perp, sizeof(double) * b.d_m, hipMemcpyDeviceToHost));
+        if (modes)
+            for (int j = 0; j < b.r; ++j) {
+                modes[2 * j] = b.k1[j];
+                modes[2 * j + 1] = b.k2[j];
+            }
+    });
+}
+
+dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds, const int32_t* fan_out,
+                              const int32_t* fan_in, const double* const* W, const double* const* b) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && kinds && fan_out && fan_in && W, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "cannot replace the network under live problems");
+        DINO_REQUIRE(n_layers >= 1 && n_layers <= 16, DINO_EINVAL, "1..16 layers supported");
+        DINO_REQUIRE(kinds[n_layers - 1] == DINO_LAYER_LINEAR, DINO_EINVAL, "the last layer must be linear");
+        int wmax = 0, n_act = 0;
+        for (int l = 0; l < n_layers; ++l) {
+            DINO_REQUIRE(kinds[l] >= 0 && kinds[l] <= 2, DINO_EINVAL, "unknown layer kind");
+            DINO_REQUIRE(fan_out[l] >= 1 && fan_out[l] <= 1024 && fan_in[l] >= 1 && fan_in[l] <= 1024, DINO_EINVAL,
+                         "layer widths must be in 1..1024");
+            DINO_REQUIRE(W[l], DINO_EINVAL, "null weight matrix");
+            if (l > 0) DINO_REQUIRE(fan_in[l] == fan_out[l - 1], DINO_EINVAL, "layer widths do not chain");
+            if (kinds[l] == DINO_LAYER_RESID)
+                DINO_REQUIRE(fan_in[l] == fan_out[l], DINO_EINVAL, "residual layers must be square");
+            if (kinds[l] != DINO_LAYER_LINEAR) ++n_act;
+            wmax = std::max(wmax, fan_in[l]);
+            if (l < n_layers - 1) wmax = std::max(wmax, fan_out[l]);
+            const size_t cnt = (size_t)fan_out[l] * fan_in[l];
+            for (size_t e = 0; e < cnt; ++e)
+                DINO_REQUIRE(std::isfinite(W[l][e]), DINO_ENUMERIC, "non-finite weight");
+            if (b && b[l])
+                for (int e = 0; e < fan_out[l]; ++e)
+                    DINO_REQUIRE(std::isfinite(b[l][e]), DINO_ENUMERIC, "non-finite bias");
+        }
+        DINO_HIP(hipSetDevice(ctx->device));
+        std::vector<Layer> ls(n_layers);
+        try {
+            for (int l = 0; l < n_layers; ++l) {
+                Layer& ly = ls[l];
+                ly.kind = kinds[l];
+                ly.fan_out = fan_out[l];
+                ly.fan_in = fan_in[l];
+                const size_t cnt = (size_t)ly.fan_out * ly.fan_in;
+                ly.hostW.assign(W[l], W[l] + cnt);
+                ly.hostb.assign(ly.fan_out, 0.0);
+                if (b && b[l]) std::copy(b[l], b[l] + ly.fan_out, ly.hostb.begin());
+                std::vector<float> w32(cnt), b32(ly.fan_out);
+                for (size_t e = 0; e < cnt; ++e) w32[e] = (float)ly.hostW[e];
+                for (int e = 0; e < ly.fan_out; ++e) b32[e] = (float)ly.hostb[e];
+                DINO_HIP(hipMalloc(&ly.W64, sizeof(double) * cnt));
+                DINO_HIP(hipMalloc(&ly.b64, sizeof(double) * ly.fan_out));
+                DINO_HIP(hipMalloc(&ly.W32, sizeof(float) * cnt));
+                DINO_HIP(hipMalloc(&ly.b32, sizeof(float) * ly.fan_out));
+                DINO_HIP(hipMemcpy(ly.W64, ly.hostW.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+                DINO_HIP(hipMemcpy(ly.b64, ly.hostb.data(), sizeof(double) * ly.fan_out, hipMemcpyHostToDevice));
+                DINO_HIP(hipMemcpy(ly.W32, w32.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
+                DINO_HIP(hipMemcpy(ly.b32, b32.data(), sizeof(float) * ly.fan_out, hipMemcpyHostToDevice));
+            }
+        } catch (...) {
+            free_layers(ls);
+            throw;
+        }
+        free_layers(ctx->layers);
+        ctx->layers = std::move(ls);
+        ctx->r_in = fan_in[0];
+        ctx->d_out = fan_out[n_layers - 1];
+        ctx->max_width = wmax;
+        ctx->n_act = n_act;
+    });
+}
+
+dino_status dino_problem_workspace_bytes(const dino_ctx* ctx, const dino_problem_desc* desc, size_t* bytes) {
+    return guarded([&] {
+        DINO_REQUIRE(bytes, DINO_EINVAL, "null output pointer");
+        check_desc(ctx, desc);
+        dino_problem tmp;
+        fill_dims(&tmp, const_cast<dino_ctx*>(ctx), desc);
+        Carver cv{nullptr};
+        layout(&tmp, cv);
+        *bytes = cv.off + 256;
+    });
+}
+
+dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, const double* y,
+                                const double* noise_var, void* dev_ws, size_t ws_bytes, dino_problem** out) {
+    return guarded([&] {
+        DINO_REQUIRE(out && y && noise_var, DINO_EINVAL, "null argument");
+        check_desc(ctx, desc);
+        for (int i = 0; i < desc->d_y; ++i) {
+            DINO_REQUIRE(std::isfinite(y[i]), DINO_ENUMERIC, "non-finite data value");
+            DINO_REQUIRE(noise_var[i] > 0.0, DINO_EINVAL, "noise variances must be positive");
+        }
+        DINO_HIP(hipSetDevice(ctx->device));
+        auto* p = new dino_problem();
+        try {
+            fill_dims(p, ctx, desc);
+            Carver cv{nullptr};
+            layout(p, cv);
+            const size_t need = cv.off + 256;
+            if (dev_ws) {
+                DINO_REQUIRE(ws_bytes >= need, DINO_ENOMEM, "workspace smaller than dino_problem_workspace_bytes");
+                DINO_REQUIRE(((uintptr_t)dev_ws & 255) == 0, DINO_EINVAL, "workspace must be 256-byte aligned");
+                p->ws = dev_ws;
+                p->own_ws = false;
+            } else {
+                hipError_t e = hipMalloc(&p->ws, need);
+                DINO_REQUIRE(e == hipSuccess, DINO_ENOMEM, "device allocation of the problem workspace failed");
+                p->own_ws = true;
+            }
+            p->ws_bytes = need;
+            Carver cv2{reinterpret_cast<char*>(p->ws)};
+            layout(p, cv2);
+            std::vector<double> winv(desc->d_y);
+            for (int i = 0; i < desc->d_y; ++i) winv[i] = std::isinf(noise_var[i]) ? 0.0 : 1.0 / std::sqrt(noise_var[i]);
+            DINO_HIP(hipMemcpy(p->y, y, sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
+            DINO_HIP(hipMemcpy(p->winv, winv.data(), sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
+        } catch (...) {
+            if (p->own_ws && p->ws) hipFree(p->ws);
+            delete p;
+            throw;
+        }
+        ctx->live_problems += 1;
+        *out = p;
+    });
+}
+
+dino_status dino_problem_destroy(dino_problem* p) {
+    return guarded([&] {
+        if (!p) return;
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        if (p->last_stream) hipStreamSynchronize(p->last_stream);
+        else hipDeviceSynchronize();
+        if (p->own_ws && p->ws) (void)hipFree(p->ws);
+        for (auto& e : p->ev)
+            if (e) (void)hipEventDestroy(e);
+        p->ctx->live_problems -= 1;
+        delete p;
+    });
+}
+
+dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        const size_t C = p->C, r = p->r;
+        if (x0) {
+            for (size_t e = 0; e < C * r; ++e) DINO_REQUIRE(std::isfinite(x0[e]), DINO_ENUMERIC, "non-finite x0");
+            DINO_HIP(hipMemcpyAsync(p->x, x0, sizeof(double) * C * r, hipMemcpyHostToDevice, st));
+        }
+        if (p->z && z0) {
+            const int ldz = ldz_of(p->d_perp);
+            DINO_HIP(hipMemcpy2DAsync(p->z, sizeof(float) * ldz, z0, sizeof(float) * p->d_perp,
+                                      sizeof(float) * p->d_perp, C, hipMemcpyHostToDevice, st));
+        }
+        launch_init_draws(p, x0 == nullptr, z0 == nullptr, st);
+        DINO_HIP(hipMemsetAsync(p->cur, 0, sizeof(int32_t) * C, st));
+        DINO_HIP(hipMemsetAsync(p->accepts, 0, sizeof(int64_t) * C, st));
+        DINO_HIP(hipMemsetAsync(p->failures, 0, sizeof(int64_t) * C, st));
+        const long rr = (long)r * r;
+        geometry_at(p, p->C, p->x, p->f, p->phi, p->g, p->Lbuf, rr, nullptr, 0, 0, p->logdet, p->okp, st);
+        DINO_HIP(hipStreamSynchronize(st));
+        p->step = 0;
+        p->recorded = 0;
+        p->initialised = true;
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        DINO_REQUIRE(p->initialised, DINO_ESTATE, "dino_chains_init must precede dino_step");
+        DINO_REQUIRE(n_steps >= 0, DINO_EINVAL, "negative step count");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        const long rr = (long)p->r * p->r;
+        const long half = (long)p->C * rr;
+        const int L = (int)p->ctx->layers.size();
+        const int32_t launches[DINO_N_STAGES] = {1, L, L, 1, 1, 1, 1, 1, 1};
+        auto mark = [&](int i) {
+            if (p->profile) DINO_HIP(hipEventRecord(p->ev[i], st));
+        };
+        for (int k = 0; k < n_steps; ++k) {
+            const int64_t step = p->step;
+            mark(0);
+            launch_propose_slot(p, p->C, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, step, p->xp, p->lfwd,
+                                p->logdet, st);
+            mark(1);
+            launch_forward(p, p->C, p->xp, p->f, st);
+            mark(2);
+            launch_reverse_jacobian(p, p->C, p->Bj, st);
+            mark(3);
+            launch_misfit_grad(p, p->C, p->f, p->Bj, p->phip, p->gp, st);
+            mark(4);
+            launch_gn_hessian_slot(p, p->C, p->Bj, p->Lbuf, rr, p->cur, 1, half, 1, 0, st);
+            mark(5);
+            launch_cholesky_slot(p->C, p->r, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
+            mark(6);
+            launch_accept(p, step, st);
+            mark(7);
+            launch_complement(p, step, st);
+            mark(8);
+            if (p->xtrace && p->recorded < p->desc.trace_capacity) {
+                launch_trace(p, p->recorded, st);
+                p->recorded += 1;
+            }
+            mark(9);
+            if (p->profile) {
+                DINO_HIP(hipEventSynchronize(p->ev[DINO_N_STAGES]));
+                for (int i = 0; i < DINO_N_STAGES; ++i) {
+                    float ms = 0.f;
+                    DINO_HIP(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
+                    p->stage_ms[i] += ms;
+                    p->stage_launches[i] = launches[i];
+                }
+                p->profiled_steps += 1;
+            }
+            p->step += 1;
+        }
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_set_profiling(dino_problem* p, int enable) {
+    return guarded([&] {
+        DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        if (enable && !p->ev[0])
+            for (auto& e : p->ev) DINO_HIP(hipEventCreate(&e));
+        p->profile = enable != 0;
+        for (int i = 0; i < DINO_N_STAGES; ++i) {
+            p->stage_ms[i] = 0.0;
+            p->stage_launches[i] = 0;
+        }
+        p->profiled_steps = 0;
+    });
+}
+
+dino_status dino_read_profile(dino_problem* p, double* stage_ms, int32_t* launches, int64_t* steps) {
+    return guarded([&] {
+        DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        for (int i = 0; i < DINO_N_STAGES; ++i) {
+            if (stage_ms) stage_ms[i] = p->stage_ms[i];
+            if (launches) launches[i] = p->stage_launches[i];
+        }
+        if (steps) *steps = p->profiled_steps;
+    });
+}
+
+const char* dino_stage_name(int stage) {
+    static const char* names[DINO_N_STAGES] = {"proposal", "forward", "jacobian", "misfit_ppg", "gn_hessian",
+                                               "cholesky", "accept", "complement", "trace"};
+    return (stage >= 0 && stage < DINO_N_STAGES) ? names[stage] : "";
+}
+
+dino_status dino_read_states(dino_problem* p, double* x, float* z) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (x) DINO_HIP(hipMemcpy(x, p->x, sizeof(double) * p->C * p->r, hipMemcpyDeviceToHost));
+        if (z) {
+            DINO_REQUIRE(p->z, DINO_ESTATE, "complement not tracked");
+            DINO_HIP(hipMemcpy2D(z, sizeof(float) * p->d_perp, p->z, sizeof(float) * ldz_of(p->d_perp),
+                                 sizeof(float) * p->d_perp, p->C, hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+dino_status dino_read_cache(dino_problem* p, double* phi, double* g, double* L) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (phi) DINO_HIP(hipMemcpy(phi, p->phi, sizeof(double) * p->C, hipMemcpyDeviceToHost));
+        if (g) DINO_HIP(hipMemcpy(g, p->g, sizeof(double) * p->C * p->r, hipMemcpyDeviceToHost));
+        if (L) {
+            std::vector<int32_t> cur(p->C);
+            DINO_HIP(hipMemcpy(cur.data(), p->cur, sizeof(int32_t) * p->C, hipMemcpyDeviceToHost));
+            const size_t rr = (size_t)p->r * p->r;
+            for (int c = 0; c < p->C; ++c)
+                DINO_HIP(hipMemcpy(L + c * rr, p->Lbuf + ((size_t)cur[c] * p->C + c) * rr, sizeof(double) * rr,
+                                   hipMemcpyDeviceToHost));
+        }
+    });
+}
+
+dino_status dino_read_diagnostics(dino_problem* p, int64_t* accepts, int64_t* failures, int64_t* steps) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (accepts) DINO_HIP(hipMemcpy(accepts, p->accepts, sizeof(int64_t) * p->C, hipMemcpyDeviceToHost));
+        if (failures) DINO_HIP(hipMemcpy(failures, p->failures, sizeof(int64_t) * p->C, hipMemcpyDeviceToHost));
+        if (steps) *steps = p->step;
+    });
+}
+
+dino_status dino_read_trace(dino_problem* p, float* x_trace, double* phi_trace, int64_t* n_recorded) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (n_recorded) *n_recorded = p->recorded;
+        if (p->recorded == 0) return;
+        if (x_trace)
+            DINO_HIP(hipMemcpy(x_trace, p->xtrace, sizeof(float) * p->recorded * p->C * p->r, hipMemcpyDeviceToHost));
+        if (phi_trace)
+            DINO_HIP(hipMemcpy(phi_trace, p->phitrace, sizeof(double) * p->recorded * p->C, hipMemcpyDeviceToHost));
+    });
+}
+
+dino_status dino_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_REQUIRE(burn_in >= 0 && burn_in < p->recorded, DINO_EINVAL, "burn_in must leave recorded steps");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = p->last_stream;
+        const int r = p->r, d_m = p->d_m;
+        double *dm = nullptr, *dv = nullptr, *dx = nullptr, *dS = nullptr;
+        DINO_HIP(hipMalloc(&dm, sizeof(double) * d_m));
+        DINO_HIP(hipMalloc(&dv, sizeof(double) * d_m));
+        DINO_HIP(hipMalloc(&dx, sizeof(double) * r));
+        DINO_HIP(hipMalloc(&dS, sizeof(double) * r * r));
+        launch_posterior(p, burn_in, dm, dv, dx, dS, st);
+        DINO_HIP(hipStreamSynchronize(st));
+        if (mean) DINO_HIP(hipMemcpy(mean, dm, sizeof(double) * d_m, hipMemcpyDeviceToHost));
+        if (var) DINO_HIP(hipMemcpy(var, dv, sizeof(double) * d_m, hipMemcpyDeviceToHost));
+        if (xbar) DINO_HIP(hipMemcpy(xbar, dx, sizeof(double) * r, hipMemcpyDeviceToHost));
+        if (S) DINO_HIP(hipMemcpy(S, dS, sizeof(double) * r * r, hipMemcpyDeviceToHost));
+        hipFree(dm);
+        hipFree(dv);
+        hipFree(dx);
+        hipFree(dS);
+    });
+}
+
+dino_status dino_ess(dino_problem* p, int burn_in, double* ess) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised && ess, DINO_EINVAL, "bad arguments");
+        DINO_REQUIRE(burn_in >= 0 && p->recorded - burn_in >= 2, DINO_EINVAL, "need two recorded steps after burn_in");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        double* d = nullptr;
+        DINO_HIP(hipMalloc(&d, sizeof(double) * p->r));
+        launch_ess(p, burn_in, d, p->last_stream);
+        DINO_HIP(hipMemcpy(ess, d, sizeof(double) * p->r, hipMemcpyDeviceToHost));
+        hipFree(d);
+    });
+}
+
+dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* f, double* phi, double* g,
+                               double* H, double* L, double* logdet, int32_t* ok, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && f && phi && g && L && logdet && ok, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        const long rr = (long)p->r * p->r;
+        launch_forward(p, n, x, f, st);
+        launch_reverse_jacobian(p, n, p->Bj, st);
+        launch_misfit_grad(p, n, f, p->Bj, phi, g, st);
+        if (H) launch_gn_hessian_slot(p, n, p->Bj, H, rr, nullptr, 0, 0, 0, 1, st);
+        launch_gn_hessian_slot(p, n, p->Bj, L, rr, nullptr, 0, 0, 1, 0, st);
+        launch_cholesky_slot(n, p->r, L, rr, nullptr, 0, 0, logdet, ok, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_eval_propose(dino_problem* p, int n, const double* x, const double* g, const double* L,
+                              const double* xi, double* xp, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && g && L && xi && xp, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_propose_slot(p, n, x, g, L, (long)p->r * p->r, nullptr, 0, 0, xi, 0, xp, nullptr, nullptr, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                              const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
+                              const double* g_p, const double* L_p, const double* logdet_p, double* log_rho,
+                              void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && phi_x && g_x && L_x && logdet_x && xp && phi_p && g_p && L_p && logdet_p && log_rho,
+                     DINO_EINVAL, "null argument");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_log_rho(p, n, x, phi_x, g_x, L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, log_rho, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_eval_normals(dino_problem* p, int n, int stream_id, int64_t step, int count, double* out,
+                              void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && out, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(n >= 1 && count >= 1 && stream_id >= 0 && step >= 0, DINO_EINVAL, "bad sizes");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_normals(p->desc.seed, p->desc.request_id, n, stream_id, step, count, out, st);
+        p->last_stream = st;
+    });
+}
+
+}  // extern "C"

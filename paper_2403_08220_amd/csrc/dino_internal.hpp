@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -185,6 +187,15 @@ struct dino_problem {
     double* lam0 = nullptr;   // C x d_y x wmax   reverse-sweep buffers (FP64 path)
     double* lam1 = nullptr;
     double* Bj = nullptr;     // C x d_y x r whitened reduced Jacobian Gamma^-1/2 J
+    // mixed-precision path buffers
+    int ldd32 = 0;            // row length of d32 (width rounded up to 32)
+    float* xpf = nullptr;     // C x r reduced point in FP32
+    float* h0f = nullptr;     // C x wmax FP32 activations
+    float* h1f = nullptr;
+    float* f32 = nullptr;     // C x d_y FP32 network output
+    float* e32 = nullptr;     // C x d_y whitened residual
+    float* d32 = nullptr;     // n_act x C x ldd32 gelu'(z), zero padded
+    __hip_bfloat16* B16 = nullptr;  // C x d_y x r BF16 whitened Jacobian
     // trace
     float* xtrace = nullptr;  // capacity x C x r
     double* phitrace = nullptr;
@@ -230,5 +241,18 @@ void launch_posterior(dino_problem* p, int burn_in, double* mean, double* var, d
 void launch_ess(dino_problem* p, int burn_in, double* ess, hipStream_t st);
 
 NetView net_view(const dino_ctx* ctx);
+
+// mixed-precision path (kernels_mfma.hip, kernels_geometry.hip)
+int sweep_nmb(const dino_ctx* ctx);
+void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<uint16_t>& out,
+                      int& nmb_out);
+void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hipStream_t st);
+void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st);
+void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
+                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
+void launch_to_float(long count, const double* x, float* xf, hipStream_t st);
+void launch_to_double(long count, const float* xf, double* x, hipStream_t st);
+void launch_sym_from_lower(int n, int r, const double* A, double* H, hipStream_t st);
+void launch_residual(dino_problem* p, int n, const float* f, float* e, double* phi, hipStream_t st);
 
 }  // namespace dino

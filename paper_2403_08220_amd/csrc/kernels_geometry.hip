@@ -28,50 +28,57 @@ __device__ __forceinline__ float gelu_prime_t<float>(float z) {
 
 // ---------------------------------------------------------------------------------
 // Forward layer: out[m][n] = epi(sum_k in[m][k] W[n][k] + b[n]).
-// Tile 64 (rows) x 64 (outputs) x 16 (k); 256 threads, 4x4 outputs each at
-// rows ty + 16 i, columns tx + 16 j.
-template <typename T>
+// Tile (16 TM rows) x (16 TN outputs) x 16 (k); 256 threads, TM x TN outputs each at
+// rows ty + 16 i, columns tx + 16 j. The launcher picks the tile so that a small
+// batch of chains still fills the GPU.
+template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void fwd_layer_kernel(int M, int K, int N, const T* __restrict__ in, int ldin,
                                                         const T* __restrict__ W, const T* __restrict__ b,
                                                         int kind, T* __restrict__ out, int ldout,
                                                         T* __restrict__ dprime, int ldd) {
-    __shared__ T As[16][64 + 1];
-    __shared__ T Ws[16][64 + 1];
+    constexpr int BM = 16 * TM, BN = 16 * TN;
+    __shared__ T As[16][BM + 1];
+    __shared__ T Ws[16][BN + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    T acc[4][4];
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    T acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+        for (int j = 0; j < TN; ++j) acc[i][j] = T(0);
     for (int k0 = 0; k0 < K; k0 += 16) {
+        const int k = k0 + tx;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = ty + 16 * q, k = k0 + tx;
+        for (int q = 0; q < TM; ++q) {
+            const int row = ty + 16 * q;
             As[tx][row] = (m0 + row < M && k < K) ? in[(long)(m0 + row) * ldin + k] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < TN; ++q) {
+            const int row = ty + 16 * q;
             Ws[tx][row] = (n0 + row < N && k < K) ? W[(long)(n0 + row) * K + k] : T(0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 16; ++kk) {
-            T a[4], w[4];
+            T a[TM], w[TN];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+            for (int i = 0; i < TM; ++i) a[i] = As[kk][ty + 16 * i];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = Ws[kk][tx + 16 * j];
+            for (int j = 0; j < TN; ++j) w[j] = Ws[kk][tx + 16 * j];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * w[j];
+                for (int j = 0; j < TN; ++j) acc[i][j] += a[i] * w[j];
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < TM; ++i) {
         const int m = m0 + ty + 16 * i;
         if (m >= M) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < TN; ++j) {
             const int n = n0 + tx + 16 * j;
             if (n >= N) continue;
             const T z = acc[i][j] + (b ? b[n] : T(0));
@@ -240,6 +247,22 @@ __global__ __launch_bounds__(256) void gn_hessian_kernel(int dy, int r, const do
 // Host launchers.
 static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
 
+// One forward layer with the largest tile that still gives >= 1024 blocks.
+template <typename T>
+static void fwd_layer(int M, int K, int N, const T* in, int ldin, const T* W, const T* b, int kind, T* out,
+                      int ldout, T* dprime, int ldd, hipStream_t st) {
+    auto blocks = [&](int bm, int bn) { return (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
+    if (blocks(64, 64) >= 1024)
+        hipLaunchKernelGGL((fwd_layer_kernel<T, 4, 4>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M, K, N,
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+    else if (blocks(32, 32) >= 1024)
+        hipLaunchKernelGGL((fwd_layer_kernel<T, 2, 2>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st, M, K, N,
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+    else
+        hipLaunchKernelGGL((fwd_layer_kernel<T, 1, 1>), dim3((N + 15) / 16, (M + 15) / 16), dim3(256), 0, st, M, K, N,
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+}
+
 void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
     const int L = (int)ctx->layers.size();
@@ -262,8 +285,30 @@ void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipS
         const int N = last ? p->d_y : ly.fan_out;
         double* dp = nullptr;
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->dprime + (long)act * p->C * p->wmax;
-        hipLaunchKernelGGL(fwd_layer_kernel<double>, grid2(n, N), dim3(256), 0, st, n, ly.fan_in, N, in, ldin,
-                           ly.W64, ly.b64, ly.kind, out, ldout, dp, p->wmax);
+        fwd_layer<double>(n, ly.fan_in, N, in, ldin, ly.W64, ly.b64, ly.kind, out, ldout, dp, p->wmax, st);
+        if (ly.kind != DINO_LAYER_LINEAR) ++act;
+        in = out;
+        ldin = ldout;
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+// FP32 forward of the mixed-precision path: gelu'(z) into d32 (row length ldd32).
+void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hipStream_t st) {
+    const dino_ctx* ctx = p->ctx;
+    const int L = (int)ctx->layers.size();
+    const float* in = xf;
+    int ldin = p->r;
+    int act = 0;
+    for (int l = 0; l < L; ++l) {
+        const Layer& ly = ctx->layers[l];
+        const bool last = (l == L - 1);
+        float* out = last ? f_out : ((l % 2 == 0) ? p->h0f : p->h1f);
+        const int ldout = last ? p->d_y : p->wmax;
+        const int N = last ? p->d_y : ly.fan_out;
+        float* dp = nullptr;
+        if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
+        fwd_layer<float>(n, ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32, st);
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;

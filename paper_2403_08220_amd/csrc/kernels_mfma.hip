@@ -1,0 +1,451 @@
+// BF16 MFMA kernels of the mixed-precision path (gfx950):
+//  * fused reverse-mode reduced Jacobian (the display after eq. rb_dino): all layers of
+//    the sweep Lambda <- Lambda [+] (Lambda D_l) W_l in one launch, Lambda kept in
+//    registers in FP32, products on v_mfma_f32_32x32x16_bf16;
+//  * Gauss-Newton Hessian I + B^T B (eq. surrogate_rppgnh) and reduced ppg B^T e
+//    (eq. surrogate_rppg, sign as in eq. ppg) per chain, written in FP64 for the
+//    Cholesky factorisation;
+//  * FP32 forward helpers (input conversion, whitened residual and misfit).
+//
+// Layout of the sweep. A wave owns 32 columns R = (chain, output) of Lambda^T (width
+// rows x 32). One 32x32x16 MFMA takes A (32 x 16) with lane (m, h) holding
+// A[m][8h + j], B (16 x 32) with lane (n, h) holding B[8h + j][n], and returns D
+// (32 x 32) with lane (n, h), register j holding D[8(j/4) + 4h + j%4][n]. The 8
+// registers 8q..8q+7 of a D block therefore hold, for lane (n, h), rows
+// 16q + pi(h, jj) with pi(h, jj) = 8(jj/4) + 4h + jj%4 - exactly one B operand of a
+// 16-deep K chunk up to the permutation pi of K inside the chunk. The weight tiles
+// (the A operands, W_l^T) are packed on the host with the same permutation, so the
+// result of one layer feeds the next layer's products without leaving registers.
+#include "dino_internal.hpp"
+
+namespace dino {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(16))) _Float16 f16x16;
+
+constexpr int JAC_WAVES = 4;          // waves per block of the sweep kernel
+constexpr int JAC_TPB = 64 * JAC_WAVES;
+
+__device__ __forceinline__ int pi_row(int h, int jj) { return 8 * (jj >> 2) + 4 * h + (jj & 3); }
+
+// ---------------------------------------------------------------------------------
+// Sweep arguments: reverse layers in processing order (output side first). The
+// packed tiles of one (layer, output block) work item are contiguous: NT(NMB) tiles
+// of 1 KB, of which the first 2*NMB hold the K chunks (zero beyond the layer's K).
+constexpr int MAX_ITEMS = 240;
+
+struct SweepLayer {
+    const float* d;       // gelu'(z) of the layer (C x ldd, zero padded) or null
+    int nmb_out;          // output row blocks of 32 (ceil(fan_in / 32))
+    int resid;            // Lambda <- Lambda + ...
+};
+
+struct SweepArgs {
+    int n_cols;           // C * dy
+    int dy;
+    int w_out;            // fan_in of the output layer (rows of Lambda_L)
+    int ldd;              // row length of the d buffers
+    int r;                // rows of the final B^T
+    int n_layers;
+    int n_items;
+    const float* Wout;    // output layer weights (d_out x w_out), FP32
+    const double* winv;   // Gamma^-1/2 diagonal (dy)
+    __hip_bfloat16* B;    // out: C*dy x r, BF16
+    SweepLayer layer[15];
+    const bf16x8* item_tiles[MAX_ITEMS];
+};
+
+constexpr int sweep_nt(int nmb) { return (2 * nmb + 3) / 4 * 4; }  // tiles per item, multiple of 4
+constexpr int SWEEP_NBUF = 3;                                         // LDS ring depth (prefetch distance 2)
+
+// Four consecutive 1 KB tiles of the current item from LDS; the wait stays inside the
+// asm block so no load is in flight when the registers are handed back.
+__device__ __forceinline__ void lds_read4(uint32_t addr, bf16x8& a0, bf16x8& a1, bf16x8& a2, bf16x8& a3) {
+    int4 r0, r1, r2, r3;
+    asm volatile(
+        "ds_read_b128 %0, %4\n\t"
+        "ds_read_b128 %1, %4 offset:1024\n\t"
+        "ds_read_b128 %2, %4 offset:2048\n\t"
+        "ds_read_b128 %3, %4 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)  // early clobber: never share the address VGPR
+        : "v"(addr)
+        : "memory");
+    a0 = __builtin_bit_cast(bf16x8, r0);
+    a1 = __builtin_bit_cast(bf16x8, r1);
+    a2 = __builtin_bit_cast(bf16x8, r2);
+    a3 = __builtin_bit_cast(bf16x8, r3);
+}
+
+template <int NMB>
+__global__ __launch_bounds__(JAC_TPB) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void jac_sweep_bf16_kernel(SweepArgs args) {
+    constexpr int NKC = 2 * NMB;          // K chunks per item (MFMAs per item)
+    constexpr int NT = sweep_nt(NMB);     // tiles per item (copies per wave: NT / 4)
+    constexpr int NKC4 = (NKC + 3) / 4;   // groups of four tile reads
+    extern __shared__ bf16x8 tiles_lds[]; // SWEEP_NBUF buffers x NT tiles x 64 lanes
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nl = lane & 31, h = lane >> 5;
+    const int col = (blockIdx.x * JAC_WAVES + wave) * 32 + nl;
+    const bool valid = col < args.n_cols;
+    const int c = valid ? col / args.dy : 0;
+    const int i = valid ? col % args.dy : 0;
+
+    // The residual stream Lambda^T is kept without the Gamma^-1/2 row factor (applied
+    // when B is written) and stored between layers in FP16 registers (D layout);
+    // every product runs on BF16 operands with FP32 accumulation.
+    f16x16 lam[NMB];
+    {
+        const float* wrow = args.Wout + (long)i * args.w_out;
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int row = 32 * mb + 8 * (j >> 2) + 4 * h + (j & 3);
+                lam[mb][j] = (_Float16)((valid && row < args.w_out) ? wrow[row] : 0.f);
+            }
+    }
+    const float wi = valid ? (float)args.winv[i] : 0.f;
+
+    // Work items (layer, output block) are walked in lockstep by all waves. Direct
+    // global -> LDS copies (global_load_lds_dwordx4) move whole 1 KB tiles (64 lanes x
+    // 16 B at a wave-uniform LDS base); every wave copies NT/4 tiles of an item, two
+    // items ahead, into a ring of SWEEP_NBUF buffers.
+    auto stage = [&](int item) {
+        const bf16x8* src = args.item_tiles[item];
+        bf16x8* dst = tiles_lds + (long)(item % SWEEP_NBUF) * NT * 64;
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) {
+            const int kc = wave + 4 * q;
+            __builtin_amdgcn_global_load_lds((const void*)(src + kc * 64 + lane),
+                                             (__attribute__((address_space(3))) void*)(dst + kc * 64), 16, 0, 0);
+        }
+    };
+    // Item `item` is resident once this wave has at most the copies of the one
+    // younger item in flight, and every wave has passed the barrier.
+    auto wait_item = [&]() {
+        asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(NT / 4) : "memory");
+    };
+    auto wait_all = [&]() { asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory"); };
+
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) bf16x8*)tiles_lds;
+    if (args.n_items > 0) stage(0);
+    if (args.n_items > 1) stage(1);
+    if (args.n_items > 1) wait_item();
+    else wait_all();
+    __hip_bfloat16* brow = args.B + (long)col * args.r;
+
+    int item = 0;
+    for (int li = 0; li < args.n_layers; ++li) {
+        const SweepLayer L = args.layer[li];
+        const bool last = (li == args.n_layers - 1);
+        // B operands: bf16(d * Lambda) for every K chunk of this layer
+        bf16x8 bop[NKC];
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                float dv[8];
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) dv[jj] = 1.f;
+                if (L.d) {
+                    const float* drow = L.d + (long)c * args.ldd + 32 * mb + 16 * q + 4 * h;
+                    const float4 d0 = *reinterpret_cast<const float4*>(drow);
+                    const float4 d1 = *reinterpret_cast<const float4*>(drow + 8);
+                    dv[0] = d0.x; dv[1] = d0.y; dv[2] = d0.z; dv[3] = d0.w;
+                    dv[4] = d1.x; dv[5] = d1.y; dv[6] = d1.z; dv[7] = d1.w;
+                }
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj)
+                    bop[2 * mb + q][jj] = (__bf16)((float)lam[mb][8 * q + jj] * dv[jj]);
+            }
+        }
+#pragma unroll
+        for (int mob = 0; mob < NMB; ++mob) {
+            if (mob < L.nmb_out) {
+                if (item + 2 < args.n_items) stage(item + 2);
+                const uint32_t cur = lds_base + (uint32_t)((item % SWEEP_NBUF) * NT * 64 * 16) + lane * 16;
+                f32x16 acc;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc[j] = L.resid ? (float)lam[mob][j] : 0.f;
+#pragma unroll
+                for (int g4 = 0; g4 < NKC4; ++g4) {
+                    bf16x8 a[4];
+                    lds_read4(cur + g4 * 4096, a[0], a[1], a[2], a[3]);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (4 * g4 + t < NKC)
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], bop[4 * g4 + t], acc, 0, 0, 0);
+                }
+                if (!last) {
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) lam[mob][j] = (_Float16)acc[j];
+                } else if (valid) {
+                    // B[col][m] = winv_i Lambda_0^T[m][col] for m < r
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int m0 = 32 * mob + 8 * b + 4 * h;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (m0 + t < args.r) brow[m0 + t] = __float2bfloat16(wi * acc[4 * b + t]);
+                    }
+                }
+                ++item;
+                if (item + 1 < args.n_items) wait_item();
+                else wait_all();
+            }
+        }
+        // rows beyond this layer's output are zero (no stale values when widths shrink)
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+            if (mb >= L.nmb_out)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) lam[mb][j] = (_Float16)0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Per chain: A = I + B^T B (lower triangle, FP64, into the factor slot) and
+// g = B^T e, with B the chain's dy x r whitened Jacobian (BF16) and e the whitened
+// residual (FP32). B^T is staged in LDS (r_pad x dy_pad) so that every MFMA operand
+// is one 16-byte read.
+constexpr int HES_TPB = 256;
+
+__global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int dy_pad, int ldt,
+                                                            const __hip_bfloat16* __restrict__ B,
+                                                            const float* __restrict__ e, double* A, long strideA,
+                                                            const int32_t* slot, int slot_xor, long slot_stride,
+                                                            double* __restrict__ g) {
+    extern __shared__ __hip_bfloat16 bt[];  // r_pad x ldt
+    const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nmb = (r + 31) / 32;
+    const int r_pad = nmb * 32;
+    const __hip_bfloat16* Bc = B + (long)c * dy * r;
+    // transpose into LDS: bt[j][i] = B[i][j], zero padded
+    for (int e2 = tid; e2 < r_pad * dy_pad; e2 += HES_TPB) {
+        const int j = e2 / dy_pad, ii = e2 % dy_pad;
+        bt[(long)j * ldt + ii] = (j < r && ii < dy) ? Bc[(long)ii * r + j] : __float2bfloat16(0.f);
+    }
+    __syncthreads();
+    // gradient g_j = sum_i B[i][j] e[i]
+    for (int j = tid; j < r; j += HES_TPB) {
+        double acc = 0.0;
+        for (int ii = 0; ii < dy; ++ii) acc += (double)__bfloat162float(bt[(long)j * ldt + ii]) * (double)e[(long)c * dy + ii];
+        g[(long)c * r + j] = acc;
+    }
+    double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    const int nl = lane & 31, h = lane >> 5;
+    const int nkc = dy_pad / 16;
+    // lower 32x32 blocks (bj >= bk) distributed over the waves
+    const int nblocks = nmb * (nmb + 1) / 2;
+    for (int bidx = wave; bidx < nblocks; bidx += HES_TPB / 64) {
+        int bj = 0;
+        while ((bj + 1) * (bj + 2) / 2 <= bidx) ++bj;
+        const int bk = bidx - bj * (bj + 1) / 2;
+        f32x16 acc;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+        for (int kc = 0; kc < nkc; ++kc) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(bt + (long)(32 * bj + nl) * ldt + 16 * kc + 8 * h);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(bt + (long)(32 * bk + nl) * ldt + 16 * kc + 8 * h);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        const int col = 32 * bk + nl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int row = 32 * bj + 8 * (j >> 2) + 4 * h + (j & 3);
+            if (row < r && col < r && col <= row) Ac[(long)row * r + col] = (double)acc[j] + (row == col ? 1.0 : 0.0);
+        }
+    }
+}
+
+// x (double) -> xf (float)
+__global__ void to_float_kernel(long n, const double* __restrict__ x, float* __restrict__ xf) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        xf[e] = (float)x[e];
+}
+
+__global__ void to_double_kernel(long n, const float* __restrict__ xf, double* __restrict__ x) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
+        x[e] = (double)xf[e];
+}
+
+// Whitened residual e = winv (f - y) (FP32 out) and misfit phi = |e|^2 / 2 (FP64).
+__global__ __launch_bounds__(256) void residual_kernel(int dy, const float* __restrict__ f,
+                                                       const double* __restrict__ y,
+                                                       const double* __restrict__ winv, float* __restrict__ e,
+                                                       double* __restrict__ phi) {
+    __shared__ double red[4];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    double part = 0.0;
+    for (int i = tid; i < dy; i += 256) {
+        const double w = winv[i];
+        const double v = (w == 0.0) ? 0.0 : ((double)f[(long)c * dy + i] - y[i]) * w;
+        e[(long)c * dy + i] = (float)v;
+        part += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) phi[c] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------------
+// Host side.
+
+// The sweep kernel instance (its NMB) used for a network whose widest reverse
+// operand spans nmb row blocks of 32.
+int sweep_template_nmb(int nmb) {
+    if (nmb <= 2) return 2;
+    if (nmb <= 4) return 4;
+    if (nmb <= 7) return 7;
+    if (nmb <= 13) return 13;
+    return 16;
+}
+
+int sweep_nmb(const dino_ctx* ctx) {
+    int m = (ctx->r_in + 31) / 32;
+    for (size_t l = 0; l + 1 < ctx->layers.size(); ++l) {
+        m = std::max(m, (ctx->layers[l].fan_in + 31) / 32);
+        m = std::max(m, (ctx->layers[l].fan_out + 31) / 32);
+    }
+    return sweep_template_nmb(m);
+}
+
+// Pack A = W^T tiles for one layer W (fan_out x fan_in) for the sweep instance nmb_t:
+// work item mo (output rows 32 mo .. 32 mo + 31) holds sweep_nt(nmb_t) tiles; tile kc,
+// lane (m, h), slot jj = W[16 kc + pi(h, jj)][32 mo + m] (zero outside W).
+void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t,
+                      std::vector<uint16_t>& out, int& nmb_out) {
+    nmb_out = (fan_in + 31) / 32;
+    const int nt = sweep_nt(nmb_t);
+    out.assign((size_t)nmb_out * nt * 64 * 8, 0);
+    for (int mo = 0; mo < nmb_out; ++mo)
+        for (int kc = 0; kc < 2 * nmb_t; ++kc)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int m = lane & 31, h = lane >> 5;
+                for (int jj = 0; jj < 8; ++jj) {
+                    const int k = 16 * kc + 8 * (jj >> 2) + 4 * h + (jj & 3);
+                    const int n = 32 * mo + m;
+                    float v = 0.f;
+                    if (k < fan_out && n < fan_in) v = (float)W[(size_t)k * fan_in + n];
+                    uint32_t u;  // round to nearest even BF16
+                    std::memcpy(&u, &v, 4);
+                    u += 0x7FFFu + ((u >> 16) & 1u);
+                    out[(((size_t)mo * nt + kc) * 64 + lane) * 8 + jj] = (uint16_t)(u >> 16);
+                }
+            }
+}
+
+template <int NMB>
+static void launch_sweep_t(const SweepArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)SWEEP_NBUF * sweep_nt(NMB) * 64 * sizeof(bf16x8);
+    static bool attr = false;
+    if (!attr) {
+        DINO_HIP(hipFuncSetAttribute((const void*)jac_sweep_bf16_kernel<NMB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr = true;
+    }
+    const int blocks = (a.n_cols + 32 * JAC_WAVES - 1) / (32 * JAC_WAVES);
+    hipLaunchKernelGGL(jac_sweep_bf16_kernel<NMB>, dim3(blocks), dim3(JAC_TPB), lds, st, a);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st) {
+    const dino_ctx* ctx = p->ctx;
+    const int L = (int)ctx->layers.size();
+    const int nmb_t = sweep_nmb(ctx);
+    SweepArgs a{};
+    a.n_cols = n * p->d_y;
+    a.dy = p->d_y;
+    a.w_out = ctx->layers[L - 1].fan_in;
+    a.ldd = ldd;
+    a.r = p->r;
+    a.Wout = ctx->layers[L - 1].W32;
+    a.winv = p->winv;
+    a.B = Bout;
+    a.n_layers = L - 1;
+    DINO_REQUIRE(ldd >= 32 * nmb_t, DINO_EINVAL, "gelu' buffer rows shorter than the sweep width");
+    int act = p->n_act, items = 0;
+    const int nt = sweep_nt(nmb_t);
+    for (int k = 0; k < L - 1; ++k) {
+        const int l = L - 2 - k;
+        const Layer& ly = ctx->layers[l];
+        SweepLayer& s = a.layer[k];
+        s.nmb_out = (ly.fan_in + 31) / 32;
+        s.resid = ly.kind == DINO_LAYER_RESID ? 1 : 0;
+        if (ly.kind != DINO_LAYER_LINEAR) {
+            --act;
+            s.d = d32 + (long)act * p->C * ldd;
+        } else {
+            s.d = nullptr;
+        }
+        for (int mo = 0; mo < s.nmb_out; ++mo) {
+            DINO_REQUIRE(items < MAX_ITEMS, DINO_EINVAL, "network too large for the BF16 sweep");
+            a.item_tiles[items++] = reinterpret_cast<const bf16x8*>(ly.WtB) + (long)mo * nt * 64;
+        }
+    }
+    a.n_items = items;
+    if (nmb_t == 2) launch_sweep_t<2>(a, st);
+    else if (nmb_t == 4) launch_sweep_t<4>(a, st);
+    else if (nmb_t == 7) launch_sweep_t<7>(a, st);
+    else if (nmb_t == 13) launch_sweep_t<13>(a, st);
+    else launch_sweep_t<16>(a, st);
+}
+
+void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
+                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
+    const int r = p->r, dy = p->d_y;
+    const int dy_pad = (dy + 15) / 16 * 16;
+    const int ldt = dy_pad + 8;  // 16-byte aligned rows, shifted banks
+    const int r_pad = (r + 31) / 32 * 32;
+    const size_t lds = (size_t)r_pad * ldt * sizeof(__hip_bfloat16);
+    DINO_REQUIRE(lds <= 160 * 1024, DINO_EINVAL, "r x d_y too large for the LDS-staged Hessian");
+    static bool attr = false;
+    if (!attr) {
+        DINO_HIP(hipFuncSetAttribute((const void*)hess_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL(hess_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, dy_pad, ldt, B, e, A, strideA,
+                       slot, slot_xor, slot_stride, g);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_to_float(long count, const double* x, float* xf, hipStream_t st) {
+    const int blocks = (int)std::min<long>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_float_kernel, dim3(blocks), dim3(256), 0, st, count, x, xf);
+    DINO_HIP(hipGetLastError());
+}
+
+// H[c][j][k] = A[c][max(j,k)][min(j,k)] - [j == k]: the full H from the lower I + H.
+__global__ void sym_from_lower_kernel(int n, int r, const double* __restrict__ A, double* __restrict__ H) {
+    const long rr = (long)r * r, total = (long)n * rr;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long c = e / rr;
+        const int j = (int)((e % rr) / r), k = (int)(e % r);
+        const int hi = j > k ? j : k, lo = j > k ? k : j;
+        H[e] = A[c * rr + (long)hi * r + lo] - (j == k ? 1.0 : 0.0);
+    }
+}
+
+void launch_sym_from_lower(int n, int r, const double* A, double* H, hipStream_t st) {
+    const long total = (long)n * r * r;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(sym_from_lower_kernel, dim3(blocks), dim3(256), 0, st, n, r, A, H);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_to_double(long count, const float* xf, double* x, hipStream_t st) {
+    const int blocks = (int)std::min<long>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(to_double_kernel, dim3(blocks), dim3(256), 0, st, count, xf, x);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_residual(dino_problem* p, int n, const float* f, float* e, double* phi, hipStream_t st) {
+    hipLaunchKernelGGL(residual_kernel, dim3(n), dim3(256), 0, st, p->d_y, f, p->y, p->winv, e, phi);
+    DINO_HIP(hipGetLastError());
+}
+
+}  // namespace dino

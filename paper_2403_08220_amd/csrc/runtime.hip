@@ -106,12 +106,23 @@ static void layout(dino_problem* p, Carver& cv) {
     p->lfwd = cv.take<double>(C);
     p->acc = cv.take<int32_t>(C);
     p->f = cv.take<double>(C * dy);
-    p->h0 = cv.take<double>(C * w);
-    p->h1 = cv.take<double>(C * w);
-    p->dprime = cv.take<double>((size_t)std::max(p->n_act, 1) * C * w);
-    p->lam0 = cv.take<double>(C * dy * w);
-    p->lam1 = cv.take<double>(C * dy * w);
-    p->Bj = cv.take<double>(C * dy * r);
+    if (p->desc.precision == DINO_PREC_F64) {
+        p->h0 = cv.take<double>(C * w);
+        p->h1 = cv.take<double>(C * w);
+        p->dprime = cv.take<double>((size_t)std::max(p->n_act, 1) * C * w);
+        p->lam0 = cv.take<double>(C * dy * w);
+        p->lam1 = cv.take<double>(C * dy * w);
+        p->Bj = cv.take<double>(C * dy * r);
+    } else {
+        p->ldd32 = 32 * sweep_nmb(p->ctx);  // the sweep reads gelu' rows of its full instance width
+        p->xpf = cv.take<float>(C * r);
+        p->h0f = cv.take<float>(C * w);
+        p->h1f = cv.take<float>(C * w);
+        p->f32 = cv.take<float>(C * dy);
+        p->e32 = cv.take<float>(C * dy);
+        p->d32 = cv.take<float>((size_t)std::max(p->n_act, 1) * C * p->ldd32);
+        p->B16 = cv.take<__hip_bfloat16>(C * dy * r);
+    }
     const size_t cap = (size_t)std::max(p->desc.trace_capacity, 0);
     p->xtrace = cap ? cv.take<float>(cap * C * r) : nullptr;
     p->phitrace = cap ? cv.take<double>(cap * C) : nullptr;
@@ -147,13 +158,42 @@ static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d
 
 static hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Geometry stages at reduced points x (Sec. 5.1): each function is one profiled stage.
+// A (slot-selected) receives I + H, later factorised in place.
+static void stage_forward(dino_problem* p, int n, const double* x, double* f64, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) {
+        launch_forward(p, n, x, f64, st);
+    } else {
+        launch_to_float((long)n * p->r, x, p->xpf, st);
+        launch_forward32(p, n, p->xpf, p->f32, st);
+    }
+}
+
+static void stage_jacobian(dino_problem* p, int n, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) launch_reverse_jacobian(p, n, p->Bj, st);
+    else launch_sweep_bf16(p, n, p->d32, p->ldd32, p->B16, st);
+}
+
+static void stage_misfit(dino_problem* p, int n, const double* f64, double* phi, double* g, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) launch_misfit_grad(p, n, f64, p->Bj, phi, g, st);
+    else launch_residual(p, n, p->f32, p->e32, phi, st);
+}
+
+static void stage_hessian(dino_problem* p, int n, double* g, double* A, long strideA, const int32_t* slot,
+                          int slot_xor, long slot_stride, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64)
+        launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
+    else
+        launch_hess_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
+}
+
 static void geometry_at(dino_problem* p, int n, const double* x, double* f, double* phi, double* g, double* A,
                         long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* logdet,
                         int32_t* ok, hipStream_t st) {
-    launch_forward(p, n, x, f, st);
-    launch_reverse_jacobian(p, n, p->Bj, st);
-    launch_misfit_grad(p, n, f, p->Bj, phi, g, st);
-    launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
+    stage_forward(p, n, x, f, st);
+    stage_jacobian(p, n, st);
+    stage_misfit(p, n, f, phi, g, st);  // the FP64 ppg reads the Jacobian
+    stage_hessian(p, n, g, A, strideA, slot, slot_xor, slot_stride, st);
     launch_cholesky_slot(n, p->r, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
 }
 
@@ -300,6 +340,25 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
                 DINO_HIP(hipMemcpy(ly.W32, w32.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
                 DINO_HIP(hipMemcpy(ly.b32, b32.data(), sizeof(float) * ly.fan_out, hipMemcpyHostToDevice));
             }
+            // BF16 MFMA operand tiles of W^T for the reverse sweep, packed for the sweep
+            // instance that covers the widest layer
+            dino_ctx probe;
+            probe.r_in = fan_in[0];
+            for (int l = 0; l < n_layers; ++l) {
+                probe.layers.emplace_back();
+                probe.layers.back().fan_in = fan_in[l];
+                probe.layers.back().fan_out = fan_out[l];
+            }
+            const int nmb_t = sweep_nmb(&probe);
+            probe.layers.clear();
+            for (int l = 0; l + 1 < n_layers; ++l) {
+                Layer& ly = ls[l];
+                std::vector<uint16_t> tiles;
+                int nmb_out = 0;
+                pack_sweep_tiles(ly.hostW, ly.fan_out, ly.fan_in, nmb_t, tiles, nmb_out);
+                DINO_HIP(hipMalloc(&ly.WtB, sizeof(uint16_t) * tiles.size()));
+                DINO_HIP(hipMemcpy(ly.WtB, tiles.data(), sizeof(uint16_t) * tiles.size(), hipMemcpyHostToDevice));
+            }
         } catch (...) {
             free_layers(ls);
             throw;
@@ -358,6 +417,8 @@ dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, co
             for (int i = 0; i < desc->d_y; ++i) winv[i] = std::isinf(noise_var[i]) ? 0.0 : 1.0 / std::sqrt(noise_var[i]);
             DINO_HIP(hipMemcpy(p->y, y, sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
             DINO_HIP(hipMemcpy(p->winv, winv.data(), sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
+            if (p->d32)  // the sweep reads gelu' rows up to a multiple of 32: the padding stays zero
+                DINO_HIP(hipMemset(p->d32, 0, sizeof(float) * std::max(p->n_act, 1) * p->C * p->ldd32));
         } catch (...) {
             if (p->own_ws && p->ws) hipFree(p->ws);
             delete p;
@@ -421,7 +482,8 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
         const long rr = (long)p->r * p->r;
         const long half = (long)p->C * rr;
         const int L = (int)p->ctx->layers.size();
-        const int32_t launches[DINO_N_STAGES] = {1, L, L, 1, 1, 1, 1, 1, 1};
+        const bool f64 = p->desc.precision == DINO_PREC_F64;
+        const int32_t launches[DINO_N_STAGES] = {1, f64 ? L : L + 1, f64 ? L : 1, 1, 1, 1, 1, 1, 1};
         auto mark = [&](int i) {
             if (p->profile) DINO_HIP(hipEventRecord(p->ev[i], st));
         };
@@ -431,13 +493,13 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
             launch_propose_slot(p, p->C, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, step, p->xp, p->lfwd,
                                 p->logdet, st);
             mark(1);
-            launch_forward(p, p->C, p->xp, p->f, st);
+            stage_forward(p, p->C, p->xp, p->f, st);
             mark(2);
-            launch_reverse_jacobian(p, p->C, p->Bj, st);
+            stage_jacobian(p, p->C, st);
             mark(3);
-            launch_misfit_grad(p, p->C, p->f, p->Bj, p->phip, p->gp, st);
+            stage_misfit(p, p->C, p->f, p->phip, p->gp, st);
             mark(4);
-            launch_gn_hessian_slot(p, p->C, p->Bj, p->Lbuf, rr, p->cur, 1, half, 1, 0, st);
+            stage_hessian(p, p->C, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
             mark(5);
             launch_cholesky_slot(p->C, p->r, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
             mark(6);
@@ -601,11 +663,12 @@ dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* 
         DINO_HIP(hipSetDevice(p->ctx->device));
         hipStream_t st = as_stream(stream);
         const long rr = (long)p->r * p->r;
-        launch_forward(p, n, x, f, st);
-        launch_reverse_jacobian(p, n, p->Bj, st);
-        launch_misfit_grad(p, n, f, p->Bj, phi, g, st);
-        if (H) launch_gn_hessian_slot(p, n, p->Bj, H, rr, nullptr, 0, 0, 0, 1, st);
-        launch_gn_hessian_slot(p, n, p->Bj, L, rr, nullptr, 0, 0, 1, 0, st);
+        stage_forward(p, n, x, f, st);
+        stage_jacobian(p, n, st);
+        stage_misfit(p, n, f, phi, g, st);
+        stage_hessian(p, n, g, L, rr, nullptr, 0, 0, st);
+        if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
+        if (H) launch_sym_from_lower(n, p->r, L, H, st);
         launch_cholesky_slot(n, p->r, L, rr, nullptr, 0, 0, logdet, ok, st);
         p->last_stream = st;
     });

@@ -105,7 +105,6 @@ struct Layer {
     double* b64 = nullptr;
     float* W32 = nullptr;
     float* b32 = nullptr;
-    __hip_bfloat16* WtB = nullptr;  // bf16 copy in the layout of the reverse sweep
     std::vector<double> hostW, hostb;
 };
 
@@ -128,6 +127,7 @@ struct dino_ctx {
     std::vector<dino::Layer> layers;
     int r_in = 0, d_out = 0, max_width = 0, n_act = 0;
     int live_problems = 0;
+    __hip_bfloat16* sweep_tiles = nullptr;  // BF16 W^T tiles of the reverse sweep, in work-item order
 };
 
 namespace dino {

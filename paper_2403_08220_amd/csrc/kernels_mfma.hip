@@ -33,7 +33,6 @@ __device__ __forceinline__ int pi_row(int h, int jj) { return 8 * (jj >> 2) + 4 
 // Sweep arguments: reverse layers in processing order (output side first). The
 // packed tiles of one (layer, output block) work item are contiguous: NT(NMB) tiles
 // of 1 KB, of which the first 2*NMB hold the K chunks (zero beyond the layer's K).
-constexpr int MAX_ITEMS = 240;
 
 struct SweepLayer {
     const float* d;       // gelu'(z) of the layer (C x ldd, zero padded) or null
@@ -47,35 +46,26 @@ struct SweepArgs {
     int w_out;            // fan_in of the output layer (rows of Lambda_L)
     int ldd;              // row length of the d buffers
     int r;                // rows of the final B^T
+    int ldb;              // row stride of B (r rounded up to 32)
     int n_layers;
     int n_items;
     const float* Wout;    // output layer weights (d_out x w_out), FP32
     const double* winv;   // Gamma^-1/2 diagonal (dy)
     __hip_bfloat16* B;    // out: C*dy x r, BF16
     SweepLayer layer[15];
-    const bf16x8* item_tiles[MAX_ITEMS];
+    const bf16x8* tiles;  // all work items' tiles, contiguous in processing order
 };
 
 constexpr int sweep_nt(int nmb) { return (2 * nmb + 3) / 4 * 4; }  // tiles per item, multiple of 4
-constexpr int SWEEP_NBUF = 3;                                         // LDS ring depth (prefetch distance 2)
+// LDS ring depth (a power of two): items are copied NBUF - 1 ahead; the ring fits in 150 KB.
+constexpr int sweep_nbuf(int nmb) { return sweep_nt(nmb) * 4 <= 150 ? 4 : 2; }
 
-// Four consecutive 1 KB tiles of the current item from LDS; the wait stays inside the
-// asm block so no load is in flight when the registers are handed back.
-__device__ __forceinline__ void lds_read4(uint32_t addr, bf16x8& a0, bf16x8& a1, bf16x8& a2, bf16x8& a3) {
-    int4 r0, r1, r2, r3;
-    asm volatile(
-        "ds_read_b128 %0, %4\n\t"
-        "ds_read_b128 %1, %4 offset:1024\n\t"
-        "ds_read_b128 %2, %4 offset:2048\n\t"
-        "ds_read_b128 %3, %4 offset:3072\n\t"
-        "s_waitcnt lgkmcnt(0)"
-        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)  // early clobber: never share the address VGPR
-        : "v"(addr)
-        : "memory");
-    a0 = __builtin_bit_cast(bf16x8, r0);
-    a1 = __builtin_bit_cast(bf16x8, r1);
-    a2 = __builtin_bit_cast(bf16x8, r2);
-    a3 = __builtin_bit_cast(bf16x8, r3);
+// One 1 KB tile copy global -> LDS (global_load_lds_dwordx4): every lane moves 16 B of
+// its own address to lds_base + 16 * lane. Issued from asm so that the compiler's
+// LDS-read scheduling is not serialised behind the copy; completion is tracked by
+// the explicit vmcnt waits of the kernel (the copy has no VGPR result).
+__device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base) : "memory");
 }
 
 template <int NMB>
@@ -83,8 +73,9 @@ __global__ __launch_bounds__(JAC_TPB) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void jac_sweep_bf16_kernel(SweepArgs args) {
     constexpr int NKC = 2 * NMB;          // K chunks per item (MFMAs per item)
     constexpr int NT = sweep_nt(NMB);     // tiles per item (copies per wave: NT / 4)
-    constexpr int NKC4 = (NKC + 3) / 4;   // groups of four tile reads
-    extern __shared__ bf16x8 tiles_lds[]; // SWEEP_NBUF buffers x NT tiles x 64 lanes
+    constexpr int NBUF = sweep_nbuf(NMB); // ring depth
+    constexpr int YOUNGER = (NBUF - 2) * (NT / 4);  // copies of younger items allowed in flight
+    extern __shared__ bf16x8 tiles_lds[]; // NBUF buffers x NT tiles x 64 lanes
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nl = lane & 31, h = lane >> 5;
     const int col = (blockIdx.x * JAC_WAVES + wave) * 32 + nl;
@@ -92,10 +83,10 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
     const int c = valid ? col / args.dy : 0;
     const int i = valid ? col % args.dy : 0;
 
-    // The residual stream Lambda^T is kept without the Gamma^-1/2 row factor (applied
-    // when B is written) and stored between layers in FP16 registers (D layout);
-    // every product runs on BF16 operands with FP32 accumulation.
-    f16x16 lam[NMB];
+    // The residual stream Lambda^T is kept in FP32 without the Gamma^-1/2 row factor
+    // (applied when B is written); each 32-row block is the accumulator of its own
+    // MFMA chain, updated in place (D layout). Products run on BF16 operands.
+    f32x16 lam[NMB];
     {
         const float* wrow = args.Wout + (long)i * args.w_out;
 #pragma unroll
@@ -103,38 +94,38 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
 #pragma unroll
             for (int j = 0; j < 16; ++j) {
                 const int row = 32 * mb + 8 * (j >> 2) + 4 * h + (j & 3);
-                lam[mb][j] = (_Float16)((valid && row < args.w_out) ? wrow[row] : 0.f);
+                lam[mb][j] = (valid && row < args.w_out) ? wrow[row] : 0.f;
             }
     }
     const float wi = valid ? (float)args.winv[i] : 0.f;
 
     // Work items (layer, output block) are walked in lockstep by all waves. Direct
     // global -> LDS copies (global_load_lds_dwordx4) move whole 1 KB tiles (64 lanes x
-    // 16 B at a wave-uniform LDS base); every wave copies NT/4 tiles of an item, two
-    // items ahead, into a ring of SWEEP_NBUF buffers.
+    // 16 B at a wave-uniform LDS base); every wave copies NT/4 tiles of an item,
+    // NBUF - 1 items ahead, into a ring of NBUF buffers.
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) bf16x8*)tiles_lds;
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
     auto stage = [&](int item) {
-        const bf16x8* src = args.item_tiles[item];
-        bf16x8* dst = tiles_lds + (long)(item % SWEEP_NBUF) * NT * 64;
+        const bf16x8* src = args.tiles + (long)item * NT * 64;
+        const uint32_t dst = lds_base + (uint32_t)((item & (NBUF - 1)) * NT * 64 * 16);
 #pragma unroll
         for (int q = 0; q < NT / 4; ++q) {
-            const int kc = wave + 4 * q;
-            __builtin_amdgcn_global_load_lds((const void*)(src + kc * 64 + lane),
-                                             (__attribute__((address_space(3))) void*)(dst + kc * 64), 16, 0, 0);
+            const int kc = wave_u + 4 * q;
+            dma_tile(src + kc * 64 + lane, __builtin_amdgcn_readfirstlane(dst + (uint32_t)kc * 1024u));
         }
     };
-    // Item `item` is resident once this wave has at most the copies of the one
-    // younger item in flight, and every wave has passed the barrier.
-    auto wait_item = [&]() {
-        asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(NT / 4) : "memory");
+    // Item k is resident once this wave has at most the copies of the NBUF - 2 items
+    // younger than k in flight (copies land in issue order) and every wave has passed
+    // the barrier. Near the end of the sequence, where fewer younger items exist, the
+    // wait drains everything.
+    auto wait_for = [&](int k) {
+        if (k + NBUF - 2 <= args.n_items - 1) asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(YOUNGER) : "memory");
+        else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
     };
-    auto wait_all = [&]() { asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory"); };
 
-    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) bf16x8*)tiles_lds;
-    if (args.n_items > 0) stage(0);
-    if (args.n_items > 1) stage(1);
-    if (args.n_items > 1) wait_item();
-    else wait_all();
-    __hip_bfloat16* brow = args.B + (long)col * args.r;
+    for (int k = 0; k < NBUF - 1 && k < args.n_items; ++k) stage(k);
+    wait_for(0);
+    __hip_bfloat16* brow = args.B + (long)col * args.ldb;
 
     int item = 0;
     for (int li = 0; li < args.n_layers; ++li) {
@@ -142,58 +133,54 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
         const bool last = (li == args.n_layers - 1);
         // B operands: bf16(d * Lambda) for every K chunk of this layer
         bf16x8 bop[NKC];
+        if (L.d) {
+            const float4* drow = reinterpret_cast<const float4*>(L.d + (long)c * args.ldd + 4 * h);
 #pragma unroll
-        for (int mb = 0; mb < NMB; ++mb) {
+            for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                float dv[8];
+                for (int q = 0; q < 2; ++q) {
+                    const float4 d0 = drow[8 * mb + 4 * q];
+                    const float4 d1 = drow[8 * mb + 4 * q + 2];
+                    const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) dv[jj] = 1.f;
-                if (L.d) {
-                    const float* drow = L.d + (long)c * args.ldd + 32 * mb + 16 * q + 4 * h;
-                    const float4 d0 = *reinterpret_cast<const float4*>(drow);
-                    const float4 d1 = *reinterpret_cast<const float4*>(drow + 8);
-                    dv[0] = d0.x; dv[1] = d0.y; dv[2] = d0.z; dv[3] = d0.w;
-                    dv[4] = d1.x; dv[5] = d1.y; dv[6] = d1.z; dv[7] = d1.w;
+                    for (int jj = 0; jj < 8; ++jj) bop[2 * mb + q][jj] = (__bf16)(lam[mb][8 * q + jj] * dv[jj]);
+                    __builtin_amdgcn_sched_barrier(0);  // keep only one block's gelu' values live
                 }
+        } else {
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj)
-                    bop[2 * mb + q][jj] = (__bf16)((float)lam[mb][8 * q + jj] * dv[jj]);
-            }
+            for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) bop[2 * mb + q][jj] = (__bf16)lam[mb][8 * q + jj];
         }
 #pragma unroll
         for (int mob = 0; mob < NMB; ++mob) {
             if (mob < L.nmb_out) {
-                if (item + 2 < args.n_items) stage(item + 2);
-                const uint32_t cur = lds_base + (uint32_t)((item % SWEEP_NBUF) * NT * 64 * 16) + lane * 16;
-                f32x16 acc;
+                if (item + NBUF - 1 < args.n_items) stage(item + NBUF - 1);
+                const bf16x8* cur = tiles_lds + (long)(item & (NBUF - 1)) * NT * 64 + lane;
+                if (!L.resid)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) acc[j] = L.resid ? (float)lam[mob][j] : 0.f;
+                    for (int j = 0; j < 16; ++j) lam[mob][j] = 0.f;
 #pragma unroll
-                for (int g4 = 0; g4 < NKC4; ++g4) {
-                    bf16x8 a[4];
-                    lds_read4(cur + g4 * 4096, a[0], a[1], a[2], a[3]);
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (4 * g4 + t < NKC)
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[t], bop[4 * g4 + t], acc, 0, 0, 0);
-                }
-                if (!last) {
-#pragma unroll
-                    for (int j = 0; j < 16; ++j) lam[mob][j] = (_Float16)acc[j];
-                } else if (valid) {
-                    // B[col][m] = winv_i Lambda_0^T[m][col] for m < r
+                for (int kc = 0; kc < NKC; ++kc)
+                    lam[mob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[kc * 64], bop[kc], lam[mob], 0, 0, 0);
+                const f32x16& acc = lam[mob];
+                if (last && valid) {
+                    // B[col][m] = winv_i Lambda_0^T[m][col]; rows padded to ldb (a multiple of
+                    // 32), so whole blocks are written with 8-byte streaming stores
 #pragma unroll
                     for (int b = 0; b < 4; ++b) {
                         const int m0 = 32 * mob + 8 * b + 4 * h;
+                        uint64_t v = 0;
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
-                            if (m0 + t < args.r) brow[m0 + t] = __float2bfloat16(wi * acc[4 * b + t]);
+                            v |= (uint64_t)__builtin_bit_cast(uint16_t, __float2bfloat16(wi * acc[4 * b + t])) << (16 * t);
+                        __builtin_nontemporal_store(v, reinterpret_cast<uint64_t*>(brow + m0));
                     }
                 }
                 ++item;
-                if (item + 1 < args.n_items) wait_item();
-                else wait_all();
+                if (item < args.n_items) wait_for(item);
             }
         }
         // rows beyond this layer's output are zero (no stale values when widths shrink)
@@ -201,7 +188,7 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
         for (int mb = 0; mb < NMB; ++mb)
             if (mb >= L.nmb_out)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) lam[mb][j] = (_Float16)0.f;
+                for (int j = 0; j < 16; ++j) lam[mb][j] = 0.f;
     }
 }
 
@@ -212,7 +199,7 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
 // is one 16-byte read.
 constexpr int HES_TPB = 256;
 
-__global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int dy_pad, int ldt,
+__global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int ldb, int dy_pad, int ldt,
                                                             const __hip_bfloat16* __restrict__ B,
                                                             const float* __restrict__ e, double* A, long strideA,
                                                             const int32_t* slot, int slot_xor, long slot_stride,
@@ -221,11 +208,11 @@ __global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int d
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nmb = (r + 31) / 32;
     const int r_pad = nmb * 32;
-    const __hip_bfloat16* Bc = B + (long)c * dy * r;
+    const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
     // transpose into LDS: bt[j][i] = B[i][j], zero padded
     for (int e2 = tid; e2 < r_pad * dy_pad; e2 += HES_TPB) {
         const int j = e2 / dy_pad, ii = e2 % dy_pad;
-        bt[(long)j * ldt + ii] = (j < r && ii < dy) ? Bc[(long)ii * r + j] : __float2bfloat16(0.f);
+        bt[(long)j * ldt + ii] = (j < r && ii < dy) ? Bc[(long)ii * ldb + j] : __float2bfloat16(0.f);
     }
     __syncthreads();
     // gradient g_j = sum_i B[i][j] e[i]
@@ -340,7 +327,7 @@ void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int
 
 template <int NMB>
 static void launch_sweep_t(const SweepArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)SWEEP_NBUF * sweep_nt(NMB) * 64 * sizeof(bf16x8);
+    const size_t lds = (size_t)sweep_nbuf(NMB) * sweep_nt(NMB) * 64 * sizeof(bf16x8);
     static bool attr = false;
     if (!attr) {
         DINO_HIP(hipFuncSetAttribute((const void*)jac_sweep_bf16_kernel<NMB>,
@@ -362,10 +349,12 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
     a.w_out = ctx->layers[L - 1].fan_in;
     a.ldd = ldd;
     a.r = p->r;
+    a.ldb = (p->r + 31) / 32 * 32;
     a.Wout = ctx->layers[L - 1].W32;
     a.winv = p->winv;
     a.B = Bout;
     a.n_layers = L - 1;
+    a.tiles = reinterpret_cast<const bf16x8*>(ctx->sweep_tiles);
     DINO_REQUIRE(ldd >= 32 * nmb_t, DINO_EINVAL, "gelu' buffer rows shorter than the sweep width");
     int act = p->n_act, items = 0;
     const int nt = sweep_nt(nmb_t);
@@ -381,10 +370,7 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
         } else {
             s.d = nullptr;
         }
-        for (int mo = 0; mo < s.nmb_out; ++mo) {
-            DINO_REQUIRE(items < MAX_ITEMS, DINO_EINVAL, "network too large for the BF16 sweep");
-            a.item_tiles[items++] = reinterpret_cast<const bf16x8*>(ly.WtB) + (long)mo * nt * 64;
-        }
+        items += s.nmb_out;
     }
     a.n_items = items;
     if (nmb_t == 2) launch_sweep_t<2>(a, st);
@@ -408,7 +394,7 @@ void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
                                      160 * 1024));
         attr = true;
     }
-    hipLaunchKernelGGL(hess_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, dy_pad, ldt, B, e, A, strideA,
+    hipLaunchKernelGGL(hess_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, r_pad, dy_pad, ldt, B, e, A, strideA,
                        slot, slot_xor, slot_stride, g);
     DINO_HIP(hipGetLastError());
 }

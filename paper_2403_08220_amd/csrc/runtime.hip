@@ -48,7 +48,6 @@ static void free_layers(std::vector<Layer>& ls) {
         if (l.b64) hipFree(l.b64);
         if (l.W32) hipFree(l.W32);
         if (l.b32) hipFree(l.b32);
-        if (l.WtB) hipFree(l.WtB);
     }
     ls.clear();
 }
@@ -121,7 +120,7 @@ static void layout(dino_problem* p, Carver& cv) {
         p->f32 = cv.take<float>(C * dy);
         p->e32 = cv.take<float>(C * dy);
         p->d32 = cv.take<float>((size_t)std::max(p->n_act, 1) * C * p->ldd32);
-        p->B16 = cv.take<__hip_bfloat16>(C * dy * r);
+        p->B16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));  // rows padded to 32
     }
     const size_t cap = (size_t)std::max(p->desc.trace_capacity, 0);
     p->xtrace = cap ? cv.take<float>(cap * C * r) : nullptr;
@@ -226,6 +225,7 @@ dino_status dino_ctx_destroy(dino_ctx* ctx) {
         DINO_HIP(hipSetDevice(ctx->device));
         free_basis(ctx->basis);
         free_layers(ctx->layers);
+        if (ctx->sweep_tiles) (void)hipFree(ctx->sweep_tiles);
         delete ctx;
     });
 }
@@ -318,6 +318,7 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         }
         DINO_HIP(hipSetDevice(ctx->device));
         std::vector<Layer> ls(n_layers);
+        __hip_bfloat16* new_tiles = nullptr;
         try {
             for (int l = 0; l < n_layers; ++l) {
                 Layer& ly = ls[l];
@@ -351,19 +352,26 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
             }
             const int nmb_t = sweep_nmb(&probe);
             probe.layers.clear();
-            for (int l = 0; l + 1 < n_layers; ++l) {
-                Layer& ly = ls[l];
+            // reverse processing order: layer n_layers-2 first, output blocks ascending
+            std::vector<uint16_t> all;
+            for (int l = n_layers - 2; l >= 0; --l) {
                 std::vector<uint16_t> tiles;
                 int nmb_out = 0;
-                pack_sweep_tiles(ly.hostW, ly.fan_out, ly.fan_in, nmb_t, tiles, nmb_out);
-                DINO_HIP(hipMalloc(&ly.WtB, sizeof(uint16_t) * tiles.size()));
-                DINO_HIP(hipMemcpy(ly.WtB, tiles.data(), sizeof(uint16_t) * tiles.size(), hipMemcpyHostToDevice));
+                pack_sweep_tiles(ls[l].hostW, ls[l].fan_out, ls[l].fan_in, nmb_t, tiles, nmb_out);
+                all.insert(all.end(), tiles.begin(), tiles.end());
+            }
+            if (!all.empty()) {
+                DINO_HIP(hipMalloc(&new_tiles, sizeof(uint16_t) * all.size()));
+                DINO_HIP(hipMemcpy(new_tiles, all.data(), sizeof(uint16_t) * all.size(), hipMemcpyHostToDevice));
             }
         } catch (...) {
             free_layers(ls);
+            if (new_tiles) (void)hipFree(new_tiles);
             throw;
         }
         free_layers(ctx->layers);
+        if (ctx->sweep_tiles) (void)hipFree(ctx->sweep_tiles);
+        ctx->sweep_tiles = new_tiles;
         ctx->layers = std::move(ls);
         ctx->r_in = fan_in[0];
         ctx->d_out = fan_out[n_layers - 1];

@@ -71,7 +71,8 @@ __device__ void l_matvec(const double* __restrict__ L, int r, const double* v, d
 // Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
 // a block first subtract the already solved part (8 threads per row), then lanes
 // 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
-__device__ void l_solve(const double* __restrict__ L, int r, const double* b, double* w, double* acc_s) {
+__device__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
+                        double* acc_s) {
     const int tid = threadIdx.x;
     for (int b0 = 0; b0 < r; b0 += SB) {
         const int nb = min(SB, r - b0);
@@ -105,7 +106,7 @@ __device__ void l_solve(const double* __restrict__ L, int r, const double* b, do
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj) {
                 if (jj < nb) {
-                    const double wj = __shfl(a / row[jj], jj);  // valid on lane jj
+                    const double wj = __shfl(a * invd[b0 + jj], jj);  // valid on lane jj
                     if (lane == jj) sol = wj;
                     if (lane > jj) a -= row[jj] * wj;
                 }
@@ -119,7 +120,8 @@ __device__ void l_solve(const double* __restrict__ L, int r, const double* b, do
 // Backward substitution L^T x = b. Blocks from the bottom: rows of the block subtract
 // the solved part below through column reads (32 consecutive columns per row), then
 // lanes 0..SB-1 of wave 0 finish the block's transposed triangle.
-__device__ void lt_solve(const double* __restrict__ L, int r, const double* b, double* x, double* part) {
+__device__ void lt_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* x,
+                         double* part) {
     const int tid = threadIdx.x;
     const int nblk = (r + SB - 1) / SB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -153,7 +155,7 @@ __device__ void lt_solve(const double* __restrict__ L, int r, const double* b, d
 #pragma unroll
             for (int jj = SB - 1; jj >= 0; --jj) {
                 if (jj < nb) {
-                    const double xj = __shfl(a / col[jj], jj);
+                    const double xj = __shfl(a * invd[b0 + jj], jj);
                     if (lane == jj) sol = xj;
                     if (lane < jj) a -= col[jj] * xj;
                 }
@@ -162,6 +164,12 @@ __device__ void lt_solve(const double* __restrict__ L, int r, const double* b, d
         }
         __syncthreads();
     }
+}
+
+// 1 / L_jj for j < r into LDS (the solves multiply instead of dividing).
+__device__ __forceinline__ void load_inv_diag(const double* __restrict__ L, int r, double* invd) {
+    for (int j = threadIdx.x; j < r; j += TPB) invd[j] = 1.0 / L[(long)j * r + j];
+    __syncthreads();
 }
 
 __device__ __forceinline__ long slot_offset(const int32_t* slot, int slot_xor, long slot_stride, int c) {
@@ -193,25 +201,24 @@ __global__ __launch_bounds__(TPB) void cholesky_kernel(int r, double* A, long st
             if (jj < jb) P[i * CLDP + jj] = a[(long)(j0 + i) * r + j0 + jj];
         }
         __syncthreads();
+        // Column jj of the panel: every thread forms the pivot from the finished entry,
+        // scales its rows, then threads (column kk = tid % 32, row group tid / 32) apply
+        // the rank-1 update to the panel columns right of jj.
+        const int kk = tid & (CNB - 1), rg = tid >> 5;
         for (int jj = 0; jj < jb; ++jj) {
             const double piv = P[jj * CLDP + jj];
             const double dgl = sqrt(piv);
             const double inv = 1.0 / dgl;
+            for (int i = jj + 1 + tid; i < rows; i += TPB) P[i * CLDP + jj] *= inv;
             __syncthreads();
             if (tid == 0) {
                 if (!(piv > 0.0)) fail = 1;
                 else ld_acc += log(dgl);
                 P[jj * CLDP + jj] = dgl;
             }
-            for (int i = jj + 1 + tid; i < rows; i += TPB) P[i * CLDP + jj] *= inv;
-            __syncthreads();
-            const int ncol = jb - jj - 1;
-            if (ncol > 0) {
-                const int nrow = rows - jj - 1;
-                for (int e = tid; e < nrow * ncol; e += TPB) {
-                    const int i = jj + 1 + e / ncol, k = jj + 1 + e % ncol;
-                    if (k <= i) P[i * CLDP + k] -= P[i * CLDP + jj] * P[k * CLDP + jj];
-                }
+            if (kk > jj && kk < jb) {
+                const double lk = P[kk * CLDP + jj];
+                for (int i = kk + rg; i < rows; i += TPB / CNB) P[i * CLDP + kk] -= P[i * CLDP + jj] * lk;
             }
             __syncthreads();
         }
@@ -274,11 +281,12 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
                                                       const double* __restrict__ xi_given,
                                                       const double* __restrict__ logdet, double* __restrict__ xp,
                                                       double* __restrict__ lfwd) {
-    __shared__ double xs[MAXR], gs[MAXR], u[MAXR], t[MAXR], w[MAXR], xi[MAXR];
+    __shared__ double xs[MAXR], gs[MAXR], u[MAXR], t[MAXR], w[MAXR], xi[MAXR], invd[MAXR];
     __shared__ double part[4 * MAXR];
     __shared__ double red[TPB / 64];
     const int c = blockIdx.x, tid = threadIdx.x;
     const double* Lc = L + (long)c * strideL + slot_offset(slot, slot_xor, slot_stride, c);
+    load_inv_diag(Lc, r, invd);
     for (int j = tid; j < r; j += TPB) {
         xs[j] = x[(long)c * r + j];
         gs[j] = g[(long)c * r + j];
@@ -299,10 +307,10 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
     l_matvec(Lc, r, u, t);
     for (int j = tid; j < r; j += TPB) t[j] -= (1.0 - s) * (xs[j] + gs[j]);
     __syncthreads();
-    l_solve(Lc, r, t, w, part);
+    l_solve(Lc, invd, r, t, w, part);
     for (int j = tid; j < r; j += TPB) w[j] += beta * xi[j];
     __syncthreads();
-    lt_solve(Lc, r, w, u, part);
+    lt_solve(Lc, invd, r, w, u, part);
     double nxi = 0.0, nm = 0.0;
     for (int j = tid; j < r; j += TPB) {
         xp[(long)c * r + j] = u[j];
@@ -323,8 +331,9 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
 // Uses L^-1 v = L^T a - L^-1 (a + g) and mhat.v = (L^T mhat).(L^T a) - mhat.(a + g).
 __device__ double log_rho0_dev(const double* La, int r, double dt, double s, double beta, const double* a,
                                const double* b, const double* ga, double logdet_a, double* u1, double* w2,
-                               double* m, double* u2, double* tmp, double* part, double* red) {
+                               double* m, double* u2, double* tmp, double* part, double* red, double* invd) {
     const int tid = threadIdx.x;
+    load_inv_diag(La, r, invd);
     for (int j = tid; j < r; j += TPB) {
         tmp[j] = a[j] + ga[j];
         m[j] = (b[j] - s * a[j]) / beta;
@@ -332,7 +341,7 @@ __device__ double log_rho0_dev(const double* La, int r, double dt, double s, dou
     __syncthreads();
     lt_matvec(La, r, a, u1, part);
     lt_matvec(La, r, m, u2, part);
-    l_solve(La, r, tmp, w2, part);
+    l_solve(La, invd, r, tmp, w2, part);
     double q1 = 0.0, d1 = 0.0, d2 = 0.0, n2 = 0.0, n3 = 0.0;
     for (int j = tid; j < r; j += TPB) {
         const double lv = u1[j] - w2[j];
@@ -355,7 +364,7 @@ __global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s
                                                       const double* logdet_x, const double* xp,
                                                       const double* phi_p, const double* g_p, const double* L_p,
                                                       const double* logdet_p, double* out) {
-    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR];
+    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR], invd[MAXR];
     __shared__ double part[4 * MAXR];
     __shared__ double red[TPB / 64];
     const int c = blockIdx.x, tid = threadIdx.x;
@@ -367,11 +376,11 @@ __global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s
     }
     __syncthreads();
     const double fwd = log_rho0_dev(L_x + c * rr, r, dt, s, beta, xs, ps, ga, logdet_x[c], u1, w2, m, u2, tmp,
-                                    part, red);
+                                    part, red, invd);
     for (int j = tid; j < r; j += TPB) ga[j] = g_p[(long)c * r + j];
     __syncthreads();
     const double rev = log_rho0_dev(L_p + c * rr, r, dt, s, beta, ps, xs, ga, logdet_p[c], u1, w2, m, u2, tmp,
-                                    part, red);
+                                    part, red, invd);
     if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
 }
 
@@ -383,7 +392,7 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
                                                      const double* phip, const double* logdetp,
                                                      const int32_t* okp, const double* lfwd, int64_t* accepts,
                                                      int64_t* failures, int32_t* accflag) {
-    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR];
+    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR], invd[MAXR];
     __shared__ double part[4 * MAXR];
     __shared__ double red[TPB / 64];
     __shared__ int decision;
@@ -399,7 +408,7 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
     __syncthreads();
     const int okc = okp[c];
     double rev = 0.0;
-    if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red);
+    if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red, invd);
     if (tid == 0) {
         const double lr = phi[c] - phip[c] + rev - lfwd[c];
         const double u = philox_uniform(seed, rid, (uint64_t)step, (uint64_t)c);

@@ -2,19 +2,27 @@
 
 Workload (the one the headline throughput is quoted on): 129x129 grid Matern prior
 (gamma 0.1, delta 1), r = 200 KLE basis, ResNet width 400 depth 4 with exact GELU,
-d_y = 100 observations with sigma = 1% of max |f(x_true)|, 512 chains. One step is
-one Markov transition of every chain through every stage of the hot path (proposal,
-surrogate forward, reduced Jacobian, misfit/ppg, GN Hessian, Cholesky, acceptance,
-complement, trace). Inputs are seeded and synthetic (no PDE data exists for this
-surrogate); chain states stay resident in HBM for the whole timed region.
+d_y = 100 observations with sigma = 1% of max |f(x_true)|, 512 chains, dt = 3e-4
+(tuned by the appendix's rule and frozen). One step is one Markov transition of
+every chain through every stage of the hot path (proposal, surrogate forward,
+reduced Jacobian, misfit/ppg, GN Hessian, Cholesky, acceptance, complement, trace).
+Inputs are seeded and synthetic (no PDE data or trained weights exist for this
+surrogate); chains start from Laplace-approximation samples around the device
+Gauss-Newton MAP, and their states stay resident in HBM for the whole timed region.
+
+The primary path is the mixed-precision one (FP32 forward, BF16 MFMA Jacobian and
+GN Hessian with FP32 accumulation, FP64 Cholesky, proposal and MH); the plain FP64
+device path is timed beside it on the same workload, and the FP64 CPU oracle on a
+bounded sample of it. Per-stage device times come from HIP events the library
+records on its stream during the timed steps.
 
 Prints ONE JSON line. --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -27,10 +35,19 @@ sys.path.insert(0, ROOT)
 PEAKS = {  # MI355X published peaks
     "hbm_GBps": 8000.0,
     "bf16_TFLOPs": 2500.0,
-    "fp8_TFLOPs": 5000.0,
     "fp32_TFLOPs": 157.3,
     "fp64_TFLOPs": 78.6,
 }
+
+# device kernel of each stage on the mixed-precision path (rocprofv3 kernel names)
+STAGE_KERNEL = {
+    "proposal": "propose_kernel", "forward": "fwd_layer_kernel", "jacobian": "jac_sweep_bf16_kernel",
+    "misfit_ppg": "residual_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_kernel",
+    "accept": "accept_kernel", "complement": "complement_kernel", "trace": "trace_kernel",
+}
+KERNEL_SOURCES = {"cholesky_kernel": "kernels_chain.hip", "propose_kernel": "kernels_chain.hip",
+                  "accept_kernel": "kernels_chain.hip", "jac_sweep_bf16_kernel": "kernels_mfma.hip",
+                  "hess_bf16_kernel": "kernels_mfma.hip", "fwd_layer_kernel": "kernels_geometry.hip"}
 
 
 def log(msg):
@@ -38,16 +55,15 @@ def log(msg):
 
 
 def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec):
-    """Algorithmic work of one launch group of a stage for one step of C chains.
-    Returns (amount, unit, bound, peak)."""
-    width = w
+    """Algorithmic work of one step of a stage over C chains.
+    Returns (amount, unit, bound, peak); the per-chain figures are in the design notes."""
     if stage == "jacobian":
-        flops = C * 2.0 * (L_res * dy * width * width + dy * width * r)
+        flops = C * 2.0 * (L_res * dy * w * w + dy * w * r)
         if prec == "bf16":
             return flops, "TFLOP/s", "mfma", PEAKS["bf16_TFLOPs"]
         return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if stage == "forward":
-        flops = C * 2.0 * (r * width + L_res * width * width + width * dy)
+        flops = C * 2.0 * (r * w + L_res * w * w + w * dy)
         return flops, "TFLOP/s", "alu", PEAKS["fp32_TFLOPs"] if prec == "bf16" else PEAKS["fp64_TFLOPs"]
     if stage == "gn_hessian":
         flops = C * 2.0 * r * r * dy / 2.0  # symmetric product, lower half
@@ -57,18 +73,22 @@ def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec):
     if stage == "cholesky":
         return C * r ** 3 / 3.0, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if stage in ("proposal", "accept"):
-        # one read of the packed-equivalent lower triangle of the factor per chain
+        # one read of the lower triangle of an FP64 factor per chain
         return C * r * (r + 1) / 2.0 * 8.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "complement":
+        # read + write of the FP32 complement of the accepted chains
         return C * accepted_frac * d_perp * 8.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "misfit_ppg":
+        # residual: read f and y, write e (FP32 path) / read B (FP64 path)
+        if prec == "bf16":
+            return C * dy * 12.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
         return C * dy * r * 8.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "trace":
         return C * r * (8.0 + 4.0), "GB/s", "hbm", PEAKS["hbm_GBps"]
     return 0.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
 
 
-def make_problem_inputs(w, layers, ctx_builder):
+def make_problem_inputs(w, ctx_builder):
     """Data y = f(x_true) + sigma eps with f evaluated by the device path."""
     import torch
     from synth import draw_noise, draw_true_state
@@ -85,12 +105,23 @@ def make_problem_inputs(w, layers, ctx_builder):
     return ctx, y, np.full(w.d_y, sigma ** 2)
 
 
-def cpu_baseline(w, layers, chains=32, budget_s=20.0, max_steps=6):
-    """The FP64 oracle on a bounded sample of the same workload."""
+def laplace_start(w, ctx, y, nv):
+    from paper_2403_08220_amd import laplace
+    from synth import draw_initial_states, draw_laplace_normals
+
+    t0 = time.perf_counter()
+    m = laplace.gauss_newton_map(ctx, y, nv)
+    x0 = laplace.laplace_samples(ctx, y, nv, m.x, draw_laplace_normals(w))
+    _, z0 = draw_initial_states(w)
+    return x0, z0, dict(J_map=m.J, gn_iters=m.iters, seconds=round(time.perf_counter() - t0, 3))
+
+
+def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=6):
+    """The FP64 oracle on a bounded sample of the same workload (same starting states)."""
     from threadpoolctl import threadpool_info
 
     from oracle import mcmc, network
-    from synth import draw_initial_states, draw_noise, draw_true_state
+    from synth import draw_noise, draw_true_state
 
     x_true = draw_true_state(w)[: w.r]
     f_true, _ = network.forward(layers, x_true[None])
@@ -98,8 +129,7 @@ def cpu_baseline(w, layers, chains=32, budget_s=20.0, max_steps=6):
     sigma = w.sigma * np.max(np.abs(f_true)) if w.sigma_rule == "rel_max" else w.sigma
     y = f_true + sigma * draw_noise(w)
     prob = mcmc.Problem(layers, y, np.full(w.d_y, sigma ** 2), w.dt, seed=w.chain_seed)
-    x0, z0 = draw_initial_states(w, chains=chains)
-    st = mcmc.init_state(prob, x0, z0.astype(np.float64))
+    st = mcmc.init_state(prob, x0[:chains], z0[:chains].astype(np.float64))
     t0 = time.perf_counter()
     steps = 0
     while steps < max_steps and (time.perf_counter() - t0) < budget_s:
@@ -107,26 +137,38 @@ def cpu_baseline(w, layers, chains=32, budget_s=20.0, max_steps=6):
         steps += 1
     dt = time.perf_counter() - t0
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    return {"value": chains * steps / dt, "unit": "chain-steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{chains} chains x {steps} steps of the same workload (FP64 NumPy/SciPy oracle, "
-                      f"{dt:.1f} s), the complement tracked", "seconds": dt}
+    return {"value": round(chains * steps / dt, 2), "unit": "chain-steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{chains} of the {w.chains} chains x {steps} steps of the same workload and starting states "
+                      f"(FP64 NumPy/SciPy oracle, complement tracked, {dt:.1f} s)"}
 
 
-def run_path(w, layers, ctx, y, nv, precision, steps, warmup, profile_steps, want_ess=True):
+def copy_calibration(nbytes=1 << 29):
+    """A plain device copy of known size (read nbytes + write nbytes): the reference
+    kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    return nbytes
+
+
+def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True):
     import torch
     from paper_2403_08220_amd import Problem
-    from synth import draw_initial_states
 
     C = w.chains
-    cap = warmup + steps if want_ess else 0
+    cap = warmup + steps
     p = Problem(ctx, C, y, nv, w.dt, seed=w.chain_seed, precision=precision, track_complement=True,
                 trace_capacity=cap)
-    x0, z0 = draw_initial_states(w, chains=C)
     p.init(x0, z0)
     stream = torch.cuda.current_stream()
     p.step(warmup)
     torch.cuda.synchronize()
     a0, _, _ = p.diagnostics()
+    if profile:
+        p.set_profiling(True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -138,33 +180,48 @@ def run_path(w, layers, ctx, y, nv, precision, steps, warmup, profile_steps, wan
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
     acc, fail, nst = p.diagnostics()
-    accept_frac = float((acc - a0).sum()) / (C * steps)
-    out = dict(wall_s=wall, gpu_ms=gpu_ms, accept_rate=accept_frac, failures=int(fail.sum()))
-    if want_ess:
-        burn = warmup + int(0.2 * steps)
-        e = p.ess(burn)
-        n_post = warmup + steps - burn
-        ess = e * C * n_post
-        out["median_ess"] = float(np.nanmedian(ess))
-        out["median_ess_frac"] = float(np.nanmedian(e))
-    if profile_steps > 0:
-        p.set_profiling(True)
-        p.step(profile_steps)
+    out = dict(wall_s=wall, gpu_ms=gpu_ms, accept_rate=float((acc - a0).sum()) / (C * steps),
+               failures=int(fail.sum()))
+    if profile:
         prof, nprof = p.profile()
         p.set_profiling(False)
-        out["profile"] = {k: dict(ms_per_step=v["ms"] / max(nprof, 1), launches=v["launches"]) for k, v in prof.items()}
+        out["profile"] = {k: dict(ms_per_step=v["ms"] / max(nprof, 1), launches=v["launches"])
+                          for k, v in prof.items()}
+    burn = int(0.2 * (warmup + steps))
+    e = p.ess(burn)
+    n_post = warmup + steps - burn
+    out["median_ess"] = float(np.nanmedian(e * C * n_post))
+    out["median_ess_frac"] = float(np.nanmedian(e))
     p.close()
     return out
+
+
+def traffic_record(kernel, workload_tag):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
+    None when that summary is missing or was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = os.path.join(ROOT, "paper_2403_08220_amd", "csrc", KERNEL_SOURCES.get(kernel, ""))
+    if not os.path.isfile(src):
+        return None
+    with open(src, "rb") as fh:
+        sha = hashlib.sha256(fh.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--precision", default="f64", choices=["f64", "bf16"])
-    ap.add_argument("--compare-f64", action="store_true", help="also time the plain FP64 path")
-    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="bf16", choices=["f64", "bf16"])
+    ap.add_argument("--fp64-steps", type=int, default=100, help="steps of the plain FP64 leg (0: skip)")
+    ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -173,7 +230,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    import torch  # noqa: F401
     from paper_2403_08220_amd import Context
     from synth import draw_network, workload
 
@@ -188,20 +245,25 @@ def main():
         return c
 
     log(f"bench: workload mid, {w.chains} chains, precision {args.precision}, steps {args.steps}")
-    ctx, y, nv = make_problem_inputs(w, layers, ctx_builder)
-    res = run_path(w, layers, ctx, y, nv, args.precision, args.steps, args.warmup, args.profile_steps)
-    log(f"bench: {args.precision} path done: {res['wall_s']:.3f} s, accept {res['accept_rate']:.3f}")
-    extra = {}
-    if args.compare_f64 and args.precision != "f64":
-        r64 = run_path(w, layers, ctx, y, nv, "f64", max(args.steps // 4, 10), args.warmup, 0)
-        extra["fp64_plain"] = dict(value=w.chains * max(args.steps // 4, 10) / r64["wall_s"],
-                                   unit="chain-steps/s", accept_rate=r64["accept_rate"],
-                                   ess_per_s=r64["median_ess"] / r64["wall_s"])
+    ctx, y, nv = make_problem_inputs(w, ctx_builder)
+    x0, z0, init_info = laplace_start(w, ctx, y, nv)
+    log(f"bench: Laplace start ready {init_info}")
+    copy_calibration()
+    res = run_path(w, ctx, y, nv, x0, z0, args.precision, args.steps, args.warmup, profile=not args.no_profile)
+    log(f"bench: {args.precision} path: {res['wall_s']:.3f} s, accept {res['accept_rate']:.3f}")
     C, steps = w.chains, args.steps
     value = C * steps / res["wall_s"]
     ms_per_step = 1e3 * res["wall_s"] / steps
 
-    # roofline of the dominant stage, from the live HIP-event profile
+    fp64 = None
+    if args.fp64_steps > 0 and args.precision != "f64":
+        r64 = run_path(w, ctx, y, nv, x0, z0, "f64", args.fp64_steps, args.warmup, profile=False)
+        fp64 = dict(value=round(C * args.fp64_steps / r64["wall_s"], 1), unit="chain-steps/s",
+                    steps=args.fp64_steps, ms_per_step=round(1e3 * r64["wall_s"] / args.fp64_steps, 4),
+                    accept_rate=round(r64["accept_rate"], 4),
+                    ess_per_s=round(r64["median_ess"] / r64["wall_s"], 3))
+        log(f"bench: f64 path: {r64['wall_s']:.3f} s, accept {r64['accept_rate']:.3f}")
+
     prof = res.get("profile", {})
     stages = {}
     for name, v in prof.items():
@@ -211,16 +273,18 @@ def main():
         ach = (amt / t / (1e12 if unit == "TFLOP/s" else 1e9)) if t > 0 else 0.0
         stages[name] = dict(ms=round(v["ms_per_step"], 4), launches=v["launches"], bound=bound,
                             achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
-    dom = max(stages, key=lambda k: stages[k]["ms"]) if stages else None
     roof = None
-    if dom:
+    if stages:
+        dom = max(stages, key=lambda k: stages[k]["ms"])
         s = stages[dom]
-        roof = dict(kernel=dom, bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"],
-                    frac=s["frac"], traffic=None, launches_per_step=s["launches"])
+        kern = STAGE_KERNEL[dom] if args.precision == "bf16" else dom
+        roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
+                    traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
+                    kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4))
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, layers)
+        cpu = cpu_baseline(w, layers, x0, z0)
     line = {
         "metric": "chain-steps/s",
         "value": round(value, 1),
@@ -232,19 +296,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "bf16+f32+f64",
-        "data": "synthetic (seeded Xavier-normal ResNet, KLE prior draws; no trained weights or PDE data)",
-        "config": {"workload": "129x129 grid, r=200 KLE, ResNet 400x4 GELU, d_y=100, 512 chains",
+        "dtype": "f64" if args.precision == "f64" else "bf16",
+        "data": "synthetic: seeded Xavier-normal ResNet and KLE prior draws (no trained weights or PDE data); "
+                "chains start from Laplace samples at the Gauss-Newton MAP",
+        "config": {"workload": "129x129 grid, r=200 KLE, ResNet 400x4 GELU, d_y=100, 512 chains, dt=3e-4",
                    "grid": w.n, "r": w.r, "width": w.width, "depth": w.depth, "d_y": w.d_y, "chains": C,
                    "dt": w.dt, "precision": args.precision},
-        "ess_per_s": round(res["median_ess"] / res["wall_s"], 2),
+        "ess_per_s": round(res["median_ess"] / res["wall_s"], 3),
         "median_ess_frac": res["median_ess_frac"],
         "accept_rate": round(res["accept_rate"], 4),
         "roofline": roof,
         "stages": stages,
+        "fp64_plain": fp64,
         "cpu_baseline": cpu,
+        "init": init_info,
     }
-    line.update(extra)
     ctx.close()
     print(json.dumps(line), flush=True)
 

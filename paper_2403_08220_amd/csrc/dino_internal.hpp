@@ -201,7 +201,10 @@ struct dino_problem {
     double* phitrace = nullptr;
     // stage profiling
     bool profile = false;
-    hipEvent_t ev[DINO_N_STAGES + 1] = {};
+    // ring of per-step stage events, drained when full and on read (no per-step host wait)
+    static constexpr int PROFILE_RING = 128;
+    std::vector<hipEvent_t> ev;   // PROFILE_RING x (DINO_N_STAGES + 1)
+    int ring_used = 0;
     double stage_ms[DINO_N_STAGES] = {};
     int32_t stage_launches[DINO_N_STAGES] = {};
     int64_t profiled_steps = 0;

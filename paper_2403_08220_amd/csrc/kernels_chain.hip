@@ -270,6 +270,115 @@ __global__ __launch_bounds__(TPB) void cholesky_kernel(int r, double* A, long st
     }
 }
 
+// Register-resident Cholesky for r <= min(G MR, 32 MC), G = NT / 32: the NT threads of a
+// block hold the lower triangle in a 2-D cyclic layout, thread t = 32 g + q owning rows
+// i = g + G m (m < MR) and columns k = q + 32 c (c < MC). A (m, c) pair is kept only if
+// it can hold a lower-triangle element (32 c <= G m + G - 1), which halves the registers.
+// Column j of the Schur complement is broadcast through LDS (double buffered, one
+// barrier per column); every thread then applies
+//     a_ik -= a_ij a_kj / a_jj        (i, k > j)
+// and the owners of column j scale it to L_ij = a_ij / sqrt(a_jj). The columns are
+// walked in phases of G: within phase p the row blocks m < p and the column blocks
+// c < (G p) / 32 are finished, and both bounds are compile-time constants of the
+// unrolled phase, so a phase's body holds only its live updates and no skip branches.
+// The pivots go to LDS; log det L = (1/2) sum_j log a_jj is reduced at the end.
+template <int G>
+__host__ __device__ constexpr bool chol_pair(int m, int c) { return 32 * c <= G * m + G - 1; }
+
+template <int NT, int MR, int MC>
+__global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long strideA, const int32_t* slot,
+                                                          int slot_xor, long slot_stride, double* logdet,
+                                                          int32_t* ok) {
+    constexpr int G = NT / 32;
+    constexpr int NB = (G * MR > 32 * MC) ? G * MR : 32 * MC;
+    __shared__ double colbuf[2][NB];
+    __shared__ double pivs[NB];
+    __shared__ double red[NT / 64];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int g = tid >> 5, q = tid & 31;
+    double* a = A + (long)c * strideA + slot_offset(slot, slot_xor, slot_stride, c);
+    for (int e = tid; e < 2 * NB; e += NT) (&colbuf[0][0])[e] = 0.0;
+    double v[MR][MC];
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+        const int i = g + G * m;
+#pragma unroll
+        for (int cc = 0; cc < MC; ++cc) {
+            if (chol_pair<G>(m, cc)) {
+                const int k = q + 32 * cc;
+                v[m][cc] = (i < r && k <= i) ? a[i * r + k] : 0.0;
+            }
+        }
+    }
+    bool bad = false;
+#pragma unroll
+    for (int ph = 0; ph < MR; ++ph) {
+        const int cj = (G * ph) / 32;   // column block of every j in this phase (G divides 32)
+        const int j1 = min(G * (ph + 1), r);
+        for (int j = G * ph; j < j1; ++j) {
+            const int buf = j & 1;
+            const int qj = j & 31;
+            // owners of column j publish it (only rows > j are read)
+            if (q == qj) {
+#pragma unroll
+                for (int m = ph; m < MR; ++m)
+                    if (chol_pair<G>(m, cj)) colbuf[buf][g + G * m] = v[m][cj];
+            }
+            __syncthreads();
+            const double piv = colbuf[buf][j];
+            bad |= !(piv > 0.0);
+            const double isq = 1.0 / sqrt(piv);
+            const double inv = isq * isq;
+            if (tid == 0) pivs[j] = piv;
+            double bk[MC];
+#pragma unroll
+            for (int cc = cj; cc < MC; ++cc) {
+                const int k = q + 32 * cc;
+                const double t = colbuf[buf][k];
+                bk[cc] = (k > j) ? t : 0.0;
+            }
+#pragma unroll
+            for (int m = ph; m < MR; ++m) {
+                const int i = g + G * m;
+                const double t = colbuf[buf][i] * inv;
+                const double am = (i > j) ? t : 0.0;
+#pragma unroll
+                for (int cc = cj; cc < MC; ++cc)
+                    if (chol_pair<G>(m, cc)) v[m][cc] -= am * bk[cc];
+            }
+            if (q == qj) {
+#pragma unroll
+                for (int m = ph; m < MR; ++m)
+                    if (chol_pair<G>(m, cj) && g + G * m >= j) v[m][cj] *= isq;
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+        const int i = g + G * m;
+#pragma unroll
+        for (int cc = 0; cc < MC; ++cc) {
+            if (chol_pair<G>(m, cc)) {
+                const int k = q + 32 * cc;
+                if (i < r && k <= i) a[i * r + k] = v[m][cc];
+            }
+        }
+    }
+    __syncthreads();
+    double ls = 0.0;
+    for (int j = tid; j < r; j += NT) ls += log(pivs[j]);
+    ls = wave_sum(ls);
+    if ((tid & 63) == 0) red[tid >> 6] = ls;
+    const int any_bad = __syncthreads_or(bad ? 1 : 0);
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        if (logdet) logdet[c] = 0.5 * t;
+        if (ok) ok[c] = any_bad ? 0 : 1;
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi).
 // lfwd (optional) = log rho_0(x -> xp) = -|xi|^2/2 + |mhat|^2/2 + logdet_x, the
@@ -501,8 +610,22 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
                                      160 * 1024 - 256));
         attr_set = true;
     }
-    hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), lds, st, r, A, strideA, slot, slot_xor, slot_stride,
-                       logdet, ok);
+    if (r <= 32) {
+        hipLaunchKernelGGL((cholesky_reg_kernel<256, 4, 1>), dim3(n), dim3(256), 0, st, r, A, strideA, slot,
+                           slot_xor, slot_stride, logdet, ok);
+    } else if (r <= 64) {
+        hipLaunchKernelGGL((cholesky_reg_kernel<256, 8, 2>), dim3(n), dim3(256), 0, st, r, A, strideA, slot,
+                           slot_xor, slot_stride, logdet, ok);
+    } else if (r <= 128) {
+        hipLaunchKernelGGL((cholesky_reg_kernel<512, 8, 4>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
+                           slot_xor, slot_stride, logdet, ok);
+    } else if (r <= 208) {
+        hipLaunchKernelGGL((cholesky_reg_kernel<512, 13, 7>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
+                           slot_xor, slot_stride, logdet, ok);
+    } else {
+        hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), lds, st, r, A, strideA, slot, slot_xor, slot_stride,
+                           logdet, ok);
+    }
     DINO_HIP(hipGetLastError());
 }
 

@@ -480,6 +480,22 @@ dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0,
     });
 }
 
+// Adds the stage times of the recorded ring entries to the totals (waits for the last one).
+static void drain_profile(dino_problem* p) {
+    if (p->ring_used == 0) return;
+    const int E = DINO_N_STAGES + 1;
+    DINO_HIP(hipEventSynchronize(p->ev[(p->ring_used - 1) * E + DINO_N_STAGES]));
+    for (int k = 0; k < p->ring_used; ++k) {
+        for (int i = 0; i < DINO_N_STAGES; ++i) {
+            float ms = 0.f;
+            DINO_HIP(hipEventElapsedTime(&ms, p->ev[k * E + i], p->ev[k * E + i + 1]));
+            p->stage_ms[i] += ms;
+        }
+    }
+    p->profiled_steps += p->ring_used;
+    p->ring_used = 0;
+}
+
 dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
     return guarded([&] {
         DINO_REQUIRE(p, DINO_EINVAL, "null problem");
@@ -493,7 +509,7 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
         const bool f64 = p->desc.precision == DINO_PREC_F64;
         const int32_t launches[DINO_N_STAGES] = {1, f64 ? L : L + 1, f64 ? L : 1, 1, 1, 1, 1, 1, 1};
         auto mark = [&](int i) {
-            if (p->profile) DINO_HIP(hipEventRecord(p->ev[i], st));
+            if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
         };
         for (int k = 0; k < n_steps; ++k) {
             const int64_t step = p->step;
@@ -521,14 +537,8 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
             }
             mark(9);
             if (p->profile) {
-                DINO_HIP(hipEventSynchronize(p->ev[DINO_N_STAGES]));
-                for (int i = 0; i < DINO_N_STAGES; ++i) {
-                    float ms = 0.f;
-                    DINO_HIP(hipEventElapsedTime(&ms, p->ev[i], p->ev[i + 1]));
-                    p->stage_ms[i] += ms;
-                    p->stage_launches[i] = launches[i];
-                }
-                p->profiled_steps += 1;
+                for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches[i];
+                if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
             }
             p->step += 1;
         }
@@ -540,9 +550,13 @@ dino_status dino_set_profiling(dino_problem* p, int enable) {
     return guarded([&] {
         DINO_REQUIRE(p, DINO_EINVAL, "null problem");
         DINO_HIP(hipSetDevice(p->ctx->device));
-        if (enable && !p->ev[0])
+        if (enable && p->ev.empty()) {
+            p->ev.assign((size_t)dino_problem::PROFILE_RING * (DINO_N_STAGES + 1), nullptr);
             for (auto& e : p->ev) DINO_HIP(hipEventCreate(&e));
+        }
+        if (p->profile) drain_profile(p);
         p->profile = enable != 0;
+        p->ring_used = 0;
         for (int i = 0; i < DINO_N_STAGES; ++i) {
             p->stage_ms[i] = 0.0;
             p->stage_launches[i] = 0;
@@ -554,6 +568,10 @@ dino_status dino_set_profiling(dino_problem* p, int enable) {
 dino_status dino_read_profile(dino_problem* p, double* stage_ms, int32_t* launches, int64_t* steps) {
     return guarded([&] {
         DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        if (!p->ev.empty()) {
+            DINO_HIP(hipSetDevice(p->ctx->device));
+            drain_profile(p);
+        }
         for (int i = 0; i < DINO_N_STAGES; ++i) {
             if (stage_ms) stage_ms[i] = p->stage_ms[i];
             if (launches) launches[i] = p->stage_launches[i];

@@ -8,8 +8,10 @@ and the two never import each other.
 """
 from .workloads import (  # noqa: F401
     CONFIGS,
+    TUNED_DT,
     Workload,
     draw_initial_states,
+    draw_laplace_normals,
     draw_network,
     draw_noise,
     draw_requests,

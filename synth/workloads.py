@@ -8,10 +8,17 @@ weights and meshes are not available:
     tiny  : 33x33 grid, r=32,  MLP 32->64->64->16 GELU, d_y=16, 4 chains x 2000 steps, dt=0.1,
             sigma = 0.01 absolute (FP64 path; also the BF16 precision study)
     mid   : 129x129 grid, r=200, ResNet width 400 depth 4, d_y=100, 512 chains x 1000 steps,
-            sigma = 1% of max |f(x_true)|
+            sigma = 1% of max |f(x_true)|, dt = 3e-4
     serve : 129x129 grid, r=200, ResNet 400x4 (100 outputs); requests with d_y in {25,50,100},
             chains uniform in [8,128], steps uniform in [500,5000], Poisson arrivals
     large : 257x257 grid, r=400, ResNet width 800 depth 6, d_y=400, 4096 chains x 2000 steps
+
+Step sizes: tiny keeps the literal dt = 0.1 of its definition; mid and serve use the
+value chosen once by the appendix's tuning rule (AR decreasing and MSJ increasing up
+to dt_max, then the largest median ESS%) on the FP64 device path from Laplace
+samples, over the candidates 3e-5, 1e-4, 3e-4, 1e-3, 3e-3: 3e-4 (AR 0.27), and
+frozen here. TUNED_DT records the tuned value of every workload that has one (tiny:
+3e-3 over 1e-4 .. 3e-2, AR 0.13). large is not tuned.
 
 Prior: (-gamma Lap + delta I)^-2 with gamma = 0.1, delta = 1 on every grid.
 Weights: Xavier/Glorot normal, std sqrt(2/(fan_in + fan_out)), drawn with
@@ -47,6 +54,7 @@ class Workload:
     noise_seed: int = 3
     chain_seed: int = 4
     init_seed: int = 5
+    laplace_seed: int = 6
 
     @property
     def d_m(self) -> int:
@@ -55,10 +63,12 @@ class Workload:
 
 CONFIGS = {
     "tiny": Workload("tiny", 33, 0.1, 1.0, 32, "mlp", 64, 2, 16, 16, 4, 2000, 0.1, "abs", 0.01),
-    "mid": Workload("mid", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 512, 1000, 0.1, "rel_max", 0.01),
-    "serve": Workload("serve", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 68, 2750, 0.1, "rel_max", 0.01),
-    "large": Workload("large", 257, 0.1, 1.0, 400, "resnet", 800, 6, 400, 400, 4096, 2000, 0.1, "rel_max", 0.01),
+    "mid": Workload("mid", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 512, 1000, 3e-4, "rel_max", 0.01),
+    "serve": Workload("serve", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 68, 2750, 3e-4, "rel_max", 0.01),
+    "large": Workload("large", 257, 0.1, 1.0, 400, "resnet", 800, 6, 400, 400, 4096, 2000, 3e-4, "rel_max", 0.01),
 }
+
+TUNED_DT = {"tiny": 3e-3, "mid": 3e-4, "serve": 3e-4}
 
 
 def workload(name: str, **overrides) -> Workload:
@@ -120,6 +130,13 @@ def draw_initial_states(w: Workload, chains: int | None = None, seed: int | None
     x0 = rng.standard_normal((C, w.r))
     z0 = rng.standard_normal((C, w.d_m - w.r)).astype(np.float32) if complement else None
     return x0, z0
+
+
+def draw_laplace_normals(w: Workload, chains: int | None = None, seed: int | None = None) -> np.ndarray:
+    """Standard normals xi (C, r) that map to Laplace-approximation samples x_map + L^-T xi."""
+    C = w.chains if chains is None else chains
+    rng = np.random.default_rng(w.laplace_seed if seed is None else seed)
+    return rng.standard_normal((C, w.r))
 
 
 @dataclass

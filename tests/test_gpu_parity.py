@@ -52,9 +52,20 @@ def test_normals_parity():
     ctx.close()
 
 
-@pytest.mark.parametrize("kind", ["mlp", "resnet"])
+def geometry_case(kind):
+    if kind == "mlp":
+        return make_case("tiny", chains=70, bias_scale=0.3, noise_scale=0.2)
+    if kind == "resnet":
+        return small_resnet_case()
+    # reduced dimensions that select the other factorisation kernels (r in 65..128 and r > 208)
+    r = 100 if kind == "resnet-r100" else 230
+    return make_case("tiny", chains=70, arch="resnet", r=r, width=96, depth=2, d_out=80, d_y=70,
+                     bias_scale=0.3, noise_scale=0.2)
+
+
+@pytest.mark.parametrize("kind", ["mlp", "resnet", "resnet-r100", "resnet-r230"])
 def test_geometry_parity(kind):
-    case = make_case("tiny", chains=70, bias_scale=0.3, noise_scale=0.2) if kind == "mlp" else small_resnet_case()
+    case = geometry_case(kind)
     print(f"geometry {kind}", flush=True)
     ctx, p = device_problem(case)
     x = np.random.default_rng(1).standard_normal((70, case["w"].r))

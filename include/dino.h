@@ -5,7 +5,7 @@
  * The library runs the first stage of Alg. 1 (surrogate-driven mMALA with the
  * surrogate misfit deciding acceptance, eq. da_dino_trr_1) for many independent
  * chains at once, together with the pCN move of the complement subspace
- * (Prop. 4.2 item 1). Every step of the path runs in HIP kernels on the device:
+ * (splitting proposition of Sec. 5.3, item 1). Every step of the path runs in HIP kernels on the device:
  * reduced proposal (eq. reduced_space_sampling), surrogate forward and reduced
  * Jacobian (eq. rb_dino and the reduced Jacobian that follows it), surrogate
  * misfit, reduced ppg and reduced ppGNH (Sec. 5.1), Cholesky factor of I + H,
@@ -143,7 +143,7 @@ dino_status dino_problem_destroy(dino_problem* p);
  * acceptance counts and trace. */
 dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0, void* stream);
 
-/* Advance every chain n_steps transitions (Alg. 1 first stage + Prop. 4.2).
+/* Advance every chain n_steps transitions (Alg. 1 first stage + the splitting proposition of Sec. 5.3).
  * Asynchronous on stream. Per-chain numerical failures (non-finite misfit,
  * I + H not positive definite) reject the proposal and are counted; they do
  * not fail the call. */
@@ -169,7 +169,7 @@ dino_status dino_read_trace(dino_problem* p, float* x_trace, double* phi_trace, 
 /* Posterior field mean and pointwise variance (d_m each, host FP64) from the
  * recorded trace after discarding the first burn_in recorded steps: mean =
  * Psi_r xbar and var = diag(Psi_r S Psi_r^T) + var_perp (the complement is
- * prior distributed and independent of the reduced part, Lemma 4.1). Also the
+ * prior distributed and independent of the reduced part, the Gaussian lemma of Sec. 5.3). Also the
  * reduced mean xbar (r) and covariance S (r x r) if the pointers are non-NULL.
  * Computed on the device. */
 dino_status dino_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S);

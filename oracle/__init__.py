@@ -17,7 +17,7 @@ Modules, each written from the paper (sections/equations cited per function):
 * ``network`` - reduced-basis neural operator f_NN (eq. rb_dino): MLP and ResNet,
   exact GELU, reverse- and forward-mode reduced Jacobian.
 * ``mcmc``    - surrogate misfit / reduced ppg / reduced ppGNH (Sec. 5.1), the
-  surrogate mMALA proposal split (Prop. 4.2, eq. reduced_space_sampling), the
+  surrogate mMALA proposal split (the splitting proposition of Sec. 5.3, eq. reduced_space_sampling), the
   reduced RN derivative and first-stage ratio (Sec. 5.4, eq. da_dino_trr_1),
   Alg. 1 first stage with the pCN complement move, N-step runs.
 * ``stats``   - multichain ESS% (Sec. 6.2.2, eq. ess), Rao-Blackwellised posterior

@@ -1,9 +1,9 @@
-"""DINO-mMALA in reduced coordinates: Alg. 1 first stage + Prop. 4.2 (oracle; test infrastructure).
+"""DINO-mMALA in reduced coordinates: Alg. 1 first stage + the splitting proposition of Sec. 5.3 (oracle; test infrastructure).
 
 State of a chain: reduced whitened KLE coordinates x in R^r and the complement
 coordinates z_perp in R^(d_m - r) (prior N(0, I) in both). Everything the MH
 decision depends on lives in R^r (Sec. 5.4: the first stage runs entirely in the
-reduced coefficient space); the complement follows the pCN move of Prop. 4.2.
+reduced coefficient space); the complement follows the pCN move of the splitting proposition of Sec. 5.3.
 
 Readings of the paper taken here (listed with reasons in the design notes):
 * Observable basis: the network outputs physical observables and each problem has
@@ -14,7 +14,7 @@ Readings of the paper taken here (listed with reasons in the design notes):
   J^T Gamma^-1 (f - y), as in eq. ppg; the printed form has the opposite sign.
 * The determinant factor of the reduced RN derivative (Sec. 5.4) multiplies the
   exponential, prod_j (d_j + 1)^(1/2), as in eq. mmala_trr; the printed form adds it.
-* The complement move is the pCN move of Prop. 4.2 (item 1), z_perp <- s z_perp + beta zeta.
+* The complement move is the pCN move of the splitting proposition of Sec. 5.3 (item 1), z_perp <- s z_perp + beta zeta.
 * The noise of the reduced proposal (eq. reduced_space_sampling) is mapped through the
   Cholesky factor L of I + H (L L^T = I + H) instead of P (d+1)^-1/2: the same law,
   N(0, (1 - s^2)(I + H)^-1), with a unique factor, so both sides draw the same point.
@@ -105,7 +105,7 @@ def geometry(prob: Problem, x: np.ndarray) -> Cache:
 
 
 def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:
-    """Reduced proposal of Prop. 4.2 item 2 (eq. reduced_space_sampling):
+    """Reduced proposal of the splitting proposition of Sec. 5.3, item 2 (eq. reduced_space_sampling):
 
         x+ = P diag((d+s)/(d+1)) P^T x - P diag((1-s)/(d+1)) P^T g + noise,
 
@@ -191,7 +191,7 @@ class StepRecord:
 
 
 def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> StepRecord:
-    """One Markov transition for every chain (Alg. 1 first stage, Prop. 4.2).
+    """One Markov transition for every chain (Alg. 1 first stage, the splitting proposition of Sec. 5.3).
 
     xi (C, r), u (C,) and zeta (C, d_m - r) default to the Philox streams at the
     current step; pass them to evaluate the transition at given draws."""
@@ -208,7 +208,7 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
     log_u = np.log(u)
     acc = log_u <= lr
     st.failures += (~cp.ok).astype(np.int64)
-    # Prop. 4.2 item 1: pCN move of the complement, realised on accepted moves only
+    # splitting proposition of Sec. 5.3, item 1: pCN move of the complement, realised on accepted moves only
     if st.z is not None and np.any(acc):
         idx = np.nonzero(acc)[0]
         if zeta is None:

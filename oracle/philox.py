@@ -1,7 +1,7 @@
 """Philox4x64-10 and the draw maps of Alg. 1 (oracle side; test infrastructure only).
 
 Alg. 1 draws a reduced normal vector xi_r ~ N(0, I_r) for the proposal, a uniform
-xi_1 for the first-stage decision, and Prop. 4.2 draws a prior sample M ~ mu for
+xi_1 for the first-stage decision, and the splitting proposition of Sec. 5.3 draws a prior sample M ~ mu for
 the complement move. Both the oracle and the device path generate these from one
 counter-based generator so that chains can be compared draw for draw.
 

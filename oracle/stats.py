@@ -14,7 +14,7 @@ mean within-chain variance and v the 1-D pooled variance of eq. covariance_estim
 where n' is the largest index such that every pair sum rho_{2t'} + rho_{2t'+1},
 t' = 0..n', is positive (rho_0 = 1).
 
-Posterior moments (Lemma 4.1: the complement is prior distributed and independent
+Posterior moments (the Gaussian lemma of Sec. 5.3: the complement is prior distributed and independent
 of the reduced part under the surrogate posterior): field mean Psi_r xbar and field
 variance diag(Psi_r S Psi_r^T) + var_perp, with xbar, S the pooled sample mean and
 covariance of the reduced coordinates.

@@ -1,5 +1,5 @@
 // KLE basis of the grid Matern prior (Sec. 4.2), Rao-Blackwellised posterior
-// moments (Lemma 4.1) and the multichain ESS fraction (Sec. 6.2.2, eq. ess).
+// moments (the Gaussian lemma of Sec. 5.3) and the multichain ESS fraction (Sec. 6.2.2, eq. ess).
 #include "dino_internal.hpp"
 
 namespace dino {

@@ -1,9 +1,9 @@
 // Per-chain FP64 kernels of the reduced mMALA transition:
 //  * Cholesky factor of I + H (replaces the eigendecomposition of Sec. 5.2),
-//  * reduced proposal (Prop. 4.2 item 2, eq. reduced_space_sampling),
+//  * reduced proposal (splitting proposition of Sec. 5.3, item 2, eq. reduced_space_sampling),
 //  * reduced RN derivative and first-stage ratio (Sec. 5.4, eq. da_dino_trr_1),
 //  * MH decision (Alg. 1: reject iff alpha < xi_1) and state swap,
-//  * pCN move of the complement (Prop. 4.2 item 1), trace rows, draws.
+//  * pCN move of the complement (splitting proposition of Sec. 5.3, item 1), trace rows, draws.
 #include "dino_internal.hpp"
 
 namespace dino {
@@ -39,6 +39,7 @@ __device__ void lt_matvec(const double* __restrict__ L, int r, const double* v, 
         const int j = jb + lane;
         double acc = 0.0;
         if (j < r)
+#pragma unroll 8
             for (int i = jb + ((wave - jb) & 3); i < r; i += 4)
                 if (i >= j) acc += L[(long)i * r + j] * v[i];
         if (j < r) part[wave * MAXR + j] = acc;
@@ -57,6 +58,7 @@ __device__ void l_matvec(const double* __restrict__ L, int r, const double* v, d
         const int i = i0 + rloc;
         double acc = 0.0;
         if (i < r)
+#pragma unroll 4
             for (int j = 4 * sub; j <= i; j += 64)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
@@ -81,6 +83,7 @@ __device__ void l_solve(const double* __restrict__ L, const double* invd, int r,
             const int i = b0 + il;
             double acc = 0.0;
             if (il < nb)
+#pragma unroll 4
                 for (int j = 4 * sub; j < b0; j += 32)
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
@@ -131,6 +134,7 @@ __device__ void lt_solve(const double* __restrict__ L, const double* invd, int r
             const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
             double acc = 0.0;
             if (il < nb)
+#pragma unroll 8
                 for (int j = b0 + nb + grp; j < r; j += 8) acc += L[(long)j * r + b0 + il] * x[j];
             part[grp * SB + il] = acc;
         }

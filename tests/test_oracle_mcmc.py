@@ -1,4 +1,4 @@
-"""Pins for oracle/mcmc.py (Alg. 1 first stage, Prop. 4.2, Sec. 5.4 ratios).
+"""Pins for oracle/mcmc.py (Alg. 1 first stage, the splitting proposition of Sec. 5.3, Sec. 5.4 ratios).
 
 * The paper-form first-stage ratio equals the textbook finite-dimensional MH ratio
   built from explicit Gaussian proposal densities (scipy), and rho_0 equals the

@@ -1,8 +1,8 @@
 """Workload sizes and seeded draws (no method arithmetic here).
 
 Workloads mirror the shapes of the paper's experiments (reduced dimension r = 200
-and width-400 GELU networks in Sec. 7.2/8.2, tens to hundreds of observables in
-Sec. 7.1/8.1) on a synthetic grid Matern prior, since the paper's PDE data, trained
+and width-400 GELU networks in Sec. 7.4/8.5, tens to hundreds of observables in
+Sec. 7.2/8.3) on a synthetic grid Matern prior, since the paper's PDE data, trained
 weights and meshes are not available:
 
     tiny  : 33x33 grid, r=32,  MLP 32->64->64->16 GELU, d_y=16, 4 chains x 2000 steps, dt=0.1,

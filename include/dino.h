@@ -222,6 +222,82 @@ dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const dou
 dino_status dino_eval_normals(dino_problem* p, int n, int stream_id, int64_t step, int count, double* out,
                               void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of many inverse problems (one problem = one request:
+ * its own data y, noise variances, observation count, chain count and step budget)
+ * on the context's GPU. Each request runs the same chains as dino_step would
+ * (Alg. 1 first stage + the splitting proposition of Sec. 5.3) with Philox key
+ * (seed, request_id), prior initial states drawn from streams 3 and 4, and chain
+ * index 0..n_chains-1, so its draws do not depend on what else is served.
+ *
+ * Every bucket b serves requests with d_y <= bucket_dy[b] that no smaller bucket
+ * serves, in a pool of bucket_slots[b] preallocated chain slots and max_requests
+ * request rows; outputs beyond a request's d_y are unobserved (Gamma^-1/2 = 0), the
+ * request observing the first d_y network outputs. A request is admitted, in arrival
+ * order, when its chains fit a contiguous free slot range and a row is free; all
+ * occupied slots of a pool advance together in quanta of steps_per_quantum steps on
+ * the pool's own stream, and the pools of different buckets overlap on the device.
+ * A request's result is its posterior mean field Psi_r xbar (xbar: the mean of the
+ * reduced states after the first 20% of its steps, over its chains and steps; the
+ * complement has mean zero, the Gaussian lemma of Sec. 5.3) with its acceptance
+ * counts and server-clock timestamps. The library allocates the pools in
+ * dino_server_create (hipMalloc, pinned host buffers) and nothing afterwards. */
+#define DINO_MAX_BUCKETS 8
+
+typedef struct dino_server dino_server;
+
+typedef struct {
+    int32_t n_buckets;                        /* 1..DINO_MAX_BUCKETS */
+    int32_t bucket_dy[DINO_MAX_BUCKETS];      /* ascending observation counts, <= network outputs */
+    int32_t bucket_slots[DINO_MAX_BUCKETS];   /* chain slots of each bucket's pool */
+    int32_t max_requests;                     /* request rows per pool (concurrent requests) */
+    int32_t steps_per_quantum;                /* steps enqueued per pool between scheduling passes */
+    int32_t precision;                        /* DINO_PREC_F64 or DINO_PREC_BF16 */
+    int32_t track_complement;                 /* keep and move the complement state */
+    int32_t reserved;
+    double dt;                                /* step size of every request */
+    double hbm_budget_bytes;                  /* > 0: DINO_ENOMEM if the pools need more */
+} dino_server_cfg;
+
+typedef struct {
+    uint64_t seed;                            /* Philox key word 0 */
+    uint64_t request_id;                      /* Philox key word 1, and the result's id */
+    int32_t d_y;                              /* observed outputs: the first d_y of the network */
+    int32_t n_chains;                         /* 1..slots of its bucket */
+    int64_t n_steps;                          /* Markov steps per chain (burn-in: the first 20%) */
+    const double* y;                          /* host, d_y; copied by dino_server_submit */
+    const double* noise_var;                  /* host, d_y; > 0 (inf: unobserved) */
+    double arrival;                           /* server-clock seconds from which it may be admitted */
+} dino_request;
+
+typedef struct {
+    uint64_t request_id;
+    int32_t d_y, n_chains;
+    int64_t n_steps;
+    double arrival, admitted, finished;       /* server-clock seconds; finished = mean in host memory */
+    int64_t accepts, failures;                /* summed over the request's chains */
+} dino_result;
+
+/* Pools for cfg on ctx's device (prior and network loaded). Errors: DINO_EINVAL (bad
+ * cfg), DINO_ESTATE (ctx not ready), DINO_ENOMEM (pools exceed hbm_budget_bytes or the
+ * device). The context must outlive the server. */
+dino_status dino_server_create(dino_ctx* ctx, const dino_server_cfg* cfg, dino_server** out);
+dino_status dino_server_destroy(dino_server* srv);
+/* Seconds since dino_server_create (monotonic clock of the server). */
+dino_status dino_server_clock(const dino_server* srv, double* seconds);
+/* Queues a request (its data is copied). DINO_EINVAL if no bucket serves d_y or
+ * n_chains exceeds the bucket's slots; DINO_ENUMERIC on non-finite data. */
+dino_status dino_server_submit(dino_server* srv, const dino_request* req);
+/* Runs the scheduler in the calling thread until every submitted request has
+ * finished, or until the server clock reaches `until` (until >= 0). n_finished
+ * (optional) receives the number of requests finished during the call. */
+dino_status dino_server_run(dino_server* srv, double until, int* n_finished);
+/* Moves up to max finished results, oldest first, into out[0..n) and, if means is not
+ * NULL, their mean fields into means (max x d_m doubles, caller-owned). */
+dino_status dino_server_poll(dino_server* srv, int max, dino_result* out, double* means, int* n);
+/* Chain-steps of the finished requests, and counts of waiting and admitted requests. */
+dino_status dino_server_stats(const dino_server* srv, int64_t* chain_steps, int64_t* pending, int64_t* live);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,51 @@ class ProblemDesc(ct.Structure):
     ]
 
 
+MAX_BUCKETS = 8
+
+
+class ServerCfg(ct.Structure):
+    _fields_ = [
+        ("n_buckets", ct.c_int32),
+        ("bucket_dy", ct.c_int32 * MAX_BUCKETS),
+        ("bucket_slots", ct.c_int32 * MAX_BUCKETS),
+        ("max_requests", ct.c_int32),
+        ("steps_per_quantum", ct.c_int32),
+        ("precision", ct.c_int32),
+        ("track_complement", ct.c_int32),
+        ("reserved", ct.c_int32),
+        ("dt", ct.c_double),
+        ("hbm_budget_bytes", ct.c_double),
+    ]
+
+
+class Request(ct.Structure):
+    _fields_ = [
+        ("seed", ct.c_uint64),
+        ("request_id", ct.c_uint64),
+        ("d_y", ct.c_int32),
+        ("n_chains", ct.c_int32),
+        ("n_steps", ct.c_int64),
+        ("y", ct.POINTER(ct.c_double)),
+        ("noise_var", ct.POINTER(ct.c_double)),
+        ("arrival", ct.c_double),
+    ]
+
+
+class Result(ct.Structure):
+    _fields_ = [
+        ("request_id", ct.c_uint64),
+        ("d_y", ct.c_int32),
+        ("n_chains", ct.c_int32),
+        ("n_steps", ct.c_int64),
+        ("arrival", ct.c_double),
+        ("admitted", ct.c_double),
+        ("finished", ct.c_double),
+        ("accepts", ct.c_int64),
+        ("failures", ct.c_int64),
+    ]
+
+
 _P = ct.c_void_p
 _D = ct.POINTER(ct.c_double)
 _F = ct.POINTER(ct.c_float)
@@ -67,14 +112,16 @@ SIGNATURES = {
     "dino_set_profiling": (ct.c_int32, [_P, ct.c_int]),
     "dino_read_profile": (ct.c_int32, [_P, _D, _I32, _I64]),
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),
+    "dino_server_create": (ct.c_int32, [_P, ct.POINTER(ServerCfg), ct.POINTER(_P)]),
+    "dino_server_destroy": (ct.c_int32, [_P]),
+    "dino_server_clock": (ct.c_int32, [_P, ct.POINTER(ct.c_double)]),
+    "dino_server_submit": (ct.c_int32, [_P, ct.POINTER(Request)]),
+    "dino_server_run": (ct.c_int32, [_P, ct.c_double, ct.POINTER(ct.c_int)]),
+    "dino_server_poll": (ct.c_int32, [_P, ct.c_int, ct.POINTER(Result), _D, ct.POINTER(ct.c_int)]),
+    "dino_server_stats": (ct.c_int32, [_P, _I64, _I64, _I64]),
 }
 
 N_STAGES = 9
-
-OPTIONAL = {
-    "dino_server_create", "dino_server_destroy", "dino_server_submit", "dino_server_run", "dino_server_poll",
-    "dino_server_stats",
-}
 
 _lib = None
 

@@ -228,3 +228,76 @@ class Problem:
         out = torch.empty((n, count), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
         check(self.lib.dino_eval_normals(self.h, n, stream_id, step, count, _tp(out), _stream_handle(stream)))
         return out
+
+
+class Server:
+    """Continuous-batching server on one GPU (include/dino.h, serving section).
+
+    buckets: list of (d_y, chain slots). Each request runs its own chains (Philox key
+    (seed, request_id), prior initial states) and returns its posterior mean field."""
+
+    def __init__(self, ctx: Context, buckets, max_requests: int, steps_per_quantum: int, dt: float,
+                 precision: str = "bf16", track_complement: bool = True, hbm_budget_bytes: float = 0.0):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        cfg = _lib.ServerCfg()
+        cfg.n_buckets = len(buckets)
+        for k, (dy, slots) in enumerate(buckets):
+            cfg.bucket_dy[k] = dy
+            cfg.bucket_slots[k] = slots
+        cfg.max_requests = max_requests
+        cfg.steps_per_quantum = steps_per_quantum
+        cfg.precision = _lib.PRECISIONS[precision]
+        cfg.track_complement = 1 if track_complement else 0
+        cfg.dt = dt
+        cfg.hbm_budget_bytes = hbm_budget_bytes
+        h = ct.c_void_p()
+        check(self.lib.dino_server_create(ctx.h, ct.byref(cfg), ct.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(self.lib.dino_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        t = ct.c_double()
+        check(self.lib.dino_server_clock(self.h, ct.byref(t)))
+        return t.value
+
+    def submit(self, seed: int, request_id: int, y, noise_var, n_chains: int, n_steps: int, arrival: float = 0.0):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        nv = np.ascontiguousarray(noise_var, dtype=np.float64)
+        req = _lib.Request(seed=seed, request_id=request_id, d_y=len(y), n_chains=n_chains, n_steps=n_steps,
+                           y=dptr(y), noise_var=dptr(nv), arrival=arrival)
+        check(self.lib.dino_server_submit(self.h, ct.byref(req)))
+
+    def run(self, until: float = -1.0) -> int:
+        n = ct.c_int()
+        check(self.lib.dino_server_run(self.h, until, ct.byref(n)))
+        return n.value
+
+    def poll(self, max_results: int = 64, with_means: bool = True):
+        out = (_lib.Result * max_results)()
+        means = np.empty((max_results, self.ctx.d_m)) if with_means else None
+        n = ct.c_int()
+        check(self.lib.dino_server_poll(self.h, max_results, out, dptr(means), ct.byref(n)))
+        res = []
+        for k in range(n.value):
+            o = out[k]
+            d = {f: getattr(o, f) for f, _ in _lib.Result._fields_}
+            if with_means:
+                d["mean"] = means[k].copy()
+            res.append(d)
+        return res
+
+    def stats(self):
+        a = np.zeros(3, dtype=np.int64)
+        check(self.lib.dino_server_stats(self.h, i64ptr(a[0:1]), i64ptr(a[1:2]), i64ptr(a[2:3])))
+        return dict(chain_steps=int(a[0]), pending=int(a[1]), live=int(a[2]))

@@ -5,6 +5,9 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <cmath>
+#include <exception>
+#include <new>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -36,6 +39,27 @@ void clear_error();
     do {                                                              \
         if (!(cond)) throw ::dino::Error{(code), std::string(text)}; \
     } while (0)
+
+// Runs fn and converts any failure into a status and the thread's error message.
+template <typename F>
+inline dino_status guarded_call(F&& fn) {
+    try {
+        fn();
+        return DINO_OK;
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return DINO_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return DINO_EDEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return DINO_EDEVICE;
+    }
+}
 
 // ----------------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11). Counter (block, stream, step, chain),
@@ -97,6 +121,28 @@ __device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t rid, ui
 }
 
 // ----------------------------------------------------------------------------------
+// Per-chain stream keys and life cycle (device arrays, one entry per chain slot). A
+// plain problem fills them uniformly (key (seed, request id), index = slot, row 0,
+// every chain live); a serving pool sets them per request when it admits one.
+enum : int32_t { CHAIN_IDLE = 0, CHAIN_LIVE = 1, CHAIN_FRESH = 2 };
+
+struct ChainMeta {
+    uint64_t* key0 = nullptr;  // Philox key word 0 (seed)
+    uint64_t* key1 = nullptr;  // Philox key word 1 (request id)
+    int64_t* step = nullptr;   // Markov steps taken: the counter's step field
+    int64_t* budget = nullptr; // the chain stops (goes idle) after this many steps
+    int64_t* burn = nullptr;   // steps before the running sums start
+    int32_t* index = nullptr;  // chain index inside its request: the counter's chain field
+    int32_t* row = nullptr;    // request row of y and Gamma^-1/2
+    int32_t* state = nullptr;  // CHAIN_IDLE / CHAIN_LIVE / CHAIN_FRESH (joins at the next step)
+};
+
+__device__ __forceinline__ int32_t chain_row(const ChainMeta& m, int c) { return m.row ? m.row[c] : 0; }
+__device__ __forceinline__ int32_t chain_state(const ChainMeta& m, int c) {
+    return m.state ? m.state[c] : (int32_t)CHAIN_LIVE;
+}
+
+// ----------------------------------------------------------------------------------
 // Host-side objects.
 struct Layer {
     int kind;
@@ -153,15 +199,19 @@ struct dino_problem {
     double s = 0, beta = 0;
     bool own_ws = false;
     bool initialised = false;
+    bool serving = false;     // a serving pool: per-request rows, running sums
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int64_t step = 0;
     int64_t recorded = 0;
     hipStream_t last_stream = nullptr;
 
-    // problem data
-    double* y = nullptr;      // d_y
-    double* winv = nullptr;   // d_y: Gamma^-1/2 diagonal
+    // problem data: one row per request (a plain problem has one)
+    int n_rows = 1;
+    double* y = nullptr;      // n_rows x d_y
+    double* winv = nullptr;   // n_rows x d_y: Gamma^-1/2 diagonal (0 for unobserved outputs)
+    dino::ChainMeta meta;     // per-chain keys, steps and life cycle
+    double* sumx = nullptr;   // C x r running sums of x after burn-in (serving pools)
     // chain state and its cache
     double* x = nullptr;      // C x r
     double* g = nullptr;      // C x r
@@ -224,18 +274,31 @@ void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, 
 void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
                           long slot_stride, double* logdet, int32_t* ok, hipStream_t st);
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
-                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given,
-                         int64_t step, double* xp, double* lfwd, const double* logdet, hipStream_t st);
-void launch_accept(dino_problem* p, int64_t step, hipStream_t st);
+                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
+                         double* xp, double* lfwd, const double* logdet, hipStream_t st);
+void launch_accept(dino_problem* p, int n, hipStream_t st);
+// Per-step bookkeeping of chains [0, n): step counters, life cycle, running sums, trace row.
+void launch_finish(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+// Sets the metadata of chains [c0, c0 + n) (index = first_index + c - c0) and zeroes their sums.
+void launch_meta_fill(dino_problem* p, int c0, int n, uint64_t key0, uint64_t key1, int64_t budget, int64_t burn,
+                      int32_t row, int32_t state, int32_t first_index, hipStream_t st);
+// Posterior mean of chains [c0, c0 + n): xbar = sum_c sumx_c / (n count), field = Psi_r xbar.
+void launch_request_mean(dino_problem* p, int c0, int n, int64_t count, double* xbar, double* field,
+                         hipStream_t st);
 void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
                     const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
                     const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st);
-void launch_complement(dino_problem* p, int64_t step, hipStream_t st);
-void launch_trace(dino_problem* p, int64_t row, hipStream_t st);
+void launch_complement(dino_problem* p, int n, hipStream_t st);
 void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st);
 void launch_normals(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count, double* out,
                     hipStream_t st);
 void launch_copy_rows(int n, int width, const double* src, double* dst, hipStream_t st);
+
+// n_steps transitions of chains [0, n) (runtime.hip).
+void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st);
+// Problem with n_rows request rows; serving pools keep running sums (runtime.hip).
+dino_problem* create_problem(dino_ctx* ctx, const dino_problem_desc* desc, int n_rows, bool serving);
+void destroy_problem(dino_problem* p);
 
 // basis
 void build_basis_device(Basis& b);

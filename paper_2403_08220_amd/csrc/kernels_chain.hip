@@ -387,8 +387,11 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
 // Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi).
 // lfwd (optional) = log rho_0(x -> xp) = -|xi|^2/2 + |mhat|^2/2 + logdet_x, the
 // mMALA over pCN log-density ratio at the drawn point, mhat = (xp - s x)/beta.
-__global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double beta, uint64_t seed, uint64_t rid,
-                                                      int64_t step, const double* __restrict__ x,
+// Chains are walked by their metadata: an idle chain is skipped, a fresh chain (one that
+// joins at this step) proposes its initial state, the prior draw of stream 3, and the
+// acceptance then takes it unconditionally.
+__global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double beta, ChainMeta meta,
+                                                      const double* __restrict__ x,
                                                       const double* __restrict__ g, const double* L, long strideL,
                                                       const int32_t* slot, int slot_xor, long slot_stride,
                                                       const double* __restrict__ xi_given,
@@ -398,6 +401,19 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
     __shared__ double part[4 * MAXR];
     __shared__ double red[TPB / 64];
     const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) return;
+    if (state == CHAIN_FRESH) {
+        for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
+            double nv[4];
+            philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_INIT_X, 0, (uint64_t)meta.index[c], nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * b4 + q < r) xp[(long)c * r + 4 * b4 + q] = nv[q];
+        }
+        if (lfwd && tid == 0) lfwd[c] = 0.0;
+        return;
+    }
     const double* Lc = L + (long)c * strideL + slot_offset(slot, slot_xor, slot_stride, c);
     load_inv_diag(Lc, r, invd);
     for (int j = tid; j < r; j += TPB) {
@@ -407,9 +423,11 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
     if (xi_given) {
         for (int j = tid; j < r; j += TPB) xi[j] = xi_given[(long)c * r + j];
     } else {
+        const uint64_t k0 = meta.key0[c], k1 = meta.key1[c];
+        const uint64_t step = (uint64_t)meta.step[c], chain = (uint64_t)meta.index[c];
         for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
             double nv[4];
-            philox_normals4(seed, rid, (uint64_t)b4, STREAM_XI, (uint64_t)step, (uint64_t)c, nv);
+            philox_normals4(k0, k1, (uint64_t)b4, STREAM_XI, step, chain, nv);
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 if (4 * b4 + q < r) xi[4 * b4 + q] = nv[q];
@@ -498,8 +516,10 @@ __global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s
 }
 
 // MH decision of the first stage and the swap of state and cache on acceptance.
-__global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s, double beta, uint64_t seed,
-                                                     uint64_t rid, int64_t step, double* x, double* g, double* phi,
+// accflag: 0 rejected or idle, 1 accepted (pCN complement move), 2 fresh chain
+// initialised (complement drawn from the prior).
+__global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
+                                                     double* x, double* g, double* phi,
                                                      double* logdet, const double* Lbuf, long half,
                                                      int32_t* cur, const double* xp, const double* gp,
                                                      const double* phip, const double* logdetp,
@@ -511,6 +531,11 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
     __shared__ int decision;
     const int c = blockIdx.x, tid = threadIdx.x;
     const long rr = (long)r * r;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) {
+        if (tid == 0) accflag[c] = 0;
+        return;
+    }
     const int other = cur[c] ^ 1;
     const double* Lp = Lbuf + (long)other * half + c * rr;
     for (int j = tid; j < r; j += TPB) {
@@ -520,22 +545,36 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
     }
     __syncthreads();
     const int okc = okp[c];
-    double rev = 0.0;
-    if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red, invd);
-    if (tid == 0) {
-        const double lr = phi[c] - phip[c] + rev - lfwd[c];
-        const double u = philox_uniform(seed, rid, (uint64_t)step, (uint64_t)c);
-        const bool good = okc && isfinite(lr);
-        const bool accept = good && (log(u) <= lr);
-        decision = accept ? 1 : 0;
-        if (!good) failures[c] += 1;
-        if (accept) {
-            accepts[c] += 1;
+    if (state == CHAIN_FRESH) {
+        // the initial state and its cache are taken as they are
+        if (tid == 0) {
+            if (!okc) failures[c] += 1;
             phi[c] = phip[c];
             logdet[c] = logdetp[c];
             cur[c] = other;
+            decision = 1;
+            accflag[c] = 2;
         }
-        accflag[c] = decision;
+        __syncthreads();
+    } else {
+        double rev = 0.0;
+        if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red, invd);
+        if (tid == 0) {
+            const double lr = phi[c] - phip[c] + rev - lfwd[c];
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)meta.step[c],
+                                            (uint64_t)meta.index[c]);
+            const bool good = okc && isfinite(lr);
+            const bool accept = good && (log(u) <= lr);
+            decision = accept ? 1 : 0;
+            if (!good) failures[c] += 1;
+            if (accept) {
+                accepts[c] += 1;
+                phi[c] = phip[c];
+                logdet[c] = logdetp[c];
+                cur[c] = other;
+            }
+            accflag[c] = decision;
+        }
     }
     __syncthreads();
     if (decision) {
@@ -547,17 +586,24 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
 }
 
 // pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state).
-__global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta,
-                                                         uint64_t seed, uint64_t rid, int64_t step,
+__global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta, ChainMeta meta,
                                                          const int32_t* __restrict__ accflag, float* z) {
     const int c = blockIdx.y;
-    if (!accflag[c]) return;
+    const int flag = accflag[c];
+    if (!flag) return;
     const int b4 = blockIdx.x * TPB + threadIdx.x;
     const int j0 = 4 * b4;
     if (j0 >= d_perp) return;
     double nv[4];
-    philox_normals4(seed, rid, (uint64_t)b4, STREAM_COMPLEMENT, (uint64_t)step, (uint64_t)c, nv);
     float* zc = z + (long)c * ldz;
+    if (flag == 2) {
+        // a fresh chain: the complement starts from a prior draw (stream 4)
+        philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_INIT_Z, 0, (uint64_t)meta.index[c], nv);
+        for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)nv[q];
+        return;
+    }
+    philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_COMPLEMENT, (uint64_t)meta.step[c],
+                    (uint64_t)meta.index[c], nv);
     if (j0 + 3 < d_perp) {
         float4 v = *reinterpret_cast<const float4*>(zc + j0);
         v.x = (float)(s * (double)v.x + beta * nv[0]);
@@ -570,12 +616,71 @@ __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, do
     }
 }
 
-__global__ void trace_kernel(int C, int r, const double* __restrict__ x, const double* __restrict__ phi,
-                             float* __restrict__ xrow, double* __restrict__ phirow) {
-    const long total = (long)C * r;
-    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
-        xrow[e] = (float)x[e];
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) phirow[c] = phi[c];
+// End of a step for one chain per block: the trace row (when recorded), the running sum
+// of x once the chain is past its burn-in, the step counter and the life cycle (a live
+// chain that has used its step budget goes idle; a fresh chain becomes live).
+__global__ __launch_bounds__(64) void finish_kernel(int r, ChainMeta meta, const double* __restrict__ x,
+                                                    const double* __restrict__ phi, double* __restrict__ sumx,
+                                                    float* __restrict__ xrow, double* __restrict__ phirow) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    const double* xc = x + (long)c * r;
+    if (xrow) {
+        for (int j = tid; j < r; j += 64) xrow[(long)c * r + j] = (float)xc[j];
+        if (tid == 0) phirow[c] = phi[c];
+    }
+    if (state == CHAIN_LIVE) {
+        const int64_t s1 = meta.step[c] + 1;
+        if (sumx && s1 > meta.burn[c])
+            for (int j = tid; j < r; j += 64) sumx[(long)c * r + j] += xc[j];
+        if (tid == 0) {
+            meta.step[c] = s1;
+            if (s1 >= meta.budget[c]) meta.state[c] = CHAIN_IDLE;
+        }
+    } else if (state == CHAIN_FRESH && tid == 0) {
+        meta.state[c] = CHAIN_LIVE;
+    }
+}
+
+__global__ void meta_fill_kernel(ChainMeta meta, double* __restrict__ sumx, int r, int c0, int n, uint64_t key0,
+                                 uint64_t key1, int64_t budget, int64_t burn, int32_t row, int32_t state,
+                                 int32_t first_index) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const int c = c0 + k;
+        meta.key0[c] = key0;
+        meta.key1[c] = key1;
+        meta.step[c] = 0;
+        meta.budget[c] = budget;
+        meta.burn[c] = burn;
+        meta.index[c] = first_index + k;
+        meta.row[c] = row;
+        meta.state[c] = state;
+        if (sumx)
+            for (int j = 0; j < r; ++j) sumx[(long)c * r + j] = 0.0;
+    }
+}
+
+// xbar_j = sum over chains [c0, c0 + n) of sumx_cj / (n count); one block.
+__global__ __launch_bounds__(256) void request_xbar_kernel(int r, int c0, int n, double inv,
+                                                           const double* __restrict__ sumx,
+                                                           double* __restrict__ xbar) {
+    for (int j = threadIdx.x; j < r; j += 256) {
+        double acc = 0.0;
+        for (int c = c0; c < c0 + n; ++c) acc += sumx[(long)c * r + j];
+        xbar[j] = acc * inv;
+    }
+}
+
+// field_p = sum_k Psi[p][k] xbar_k: one wave per node row of the basis (d_m x r).
+__global__ __launch_bounds__(256) void decode_kernel(int d_m, int r, const double* __restrict__ dec,
+                                                     const double* __restrict__ xbar, double* __restrict__ field) {
+    const int lane = threadIdx.x & 63;
+    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= d_m) return;
+    double acc = 0.0;
+    for (int k = lane; k < r; k += 64) acc += dec[(long)p * r + k] * xbar[k];
+    acc = wave_sum(acc);
+    if (lane == 0) field[p] = acc;
 }
 
 // Normals of one stream for n chains at one step: out[c][k], k < count.
@@ -604,6 +709,7 @@ __global__ void copy_rows_kernel(int n, int width, const double* __restrict__ sr
 
 // ---------------------------------------------------------------------------------
 static size_t chol_lds(int r) { return (size_t)r * CLDP * sizeof(double); }
+static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
 
 void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
                           long slot_stride, double* logdet, int32_t* ok, hipStream_t st) {
@@ -635,20 +741,20 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
 
 
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
-                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given,
-                         int64_t step, double* xp, double* lfwd, const double* logdet, hipStream_t st) {
-    hipLaunchKernelGGL(propose_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->s, p->beta, p->desc.seed,
-                       p->desc.request_id, step, x, g, L, strideL, slot, slot_xor, slot_stride, xi_given, logdet,
-                       xp, lfwd);
+                         const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
+                         double* xp, double* lfwd, const double* logdet, hipStream_t st) {
+    const ChainMeta meta = use_meta ? p->meta : ChainMeta{};
+    hipLaunchKernelGGL(propose_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->s, p->beta, meta, x, g, L, strideL, slot,
+                       slot_xor, slot_stride, xi_given, logdet, xp, lfwd);
     DINO_HIP(hipGetLastError());
 }
 
 
-void launch_accept(dino_problem* p, int64_t step, hipStream_t st) {
+void launch_accept(dino_problem* p, int n, hipStream_t st) {
     const long half = (long)p->C * p->r * p->r;
-    hipLaunchKernelGGL(accept_kernel, dim3(p->C), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->desc.seed,
-                       p->desc.request_id, step, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp,
-                       p->gp, p->phip, p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc);
+    hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
+                       p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp,
+                       p->lfwd, p->accepts, p->failures, p->acc);
     DINO_HIP(hipGetLastError());
 }
 
@@ -660,22 +766,37 @@ void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x
     DINO_HIP(hipGetLastError());
 }
 
-static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
-
-void launch_complement(dino_problem* p, int64_t step, hipStream_t st) {
+void launch_complement(dino_problem* p, int n, hipStream_t st) {
     if (!p->z || p->d_perp == 0) return;
     const int nb4 = (p->d_perp + 3) / 4;
-    dim3 grid((nb4 + TPB - 1) / TPB, p->C);
+    dim3 grid((nb4 + TPB - 1) / TPB, n);
     hipLaunchKernelGGL(complement_kernel, grid, dim3(TPB), 0, st, p->d_perp, ldz_of(p->d_perp), p->s, p->beta,
-                       p->desc.seed, p->desc.request_id, step, p->acc, p->z);
+                       p->meta, p->acc, p->z);
     DINO_HIP(hipGetLastError());
 }
 
-void launch_trace(dino_problem* p, int64_t row, hipStream_t st) {
-    const long total = (long)p->C * p->r;
-    const int blocks = (int)std::min<long>((total + 255) / 256, 2048);
-    hipLaunchKernelGGL(trace_kernel, dim3(blocks), dim3(256), 0, st, p->C, p->r, p->x, p->phi,
-                       p->xtrace + row * total, p->phitrace + row * p->C);
+void launch_finish(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+    float* xrow = trace_row >= 0 ? p->xtrace + trace_row * (long)p->C * p->r : nullptr;
+    double* phirow = trace_row >= 0 ? p->phitrace + trace_row * (long)p->C : nullptr;
+    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(64), 0, st, p->r, p->meta, p->x, p->phi, p->sumx, xrow, phirow);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_meta_fill(dino_problem* p, int c0, int n, uint64_t key0, uint64_t key1, int64_t budget, int64_t burn,
+                      int32_t row, int32_t state, int32_t first_index, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(meta_fill_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p->meta, p->sumx, p->r, c0, n,
+                       key0, key1, budget, burn, row, state, first_index);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_request_mean(dino_problem* p, int c0, int n, int64_t count, double* xbar, double* field,
+                         hipStream_t st) {
+    const double inv = 1.0 / ((double)n * (double)std::max<int64_t>(count, 1));
+    hipLaunchKernelGGL(request_xbar_kernel, dim3(1), dim3(256), 0, st, p->r, c0, n, inv, p->sumx, xbar);
+    const int d_m = p->ctx->basis.d_m;
+    hipLaunchKernelGGL(decode_kernel, dim3((d_m + 3) / 4), dim3(256), 0, st, d_m, p->r, p->ctx->basis.dec, xbar,
+                       field);
     DINO_HIP(hipGetLastError());
 }
 

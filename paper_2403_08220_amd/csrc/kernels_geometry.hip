@@ -159,27 +159,32 @@ __global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int
 // Lambda_L = diag(winv) W_out[:dy, :] for every chain: rows (c, i).
 template <typename T>
 __global__ void rev_init_kernel(int n, int dy, int w, const T* __restrict__ Wout, const double* __restrict__ winv,
-                                T* __restrict__ lam, int ldl) {
+                                const int32_t* __restrict__ rows, T* __restrict__ lam, int ldl) {
     const long total = (long)n * dy * w;
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
         const int k = (int)(e % w);
         const long R = e / w;
         const int i = (int)(R % dy);
-        lam[R * ldl + k] = (T)(winv[i]) * Wout[(long)i * w + k];
+        const long row = rows ? rows[R / dy] : 0;
+        lam[R * ldl + k] = (T)(winv[row * dy + i]) * Wout[(long)i * w + k];
     }
 }
 
 // ---------------------------------------------------------------------------------
 // Misfit and reduced ppg per chain: e = winv (f - y), phi = |e|^2 / 2, g = B^T e.
 __global__ __launch_bounds__(256) void misfit_grad_kernel(int n, int dy, int r, const double* __restrict__ f,
-                                                          const double* __restrict__ y,
-                                                          const double* __restrict__ winv,
+                                                          const double* __restrict__ y_rows,
+                                                          const double* __restrict__ winv_rows,
+                                                          const int32_t* __restrict__ rows,
                                                           const double* __restrict__ B, double* __restrict__ phi,
                                                           double* __restrict__ g) {
     __shared__ double e[1024];
     __shared__ double red[4];
     const int c = blockIdx.x;
     const int tid = threadIdx.x;
+    const long row = rows ? rows[c] : 0;
+    const double* y = y_rows + row * dy;
+    const double* winv = winv_rows + row * dy;
     double part = 0.0;
     for (int i = tid; i < dy; i += blockDim.x) {
         const double w = winv[i];
@@ -328,7 +333,7 @@ void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t 
         const long total = (long)n * dy * outl.fan_in;
         const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
         hipLaunchKernelGGL(rev_init_kernel<double>, dim3(blocks), dim3(256), 0, st, n, dy, outl.fan_in, outl.W64,
-                           p->winv, cur, ld);
+                           p->winv, p->meta.row, cur, ld);
     }
     int act = p->n_act;
     const int M = n * dy;
@@ -352,8 +357,8 @@ void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t 
 
 void launch_misfit_grad(dino_problem* p, int n, const double* f, const double* B, double* phi, double* g,
                         hipStream_t st) {
-    hipLaunchKernelGGL(misfit_grad_kernel, dim3(n), dim3(256), 0, st, n, p->d_y, p->r, f, p->y, p->winv, B, phi,
-                       g);
+    hipLaunchKernelGGL(misfit_grad_kernel, dim3(n), dim3(256), 0, st, n, p->d_y, p->r, f, p->y, p->winv,
+                       p->meta.row, B, phi, g);
     DINO_HIP(hipGetLastError());
 }
 

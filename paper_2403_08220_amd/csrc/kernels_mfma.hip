@@ -50,7 +50,8 @@ struct SweepArgs {
     int n_layers;
     int n_items;
     const float* Wout;    // output layer weights (d_out x w_out), FP32
-    const double* winv;   // Gamma^-1/2 diagonal (dy)
+    const double* winv;   // Gamma^-1/2 diagonal, one row of dy per request
+    const int32_t* rows;  // request row of every chain (null: row 0)
     __hip_bfloat16* B;    // out: C*dy x r, BF16
     SweepLayer layer[15];
     const bf16x8* tiles;  // all work items' tiles, contiguous in processing order
@@ -97,7 +98,7 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
                 lam[mb][j] = (valid && row < args.w_out) ? wrow[row] : 0.f;
             }
     }
-    const float wi = valid ? (float)args.winv[i] : 0.f;
+    const float wi = valid ? (float)args.winv[(long)(args.rows ? args.rows[c] : 0) * args.dy + i] : 0.f;
 
     // Work items (layer, output block) are walked in lockstep by all waves. Direct
     // global -> LDS copies (global_load_lds_dwordx4) move whole 1 KB tiles (64 lanes x
@@ -260,11 +261,15 @@ __global__ void to_double_kernel(long n, const float* __restrict__ xf, double* _
 
 // Whitened residual e = winv (f - y) (FP32 out) and misfit phi = |e|^2 / 2 (FP64).
 __global__ __launch_bounds__(256) void residual_kernel(int dy, const float* __restrict__ f,
-                                                       const double* __restrict__ y,
-                                                       const double* __restrict__ winv, float* __restrict__ e,
+                                                       const double* __restrict__ y_rows,
+                                                       const double* __restrict__ winv_rows,
+                                                       const int32_t* __restrict__ rows, float* __restrict__ e,
                                                        double* __restrict__ phi) {
     __shared__ double red[4];
     const int c = blockIdx.x, tid = threadIdx.x;
+    const long row = rows ? rows[c] : 0;
+    const double* y = y_rows + row * dy;
+    const double* winv = winv_rows + row * dy;
     double part = 0.0;
     for (int i = tid; i < dy; i += 256) {
         const double w = winv[i];
@@ -352,6 +357,7 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
     a.ldb = (p->r + 31) / 32 * 32;
     a.Wout = ctx->layers[L - 1].W32;
     a.winv = p->winv;
+    a.rows = p->meta.row;
     a.B = Bout;
     a.n_layers = L - 1;
     a.tiles = reinterpret_cast<const bf16x8*>(ctx->sweep_tiles);
@@ -430,7 +436,7 @@ void launch_to_double(long count, const float* xf, double* x, hipStream_t st) {
 }
 
 void launch_residual(dino_problem* p, int n, const float* f, float* e, double* phi, hipStream_t st) {
-    hipLaunchKernelGGL(residual_kernel, dim3(n), dim3(256), 0, st, p->d_y, f, p->y, p->winv, e, phi);
+    hipLaunchKernelGGL(residual_kernel, dim3(n), dim3(256), 0, st, p->d_y, f, p->y, p->winv, p->meta.row, e, phi);
     DINO_HIP(hipGetLastError());
 }
 

@@ -86,8 +86,17 @@ static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
 
 static void layout(dino_problem* p, Carver& cv) {
     const size_t C = p->C, r = p->r, dy = p->d_y, w = p->wmax;
-    p->y = cv.take<double>(dy);
-    p->winv = cv.take<double>(dy);
+    p->y = cv.take<double>((size_t)p->n_rows * dy);
+    p->winv = cv.take<double>((size_t)p->n_rows * dy);
+    p->meta.key0 = cv.take<uint64_t>(C);
+    p->meta.key1 = cv.take<uint64_t>(C);
+    p->meta.step = cv.take<int64_t>(C);
+    p->meta.budget = cv.take<int64_t>(C);
+    p->meta.burn = cv.take<int64_t>(C);
+    p->meta.index = cv.take<int32_t>(C);
+    p->meta.row = cv.take<int32_t>(C);
+    p->meta.state = cv.take<int32_t>(C);
+    p->sumx = p->serving ? cv.take<double>(C * r) : nullptr;
     p->x = cv.take<double>(C * r);
     p->g = cv.take<double>(C * r);
     p->phi = cv.take<double>(C);
@@ -380,6 +389,61 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
     });
 }
 
+// Every chain of a plain problem: key (seed, request id), its slot as chain index, request
+// row 0, no step budget, live.
+static void reset_meta(dino_problem* p, hipStream_t st) {
+    launch_meta_fill(p, 0, p->C, p->desc.seed, p->desc.request_id, INT64_MAX, 0, 0, CHAIN_LIVE, 0, st);
+}
+
+extern "C++" {
+namespace dino {
+
+dino_problem* create_problem(dino_ctx* ctx, const dino_problem_desc* desc, int n_rows, bool serving) {
+    check_desc(ctx, desc);
+    DINO_REQUIRE(n_rows >= 1, DINO_EINVAL, "a problem needs at least one request row");
+    DINO_HIP(hipSetDevice(ctx->device));
+    auto* p = new dino_problem();
+    try {
+        fill_dims(p, ctx, desc);
+        p->n_rows = n_rows;
+        p->serving = serving;
+        Carver cv{nullptr};
+        layout(p, cv);
+        const size_t need = cv.off + 256;
+        hipError_t e = hipMalloc(&p->ws, need);
+        DINO_REQUIRE(e == hipSuccess, DINO_ENOMEM, "device allocation of a pool workspace failed");
+        p->own_ws = true;
+        p->ws_bytes = need;
+        Carver cv2{reinterpret_cast<char*>(p->ws)};
+        layout(p, cv2);
+        // every slot starts idle with zero state; rows are written at admission
+        DINO_HIP(hipMemset(p->ws, 0, need));
+        launch_meta_fill(p, 0, p->C, 0, 0, 0, 0, 0, CHAIN_IDLE, 0, nullptr);
+        DINO_HIP(hipDeviceSynchronize());
+        p->initialised = true;
+    } catch (...) {
+        if (p->ws) (void)hipFree(p->ws);
+        delete p;
+        throw;
+    }
+    ctx->live_problems += 1;
+    return p;
+}
+
+void destroy_problem(dino_problem* p) {
+    if (!p) return;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipDeviceSynchronize();
+    if (p->own_ws && p->ws) (void)hipFree(p->ws);
+    for (auto& e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    p->ctx->live_problems -= 1;
+    delete p;
+}
+
+}  // namespace dino
+}  // extern "C++"
+
 dino_status dino_problem_workspace_bytes(const dino_ctx* ctx, const dino_problem_desc* desc, size_t* bytes) {
     return guarded([&] {
         DINO_REQUIRE(bytes, DINO_EINVAL, "null output pointer");
@@ -427,6 +491,8 @@ dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, co
             DINO_HIP(hipMemcpy(p->winv, winv.data(), sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
             if (p->d32)  // the sweep reads gelu' rows up to a multiple of 32: the padding stays zero
                 DINO_HIP(hipMemset(p->d32, 0, sizeof(float) * std::max(p->n_act, 1) * p->C * p->ldd32));
+            reset_meta(p, nullptr);
+            DINO_HIP(hipDeviceSynchronize());
         } catch (...) {
             if (p->own_ws && p->ws) hipFree(p->ws);
             delete p;
@@ -467,6 +533,7 @@ dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0,
                                       sizeof(float) * p->d_perp, C, hipMemcpyHostToDevice, st));
         }
         launch_init_draws(p, x0 == nullptr, z0 == nullptr, st);
+        reset_meta(p, st);
         DINO_HIP(hipMemsetAsync(p->cur, 0, sizeof(int32_t) * C, st));
         DINO_HIP(hipMemsetAsync(p->accepts, 0, sizeof(int64_t) * C, st));
         DINO_HIP(hipMemsetAsync(p->failures, 0, sizeof(int64_t) * C, st));
@@ -496,53 +563,62 @@ static void drain_profile(dino_problem* p) {
     p->ring_used = 0;
 }
 
+extern "C++" {
+namespace dino {
+
+// n_steps transitions of chains [0, n) on stream st (the body of dino_step; the serving
+// pools call it with n = the highest occupied slot + 1).
+void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
+    const long rr = (long)p->r * p->r;
+    const long half = (long)p->C * rr;
+    const int L = (int)p->ctx->layers.size();
+    const bool f64 = p->desc.precision == DINO_PREC_F64;
+    const int32_t launches[DINO_N_STAGES] = {1, f64 ? L : L + 1, f64 ? L : 1, 1, 1, 1, 1, p->z ? 1 : 0, 1};
+    auto mark = [&](int i) {
+        if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
+    };
+    for (int k = 0; k < n_steps; ++k) {
+        mark(0);
+        launch_propose_slot(p, n, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, true, p->xp, p->lfwd,
+                            p->logdet, st);
+        mark(1);
+        stage_forward(p, n, p->xp, p->f, st);
+        mark(2);
+        stage_jacobian(p, n, st);
+        mark(3);
+        stage_misfit(p, n, p->f, p->phip, p->gp, st);
+        mark(4);
+        stage_hessian(p, n, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
+        mark(5);
+        launch_cholesky_slot(n, p->r, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
+        mark(6);
+        launch_accept(p, n, st);
+        mark(7);
+        launch_complement(p, n, st);
+        mark(8);
+        int64_t row = -1;
+        if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
+        launch_finish(p, n, row, st);
+        mark(9);
+        if (p->profile) {
+            for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches[i];
+            if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
+        }
+        p->step += 1;
+    }
+    p->last_stream = st;
+}
+
+}  // namespace dino
+}  // extern "C++"
+
 dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
     return guarded([&] {
         DINO_REQUIRE(p, DINO_EINVAL, "null problem");
         DINO_REQUIRE(p->initialised, DINO_ESTATE, "dino_chains_init must precede dino_step");
         DINO_REQUIRE(n_steps >= 0, DINO_EINVAL, "negative step count");
         DINO_HIP(hipSetDevice(p->ctx->device));
-        hipStream_t st = as_stream(stream);
-        const long rr = (long)p->r * p->r;
-        const long half = (long)p->C * rr;
-        const int L = (int)p->ctx->layers.size();
-        const bool f64 = p->desc.precision == DINO_PREC_F64;
-        const int32_t launches[DINO_N_STAGES] = {1, f64 ? L : L + 1, f64 ? L : 1, 1, 1, 1, 1, 1, 1};
-        auto mark = [&](int i) {
-            if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
-        };
-        for (int k = 0; k < n_steps; ++k) {
-            const int64_t step = p->step;
-            mark(0);
-            launch_propose_slot(p, p->C, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, step, p->xp, p->lfwd,
-                                p->logdet, st);
-            mark(1);
-            stage_forward(p, p->C, p->xp, p->f, st);
-            mark(2);
-            stage_jacobian(p, p->C, st);
-            mark(3);
-            stage_misfit(p, p->C, p->f, p->phip, p->gp, st);
-            mark(4);
-            stage_hessian(p, p->C, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
-            mark(5);
-            launch_cholesky_slot(p->C, p->r, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
-            mark(6);
-            launch_accept(p, step, st);
-            mark(7);
-            launch_complement(p, step, st);
-            mark(8);
-            if (p->xtrace && p->recorded < p->desc.trace_capacity) {
-                launch_trace(p, p->recorded, st);
-                p->recorded += 1;
-            }
-            mark(9);
-            if (p->profile) {
-                for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches[i];
-                if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
-            }
-            p->step += 1;
-        }
-        p->last_stream = st;
+        run_steps(p, p->C, n_steps, as_stream(stream));
     });
 }
 
@@ -707,7 +783,7 @@ dino_status dino_eval_propose(dino_problem* p, int n, const double* x, const dou
         DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
         DINO_HIP(hipSetDevice(p->ctx->device));
         hipStream_t st = as_stream(stream);
-        launch_propose_slot(p, n, x, g, L, (long)p->r * p->r, nullptr, 0, 0, xi, 0, xp, nullptr, nullptr, st);
+        launch_propose_slot(p, n, x, g, L, (long)p->r * p->r, nullptr, 0, 0, xi, false, xp, nullptr, nullptr, st);
         p->last_stream = st;
     });
 }

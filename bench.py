@@ -42,12 +42,14 @@ PEAKS = {  # MI355X published peaks
 # device kernel of each stage on the mixed-precision path (rocprofv3 kernel names)
 STAGE_KERNEL = {
     "proposal": "propose_kernel", "forward": "fwd_layer_kernel", "jacobian": "jac_sweep_bf16_kernel",
-    "misfit_ppg": "residual_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_kernel",
+    "misfit_ppg": "residual_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_reg_kernel",
     "accept": "accept_kernel", "complement": "complement_kernel", "trace": "trace_kernel",
 }
-KERNEL_SOURCES = {"cholesky_kernel": "kernels_chain.hip", "propose_kernel": "kernels_chain.hip",
-                  "accept_kernel": "kernels_chain.hip", "jac_sweep_bf16_kernel": "kernels_mfma.hip",
-                  "hess_bf16_kernel": "kernels_mfma.hip", "fwd_layer_kernel": "kernels_geometry.hip"}
+KERNEL_SOURCES = {"cholesky_reg_kernel": "kernels_chain.hip", "propose_kernel": "kernels_chain.hip",
+                  "accept_kernel": "kernels_chain.hip", "complement_kernel": "kernels_chain.hip",
+                  "finish_kernel": "kernels_chain.hip", "jac_sweep_bf16_kernel": "kernels_mfma.hip",
+                  "hess_bf16_kernel": "kernels_mfma.hip", "residual_kernel": "kernels_mfma.hip",
+                  "fwd_layer_kernel": "kernels_geometry.hip"}
 
 
 def log(msg):
@@ -196,6 +198,74 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True):
     return out
 
 
+def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=20, seed=11):
+    """Poisson stream of inverse problems on the served workload (129x129 grid, r = 200,
+    ResNet 400x4 with 100 outputs): per request d_y in {25, 50, 100}, chains in [8, 128],
+    steps in [500, 5000], fresh seeded m_true and noise. The arrival rate is
+    load * capacity / E[C N], with the capacity measured first by a saturating burst.
+    Returns p50/p99 time-to-posterior-mean (arrival to mean field in host memory)."""
+    import torch
+    from paper_2403_08220_amd import Problem, Server
+    from synth import draw_requests
+
+    buckets = [(25, slots), (50, slots), (100, slots)]
+    srv = Server(ctx, buckets, max_requests=max_requests, steps_per_quantum=quantum, dt=w.dt, precision="bf16")
+
+    def data(reqs):
+        """y = f(x_true)[:d_y] + sigma eps, sigma = 1% of max |f(x_true)[:d_y]| (f on the device)."""
+        out = []
+        chunk = 256
+        ev = Problem(ctx, chunk, np.zeros(w.d_y), np.ones(w.d_y), 0.1, track_complement=False)
+        for k0 in range(0, len(reqs), chunk):
+            part = reqs[k0:k0 + chunk]
+            xt = np.stack([np.random.default_rng(q.truth_seed).standard_normal(w.r) for q in part])
+            f = ev.eval_geometry(torch.tensor(xt, dtype=torch.float64, device="cuda:0"), want_H=False)["f"]
+            f = f.cpu().numpy()
+            for q, fq in zip(part, f):
+                fo = fq[: q.d_y]
+                sigma = 0.01 * np.max(np.abs(fo))
+                y = fo + sigma * np.random.default_rng(q.noise_seed).standard_normal(q.d_y)
+                out.append((y, np.full(q.d_y, sigma ** 2)))
+        ev.close()
+        return out
+
+    # capacity: a saturating burst (all requests at t = 0, 300 steps each)
+    burst = draw_requests(24, 1.0, seed=seed + 1)
+    for q, (y, nv) in zip(burst, data(burst)):
+        srv.submit(seed=q.chain_seed, request_id=100000 + q.rid, y=y, noise_var=nv, n_chains=q.chains, n_steps=300)
+    t0 = srv.clock()
+    srv.run()
+    t1 = srv.clock()
+    srv.poll(len(burst), with_means=False)
+    kappa = sum(q.chains * 300 for q in burst) / (t1 - t0)
+
+    mean_work = 68.0 * 2750.0
+    rate = load * kappa / mean_work
+    reqs = draw_requests(n_requests, rate, seed=seed)
+    ys = data(reqs)
+    start = srv.clock() + 0.05
+    for q, (y, nv) in zip(reqs, ys):
+        srv.submit(seed=q.chain_seed, request_id=q.rid + 1, y=y, noise_var=nv, n_chains=q.chains, n_steps=q.steps,
+                   arrival=start + q.arrival)
+    srv.run()
+    res = srv.poll(n_requests, with_means=True)
+    srv.close()
+    lat = np.array([r["finished"] - r["arrival"] for r in res])
+    wait = np.array([r["admitted"] - r["arrival"] for r in res])
+    work = sum(r["n_chains"] * r["n_steps"] for r in res)
+    span = max(r["finished"] for r in res) - start
+    finite = all(np.all(np.isfinite(r["mean"])) for r in res)
+    return {"requests": len(res), "load": load, "capacity_chain_steps_per_s": round(kappa, 1),
+            "arrival_rate_per_s": round(rate, 4), "p50_s": round(float(np.percentile(lat, 50)), 4),
+            "p99_s": round(float(np.percentile(lat, 99)), 4), "mean_s": round(float(lat.mean()), 4),
+            "wait_p50_s": round(float(np.percentile(wait, 50)), 4),
+            "wait_p99_s": round(float(np.percentile(wait, 99)), 4),
+            "throughput_chain_steps_per_s": round(work / span, 1), "makespan_s": round(span, 3),
+            "means_finite": bool(finite),
+            "setup": f"buckets d_y 25/50/100 x {slots} slots, {max_requests} requests per bucket, "
+                     f"{quantum} steps per quantum, BF16 path, dt {w.dt}"}
+
+
 def traffic_record(kernel, workload_tag):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or
     None when that summary is missing or was taken on a different kernel source."""
@@ -214,6 +284,83 @@ def traffic_record(kernel, workload_tag):
     return rec.get("bytes_per_launch")
 
 
+def _csv_rows(path):
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="mid"):
+    """Turns rocprofv3 output (one --kernel-trace --stats run, one --pmc FETCH_SIZE and
+    one --pmc WRITE_SIZE run of the same bench command) into the committed summaries
+    under profiles/: per-kernel statistics of the step kernels, and the HBM traffic per
+    launch of every step kernel at its full-batch grid, each counter scaled by what it
+    reads for the calibration copy (a 512 MiB device copy: 512 MiB read, 512 MiB written)."""
+    prof = os.path.join(ROOT, "profiles")
+    os.makedirs(prof, exist_ok=True)
+    trace = _csv_rows(os.path.join(trace_dir, "run_kernel_trace.csv"))
+    groups = {}
+    for r in trace:
+        key = (r["Kernel_Name"].split("(")[0].replace("void ", ""),
+               int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in groups.values())
+    lines = [f"# rocprofv3 kernel statistics, {workload_tag} workload (BF16 path, 512 chains)", "",
+             f"Command: `{command['trace']}`", "",
+             "Grouped by kernel and grid size (work-items): the per-step launches cover all 512 chains; "
+             "launches at small grids belong to the Gauss-Newton start and the data setup.", "",
+             "| Kernel | Grid | Calls | Average us | Min us | Max us | Share % |", "|---|---|---|---|---|---|---|"]
+    for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
+        lines.append(f"| `{k}` | {g} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} | "
+                     f"{100.0 * sum(v) / total:.2f} |")
+    with open(os.path.join(prof, f"step_kernels_{workload_tag}_kernel_stats.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+    def per_kernel(rows):
+        out = {}
+        for r in rows:
+            key = (r["Kernel_Name"].split("(")[0].replace("void ", ""), int(r["Grid_Size"]))
+            out.setdefault(key, []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch = per_kernel(_csv_rows(os.path.join(fetch_dir, "run_counter_collection.csv")))
+    write = per_kernel(_csv_rows(os.path.join(write_dir, "run_counter_collection.csv")))
+    cal_bytes = float(1 << 29)
+    f_cal = max(v[0] for (k, g), v in fetch.items() if k == "__amd_rocclr_copyBuffer") * 1024.0
+    w_cal = max(v[0] for (k, g), v in write.items() if k == "__amd_rocclr_copyBuffer") * 1024.0
+    f_scale, w_scale = cal_bytes / f_cal, cal_bytes / w_cal
+    lines = [f"# HBM traffic per launch, {workload_tag} workload (BF16 path, 512 chains)", "",
+             f"FETCH_SIZE: `{command['fetch']}`", "", f"WRITE_SIZE: `{command['write']}`", "",
+             f"Calibration: the 512 MiB device copy reads {f_cal / 2**20:.1f} MiB by FETCH_SIZE and writes "
+             f"{w_cal / 2**20:.1f} MiB by WRITE_SIZE: scales {f_scale:.3f} (fetch) and {w_scale:.3f} (write).", "",
+             "| Kernel | Grid | Launches | Read MB | Written MB | Total MB |", "|---|---|---|---|---|---|"]
+    records = {}
+    for (k, g), fv in sorted(fetch.items(), key=lambda kv: -max(kv[1]))[:24]:
+        if not k.startswith("dino::") or (k, g) not in write:
+            continue
+        wv = write[(k, g)]
+        rd = sum(fv) / len(fv) * 1024.0 * f_scale
+        wr = sum(wv) / len(wv) * 1024.0 * w_scale
+        lines.append(f"| `{k}` | {g} | {len(fv)} | {rd / 1e6:.2f} | {wr / 1e6:.2f} | {(rd + wr) / 1e6:.2f} |")
+        base = k.split("::")[-1].split("<")[0]
+        if base not in records or g > records[base]["grid"]:
+            records[base] = dict(grid=g, read_bytes=rd, write_bytes=wr)
+    with open(os.path.join(prof, f"step_kernels_{workload_tag}_traffic.md"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    for base, rec in records.items():
+        src = os.path.join(ROOT, "paper_2403_08220_amd", "csrc", KERNEL_SOURCES.get(base, ""))
+        if not os.path.isfile(src):
+            continue
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        with open(os.path.join(prof, f"{base}_{workload_tag}_traffic.json"), "w") as fh:
+            json.dump(dict(kernel=base, grid=rec["grid"], bytes_per_launch=round(rec["read_bytes"] + rec["write_bytes"]),
+                           read_bytes=round(rec["read_bytes"]), write_bytes=round(rec["write_bytes"]),
+                           fetch_scale=f_scale, write_scale=w_scale, source_sha256=sha,
+                           commands=[command["fetch"], command["write"]]), fh, indent=1)
+            fh.write("\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,7 +370,19 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=100, help="steps of the plain FP64 leg (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --serve-requests 0 --no-cpu-baseline"
+        summarize_profiles(*args.summarize_profiles, command={
+            "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py "
+                     "--steps 100 --fp64-steps 0 --serve-requests 0 --no-cpu-baseline",
+            "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {b}",
+            "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {b}"})
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}). "
               "Chains are independent; sharding would place whole chain blocks or requests on separate GPUs.",
@@ -281,6 +440,11 @@ def main():
         roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4))
+    serving = None
+    if args.serve_requests > 0:
+        log(f"bench: serving leg, {args.serve_requests} requests at load {args.serve_load} ...")
+        serving = serving_leg(ctx, workload("serve"), args.serve_requests, args.serve_load)
+        log(f"bench: serving p50 {serving['p50_s']} s, p99 {serving['p99_s']} s")
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle) ...")
@@ -308,6 +472,7 @@ def main():
         "roofline": roof,
         "stages": stages,
         "fp64_plain": fp64,
+        "serving": serving,
         "cpu_baseline": cpu,
         "init": init_info,
     }

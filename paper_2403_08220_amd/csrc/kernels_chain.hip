@@ -31,95 +31,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
     return t;
 }
 
-// out_j = sum_{i >= j} L[i][j] v_i  (L^T v). Waves take rows i = wave (mod 4); lanes
-// read 64 consecutive columns of a row; partial sums reduced through part[4][MAXR].
-__device__ void lt_matvec(const double* __restrict__ L, int r, const double* v, double* out, double* part) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int jb = 0; jb < r; jb += 64) {
-        const int j = jb + lane;
-        double acc = 0.0;
-        if (j < r)
-#pragma unroll 8
-            for (int i = jb + ((wave - jb) & 3); i < r; i += 4)
-                if (i >= j) acc += L[(long)i * r + j] * v[i];
-        if (j < r) part[wave * MAXR + j] = acc;
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j < r; j += TPB)
-        out[j] = part[j] + part[MAXR + j] + part[2 * MAXR + j] + part[3 * MAXR + j];
-    __syncthreads();
-}
-
-// out_i = sum_{j <= i} L[i][j] v_j  (L v). Rows in passes of 16: 16 threads per row,
-// each reading 4 consecutive columns per 64-column step; shuffle-reduced per row.
-__device__ void l_matvec(const double* __restrict__ L, int r, const double* v, double* out) {
-    const int sub = threadIdx.x & 15, rloc = threadIdx.x >> 4;
-    for (int i0 = 0; i0 < r; i0 += 16) {
-        const int i = i0 + rloc;
-        double acc = 0.0;
-        if (i < r)
-#pragma unroll 4
-            for (int j = 4 * sub; j <= i; j += 64)
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    if (j + q <= i) acc += L[(long)i * r + j + q] * v[j + q];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        if (i < r && sub == 0) out[i] = acc;
-    }
-    __syncthreads();
-}
-
-// Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
-// a block first subtract the already solved part (8 threads per row), then lanes
-// 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
-__device__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
-                        double* acc_s) {
-    const int tid = threadIdx.x;
-    for (int b0 = 0; b0 < r; b0 += SB) {
-        const int nb = min(SB, r - b0);
-        {
-            const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
-            const int i = b0 + il;
-            double acc = 0.0;
-            if (il < nb)
-#pragma unroll 4
-                for (int j = 4 * sub; j < b0; j += 32)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (j + q < b0) acc += L[(long)i * r + j + q] * w[j + q];
-#pragma unroll
-            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-            if (il < nb && sub == 0) acc_s[il] = b[i] - acc;
-        }
-        __syncthreads();
-        if (tid < 64) {
-            const int lane = tid;
-            double row[SB];
-            double a = 0.0;
-            if (lane < nb) {
-#pragma unroll
-                for (int jj = 0; jj < SB; ++jj) row[jj] = (jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
-                a = acc_s[lane];
-            } else {
-#pragma unroll
-                for (int jj = 0; jj < SB; ++jj) row[jj] = 0.0;
-            }
-            double sol = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < SB; ++jj) {
-                if (jj < nb) {
-                    const double wj = __shfl(a * invd[b0 + jj], jj);  // valid on lane jj
-                    if (lane == jj) sol = wj;
-                    if (lane > jj) a -= row[jj] * wj;
-                }
-            }
-            if (lane < nb) w[b0 + lane] = sol;
-        }
-        __syncthreads();
-    }
-}
-
 // Backward substitution L^T x = b. Blocks from the bottom: rows of the block subtract
 // the solved part below through column reads (32 consecutive columns per row), then
 // lanes 0..SB-1 of wave 0 finish the block's transposed triangle.
@@ -174,6 +85,106 @@ __device__ void lt_solve(const double* __restrict__ L, const double* invd, int r
 __device__ __forceinline__ void load_inv_diag(const double* __restrict__ L, int r, double* invd) {
     for (int j = threadIdx.x; j < r; j += TPB) invd[j] = 1.0 / L[(long)j * r + j];
     __syncthreads();
+}
+
+// out1_j = sum_{i >= j} L[i][j] v1_i (L^T v1) and, if v2, out2 = L^T v2, in one pass
+// over L. Waves take rows i = wave (mod 4); lanes read 64 consecutive columns of a row;
+// partial sums are reduced through part (4 r doubles per product).
+__device__ void lt_matvec2(const double* __restrict__ L, int r, const double* v1, double* out1, const double* v2,
+                           double* out2, double* part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int jb = 0; jb < r; jb += 64) {
+        const int j = jb + lane;
+        double a1 = 0.0, a2 = 0.0;
+        if (j < r) {
+#pragma unroll 8
+            for (int i = jb + ((wave - jb) & 3); i < r; i += 4) {
+                if (i >= j) {
+                    const double lij = L[(long)i * r + j];
+                    a1 += lij * v1[i];
+                    if (v2) a2 += lij * v2[i];
+                }
+            }
+            part[wave * r + j] = a1;
+            if (v2) part[(4 + wave) * r + j] = a2;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < r; j += TPB) {
+        out1[j] = part[j] + part[r + j] + part[2 * r + j] + part[3 * r + j];
+        if (v2) out2[j] = part[4 * r + j] + part[5 * r + j] + part[6 * r + j] + part[7 * r + j];
+    }
+    __syncthreads();
+}
+
+// Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
+// a block first subtract the already solved part (8 threads per row), then lanes
+// 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
+__device__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
+                        double* acc_s) {
+    const int tid = threadIdx.x;
+    for (int b0 = 0; b0 < r; b0 += SB) {
+        const int nb = min(SB, r - b0);
+        {
+            const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
+            const int i = b0 + il;
+            double acc = 0.0;
+            if (il < nb)
+#pragma unroll 4
+                for (int j = 4 * sub; j < b0; j += 32)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (j + q < b0) acc += L[(long)i * r + j + q] * w[j + q];
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+            if (il < nb && sub == 0) acc_s[il] = b[i] - acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            double row[SB];
+            double a = lane < nb ? acc_s[lane] : 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+            double sol = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj) {
+                if (jj < nb) {
+                    const double wj = __shfl(a * invd[b0 + jj], jj);  // valid on lane jj
+                    if (lane == jj) sol = wj;
+                    if (lane > jj) a -= row[jj] * wj;
+                }
+            }
+            if (lane < nb) w[b0 + lane] = sol;
+        }
+        __syncthreads();
+    }
+}
+
+// Dynamic LDS of the per-chain transition kernels: CH_NV vectors of length r, the
+// triangular-solve scratch and the partial sums of the transposed products.
+constexpr int CH_NV = 10;
+struct ChainLds {
+    double* v[CH_NV];
+    double* acc;   // SB
+    double* part;  // max(8 SB, 8 r)
+    double* red;   // TPB / 64
+};
+
+__host__ __device__ inline size_t chain_lds_doubles(int r) {
+    return (size_t)CH_NV * r + SB + (size_t)8 * max(r, SB) + TPB / 64;
+}
+
+__device__ inline ChainLds carve_chain_lds(double* base, int r) {
+    ChainLds S;
+#pragma unroll
+    for (int k = 0; k < CH_NV; ++k) S.v[k] = base + (size_t)k * r;
+    double* p = base + (size_t)CH_NV * r;
+    S.acc = p;
+    S.part = p + SB;
+    S.red = p + SB + (size_t)8 * max(r, SB);
+    return S;
 }
 
 __device__ __forceinline__ long slot_offset(const int32_t* slot, int slot_xor, long slot_stride, int c) {
@@ -384,22 +395,25 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
 }
 
 // ---------------------------------------------------------------------------------
-// Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi).
+// Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi)
+//                      = L^-T (L^T x - (1-s) L^-1 (x + g) + beta xi),
+// a transposed product, a forward and a backward solve.
 // lfwd (optional) = log rho_0(x -> xp) = -|xi|^2/2 + |mhat|^2/2 + logdet_x, the
 // mMALA over pCN log-density ratio at the drawn point, mhat = (xp - s x)/beta.
 // Chains are walked by their metadata: an idle chain is skipped, a fresh chain (one that
 // joins at this step) proposes its initial state, the prior draw of stream 3, and the
 // acceptance then takes it unconditionally.
-__global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double beta, ChainMeta meta,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void propose_kernel(int r, double s, double beta, ChainMeta meta,
                                                       const double* __restrict__ x,
                                                       const double* __restrict__ g, const double* L, long strideL,
                                                       const int32_t* slot, int slot_xor, long slot_stride,
                                                       const double* __restrict__ xi_given,
                                                       const double* __restrict__ logdet, double* __restrict__ xp,
                                                       double* __restrict__ lfwd) {
-    __shared__ double xs[MAXR], gs[MAXR], u[MAXR], t[MAXR], w[MAXR], xi[MAXR], invd[MAXR];
-    __shared__ double part[4 * MAXR];
-    __shared__ double red[TPB / 64];
+    extern __shared__ double dyn[];
+    const ChainLds S = carve_chain_lds(dyn, r);
+    double *xs = S.v[0], *gs = S.v[1], *xi = S.v[2], *u = S.v[3], *w = S.v[4], *t = S.v[5], *invd = S.v[6],
+           *rhs = S.v[7];
     const int c = blockIdx.x, tid = threadIdx.x;
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) return;
@@ -419,6 +433,7 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
     for (int j = tid; j < r; j += TPB) {
         xs[j] = x[(long)c * r + j];
         gs[j] = g[(long)c * r + j];
+        rhs[j] = xs[j] + gs[j];
     }
     if (xi_given) {
         for (int j = tid; j < r; j += TPB) xi[j] = xi_given[(long)c * r + j];
@@ -434,14 +449,11 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
         }
     }
     __syncthreads();
-    lt_matvec(Lc, r, xs, u, part);
-    l_matvec(Lc, r, u, t);
-    for (int j = tid; j < r; j += TPB) t[j] -= (1.0 - s) * (xs[j] + gs[j]);
+    lt_matvec2(Lc, r, xs, u, nullptr, nullptr, S.part);
+    l_solve(Lc, invd, r, rhs, w, S.acc);
+    for (int j = tid; j < r; j += TPB) t[j] = u[j] - (1.0 - s) * w[j] + beta * xi[j];
     __syncthreads();
-    l_solve(Lc, invd, r, t, w, part);
-    for (int j = tid; j < r; j += TPB) w[j] += beta * xi[j];
-    __syncthreads();
-    lt_solve(Lc, invd, r, w, u, part);
+    lt_solve(Lc, invd, r, t, u, S.part);
     double nxi = 0.0, nm = 0.0;
     for (int j = tid; j < r; j += TPB) {
         xp[(long)c * r + j] = u[j];
@@ -450,8 +462,8 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
         nm += m * m;
     }
     if (lfwd) {
-        nxi = block_sum(nxi, red);
-        nm = block_sum(nm, red);
+        nxi = block_sum(nxi, S.red);
+        nm = block_sum(nm, S.red);
         if (tid == 0) lfwd[c] = -0.5 * nxi + 0.5 * nm + logdet[c];
     }
 }
@@ -459,20 +471,20 @@ __global__ __launch_bounds__(TPB) void propose_kernel(int r, double s, double be
 // log rho_0(a -> b) with the cache (g_a, L_a, logdet_a) of a, Sec. 5.4 with
 // I + H = L L^T:  -(dt/8)|L^-1 v|^2 + (sqrt(dt)/2) mhat.v - (|L^T mhat|^2 - |mhat|^2)/2
 // + logdet, v = H a - g = L L^T a - a - g, mhat = (b - s a)/beta.
-// Uses L^-1 v = L^T a - L^-1 (a + g) and mhat.v = (L^T mhat).(L^T a) - mhat.(a + g).
-__device__ double log_rho0_dev(const double* La, int r, double dt, double s, double beta, const double* a,
-                               const double* b, const double* ga, double logdet_a, double* u1, double* w2,
-                               double* m, double* u2, double* tmp, double* part, double* red, double* invd) {
+// Uses L^-1 v = L^T a - L^-1 (a + g) and mhat.v = (L^T mhat).(L^T a) - mhat.(a + g);
+// L^T a and L^T mhat come from one pass over L. a, b, ga live in S.v[0..2].
+__device__ __forceinline__ double log_rho0_dev(const double* La, int r, double dt, double s, double beta, const double* a,
+                               const double* b, const double* ga, double logdet_a, const ChainLds& S) {
     const int tid = threadIdx.x;
+    double *u1 = S.v[3], *w2 = S.v[4], *m = S.v[5], *u2 = S.v[6], *tmp = S.v[7], *invd = S.v[8];
     load_inv_diag(La, r, invd);
     for (int j = tid; j < r; j += TPB) {
         tmp[j] = a[j] + ga[j];
         m[j] = (b[j] - s * a[j]) / beta;
     }
     __syncthreads();
-    lt_matvec(La, r, a, u1, part);
-    lt_matvec(La, r, m, u2, part);
-    l_solve(La, invd, r, tmp, w2, part);
+    lt_matvec2(La, r, a, u1, m, u2, S.part);
+    l_solve(La, invd, r, tmp, w2, S.acc);
     double q1 = 0.0, d1 = 0.0, d2 = 0.0, n2 = 0.0, n3 = 0.0;
     for (int j = tid; j < r; j += TPB) {
         const double lv = u1[j] - w2[j];
@@ -482,22 +494,22 @@ __device__ double log_rho0_dev(const double* La, int r, double dt, double s, dou
         n2 += u2[j] * u2[j];
         n3 += m[j] * m[j];
     }
-    q1 = block_sum(q1, red);
-    d1 = block_sum(d1, red);
-    d2 = block_sum(d2, red);
-    n2 = block_sum(n2, red);
-    n3 = block_sum(n3, red);
+    q1 = block_sum(q1, S.red);
+    d1 = block_sum(d1, S.red);
+    d2 = block_sum(d2, S.red);
+    n2 = block_sum(n2, S.red);
+    n3 = block_sum(n3, S.red);
     return -(dt / 8.0) * q1 + 0.5 * sqrt(dt) * (d1 - d2) - 0.5 * (n2 - n3) + logdet_a;
 }
 
-__global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s, double beta, const double* x,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void log_rho_kernel(int r, double dt, double s, double beta, const double* x,
                                                       const double* phi_x, const double* g_x, const double* L_x,
                                                       const double* logdet_x, const double* xp,
                                                       const double* phi_p, const double* g_p, const double* L_p,
                                                       const double* logdet_p, double* out) {
-    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR], invd[MAXR];
-    __shared__ double part[4 * MAXR];
-    __shared__ double red[TPB / 64];
+    extern __shared__ double dyn[];
+    const ChainLds S = carve_chain_lds(dyn, r);
+    double *xs = S.v[0], *ps = S.v[1], *ga = S.v[2];
     const int c = blockIdx.x, tid = threadIdx.x;
     const long rr = (long)r * r;
     for (int j = tid; j < r; j += TPB) {
@@ -506,28 +518,26 @@ __global__ __launch_bounds__(TPB) void log_rho_kernel(int r, double dt, double s
         ga[j] = g_x[(long)c * r + j];
     }
     __syncthreads();
-    const double fwd = log_rho0_dev(L_x + c * rr, r, dt, s, beta, xs, ps, ga, logdet_x[c], u1, w2, m, u2, tmp,
-                                    part, red, invd);
+    const double fwd = log_rho0_dev(L_x + c * rr, r, dt, s, beta, xs, ps, ga, logdet_x[c], S);
     for (int j = tid; j < r; j += TPB) ga[j] = g_p[(long)c * r + j];
     __syncthreads();
-    const double rev = log_rho0_dev(L_p + c * rr, r, dt, s, beta, ps, xs, ga, logdet_p[c], u1, w2, m, u2, tmp,
-                                    part, red, invd);
+    const double rev = log_rho0_dev(L_p + c * rr, r, dt, s, beta, ps, xs, ga, logdet_p[c], S);
     if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
 }
 
 // MH decision of the first stage and the swap of state and cache on acceptance.
 // accflag: 0 rejected or idle, 1 accepted (pCN complement move), 2 fresh chain
 // initialised (complement drawn from the prior).
-__global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
                                                      double* x, double* g, double* phi,
                                                      double* logdet, const double* Lbuf, long half,
                                                      int32_t* cur, const double* xp, const double* gp,
                                                      const double* phip, const double* logdetp,
                                                      const int32_t* okp, const double* lfwd, int64_t* accepts,
                                                      int64_t* failures, int32_t* accflag) {
-    __shared__ double xs[MAXR], ps[MAXR], ga[MAXR], u1[MAXR], w2[MAXR], m[MAXR], u2[MAXR], tmp[MAXR], invd[MAXR];
-    __shared__ double part[4 * MAXR];
-    __shared__ double red[TPB / 64];
+    extern __shared__ double dyn[];
+    const ChainLds S = carve_chain_lds(dyn, r);
+    double *xs = S.v[0], *ps = S.v[1], *ga = S.v[2];
     __shared__ int decision;
     const int c = blockIdx.x, tid = threadIdx.x;
     const long rr = (long)r * r;
@@ -558,7 +568,7 @@ __global__ __launch_bounds__(TPB) void accept_kernel(int r, double dt, double s,
         __syncthreads();
     } else {
         double rev = 0.0;
-        if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], u1, w2, m, u2, tmp, part, red, invd);
+        if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], S);
         if (tid == 0) {
             const double lr = phi[c] - phip[c] + rev - lfwd[c];
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)meta.step[c],
@@ -740,29 +750,48 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
 }
 
 
+// LDS of the transition kernels (r vectors, solve scratch and product partial sums).
+constexpr size_t CH_LDS_LIMIT = 160 * 1024 - 1024;
+static size_t chain_lds_bytes(int r) { return chain_lds_doubles(r) * sizeof(double); }
+
+template <typename K>
+static void allow_large_lds(K kernel, bool& done) {
+    if (!done) {
+        DINO_HIP(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)CH_LDS_LIMIT));
+        done = true;
+    }
+}
+
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
                          const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
                          double* xp, double* lfwd, const double* logdet, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(propose_kernel, attr);
     const ChainMeta meta = use_meta ? p->meta : ChainMeta{};
-    hipLaunchKernelGGL(propose_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->s, p->beta, meta, x, g, L, strideL, slot,
-                       slot_xor, slot_stride, xi_given, logdet, xp, lfwd);
+    hipLaunchKernelGGL(propose_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->s, p->beta, meta, x,
+                       g, L, strideL, slot, slot_xor, slot_stride, xi_given, logdet, xp, lfwd);
     DINO_HIP(hipGetLastError());
 }
 
 
 void launch_accept(dino_problem* p, int n, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(accept_kernel, attr);
     const long half = (long)p->C * p->r * p->r;
-    hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
-                       p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp,
-                       p->lfwd, p->accepts, p->failures, p->acc);
+    hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s, p->beta,
+                       p->meta, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip,
+                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc);
     DINO_HIP(hipGetLastError());
 }
 
 void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
                     const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
                     const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(log_rho_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, x, phi_x, g_x,
-                       L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, out);
+    static bool attr = false;
+    allow_large_lds(log_rho_kernel, attr);
+    hipLaunchKernelGGL(log_rho_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s,
+                       p->beta, x, phi_x, g_x, L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, out);
     DINO_HIP(hipGetLastError());
 }
 

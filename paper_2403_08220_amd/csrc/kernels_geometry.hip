@@ -253,6 +253,59 @@ __global__ __launch_bounds__(256) void gn_hessian_kernel(int dy, int r, const do
 static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
 
 // One forward layer with the largest tile that still gives >= 1024 blocks.
+// FP32 layer with the whole K extent staged: a block stages 16 input rows and 16 weight
+// rows (K each, transposed to k-major with a padded stride) in LDS with one barrier,
+// then every thread forms one output with four interleaved partial sums over k.
+constexpr int FWD_LDP = 17;
+
+__global__ __launch_bounds__(256) void fwd_layer_staged_kernel(int M, int K, int N, const float* __restrict__ in,
+                                                               int ldin, const float* __restrict__ W,
+                                                               const float* __restrict__ b, int kind,
+                                                               float* __restrict__ out, int ldout,
+                                                               float* __restrict__ dprime, int ldd) {
+    extern __shared__ float fsm[];
+    float* As = fsm;                    // K x FWD_LDP: As[k][row]
+    float* Ws = fsm + (long)K * FWD_LDP;  // K x FWD_LDP: Ws[k][col]
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
+    // all 32 row loads of a k slice are issued before any store
+    for (int k = tid; k < K; k += 256) {
+        float av[16], wv[16];
+#pragma unroll
+        for (int row = 0; row < 16; ++row) {
+            av[row] = (m0 + row < M) ? in[(long)(m0 + row) * ldin + k] : 0.f;
+            wv[row] = (n0 + row < N) ? W[(long)(n0 + row) * K + k] : 0.f;
+        }
+#pragma unroll
+        for (int row = 0; row < 16; ++row) {
+            As[k * FWD_LDP + row] = av[row];
+            Ws[k * FWD_LDP + row] = wv[row];
+        }
+    }
+    __syncthreads();
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+    int k = 0;
+    for (; k + 3 < K; k += 4) {
+        a0 += As[k * FWD_LDP + ty] * Ws[k * FWD_LDP + tx];
+        a1 += As[(k + 1) * FWD_LDP + ty] * Ws[(k + 1) * FWD_LDP + tx];
+        a2 += As[(k + 2) * FWD_LDP + ty] * Ws[(k + 2) * FWD_LDP + tx];
+        a3 += As[(k + 3) * FWD_LDP + ty] * Ws[(k + 3) * FWD_LDP + tx];
+    }
+    for (; k < K; ++k) a0 += As[k * FWD_LDP + ty] * Ws[k * FWD_LDP + tx];
+    const int m = m0 + ty, n = n0 + tx;
+    if (m >= M || n >= N) return;
+    const float z = ((a0 + a1) + (a2 + a3)) + (b ? b[n] : 0.f);
+    float o;
+    if (kind == DINO_LAYER_LINEAR) {
+        o = z;
+    } else {
+        o = gelu_t<float>(z);
+        if (kind == DINO_LAYER_RESID) o += in[(long)m * ldin + n];
+        if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
+    }
+    out[(long)m * ldout + n] = o;
+}
+
 template <typename T>
 static void fwd_layer(int M, int K, int N, const T* in, int ldin, const T* W, const T* b, int kind, T* out,
                       int ldout, T* dprime, int ldd, hipStream_t st) {
@@ -313,7 +366,19 @@ void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hip
         const int N = last ? p->d_y : ly.fan_out;
         float* dp = nullptr;
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
-        fwd_layer<float>(n, ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32, st);
+        const size_t lds = (size_t)2 * ly.fan_in * FWD_LDP * sizeof(float);
+        if (lds <= 64 * 1024) {
+            static bool attr = false;
+            if (!attr) {
+                DINO_HIP(hipFuncSetAttribute((const void*)fwd_layer_staged_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+                attr = true;
+            }
+            hipLaunchKernelGGL(fwd_layer_staged_kernel, dim3((N + 15) / 16, (n + 15) / 16), dim3(256), lds, st, n,
+                               ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
+        } else {
+            fwd_layer<float>(n, ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32, st);
+        }
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;

@@ -222,6 +222,21 @@ dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const dou
 dino_status dino_eval_normals(dino_problem* p, int n, int stream_id, int64_t step, int count, double* out,
                               void* stream);
 
+/* Whitened KLE coordinates of nodal fields (the encoder of eq. projector extended to
+ * all d_m modes, Sec. 4.2 with the prior of this library): z = Lambda^-1/2 Q^T m in KLE
+ * order, computed through the separable DCT-II basis; x = z[0:r] is the reduced part
+ * and z_perp = z[r:] the complement. fields: device, n_fields x d_m (node p = j n + i);
+ * x: device, n_fields x r; z_perp: device, n_fields x (d_m - r); one of x and z_perp
+ * may be NULL. The call allocates 2 n_fields d_m doubles of device scratch and
+ * synchronises the stream. */
+dino_status dino_encode(dino_ctx* ctx, int n_fields, const double* fields, double* x, double* z_perp,
+                        void* stream);
+/* Nodal fields m = Q Lambda^1/2 z from whitened coordinates (the decoder Psi_r x plus
+ * the complement); z_perp == NULL decodes the reduced part alone. Same layouts and
+ * scratch as dino_encode. */
+dino_status dino_decode(dino_ctx* ctx, int n_fields, const double* x, const double* z_perp, double* fields,
+                        void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of many inverse problems (one problem = one request:
  * its own data y, noise variances, observation count, chain count and step budget)

@@ -112,6 +112,8 @@ SIGNATURES = {
     "dino_set_profiling": (ct.c_int32, [_P, ct.c_int]),
     "dino_read_profile": (ct.c_int32, [_P, _D, _I32, _I64]),
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),
+    "dino_encode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),
+    "dino_decode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),
     "dino_server_create": (ct.c_int32, [_P, ct.POINTER(ServerCfg), ct.POINTER(_P)]),
     "dino_server_destroy": (ct.c_int32, [_P]),
     "dino_server_clock": (ct.c_int32, [_P, ct.POINTER(ct.c_double)]),

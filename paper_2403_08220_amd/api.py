@@ -63,6 +63,23 @@ class Context:
         check(self.lib.dino_read_basis(self.h, dptr(dec), dptr(lam), dptr(vp), i32ptr(modes)))
         return dict(dec=dec, lam=lam, var_perp=vp, modes=modes)
 
+    def encode(self, fields, stream=None):
+        """Whitened KLE coordinates (x, z_perp) of device fields (n, d_m) in float64."""
+        torch = _torch()
+        n = fields.shape[0]
+        x = torch.empty((n, self.r), dtype=torch.float64, device=fields.device)
+        zp = torch.empty((n, self.d_m - self.r), dtype=torch.float64, device=fields.device)
+        check(self.lib.dino_encode(self.h, n, _tp(fields), _tp(x), _tp(zp), _stream_handle(stream)))
+        return x, zp
+
+    def decode(self, x, z_perp=None, stream=None):
+        """Device fields (n, d_m) from whitened coordinates; z_perp None decodes Psi_r x."""
+        torch = _torch()
+        n = x.shape[0]
+        out = torch.empty((n, self.d_m), dtype=torch.float64, device=x.device)
+        check(self.lib.dino_decode(self.h, n, _tp(x), _tp(z_perp), _tp(out), _stream_handle(stream)))
+        return out
+
     def load_network(self, layers):
         """layers: list of (kind, W (fan_out x fan_in), b) with kind in linear/act/resid."""
         L = len(layers)

@@ -159,9 +159,14 @@ struct Basis {
     double gamma = 0, delta = 0;
     std::vector<int32_t> k1, k2;   // kept modes
     std::vector<double> lam;       // kept eigenvalues
+    std::vector<int32_t> order;    // all d_m modes (k1 n + k2) in KLE order
+    std::vector<double> sqlam_all; // sqrt(lambda) in KLE order
     double* dec = nullptr;         // d_m x r
     double* var_perp = nullptr;    // d_m
     double* lam_dev = nullptr;     // r
+    double* q = nullptr;           // n x n DCT-II matrix Q[i][k] = q_k(i)
+    int32_t* perm = nullptr;       // d_m: order on the device
+    double* sqlam = nullptr;       // d_m: sqrt_lam_all on the device
 };
 
 struct dino_ctx_impl;
@@ -302,6 +307,12 @@ void destroy_problem(dino_problem* p);
 
 // basis
 void build_basis_device(Basis& b);
+// Whitened KLE coordinates of nf fields (x: nf x r, zp: nf x (d_m - r), either may be
+// null) and back; t1, t2 are nf x d_m scratch.
+void launch_encode(const Basis& b, int nf, const double* fields, double* x, double* zp, double* t1, double* t2,
+                   hipStream_t st);
+void launch_decode(const Basis& b, int nf, const double* x, const double* zp, double* fields, double* t1, double* t2,
+                   hipStream_t st);
 void launch_posterior(dino_problem* p, int burn_in, double* mean, double* var, double* xbar, double* S,
                       hipStream_t st);
 void launch_ess(dino_problem* p, int burn_in, double* ess, hipStream_t st);

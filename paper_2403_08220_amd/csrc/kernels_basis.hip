@@ -53,6 +53,85 @@ __global__ void vp_stage2_kernel(int n, const double* __restrict__ Q2, const dou
     vp[e] = acc;
 }
 
+// Q[i][k] = q_k(i).
+__global__ void q_kernel(int n, double* __restrict__ Q) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * n) return;
+    Q[e] = dct_q(n, e % n, e / n);
+}
+
+// One axis of the separable transform for nf fields of n x n values:
+//     out[f][b][a] = sum_c in[f][a][c] Q[c][b]   (trans = 0)
+//     out[f][b][a] = sum_c in[f][a][c] Q[b][c]   (trans = 1),
+// i.e. the last axis is contracted with Q (or Q^T) and the two axes swap.
+__global__ void sep_axis_kernel(int nf, int n, const double* __restrict__ in, const double* __restrict__ Q,
+                                int trans, double* __restrict__ out) {
+    const long nn = (long)n * n;
+    const int f = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf || e >= nn) return;
+    const int b = e / n, a = e % n;
+    const double* row = in + f * nn + (long)a * n;
+    double acc = 0.0;
+    if (trans)
+        for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)b * n + c];
+    else
+        for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)c * n + b];
+    out[f * nn + e] = acc;
+}
+
+// KLE position t holds mode perm[t] = k1 n + k2; the transformed grid is laid out
+// [k2][k1]. Encode: z_t = G[k2][k1] / sqrt(lambda_t); decode scatters G = z sqrt(lambda).
+__global__ void kle_gather_kernel(int nf, int n, int r, const double* __restrict__ G, const int32_t* __restrict__ perm,
+                                  const double* __restrict__ sqlam, double* __restrict__ x,
+                                  double* __restrict__ zp) {
+    const long nn = (long)n * n;
+    const int f = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf || t >= nn) return;
+    const int e = perm[t], k1 = e / n, k2 = e % n;
+    const double z = G[f * nn + (long)k2 * n + k1] / sqlam[t];
+    if (t < r) {
+        if (x) x[(long)f * r + t] = z;
+    } else if (zp) {
+        zp[(long)f * (nn - r) + (t - r)] = z;
+    }
+}
+
+__global__ void kle_scatter_kernel(int nf, int n, int r, const double* __restrict__ x, const double* __restrict__ zp,
+                                   const int32_t* __restrict__ perm, const double* __restrict__ sqlam,
+                                   double* __restrict__ G) {
+    const long nn = (long)n * n;
+    const int f = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf || t >= nn) return;
+    const int e = perm[t], k1 = e / n, k2 = e % n;
+    const double z = (t < r) ? x[(long)f * r + t] : (zp ? zp[(long)f * (nn - r) + (t - r)] : 0.0);
+    G[f * nn + (long)k2 * n + k1] = z * sqlam[t];
+}
+
+void launch_encode(const Basis& b, int nf, const double* fields, double* x, double* zp, double* t1, double* t2,
+                   hipStream_t st) {
+    const int n = b.n;
+    const dim3 grid((n * n + 255) / 256, nf);
+    // m[f][j][i] -> t1[f][k1][j] -> t2[f][k2][k1]
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, fields, b.q, 0, t1);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 0, t2);
+    hipLaunchKernelGGL(kle_gather_kernel, grid, dim3(256), 0, st, nf, n, b.r, t2, b.perm, b.sqlam, x, zp);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_decode(const Basis& b, int nf, const double* x, const double* zp, double* fields, double* t1, double* t2,
+                   hipStream_t st) {
+    const int n = b.n;
+    const dim3 grid((n * n + 255) / 256, nf);
+    // z -> t1[f][k2][k1] -> t2[f][i][k2] -> m[f][j][i]
+    hipLaunchKernelGGL(kle_scatter_kernel, grid, dim3(256), 0, st, nf, n, b.r, x, zp, b.perm, b.sqlam, t1);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 1, t2);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t2, b.q, 1, fields);
+    DINO_HIP(hipGetLastError());
+}
+
 void build_basis_device(Basis& b) {
     const int n = b.n, r = b.r, d_m = n * n;
     int32_t *k1d = nullptr, *k2d = nullptr;
@@ -92,6 +171,13 @@ void build_basis_device(Basis& b) {
     hipLaunchKernelGGL(q2_kernel, dim3(g), dim3(256), 0, 0, n, Q2);
     hipLaunchKernelGGL(vp_stage1_kernel, dim3(g), dim3(256), 0, 0, n, Q2, lamc, T);
     hipLaunchKernelGGL(vp_stage2_kernel, dim3(g), dim3(256), 0, 0, n, Q2, T, b.var_perp);
+    // full KLE order (mode of every position) and sqrt(lambda) for encode / decode
+    DINO_HIP(hipMalloc(&b.q, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&b.perm, sizeof(int32_t) * d_m));
+    DINO_HIP(hipMalloc(&b.sqlam, sizeof(double) * d_m));
+    hipLaunchKernelGGL(q_kernel, dim3(g), dim3(256), 0, 0, n, b.q);
+    DINO_HIP(hipMemcpy(b.perm, b.order.data(), sizeof(int32_t) * d_m, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(b.sqlam, b.sqlam_all.data(), sizeof(double) * d_m, hipMemcpyHostToDevice));
     DINO_HIP(hipGetLastError());
     DINO_HIP(hipDeviceSynchronize());
     hipFree(k1d);

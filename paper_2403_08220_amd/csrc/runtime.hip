@@ -39,7 +39,11 @@ static void free_basis(Basis& b) {
     if (b.dec) hipFree(b.dec);
     if (b.var_perp) hipFree(b.var_perp);
     if (b.lam_dev) hipFree(b.lam_dev);
-    b.dec = b.var_perp = b.lam_dev = nullptr;
+    if (b.q) hipFree(b.q);
+    if (b.perm) hipFree(b.perm);
+    if (b.sqlam) hipFree(b.sqlam);
+    b.dec = b.var_perp = b.lam_dev = b.q = b.sqlam = nullptr;
+    b.perm = nullptr;
 }
 
 static void free_layers(std::vector<Layer>& ls) {
@@ -277,6 +281,9 @@ dino_status dino_load_prior(dino_ctx* ctx, int n, double gamma, double delta, in
             const double a = gamma * key(e) / (h * h) + delta;
             nb.lam.push_back(1.0 / (a * a));
         }
+        nb.order.assign(idx.begin(), idx.end());
+        nb.sqlam_all.resize(d_m);
+        for (int t = 0; t < d_m; ++t) nb.sqlam_all[t] = 1.0 / (gamma * key(idx[t]) / (h * h) + delta);
         build_basis_device(nb);
         free_basis(ctx->basis);
         ctx->basis = nb;
@@ -296,6 +303,50 @@ dino_status dino_read_basis(dino_ctx* ctx, double* dec, double* lam, double* var
                 modes[2 * j] = b.k1[j];
                 modes[2 * j + 1] = b.k2[j];
             }
+    });
+}
+
+dino_status dino_encode(dino_ctx* ctx, int n_fields, const double* fields, double* x, double* z_perp,
+                        void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && ctx->basis.r > 0, DINO_ESTATE, "no prior loaded");
+        DINO_REQUIRE(n_fields >= 1 && n_fields <= 65535 && fields && (x || z_perp), DINO_EINVAL, "bad arguments");
+        DINO_HIP(hipSetDevice(ctx->device));
+        const size_t nn = (size_t)ctx->basis.d_m * n_fields;
+        double *t1 = nullptr, *t2 = nullptr;
+        DINO_REQUIRE(hipMalloc(&t1, sizeof(double) * nn) == hipSuccess, DINO_ENOMEM, "scratch allocation failed");
+        if (hipMalloc(&t2, sizeof(double) * nn) != hipSuccess) {
+            (void)hipFree(t1);
+            throw Error{DINO_ENOMEM, "scratch allocation failed"};
+        }
+        hipStream_t st = as_stream(stream);
+        launch_encode(ctx->basis, n_fields, fields, x, z_perp, t1, t2, st);
+        const hipError_t e = hipStreamSynchronize(st);
+        (void)hipFree(t1);
+        (void)hipFree(t2);
+        DINO_HIP(e);
+    });
+}
+
+dino_status dino_decode(dino_ctx* ctx, int n_fields, const double* x, const double* z_perp, double* fields,
+                        void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && ctx->basis.r > 0, DINO_ESTATE, "no prior loaded");
+        DINO_REQUIRE(n_fields >= 1 && n_fields <= 65535 && fields && x, DINO_EINVAL, "bad arguments");
+        DINO_HIP(hipSetDevice(ctx->device));
+        const size_t nn = (size_t)ctx->basis.d_m * n_fields;
+        double *t1 = nullptr, *t2 = nullptr;
+        DINO_REQUIRE(hipMalloc(&t1, sizeof(double) * nn) == hipSuccess, DINO_ENOMEM, "scratch allocation failed");
+        if (hipMalloc(&t2, sizeof(double) * nn) != hipSuccess) {
+            (void)hipFree(t1);
+            throw Error{DINO_ENOMEM, "scratch allocation failed"};
+        }
+        hipStream_t st = as_stream(stream);
+        launch_decode(ctx->basis, n_fields, x, z_perp, fields, t1, t2, st);
+        const hipError_t e = hipStreamSynchronize(st);
+        (void)hipFree(t1);
+        (void)hipFree(t2);
+        DINO_HIP(e);
     });
 }
 

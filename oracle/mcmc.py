@@ -18,6 +18,11 @@ Readings of the paper taken here (listed with reasons in the design notes):
 * The noise of the reduced proposal (eq. reduced_space_sampling) is mapped through the
   Cholesky factor L of I + H (L L^T = I + H) instead of P (d+1)^-1/2: the same law,
   N(0, (1 - s^2)(I + H)^-1), with a unique factor, so both sides draw the same point.
+  With factor="dual" (observation-space form, for d_y < r) the same law is drawn as
+  beta (I + H)^-1 (xi_1 + B^T xi_2), xi_1 in R^r, xi_2 in R^d_y, B = Gamma^-1/2 J: its
+  covariance is (I + H)^-1 (I + B^T B) (I + H)^-1 = (I + H)^-1, and (I + H)^-1 can then
+  be applied through the d_y x d_y matrix I + B B^T (Woodbury). xi_1 and xi_2 are the
+  first r and the next d_y normals of the proposal stream.
 * The acceptance uses the surrogate misfit (the first-stage ratio eq. da_dino_trr_1);
   accept iff log xi_1 <= log rho (Alg. 1 rejects iff alpha < xi_1, so ties accept).
 * A proposal whose misfit is not finite or whose I + H is not positive definite is
@@ -43,6 +48,7 @@ class Problem:
     dt: float
     seed: int = 0
     request_id: int = 0
+    factor: str = "primal"   # proposal noise mapping: "primal" (L^-T xi) or "dual"
 
     @property
     def d_y(self) -> int:
@@ -70,6 +76,7 @@ class Cache:
     P: np.ndarray        # (C, r, r) eigenvectors of H
     L: np.ndarray        # (C, r, r) lower Cholesky factor of I + H
     ok: np.ndarray       # (C,) finite misfit and positive definite I + H
+    B: np.ndarray = None # (C, d_y, r) whitened reduced Jacobian Gamma^-1/2 J
 
 
 def geometry(prob: Problem, x: np.ndarray) -> Cache:
@@ -101,7 +108,7 @@ def geometry(prob: Problem, x: np.ndarray) -> Cache:
             L[c] = np.linalg.cholesky(np.eye(r) + H[c])
         except np.linalg.LinAlgError:
             ok[c] = False
-    return Cache(f=f, phi=phi, g=g, H=H, d=d, P=P, L=L, ok=ok)
+    return Cache(f=f, phi=phi, g=g, H=H, d=d, P=P, L=L, ok=ok, B=Jw)
 
 
 def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:
@@ -109,14 +116,19 @@ def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.nd
 
         x+ = P diag((d+s)/(d+1)) P^T x - P diag((1-s)/(d+1)) P^T g + noise,
 
-    noise = sqrt(1 - s^2) L^-T xi (Cholesky reading of P diag((1-s^2)/(d+1))^1/2 xi)."""
+    noise = sqrt(1 - s^2) L^-T xi (Cholesky reading of P diag((1-s^2)/(d+1))^1/2 xi), or,
+    with factor "dual", sqrt(1 - s^2) (I + H)^-1 (xi_1 + B^T xi_2) (xi of length r + d_y)."""
     s, beta = prob.s, prob.beta
     C, r = x.shape
     out = np.empty_like(x)
     for c in range(C):
         d, P = cache.d[c], cache.P[c]
         mean = P @ (((d + s) / (d + 1.0)) * (P.T @ x[c])) - P @ (((1.0 - s) / (d + 1.0)) * (P.T @ cache.g[c]))
-        noise = beta * sla.solve_triangular(cache.L[c], xi[c], lower=True, trans="T")
+        if prob.factor == "dual":
+            w = xi[c, :r] + cache.B[c].T @ xi[c, r:]
+            noise = beta * np.linalg.solve(np.eye(r) + cache.H[c], w)
+        else:
+            noise = beta * sla.solve_triangular(cache.L[c], xi[c], lower=True, trans="T")
         out[c] = mean + noise
     return out
 
@@ -197,7 +209,8 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
     current step; pass them to evaluate the transition at given draws."""
     C, r = st.x.shape
     if xi is None:
-        xi = philox.normals(prob.seed, prob.request_id, philox.STREAM_XI, st.step, st.chains, r)
+        count = r + prob.d_y if prob.factor == "dual" else r
+        xi = philox.normals(prob.seed, prob.request_id, philox.STREAM_XI, st.step, st.chains, count)
     if u is None:
         u = philox.uniforms(prob.seed, prob.request_id, st.step, st.chains)
     # Alg. 1: reduced proposal sampling, surrogate evaluation at x+, first-stage ratio

@@ -156,14 +156,14 @@ def copy_calibration(nbytes=1 << 29):
     return nbytes
 
 
-def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True):
+def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, factorization="auto"):
     import torch
     from paper_2403_08220_amd import Problem
 
     C = w.chains
     cap = warmup + steps
     p = Problem(ctx, C, y, nv, w.dt, seed=w.chain_seed, precision=precision, track_complement=True,
-                trace_capacity=cap)
+                trace_capacity=cap, factorization=factorization)
     p.init(x0, z0)
     stream = torch.cuda.current_stream()
     p.step(warmup)
@@ -369,6 +369,8 @@ def main():
     ap.add_argument("--precision", default="bf16", choices=["f64", "bf16"])
     ap.add_argument("--fp64-steps", type=int, default=100, help="steps of the plain FP64 leg (0: skip)")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
+    ap.add_argument("--factorization", default="auto", choices=["auto", "primal", "dual"],
+                    help="auto: the observation-space (d_y x d_y) factorisation when d_y < r")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
@@ -408,7 +410,8 @@ def main():
     x0, z0, init_info = laplace_start(w, ctx, y, nv)
     log(f"bench: Laplace start ready {init_info}")
     copy_calibration()
-    res = run_path(w, ctx, y, nv, x0, z0, args.precision, args.steps, args.warmup, profile=not args.no_profile)
+    res = run_path(w, ctx, y, nv, x0, z0, args.precision, args.steps, args.warmup, profile=not args.no_profile,
+                   factorization=args.factorization)
     log(f"bench: {args.precision} path: {res['wall_s']:.3f} s, accept {res['accept_rate']:.3f}")
     C, steps = w.chains, args.steps
     value = C * steps / res["wall_s"]
@@ -416,7 +419,8 @@ def main():
 
     fp64 = None
     if args.fp64_steps > 0 and args.precision != "f64":
-        r64 = run_path(w, ctx, y, nv, x0, z0, "f64", args.fp64_steps, args.warmup, profile=False)
+        r64 = run_path(w, ctx, y, nv, x0, z0, "f64", args.fp64_steps, args.warmup, profile=False,
+                       factorization=args.factorization)
         fp64 = dict(value=round(C * args.fp64_steps / r64["wall_s"], 1), unit="chain-steps/s",
                     steps=args.fp64_steps, ms_per_step=round(1e3 * r64["wall_s"] / args.fp64_steps, 4),
                     accept_rate=round(r64["accept_rate"], 4),
@@ -465,7 +469,7 @@ def main():
                 "chains start from Laplace samples at the Gauss-Newton MAP",
         "config": {"workload": "129x129 grid, r=200 KLE, ResNet 400x4 GELU, d_y=100, 512 chains, dt=3e-4",
                    "grid": w.n, "r": w.r, "width": w.width, "depth": w.depth, "d_y": w.d_y, "chains": C,
-                   "dt": w.dt, "precision": args.precision},
+                   "dt": w.dt, "precision": args.precision, "factorization": args.factorization},
         "ess_per_s": round(res["median_ess"] / res["wall_s"], 3),
         "median_ess_frac": res["median_ess_frac"],
         "accept_rate": round(res["accept_rate"], 4),

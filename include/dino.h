@@ -110,16 +110,25 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  * track_complement: keep the complement state z (n_chains x (d_m - r) FP32).
  * trace_capacity: number of steps whose reduced states (FP32) and misfits are
  *   recorded for diagnostics (0 = none).
+ * factorization: DINO_FACTOR_PRIMAL factorises I + H (r x r) and draws the proposal
+ *   noise L^-T xi; DINO_FACTOR_DUAL factorises I + B B^T (d_y x d_y, B = Gamma^-1/2 J),
+ *   applies (I + H)^-1 by Woodbury and draws the noise (I + H)^-1 (xi_1 + B^T xi_2)
+ *   (the same law, N(0, (I + H)^-1); xi_2 = the d_y normals of stream 0 after the
+ *   first r); DINO_FACTOR_AUTO takes the dual form when d_y < r. The order of the
+ *   factorised matrix must not exceed 512.
  */
 #define DINO_PREC_F64 0
 #define DINO_PREC_BF16 1
+#define DINO_FACTOR_PRIMAL 0
+#define DINO_FACTOR_DUAL 1
+#define DINO_FACTOR_AUTO 2
 typedef struct {
     int32_t n_chains;
     int32_t d_y;
     int32_t precision;
     int32_t track_complement;
     int32_t trace_capacity;
-    int32_t reserved;
+    int32_t factorization;
     double dt;
     uint64_t seed;
     uint64_t request_id;
@@ -155,7 +164,9 @@ dino_status dino_read_states(dino_problem* p, double* x, float* z);
 
 /* Host copies of the cache at the current states: misfit (n_chains), reduced
  * ppg (n_chains x r) and the lower Cholesky factor of I + H (n_chains x r x r,
- * upper triangle unspecified). Any pointer may be NULL. */
+ * upper triangle unspecified; in the dual form the factor of I + B B^T, d_y x d_y
+ * with row stride d_y, in the first d_y^2 entries of each chain's r x r block). Any
+ * pointer may be NULL. */
 dino_status dino_read_cache(dino_problem* p, double* phi, double* g, double* L);
 
 /* Per-chain accepted moves and numerical failures since init, and the number of
@@ -201,7 +212,10 @@ const char* dino_stage_name(int stage);
 /* Geometry at reduced points x (n x r): network output f (n x d_y), surrogate
  * misfit phi (n), reduced ppg g (n x r), reduced ppGNH H (n x r x r, full),
  * lower Cholesky factor L of I + H (n x r x r), logdet = sum log L_ii (n) and
- * ok (n int32: 1 if finite and positive definite). H may be NULL. */
+ * ok (n int32: 1 if finite and positive definite). H may be NULL. In the dual form
+ * L receives the factor of I + B B^T (d_y x d_y, row stride d_y, in the first d_y^2
+ * entries of each chain's block; log det is the same) and H is B^T B formed from the
+ * stored B. dino_eval_propose and dino_eval_log_rho serve the primal form. */
 dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* f, double* phi, double* g,
                                double* H, double* L, double* logdet, int32_t* ok, void* stream);
 
@@ -269,7 +283,7 @@ typedef struct {
     int32_t steps_per_quantum;                /* steps enqueued per pool between scheduling passes */
     int32_t precision;                        /* DINO_PREC_F64 or DINO_PREC_BF16 */
     int32_t track_complement;                 /* keep and move the complement state */
-    int32_t reserved;
+    int32_t factorization;                    /* DINO_FACTOR_* of every pool (AUTO: per bucket) */
     double dt;                                /* step size of every request */
     double hbm_budget_bytes;                  /* > 0: DINO_ENOMEM if the pools need more */
 } dino_server_cfg;

@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
+FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
 
 
 class DinoError(RuntimeError):
@@ -28,7 +29,7 @@ class ProblemDesc(ct.Structure):
         ("precision", ct.c_int32),
         ("track_complement", ct.c_int32),
         ("trace_capacity", ct.c_int32),
-        ("reserved", ct.c_int32),
+        ("factorization", ct.c_int32),
         ("dt", ct.c_double),
         ("seed", ct.c_uint64),
         ("request_id", ct.c_uint64),
@@ -47,7 +48,7 @@ class ServerCfg(ct.Structure):
         ("steps_per_quantum", ct.c_int32),
         ("precision", ct.c_int32),
         ("track_complement", ct.c_int32),
-        ("reserved", ct.c_int32),
+        ("factorization", ct.c_int32),
         ("dt", ct.c_double),
         ("hbm_budget_bytes", ct.c_double),
     ]

@@ -101,14 +101,15 @@ class Problem:
 
     def __init__(self, ctx: Context, n_chains: int, y, noise_var, dt: float, seed: int = 0, request_id: int = 0,
                  precision: str = "f64", track_complement: bool = True, trace_capacity: int = 0,
-                 torch_workspace: bool = True):
+                 torch_workspace: bool = True, factorization: str = "primal"):
         self.ctx = ctx
         self.lib = ctx.lib
         y = np.ascontiguousarray(y, dtype=np.float64)
         nv = np.ascontiguousarray(noise_var, dtype=np.float64)
         self.desc = ProblemDesc(n_chains=n_chains, d_y=len(y), precision=_lib.PRECISIONS[precision],
                                 track_complement=1 if track_complement else 0, trace_capacity=trace_capacity,
-                                reserved=0, dt=dt, seed=seed, request_id=request_id)
+                                factorization=_lib.FACTORIZATIONS[factorization], dt=dt, seed=seed,
+                                request_id=request_id)
         self.h = None
         nbytes = ct.c_size_t()
         # the library validates the descriptor against the context's prior and network
@@ -254,7 +255,8 @@ class Server:
     (seed, request_id), prior initial states) and returns its posterior mean field."""
 
     def __init__(self, ctx: Context, buckets, max_requests: int, steps_per_quantum: int, dt: float,
-                 precision: str = "bf16", track_complement: bool = True, hbm_budget_bytes: float = 0.0):
+                 precision: str = "bf16", track_complement: bool = True, hbm_budget_bytes: float = 0.0,
+                 factorization: str = "auto"):
         self.ctx = ctx
         self.lib = ctx.lib
         cfg = _lib.ServerCfg()
@@ -266,6 +268,7 @@ class Server:
         cfg.steps_per_quantum = steps_per_quantum
         cfg.precision = _lib.PRECISIONS[precision]
         cfg.track_complement = 1 if track_complement else 0
+        cfg.factorization = _lib.FACTORIZATIONS[factorization]
         cfg.dt = dt
         cfg.hbm_budget_bytes = hbm_budget_bytes
         h = ct.c_void_p()

@@ -142,6 +142,10 @@ __device__ __forceinline__ int32_t chain_state(const ChainMeta& m, int c) {
     return m.state ? m.state[c] : (int32_t)CHAIN_LIVE;
 }
 
+// FP64 value of a stored Jacobian entry (FP64 path or BF16 path).
+__device__ __forceinline__ double to_d(double v) { return v; }
+__device__ __forceinline__ double to_d(__hip_bfloat16 v) { return (double)__bfloat162float(v); }
+
 // ----------------------------------------------------------------------------------
 // Host-side objects.
 struct Layer {
@@ -250,7 +254,13 @@ struct dino_problem {
     float* f32 = nullptr;     // C x d_y FP32 network output
     float* e32 = nullptr;     // C x d_y whitened residual
     float* d32 = nullptr;     // n_act x C x ldd32 gelu'(z), zero padded
-    __hip_bfloat16* B16 = nullptr;  // C x d_y x r BF16 whitened Jacobian
+    __hip_bfloat16* B16 = nullptr;  // C x d_y x r BF16 whitened Jacobian (at the proposal)
+    // observation-space (dual) form: the state's Jacobian; the factor buffers hold the
+    // Cholesky factors of I + B B^T (d_y x d_y) instead of I + H
+    bool dual = false;
+    int kdim = 0;                   // order of the factorised matrix: r, or d_y in the dual form
+    __hip_bfloat16* Bs16 = nullptr; // C x d_y x ldb (mixed path)
+    double* Bs64 = nullptr;         // C x d_y x r (FP64 path)
     // trace
     float* xtrace = nullptr;  // capacity x C x r
     double* phitrace = nullptr;
@@ -294,6 +304,15 @@ void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x
                     const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
                     const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st);
 void launch_complement(dino_problem* p, int n, hipStream_t st);
+// dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
+void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
+void launch_accept_dual(dino_problem* p, int n, hipStream_t st);
+void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st);
+void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
+                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
+void launch_gram_f64(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,
+                     int slot_xor, long slot_stride, hipStream_t st);
+void launch_btb(dino_problem* p, int n, double* H, hipStream_t st);
 void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st);
 void launch_normals(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count, double* out,
                     hipStream_t st);

@@ -595,6 +595,256 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     }
 }
 
+// ---------------------------------------------------------------------------------
+// Observation-space (dual) form for d_y < r. With B = Gamma^-1/2 J (d_y x r) and the
+// Cholesky factor K of M = I + B B^T (d_y x d_y), (I + H)^-1 v = v - B^T M^-1 B v
+// (Woodbury), log det (I + H) = log det M, and the proposal noise is drawn as
+// beta (I + H)^-1 (xi_1 + B^T xi_2) (xi_1 in R^r, xi_2 in R^d_y: the first r and the
+// next d_y normals of the proposal stream), which has covariance beta^2 (I + H)^-1.
+
+// y_i = sum_j B[i][j] v_j (i < dy): one wave per row, lanes over j.
+template <typename TB>
+__device__ void b_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* v, double* y) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int i = wave; i < dy; i += TPB / 64) {
+        double acc = 0.0;
+        for (int j = lane; j < r; j += 64) acc += to_d(B[(long)i * ldb + j]) * v[j];
+        acc = wave_sum(acc);
+        if (lane == 0) y[i] = acc;
+    }
+    __syncthreads();
+}
+
+// w_j = sum_i B[i][j] z_i (j < r): threads over j.
+template <typename TB>
+__device__ void bt_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* z, double* w) {
+    for (int j = threadIdx.x; j < r; j += TPB) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < dy; ++i) acc += to_d(B[(long)i * ldb + j]) * z[i];
+        w[j] = acc;
+    }
+    __syncthreads();
+}
+
+// Scratch of the dual kernels: vectors of length r and d_y in dynamic LDS, followed
+// (BF16 path) by the chain's B (d_y x ldb), staged once so that every product reads LDS.
+constexpr int DU_NR = 8, DU_NY = 6;
+__host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool stage_bf16) {
+    const size_t b = stage_bf16 ? ((size_t)dy * ldb * sizeof(__hip_bfloat16) + 7) / 8 : 0;
+    return (size_t)DU_NR * r + (size_t)DU_NY * dy + SB + (size_t)8 * SB + TPB / 64 + b;
+}
+
+// BF16 B rows are copied to LDS (16-byte moves) and used from there; FP64 B is read
+// from global memory as it is.
+__device__ __forceinline__ const double* stage_b(const double* Bg, int, int, double*) { return Bg; }
+__device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* Bg, int dy, int ldb, double* lds) {
+    __hip_bfloat16* Bl = reinterpret_cast<__hip_bfloat16*>(lds);
+    const long n16 = (long)dy * ldb / 8;  // ldb is a multiple of 32
+    const uint4* src = reinterpret_cast<const uint4*>(Bg);
+    uint4* dst = reinterpret_cast<uint4*>(Bl);
+    for (long e = threadIdx.x; e < n16; e += TPB) dst[e] = src[e];
+    __syncthreads();
+    return Bl;
+}
+
+// log rho_0(a -> b) (Sec. 5.4) with the cache (g_a, B_a, K_a, logdet_a) of a:
+//   -(dt/8) v^T (I + H)^-1 v + (sqrt(dt)/2) mhat^T v - mhat^T H mhat / 2 + logdet,
+// v = H a - g_a, mhat = (b - s a)/beta, with v^T (I + H)^-1 v = |v|^2 - |K^-1 B v|^2 and
+// mhat^T H mhat = |B mhat|^2. Vectors in R: v, mh, and in Y: t1, t2, z.
+template <typename TB>
+__device__ double dual_rho0(const TB* Ba, int ldb, const double* Ka, const double* invd, int r, int dy, double dt,
+                            double s, double beta, const double* a, const double* b, const double* ga,
+                            double logdet_a, double* v, double* mh, double* t1, double* t2, double* z,
+                            double* acc_s, double* red) {
+    const int tid = threadIdx.x;
+    b_times(Ba, dy, r, ldb, a, t1);
+    bt_times(Ba, dy, r, ldb, t1, v);
+    for (int j = tid; j < r; j += TPB) {
+        v[j] -= ga[j];
+        mh[j] = (b[j] - s * a[j]) / beta;
+    }
+    __syncthreads();
+    b_times(Ba, dy, r, ldb, v, t2);
+    l_solve(Ka, invd, dy, t2, z, acc_s);
+    b_times(Ba, dy, r, ldb, mh, t1);
+    double vv = 0.0, mv = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        vv += v[j] * v[j];
+        mv += mh[j] * v[j];
+    }
+    double zz = 0.0, bm = 0.0;
+    for (int i = tid; i < dy; i += TPB) {
+        zz += z[i] * z[i];
+        bm += t1[i] * t1[i];
+    }
+    vv = block_sum(vv, red);
+    mv = block_sum(mv, red);
+    zz = block_sum(zz, red);
+    bm = block_sum(bm, red);
+    return -(dt / 8.0) * (vv - zz) + 0.5 * sqrt(dt) * mv - 0.5 * bm + logdet_a;
+}
+
+// Proposal: u = beta (xi_1 + B^T xi_2) - (1 - s)(x + g),  xp = x + (I + H)^-1 u,
+// and lfwd = log rho_0(x -> xp) with the cache of x. B: the state's B (C x dy x ldb).
+template <typename TB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta, ChainMeta meta,
+                         const double* __restrict__ x, const double* __restrict__ g, const TB* __restrict__ B,
+                         const double* Kbuf, long strideK, const int32_t* slot, int slot_xor, long slot_stride,
+                         const double* __restrict__ logdet, double* __restrict__ xp, double* __restrict__ lfwd) {
+    extern __shared__ double dyn[];
+    double* R = dyn;
+    double *xs = R, *gs = R + r, *u = R + 2 * r, *w = R + 3 * r, *v = R + 4 * r, *mh = R + 5 * r,
+           *xi1 = R + 6 * r, *xn = R + 7 * r;
+    double* Y = dyn + (size_t)DU_NR * r;
+    double *xi2 = Y, *y = Y + dy, *z1 = Y + 2 * dy, *invd = Y + 3 * dy, *t1 = Y + 4 * dy, *t2 = Y + 5 * dy;
+    double* acc = Y + (size_t)DU_NY * dy;
+    double* part = acc + SB;
+    double* red = part + 8 * SB;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) return;
+    if (state == CHAIN_FRESH) {
+        for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
+            double nv[4];
+            philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_INIT_X, 0, (uint64_t)meta.index[c], nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * b4 + q < r) xp[(long)c * r + 4 * b4 + q] = nv[q];
+        }
+        if (lfwd && tid == 0) lfwd[c] = 0.0;
+        return;
+    }
+    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + TPB / 64);
+    const double* Kc = Kbuf + (long)c * strideK + slot_offset(slot, slot_xor, slot_stride, c);
+    load_inv_diag(Kc, dy, invd);
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        gs[j] = g[(long)c * r + j];
+    }
+    {
+        const uint64_t k0 = meta.key0[c], k1 = meta.key1[c];
+        const uint64_t step = (uint64_t)meta.step[c], chain = (uint64_t)meta.index[c];
+        for (int b4 = tid; 4 * b4 < r + dy; b4 += TPB) {
+            double nv[4];
+            philox_normals4(k0, k1, (uint64_t)b4, STREAM_XI, step, chain, nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * b4 + q;
+                if (k < r) xi1[k] = nv[q];
+                else if (k < r + dy) xi2[k - r] = nv[q];
+            }
+        }
+    }
+    __syncthreads();
+    bt_times(Bc, dy, r, ldb, xi2, w);
+    for (int j = tid; j < r; j += TPB) u[j] = beta * (xi1[j] + w[j]) - (1.0 - s) * (xs[j] + gs[j]);
+    __syncthreads();
+    b_times(Bc, dy, r, ldb, u, y);
+    l_solve(Kc, invd, dy, y, z1, acc);
+    lt_solve(Kc, invd, dy, z1, t1, part);
+    bt_times(Bc, dy, r, ldb, t1, w);
+    for (int j = tid; j < r; j += TPB) {
+        xn[j] = xs[j] + u[j] - w[j];
+        xp[(long)c * r + j] = xn[j];
+    }
+    __syncthreads();
+    if (lfwd) {
+        const double l = dual_rho0(Bc, ldb, Kc, invd, r, dy, dt, s, beta, xs, xn, gs, logdet[c], v, mh, t1, t2, z1,
+                                   acc, red);
+        if (tid == 0) lfwd[c] = l;
+    }
+}
+
+// MH decision of the dual form: reverse term with the proposal's cache (B of the
+// proposal, its factor in the other half of Kbuf); on acceptance the proposal's B
+// becomes the state's (copied), the factor half flips.
+template <typename TB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta, ChainMeta meta, double* x, double* g,
+                        double* phi, double* logdet, const double* Kbuf, long half, int32_t* cur, const double* xp,
+                        const double* gp, const double* phip, const double* logdetp, const int32_t* okp,
+                        const double* lfwd, const TB* __restrict__ Bp, TB* __restrict__ Bs, int64_t* accepts,
+                        int64_t* failures, int32_t* accflag) {
+    extern __shared__ double dyn[];
+    double* R = dyn;
+    double *xs = R, *ps = R + r, *ga = R + 2 * r, *v = R + 3 * r, *mh = R + 4 * r;
+    double* Y = dyn + (size_t)DU_NR * r;
+    double *invd = Y, *t1 = Y + dy, *t2 = Y + 2 * dy, *z = Y + 3 * dy;
+    double* acc = Y + (size_t)DU_NY * dy;
+    double* red = acc + 9 * SB;
+    __shared__ int decision;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const long kk = (long)dy * dy;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) {
+        if (tid == 0) accflag[c] = 0;
+        return;
+    }
+    const int other = cur[c] ^ 1;
+    const double* Kp = Kbuf + (long)other * half + c * kk;
+    const TB* Bpg = Bp + (long)c * dy * ldb;
+    const TB* Bpc = stage_b(Bpg, dy, ldb, red + TPB / 64);
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        ps[j] = xp[(long)c * r + j];
+        ga[j] = gp[(long)c * r + j];
+    }
+    __syncthreads();
+    const int okc = okp[c];
+    if (state == CHAIN_FRESH) {
+        if (tid == 0) {
+            if (!okc) failures[c] += 1;
+            phi[c] = phip[c];
+            logdet[c] = logdetp[c];
+            cur[c] = other;
+            decision = 1;
+            accflag[c] = 2;
+        }
+        __syncthreads();
+    } else {
+        double rev = 0.0;
+        if (okc) {
+            load_inv_diag(Kp, dy, invd);
+            rev = dual_rho0(Bpc, ldb, Kp, invd, r, dy, dt, s, beta, ps, xs, ga, logdetp[c], v, mh, t1, t2, z, acc,
+                            red);
+        }
+        if (tid == 0) {
+            const double lr = phi[c] - phip[c] + rev - lfwd[c];
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)meta.step[c],
+                                            (uint64_t)meta.index[c]);
+            const bool good = okc && isfinite(lr);
+            const bool accept = good && (log(u) <= lr);
+            decision = accept ? 1 : 0;
+            if (!good) failures[c] += 1;
+            if (accept) {
+                accepts[c] += 1;
+                phi[c] = phip[c];
+                logdet[c] = logdetp[c];
+                cur[c] = other;
+            }
+            accflag[c] = decision;
+        }
+    }
+    __syncthreads();
+    if (decision) {
+        for (int j = tid; j < r; j += TPB) {
+            x[(long)c * r + j] = ps[j];
+            g[(long)c * r + j] = ga[j];
+        }
+        TB* Bsc = Bs + (long)c * dy * ldb;
+        for (long e = tid; e < (long)dy * ldb; e += TPB) Bsc[e] = Bpg[e];
+    }
+}
+
+// Copies the Jacobian of every chain (n x dy x ldb values) into the state's buffer.
+template <typename TB>
+__global__ void copy_b_kernel(long count, const TB* __restrict__ src, TB* __restrict__ dst) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count; e += (long)gridDim.x * blockDim.x)
+        dst[e] = src[e];
+}
+
 // pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state).
 __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta, ChainMeta meta,
                                                          const int32_t* __restrict__ accflag, float* z) {
@@ -792,6 +1042,56 @@ void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x
     allow_large_lds(log_rho_kernel, attr);
     hipLaunchKernelGGL(log_rho_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s,
                        p->beta, x, phi_x, g_x, L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, out);
+    DINO_HIP(hipGetLastError());
+}
+
+template <typename TB>
+static void propose_dual_t(dino_problem* p, int n, const TB* Bs, int ldb, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(propose_dual_kernel<TB>, attr);
+    const long kk = (long)p->d_y * p->d_y;
+    const bool bf = sizeof(TB) == 2;
+    hipLaunchKernelGGL(propose_dual_kernel<TB>, dim3(n), dim3(TPB),
+                       dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
+                       st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, Bs, p->Lbuf, kk,
+                       p->cur, 0, (long)p->C * kk, p->logdet, p->xp, p->lfwd);
+    DINO_HIP(hipGetLastError());
+}
+
+template <typename TB>
+static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(accept_dual_kernel<TB>, attr);
+    const long half = (long)p->C * p->d_y * p->d_y;
+    const bool bf = sizeof(TB) == 2;
+    hipLaunchKernelGGL(accept_dual_kernel<TB>, dim3(n), dim3(TPB),
+                       dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
+                       st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, p->phi, p->logdet,
+                       p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp, p->lfwd, Bp, Bs,
+                       p->accepts, p->failures, p->acc);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_propose_dual(dino_problem* p, int n, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) propose_dual_t<double>(p, n, p->Bs64, p->r, st);
+    else propose_dual_t<__hip_bfloat16>(p, n, p->Bs16, (p->r + 31) / 32 * 32, st);
+}
+
+void launch_accept_dual(dino_problem* p, int n, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, st);
+    else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, st);
+}
+
+void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) {
+        const long count = (long)n * p->d_y * p->r;
+        hipLaunchKernelGGL(copy_b_kernel<double>, dim3((int)std::min<long>((count + 255) / 256, 8192)), dim3(256), 0,
+                           st, count, (const double*)p->Bj, p->Bs64);
+    } else {
+        const long count = (long)n * p->d_y * ((p->r + 31) / 32 * 32);
+        hipLaunchKernelGGL(copy_b_kernel<__hip_bfloat16>, dim3((int)std::min<long>((count + 255) / 256, 8192)),
+                           dim3(256), 0, st, count, (const __hip_bfloat16*)p->B16, p->Bs16);
+    }
     DINO_HIP(hipGetLastError());
 }
 

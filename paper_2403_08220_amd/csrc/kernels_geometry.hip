@@ -321,6 +321,56 @@ static void fwd_layer(int M, int K, int N, const T* in, int ldin, const T* W, co
                            in, ldin, W, b, kind, out, ldout, dprime, ldd);
 }
 
+// Observation-space Gram matrix I + B B^T of the FP64 path (lower triangle, d_y x d_y)
+// from B = Gamma^-1/2 J (d_y x r per chain); one block per chain.
+__global__ __launch_bounds__(256) void gram_f64_kernel(int dy, int r, const double* __restrict__ B, double* A,
+                                                       long strideA, const int32_t* slot, int slot_xor,
+                                                       long slot_stride) {
+    const int c = blockIdx.x;
+    const double* Bc = B + (long)c * dy * r;
+    double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    const int npairs = dy * (dy + 1) / 2;
+    for (int e = threadIdx.x; e < npairs; e += 256) {
+        int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        const int k = e - i * (i + 1) / 2;
+        double acc = (i == k) ? 1.0 : 0.0;
+        for (int j = 0; j < r; ++j) acc += Bc[(long)i * r + j] * Bc[(long)k * r + j];
+        Ac[(long)i * dy + k] = acc;
+    }
+}
+
+// H = B^T B (full r x r, FP64 products of the stored B values) per chain.
+template <typename TB>
+__global__ void btb_kernel(int dy, int r, int ldb, const TB* __restrict__ B, double* __restrict__ H) {
+    const int c = blockIdx.y;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= r * r) return;
+    const int j = e / r, k = e % r;
+    const TB* Bc = B + (long)c * dy * ldb;
+    double acc = 0.0;
+    for (int i = 0; i < dy; ++i) acc += to_d(Bc[(long)i * ldb + j]) * to_d(Bc[(long)i * ldb + k]);
+    H[(long)c * r * r + e] = acc;
+}
+
+void launch_gram_f64(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,
+                     int slot_xor, long slot_stride, hipStream_t st) {
+    hipLaunchKernelGGL(gram_f64_kernel, dim3(n), dim3(256), 0, st, p->d_y, p->r, B, A, strideA, slot, slot_xor,
+                       slot_stride);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_btb(dino_problem* p, int n, double* H, hipStream_t st) {
+    const dim3 grid((p->r * p->r + 255) / 256, n);
+    if (p->desc.precision == DINO_PREC_F64)
+        hipLaunchKernelGGL(btb_kernel<double>, grid, dim3(256), 0, st, p->d_y, p->r, p->r, (const double*)p->Bj, H);
+    else
+        hipLaunchKernelGGL(btb_kernel<__hip_bfloat16>, grid, dim3(256), 0, st, p->d_y, p->r, (p->r + 31) / 32 * 32,
+                           (const __hip_bfloat16*)p->B16, H);
+    DINO_HIP(hipGetLastError());
+}
+
 void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
     const int L = (int)ctx->layers.size();

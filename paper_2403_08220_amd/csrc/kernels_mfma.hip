@@ -386,6 +386,72 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
     else launch_sweep_t<16>(a, st);
 }
 
+// Observation-space Gram matrix I + B B^T (d_y x d_y, lower 32x32 blocks by MFMA, FP32
+// accumulation, written in FP64 for the Cholesky factorisation) and the reduced ppg
+// g = B^T e (FP64), one block per chain. The rows of B are the A and B operands of
+// v_mfma_f32_32x32x16_bf16 as they are (K = the reduced index): no transpose.
+__global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ldt,
+                                                            const __hip_bfloat16* __restrict__ B,
+                                                            const float* __restrict__ e, double* A, long strideA,
+                                                            const int32_t* slot, int slot_xor, long slot_stride,
+                                                            double* __restrict__ g) {
+    extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt
+    const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
+    for (int e2 = tid; e2 < dy_pad * k_pad; e2 += HES_TPB) {
+        const int i = e2 / k_pad, j = e2 % k_pad;
+        bs[(long)i * ldt + j] = (i < dy && j < r) ? Bc[(long)i * ldb + j] : __float2bfloat16(0.f);
+    }
+    __syncthreads();
+    for (int j = tid; j < r; j += HES_TPB) {
+        double acc = 0.0;
+        for (int i = 0; i < dy; ++i) acc += (double)__bfloat162float(bs[(long)i * ldt + j]) * (double)e[(long)c * dy + i];
+        g[(long)c * r + j] = acc;
+    }
+    double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    const int nl = lane & 31, h = lane >> 5;
+    const int nmb = dy_pad / 32, nkc = k_pad / 16;
+    const int nblocks = nmb * (nmb + 1) / 2;
+    for (int bidx = wave; bidx < nblocks; bidx += HES_TPB / 64) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= bidx) ++bi;
+        const int bk = bidx - bi * (bi + 1) / 2;
+        f32x16 acc;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+        for (int kc = 0; kc < nkc; ++kc) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(bs + (long)(32 * bi + nl) * ldt + 16 * kc + 8 * h);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(bs + (long)(32 * bk + nl) * ldt + 16 * kc + 8 * h);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        const int col = 32 * bk + nl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int row = 32 * bi + 8 * (j >> 2) + 4 * h + (j & 3);
+            if (row < dy && col <= row) Ac[(long)row * dy + col] = (double)acc[j] + (row == col ? 1.0 : 0.0);
+        }
+    }
+}
+
+void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
+                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
+    const int r = p->r, dy = p->d_y;
+    const int dy_pad = (dy + 31) / 32 * 32;
+    const int k_pad = (r + 15) / 16 * 16;
+    const int ldt = k_pad + 8;  // 16-byte aligned rows, shifted banks
+    const size_t lds = (size_t)dy_pad * ldt * sizeof(__hip_bfloat16);
+    DINO_REQUIRE(lds <= 160 * 1024, DINO_EINVAL, "d_y x r too large for the LDS-staged Gram matrix");
+    static bool attr = false;
+    if (!attr) {
+        DINO_HIP(hipFuncSetAttribute((const void*)gram_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024));
+        attr = true;
+    }
+    hipLaunchKernelGGL(gram_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, (r + 31) / 32 * 32, dy_pad, k_pad,
+                       ldt, B, e, A, strideA, slot, slot_xor, slot_stride, g);
+    DINO_HIP(hipGetLastError());
+}
+
 void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
                       const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
     const int r = p->r, dy = p->d_y;

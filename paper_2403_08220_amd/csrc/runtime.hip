@@ -105,7 +105,7 @@ static void layout(dino_problem* p, Carver& cv) {
     p->g = cv.take<double>(C * r);
     p->phi = cv.take<double>(C);
     p->logdet = cv.take<double>(C);
-    p->Lbuf = cv.take<double>(2 * C * r * r);
+    p->Lbuf = cv.take<double>(2 * C * (size_t)p->kdim * p->kdim);
     p->cur = cv.take<int32_t>(C);
     p->z = p->desc.track_complement ? cv.take<float>(C * (size_t)ldz_of(p->d_perp)) : nullptr;
     p->accepts = cv.take<int64_t>(C);
@@ -134,7 +134,9 @@ static void layout(dino_problem* p, Carver& cv) {
         p->e32 = cv.take<float>(C * dy);
         p->d32 = cv.take<float>((size_t)std::max(p->n_act, 1) * C * p->ldd32);
         p->B16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));  // rows padded to 32
+        if (p->dual) p->Bs16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));
     }
+    if (p->dual && p->desc.precision == DINO_PREC_F64) p->Bs64 = cv.take<double>(C * dy * r);
     const size_t cap = (size_t)std::max(p->desc.trace_capacity, 0);
     p->xtrace = cap ? cv.take<float>(cap * C * r) : nullptr;
     p->phitrace = cap ? cv.take<double>(cap * C) : nullptr;
@@ -152,6 +154,11 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
                  "unknown precision");
     DINO_REQUIRE(d->trace_capacity >= 0, DINO_EINVAL, "negative trace capacity");
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
+    DINO_REQUIRE(d->factorization >= DINO_FACTOR_PRIMAL && d->factorization <= DINO_FACTOR_AUTO, DINO_EINVAL,
+                 "unknown factorization");
+    const bool dual = d->factorization == DINO_FACTOR_DUAL ||
+                      (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
+    DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
 }
 
 static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d) {
@@ -164,6 +171,8 @@ static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d
     p->d_perp = p->d_m - p->r;
     p->wmax = ctx->max_width;
     p->n_act = ctx->n_act;
+    p->dual = d->factorization == DINO_FACTOR_DUAL || (d->factorization == DINO_FACTOR_AUTO && d->d_y < p->r);
+    p->kdim = p->dual ? p->d_y : p->r;
     p->s = (4.0 - d->dt) / (4.0 + d->dt);
     p->beta = std::sqrt(1.0 - p->s * p->s);
 }
@@ -191,12 +200,16 @@ static void stage_misfit(dino_problem* p, int n, const double* f64, double* phi,
     else launch_residual(p, n, p->f32, p->e32, phi, st);
 }
 
+// A receives I + H (r x r), or in the dual form I + B B^T (d_y x d_y, row stride d_y).
 static void stage_hessian(dino_problem* p, int n, double* g, double* A, long strideA, const int32_t* slot,
                           int slot_xor, long slot_stride, hipStream_t st) {
-    if (p->desc.precision == DINO_PREC_F64)
-        launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
-    else
-        launch_hess_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
+    if (p->desc.precision == DINO_PREC_F64) {
+        if (p->dual) launch_gram_f64(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, st);
+        else launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
+    } else {
+        if (p->dual) launch_gram_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
+        else launch_hess_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
+    }
 }
 
 static void geometry_at(dino_problem* p, int n, const double* x, double* f, double* phi, double* g, double* A,
@@ -206,7 +219,7 @@ static void geometry_at(dino_problem* p, int n, const double* x, double* f, doub
     stage_jacobian(p, n, st);
     stage_misfit(p, n, f, phi, g, st);  // the FP64 ppg reads the Jacobian
     stage_hessian(p, n, g, A, strideA, slot, slot_xor, slot_stride, st);
-    launch_cholesky_slot(n, p->r, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
+    launch_cholesky_slot(n, p->kdim, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
 }
 
 }  // namespace dino
@@ -588,8 +601,9 @@ dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0,
         DINO_HIP(hipMemsetAsync(p->cur, 0, sizeof(int32_t) * C, st));
         DINO_HIP(hipMemsetAsync(p->accepts, 0, sizeof(int64_t) * C, st));
         DINO_HIP(hipMemsetAsync(p->failures, 0, sizeof(int64_t) * C, st));
-        const long rr = (long)r * r;
-        geometry_at(p, p->C, p->x, p->f, p->phi, p->g, p->Lbuf, rr, nullptr, 0, 0, p->logdet, p->okp, st);
+        const long kk = (long)p->kdim * p->kdim;
+        geometry_at(p, p->C, p->x, p->f, p->phi, p->g, p->Lbuf, kk, nullptr, 0, 0, p->logdet, p->okp, st);
+        if (p->dual) launch_keep_jacobian(p, p->C, st);
         DINO_HIP(hipStreamSynchronize(st));
         p->step = 0;
         p->recorded = 0;
@@ -620,7 +634,7 @@ namespace dino {
 // n_steps transitions of chains [0, n) on stream st (the body of dino_step; the serving
 // pools call it with n = the highest occupied slot + 1).
 void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
-    const long rr = (long)p->r * p->r;
+    const long rr = (long)p->kdim * p->kdim;
     const long half = (long)p->C * rr;
     const int L = (int)p->ctx->layers.size();
     const bool f64 = p->desc.precision == DINO_PREC_F64;
@@ -630,8 +644,11 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     };
     for (int k = 0; k < n_steps; ++k) {
         mark(0);
-        launch_propose_slot(p, n, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, true, p->xp, p->lfwd,
-                            p->logdet, st);
+        if (p->dual)
+            launch_propose_dual(p, n, st);
+        else
+            launch_propose_slot(p, n, p->x, p->g, p->Lbuf, rr, p->cur, 0, half, nullptr, true, p->xp, p->lfwd,
+                                p->logdet, st);
         mark(1);
         stage_forward(p, n, p->xp, p->f, st);
         mark(2);
@@ -641,9 +658,10 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
         mark(4);
         stage_hessian(p, n, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
         mark(5);
-        launch_cholesky_slot(n, p->r, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
+        launch_cholesky_slot(n, p->kdim, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
         mark(6);
-        launch_accept(p, n, st);
+        if (p->dual) launch_accept_dual(p, n, st);
+        else launch_accept(p, n, st);
         mark(7);
         launch_complement(p, n, st);
         mark(8);
@@ -737,9 +755,9 @@ dino_status dino_read_cache(dino_problem* p, double* phi, double* g, double* L) 
         if (L) {
             std::vector<int32_t> cur(p->C);
             DINO_HIP(hipMemcpy(cur.data(), p->cur, sizeof(int32_t) * p->C, hipMemcpyDeviceToHost));
-            const size_t rr = (size_t)p->r * p->r;
+            const size_t rr = (size_t)p->r * p->r, kk = (size_t)p->kdim * p->kdim;
             for (int c = 0; c < p->C; ++c)
-                DINO_HIP(hipMemcpy(L + c * rr, p->Lbuf + ((size_t)cur[c] * p->C + c) * rr, sizeof(double) * rr,
+                DINO_HIP(hipMemcpy(L + c * rr, p->Lbuf + ((size_t)cur[c] * p->C + c) * kk, sizeof(double) * kk,
                                    hipMemcpyDeviceToHost));
         }
     });
@@ -821,8 +839,11 @@ dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* 
         stage_misfit(p, n, f, phi, g, st);
         stage_hessian(p, n, g, L, rr, nullptr, 0, 0, st);
         if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
-        if (H) launch_sym_from_lower(n, p->r, L, H, st);
-        launch_cholesky_slot(n, p->r, L, rr, nullptr, 0, 0, logdet, ok, st);
+        if (H) {
+            if (p->dual) launch_btb(p, n, H, st);
+            else launch_sym_from_lower(n, p->r, L, H, st);
+        }
+        launch_cholesky_slot(n, p->kdim, L, rr, nullptr, 0, 0, logdet, ok, st);
         p->last_stream = st;
     });
 }
@@ -831,6 +852,7 @@ dino_status dino_eval_propose(dino_problem* p, int n, const double* x, const dou
                               const double* xi, double* xp, void* stream) {
     return guarded([&] {
         DINO_REQUIRE(p && x && g && L && xi && xp, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(!p->dual, DINO_EINVAL, "dino_eval_propose serves the primal form");
         DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
         DINO_HIP(hipSetDevice(p->ctx->device));
         hipStream_t st = as_stream(stream);
@@ -846,6 +868,7 @@ dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const dou
     return guarded([&] {
         DINO_REQUIRE(p && x && phi_x && g_x && L_x && logdet_x && xp && phi_p && g_p && L_p && logdet_p && log_rho,
                      DINO_EINVAL, "null argument");
+        DINO_REQUIRE(!p->dual, DINO_EINVAL, "dino_eval_log_rho serves the primal form");
         DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
         DINO_HIP(hipSetDevice(p->ctx->device));
         hipStream_t st = as_stream(stream);

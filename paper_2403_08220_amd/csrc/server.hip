@@ -309,6 +309,7 @@ dino_status dino_server_create(dino_ctx* ctx, const dino_server_cfg* cfg, dino_s
                 d.d_y = cfg->bucket_dy[b];
                 d.precision = cfg->precision;
                 d.track_complement = cfg->track_complement;
+                d.factorization = cfg->factorization;
                 d.dt = cfg->dt;
                 Pool pl;
                 pl.dy = d.d_y;

@@ -1,0 +1,115 @@
+"""Observation-space (dual) form on the device against the oracle's dual mode.
+
+The device factorises I + B B^T (d_y x d_y) and applies (I + H)^-1 by Woodbury; the
+oracle draws the same noise (I + H)^-1 (xi_1 + B^T xi_2) with a dense r x r solve and
+evaluates the paper-form ratio with the eigendecomposition of H, so the two share
+nothing but the law. Tolerances as for the primal FP64 path: factor and geometry
+1e-10 relative, identical decisions on coupled streams, states 1e-9.
+"""
+import numpy as np
+import pytest
+
+from oracle import mcmc
+from tests.helpers import device_problem, make_case, rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def dual_case(C, **kw):
+    case = make_case("tiny", chains=C, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
+                     bias_scale=0.3, noise_scale=0.2, **kw)
+    case["prob"].factor = "dual"
+    return case
+
+
+def run_coupled(case, n_steps, precision="f64", chains_idx=None):
+    ctx, p = device_problem(case, precision=precision, factorization="dual")
+    p.init(case["x0"], case["z0"])
+    p.step(n_steps)
+    x, z = p.states()
+    acc, fail, steps = p.diagnostics()
+    assert steps == n_steps
+    idx = np.arange(case["C"]) if chains_idx is None else np.asarray(chains_idx)
+    st = mcmc.init_state(case["prob"], case["x0"][idx], case["z0"][idx].astype(np.float64), chains=idx)
+    mcmc.run(case["prob"], st, n_steps, trace=False)
+    return dict(x=x[idx], z=z[idx], acc=acc[idx], fail=fail[idx], ox=st.x, oz=st.z, oacc=st.accepts, p=p, ctx=ctx)
+
+
+def test_dual_geometry_parity():
+    case = dual_case(37)
+    print("dual geometry", flush=True)
+    ctx, p = device_problem(case, factorization="dual")
+    x = np.random.default_rng(1).standard_normal((37, 40))
+    got = {k: v.cpu().numpy() for k, v in p.eval_geometry(torch.tensor(x, device="cuda:0")).items()}
+    ref = mcmc.geometry(case["prob"], x)
+    dy = case["prob"].d_y
+    K = got["L"].reshape(37, -1)[:, : dy * dy].reshape(37, dy, dy)
+    Kref = np.linalg.cholesky(np.eye(dy)[None] + np.einsum("cir,ckr->cik", ref.B, ref.B))
+    assert rel_err(np.tril(K), Kref) < 1e-10
+    assert rel_err(got["H"], ref.H) < 1e-10
+    assert rel_err(got["g"], ref.g) < 1e-10
+    np.testing.assert_allclose(got["logdet"], np.sum(np.log(np.diagonal(ref.L, axis1=1, axis2=2)), axis=1),
+                               rtol=1e-10)
+    assert np.all(got["ok"] == 1)
+    p.close()
+    ctx.close()
+
+
+def test_dual_coupled_chains():
+    case = dual_case(70, dt=0.5)
+    print("dual coupled chains", flush=True)
+    r = run_coupled(case, 40)
+    assert np.sum(r["acc"] != r["oacc"]) == 0
+    assert r["acc"].sum() > 70 * 40 * 0.05
+    assert rel_err(r["x"], r["ox"]) < 1e-9
+    assert np.max(np.abs(r["z"] - r["oz"])) < 1e-5
+    r["p"].close()
+    r["ctx"].close()
+
+
+def test_dual_zero_likelihood_accepts_everything():
+    case = dual_case(16, dt=0.8)
+    case["prob"].noise_var = np.full(case["prob"].d_y, np.inf)
+    r = run_coupled(case, 10)
+    assert np.all(r["acc"] == 10) and np.all(r["oacc"] == 10)
+    assert rel_err(r["x"], r["ox"]) < 1e-9
+    r["p"].close()
+    r["ctx"].close()
+
+
+def test_dual_full_size_mid_sampled():
+    case = make_case("mid")
+    case["prob"].factor = "dual"
+    idx = [0, 1, 255, 256, 511]
+    print("dual full-size mid: 3 coupled steps", flush=True)
+    r = run_coupled(case, 3, chains_idx=idx)
+    np.testing.assert_array_equal(r["acc"], r["oacc"])
+    assert rel_err(r["x"], r["ox"]) < 1e-9
+    r["p"].close()
+    r["ctx"].close()
+
+
+def test_dual_bf16_against_oracle():
+    case = dual_case(64, dt=0.5)
+    print("dual bf16", flush=True)
+    ctx, p = device_problem(case, precision="bf16", factorization="dual")
+    x = np.random.default_rng(3).standard_normal((64, 40))
+    got = {k: v.cpu().numpy() for k, v in p.eval_geometry(torch.tensor(x, device="cuda:0")).items()}
+    ref = mcmc.geometry(case["prob"], x)
+    dy = case["prob"].d_y
+    K = got["L"].reshape(64, -1)[:, : dy * dy].reshape(64, dy, dy)
+    Kref = np.linalg.cholesky(np.eye(dy)[None] + np.einsum("cir,ckr->cik", ref.B, ref.B))
+    eK = float(np.linalg.norm(np.tril(K) - Kref) / np.linalg.norm(Kref))
+    print(f"bf16 dual factor rel err {eK:.2e}", flush=True)
+    assert eK < 3e-2
+    p.init(case["x0"], case["z0"])
+    p.step(60)
+    acc, fail, _ = p.diagnostics()
+    st = mcmc.init_state(case["prob"], case["x0"], case["z0"].astype(np.float64))
+    mcmc.run(case["prob"], st, 60, trace=False)
+    a_gpu, a_ref = acc.sum() / (64 * 60), st.accepts.sum() / (64 * 60)
+    print(f"acceptance bf16 dual {a_gpu:.3f} vs fp64 oracle {a_ref:.3f}", flush=True)
+    assert fail.sum() == 0 and abs(a_gpu - a_ref) < 0.08
+    p.close()
+    ctx.close()

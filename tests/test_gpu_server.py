@@ -2,8 +2,9 @@
 
 * Parity: every request's posterior mean field equals the oracle's run of the same
   request (key (seed, request id), prior initial states of streams 3 and 4, n_steps
-  transitions, burn-in 20%, Rao-Blackwellised mean Psi_r xbar), on the FP64 path, to
-  1e-9 relative; the acceptance counts are identical. Requests whose d_y is below
+  transitions, burn-in 20%, Rao-Blackwellised mean Psi_r xbar, the observation-space
+  form since every bucket has d_y < r), on the FP64 path, to 1e-9 relative; the
+  acceptance counts are identical. Requests whose d_y is below
   their bucket's observe the first d_y outputs (the oracle problem has d_y outputs).
 * Isolation: a request's result is the same alone and in a mix of requests that
   arrive while it runs and occupy other slots of its pool; the chains of different
@@ -40,7 +41,8 @@ def make_ctx():
 
 
 def oracle_mean(seed, rid, y, nv, C, N, dt, dec):
-    prob = mcmc.Problem(LAYERS, y, nv, dt, seed=seed, request_id=rid)
+    # the pools take the observation-space form when d_y < r (every bucket here)
+    prob = mcmc.Problem(LAYERS, y, nv, dt, seed=seed, request_id=rid, factor="dual" if len(y) < W.r else "primal")
     x0 = philox.normals(seed, rid, philox.STREAM_INIT_X, 0, np.arange(C), W.r)
     st = mcmc.init_state(prob, x0)
     xs, _ = mcmc.run(prob, st, N)

@@ -253,57 +253,98 @@ __global__ __launch_bounds__(256) void gn_hessian_kernel(int dy, int r, const do
 static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
 
 // One forward layer with the largest tile that still gives >= 1024 blocks.
-// FP32 layer with the whole K extent staged: a block stages 16 input rows and 16 weight
-// rows (K each, transposed to k-major with a padded stride) in LDS with one barrier,
-// then every thread forms one output with four interleaved partial sums over k.
-constexpr int FWD_LDP = 17;
+// FP32 layer on MFMA (v_mfma_f32_32x32x2_f32: FP32 products, FP32 accumulation): a
+// block forms a 32 x 32 output tile (rows = chains, columns = outputs), its four waves
+// splitting K in chunks of 8 and the partial tiles summed through LDS. Within a chunk
+// of 8, lane (i, h) holds the inputs k = 8 t + 4 h + e (e < 4) for the four MFMAs
+// e = 0..3 (float4 loads of A rows and W rows); A and W use the same k order, so the
+// products pair up. The output layout: lane (j, h), register q holds row
+// 8 (q / 4) + 4 h + q % 4 and column j of the tile.
+typedef __attribute__((ext_vector_type(16))) float f32x16g;
 
-__global__ __launch_bounds__(256) void fwd_layer_staged_kernel(int M, int K, int N, const float* __restrict__ in,
-                                                               int ldin, const float* __restrict__ W,
-                                                               const float* __restrict__ b, int kind,
-                                                               float* __restrict__ out, int ldout,
-                                                               float* __restrict__ dprime, int ldd) {
-    extern __shared__ float fsm[];
-    float* As = fsm;                    // K x FWD_LDP: As[k][row]
-    float* Ws = fsm + (long)K * FWD_LDP;  // K x FWD_LDP: Ws[k][col]
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int m0 = blockIdx.y * 16, n0 = blockIdx.x * 16;
-    // all 32 row loads of a k slice are issued before any store
-    for (int k = tid; k < K; k += 256) {
-        float av[16], wv[16];
+__global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, const float* __restrict__ in, int ldin,
+                                                       const float* __restrict__ W, const float* __restrict__ b,
+                                                       int kind, float* __restrict__ out, int ldout,
+                                                       float* __restrict__ dprime, int ldd) {
+    __shared__ float red[3][64][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    const int arow = m0 + l32, wrow = n0 + l32;
+    const bool aok = arow < M, wok = wrow < N;
+    const float* ap = in + (long)(aok ? arow : 0) * ldin;
+    const float* wp = W + (long)(wok ? wrow : 0) * K;
+    const bool vec = ((ldin & 3) == 0) && ((K & 3) == 0);
+    f32x16g acc;
 #pragma unroll
-        for (int row = 0; row < 16; ++row) {
-            av[row] = (m0 + row < M) ? in[(long)(m0 + row) * ldin + k] : 0.f;
-            wv[row] = (n0 + row < N) ? W[(long)(n0 + row) * K + k] : 0.f;
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const int nchunk = (K + 7) / 8;
+    auto load = [&](int t, float4& a4, float4& w4) {
+        const int k = 8 * t + 4 * h;
+        if (vec && k + 3 < K) {
+            a4 = aok ? *reinterpret_cast<const float4*>(ap + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            w4 = wok ? *reinterpret_cast<const float4*>(wp + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            a4.x = (aok && k < K) ? ap[k] : 0.f;
+            a4.y = (aok && k + 1 < K) ? ap[k + 1] : 0.f;
+            a4.z = (aok && k + 2 < K) ? ap[k + 2] : 0.f;
+            a4.w = (aok && k + 3 < K) ? ap[k + 3] : 0.f;
+            w4.x = (wok && k < K) ? wp[k] : 0.f;
+            w4.y = (wok && k + 1 < K) ? wp[k + 1] : 0.f;
+            w4.z = (wok && k + 2 < K) ? wp[k + 2] : 0.f;
+            w4.w = (wok && k + 3 < K) ? wp[k + 3] : 0.f;
+        }
+    };
+    auto mfma4 = [&](const float4& a4, const float4& w4) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, w4.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, w4.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, w4.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, w4.w, acc, 0, 0, 0);
+    };
+    constexpr int PRE = 16;  // chunks per wave with all loads issued before the products
+    if (nchunk <= 4 * PRE) {
+        float4 a4[PRE], w4[PRE];
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int t = wave + 4 * u;
+            if (t < nchunk) load(t, a4[u], w4[u]);
         }
 #pragma unroll
-        for (int row = 0; row < 16; ++row) {
-            As[k * FWD_LDP + row] = av[row];
-            Ws[k * FWD_LDP + row] = wv[row];
+        for (int u = 0; u < PRE; ++u)
+            if (wave + 4 * u < nchunk) mfma4(a4[u], w4[u]);
+    } else {
+        for (int t = wave; t < nchunk; t += 4) {
+            float4 a4, w4;
+            load(t, a4, w4);
+            mfma4(a4, w4);
         }
+    }
+    if (wave > 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[wave - 1][lane][q] = acc[q];
     }
     __syncthreads();
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    int k = 0;
-    for (; k + 3 < K; k += 4) {
-        a0 += As[k * FWD_LDP + ty] * Ws[k * FWD_LDP + tx];
-        a1 += As[(k + 1) * FWD_LDP + ty] * Ws[(k + 1) * FWD_LDP + tx];
-        a2 += As[(k + 2) * FWD_LDP + ty] * Ws[(k + 2) * FWD_LDP + tx];
-        a3 += As[(k + 3) * FWD_LDP + ty] * Ws[(k + 3) * FWD_LDP + tx];
+    if (wave != 0) return;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += red[0][lane][q] + red[1][lane][q] + red[2][lane][q];
+    const int n = n0 + l32;
+    if (n >= N) return;
+    const float bn = b ? b[n] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int m = m0 + 8 * (q >> 2) + 4 * h + (q & 3);
+        if (m >= M) continue;
+        const float z = acc[q] + bn;
+        float o;
+        if (kind == DINO_LAYER_LINEAR) {
+            o = z;
+        } else {
+            o = gelu_t<float>(z);
+            if (kind == DINO_LAYER_RESID) o += in[(long)m * ldin + n];
+            if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
+        }
+        out[(long)m * ldout + n] = o;
     }
-    for (; k < K; ++k) a0 += As[k * FWD_LDP + ty] * Ws[k * FWD_LDP + tx];
-    const int m = m0 + ty, n = n0 + tx;
-    if (m >= M || n >= N) return;
-    const float z = ((a0 + a1) + (a2 + a3)) + (b ? b[n] : 0.f);
-    float o;
-    if (kind == DINO_LAYER_LINEAR) {
-        o = z;
-    } else {
-        o = gelu_t<float>(z);
-        if (kind == DINO_LAYER_RESID) o += in[(long)m * ldin + n];
-        if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
-    }
-    out[(long)m * ldout + n] = o;
 }
 
 template <typename T>
@@ -416,19 +457,8 @@ void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hip
         const int N = last ? p->d_y : ly.fan_out;
         float* dp = nullptr;
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
-        const size_t lds = (size_t)2 * ly.fan_in * FWD_LDP * sizeof(float);
-        if (lds <= 64 * 1024) {
-            static bool attr = false;
-            if (!attr) {
-                DINO_HIP(hipFuncSetAttribute((const void*)fwd_layer_staged_kernel,
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-                attr = true;
-            }
-            hipLaunchKernelGGL(fwd_layer_staged_kernel, dim3((N + 15) / 16, (n + 15) / 16), dim3(256), lds, st, n,
-                               ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
-        } else {
-            fwd_layer<float>(n, ly.fan_in, N, in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32, st);
-        }
+        hipLaunchKernelGGL(fwd_mfma_kernel, dim3((N + 31) / 32, (n + 31) / 32), dim3(256), 0, st, n, ly.fan_in, N,
+                           in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;

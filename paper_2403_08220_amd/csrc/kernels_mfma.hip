@@ -395,17 +395,33 @@ __global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int l
                                                             const float* __restrict__ e, double* A, long strideA,
                                                             const int32_t* slot, int slot_xor, long slot_stride,
                                                             double* __restrict__ g) {
-    extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt
+    extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt, then e (dy floats)
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
-    for (int e2 = tid; e2 < dy_pad * k_pad; e2 += HES_TPB) {
-        const int i = e2 / k_pad, j = e2 % k_pad;
-        bs[(long)i * ldt + j] = (i < dy && j < r) ? Bc[(long)i * ldb + j] : __float2bfloat16(0.f);
+    float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
+    // 16-byte moves of 8 BF16 values; columns at or beyond r are zero, as are rows beyond dy
+    const int k8 = k_pad / 8;
+    for (int e2 = tid; e2 < dy_pad * k8; e2 += HES_TPB) {
+        const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (i < dy) {
+            if (j8 + 8 <= r) {
+                v = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
+            } else {
+                __hip_bfloat16 t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t[q] = (j8 + q < r) ? Bc[(long)i * ldb + j8 + q] : __float2bfloat16(0.f);
+                v = *reinterpret_cast<const uint4*>(t);
+            }
+        }
+        *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v;
     }
+    for (int i = tid; i < dy; i += HES_TPB) es[i] = e[(long)c * dy + i];
     __syncthreads();
     for (int j = tid; j < r; j += HES_TPB) {
         double acc = 0.0;
-        for (int i = 0; i < dy; ++i) acc += (double)__bfloat162float(bs[(long)i * ldt + j]) * (double)e[(long)c * dy + i];
+#pragma unroll 4
+        for (int i = 0; i < dy; ++i) acc += (double)__bfloat162float(bs[(long)i * ldt + j]) * (double)es[i];
         g[(long)c * r + j] = acc;
     }
     double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
@@ -439,7 +455,7 @@ void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
     const int dy_pad = (dy + 31) / 32 * 32;
     const int k_pad = (r + 15) / 16 * 16;
     const int ldt = k_pad + 8;  // 16-byte aligned rows, shifted banks
-    const size_t lds = (size_t)dy_pad * ldt * sizeof(__hip_bfloat16);
+    const size_t lds = (size_t)dy_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
     DINO_REQUIRE(lds <= 160 * 1024, DINO_EINVAL, "d_y x r too large for the LDS-staged Gram matrix");
     static bool attr = false;
     if (!attr) {

@@ -69,6 +69,108 @@ __device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
     asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base) : "memory");
 }
 
+// One work item of the width-400 instance (26 K chunks) as a single asm block: the A
+// operands (1 KB weight tiles in LDS, one ds_read_b128 per lane) run 5 reads ahead of
+// the MFMA chain in a ring of 6 register sets, a set being refilled one MFMA after its
+// last use; every read is waited for inside the block (s_waitcnt lgkmcnt counts LDS
+// reads, which return in order). The block starts with no LDS operation outstanding and
+// ends with wait states that cover the last MFMA's write of the accumulator before
+// vector instructions read it.
+#define SW_RD(t, off) "ds_read_b128 %[t" #t "], %[addr] offset:" #off "\n\t"
+#define SW_MF(t, b) "v_mfma_f32_32x32x16_bf16 %[acc], %[t" #t "], %[b" #b "], %[acc]\n\t"
+#define SW_WT(n) "s_waitcnt lgkmcnt(" #n ")\n\t"
+
+__device__ __forceinline__ void sweep_item26(f32x16& acc, const bf16x8 (&bop)[26], uint32_t addr) {
+    bf16x8 t0, t1, t2, t3, t4, t5;
+    asm volatile(
+        "s_waitcnt lgkmcnt(0)\n\t"
+        SW_RD(0, 0)
+        SW_RD(1, 1024)
+        SW_RD(2, 2048)
+        SW_RD(3, 3072)
+        SW_RD(4, 4096)
+        SW_WT(4)
+        SW_MF(0, 0)
+        SW_RD(5, 5120)
+        SW_WT(4)
+        SW_MF(1, 1)
+        SW_RD(0, 6144)
+        SW_WT(4)
+        SW_MF(2, 2)
+        SW_RD(1, 7168)
+        SW_WT(4)
+        SW_MF(3, 3)
+        SW_RD(2, 8192)
+        SW_WT(4)
+        SW_MF(4, 4)
+        SW_RD(3, 9216)
+        SW_WT(4)
+        SW_MF(5, 5)
+        SW_RD(4, 10240)
+        SW_WT(4)
+        SW_MF(0, 6)
+        SW_RD(5, 11264)
+        SW_WT(4)
+        SW_MF(1, 7)
+        SW_RD(0, 12288)
+        SW_WT(4)
+        SW_MF(2, 8)
+        SW_RD(1, 13312)
+        SW_WT(4)
+        SW_MF(3, 9)
+        SW_RD(2, 14336)
+        SW_WT(4)
+        SW_MF(4, 10)
+        SW_RD(3, 15360)
+        SW_WT(4)
+        SW_MF(5, 11)
+        SW_RD(4, 16384)
+        SW_WT(4)
+        SW_MF(0, 12)
+        SW_RD(5, 17408)
+        SW_WT(4)
+        SW_MF(1, 13)
+        SW_RD(0, 18432)
+        SW_WT(4)
+        SW_MF(2, 14)
+        SW_RD(1, 19456)
+        SW_WT(4)
+        SW_MF(3, 15)
+        SW_RD(2, 20480)
+        SW_WT(4)
+        SW_MF(4, 16)
+        SW_RD(3, 21504)
+        SW_WT(4)
+        SW_MF(5, 17)
+        SW_RD(4, 22528)
+        SW_WT(4)
+        SW_MF(0, 18)
+        SW_RD(5, 23552)
+        SW_WT(4)
+        SW_MF(1, 19)
+        SW_RD(0, 24576)
+        SW_WT(4)
+        SW_MF(2, 20)
+        SW_RD(1, 25600)
+        SW_WT(4)
+        SW_MF(3, 21)
+        SW_WT(3)
+        SW_MF(4, 22)
+        SW_WT(2)
+        SW_MF(5, 23)
+        SW_WT(1)
+        SW_MF(0, 24)
+        SW_WT(0)
+        SW_MF(1, 25)
+        "s_nop 7\n\ts_nop 7\n\ts_nop 4"
+        : [acc] "+a"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [t4] "=&v"(t4),
+          [t5] "=&v"(t5)
+        : [addr] "v"(addr), [b0] "v"(bop[0]), [b1] "v"(bop[1]), [b2] "v"(bop[2]), [b3] "v"(bop[3]), [b4] "v"(bop[4]), [b5] "v"(bop[5]), [b6] "v"(bop[6]), [b7] "v"(bop[7]), [b8] "v"(bop[8]), [b9] "v"(bop[9]), [b10] "v"(bop[10]), [b11] "v"(bop[11]), [b12] "v"(bop[12]), [b13] "v"(bop[13]), [b14] "v"(bop[14]), [b15] "v"(bop[15]), [b16] "v"(bop[16]), [b17] "v"(bop[17]), [b18] "v"(bop[18]), [b19] "v"(bop[19]), [b20] "v"(bop[20]), [b21] "v"(bop[21]), [b22] "v"(bop[22]), [b23] "v"(bop[23]), [b24] "v"(bop[24]), [b25] "v"(bop[25])
+        : "memory");
+    // the ring registers are consumed here (every read above has completed)
+    asm volatile("" ::"v"(t0), "v"(t1), "v"(t2), "v"(t3), "v"(t4), "v"(t5));
+}
+
 template <int NMB>
 __global__ __launch_bounds__(JAC_TPB) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void jac_sweep_bf16_kernel(SweepArgs args) {
@@ -163,9 +265,15 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
                 if (!L.resid)
 #pragma unroll
                     for (int j = 0; j < 16; ++j) lam[mob][j] = 0.f;
+                if constexpr (NKC == 26) {
+                    const uint32_t addr =
+                        lds_base + (uint32_t)(((item & (NBUF - 1)) * NT * 64 + lane) * (int)sizeof(bf16x8));
+                    sweep_item26(lam[mob], bop, addr);
+                } else {
 #pragma unroll
-                for (int kc = 0; kc < NKC; ++kc)
-                    lam[mob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[kc * 64], bop[kc], lam[mob], 0, 0, 0);
+                    for (int kc = 0; kc < NKC; ++kc)
+                        lam[mob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[kc * 64], bop[kc], lam[mob], 0, 0, 0);
+                }
                 const f32x16& acc = lam[mob];
                 if (last && valid) {
                     // B[col][m] = winv_i Lambda_0^T[m][col]; rows padded to ldb (a multiple of

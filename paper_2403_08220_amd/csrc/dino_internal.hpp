@@ -183,6 +183,8 @@ struct dino_ctx {
     int r_in = 0, d_out = 0, max_width = 0, n_act = 0;
     int live_problems = 0;
     __hip_bfloat16* sweep_tiles = nullptr;  // BF16 W^T tiles of the reverse sweep, in work-item order
+    const float* sweep_ones = nullptr;      // 32 * nmb FP32 ones after the tiles (same allocation)
+    const float* sweep_wout = nullptr;      // output layer rows in the sweep's register order (same allocation)
 };
 
 namespace dino {
@@ -340,6 +342,9 @@ NetView net_view(const dino_ctx* ctx);
 
 // mixed-precision path (kernels_mfma.hip, kernels_geometry.hip)
 int sweep_nmb(const dino_ctx* ctx);
+// Output layer W (fan_out x fan_in) for the sweep's initial Lambda: entry
+// ((mb * 4 + jq) * fan_out + i) * 8 + 4 h + t = W[i][32 mb + 8 jq + 4 h + t] (zero beyond fan_in).
+void pack_sweep_wout(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<float>& out);
 void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<uint16_t>& out,
                       int& nmb_out);
 void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hipStream_t st);

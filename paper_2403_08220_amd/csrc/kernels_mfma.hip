@@ -55,6 +55,9 @@ struct SweepArgs {
     __hip_bfloat16* B;    // out: C*dy x r, BF16
     SweepLayer layer[15];
     const bf16x8* tiles;  // all work items' tiles, contiguous in processing order
+    const float* ones;    // 32 * NMB ones: the d row of layers without an activation
+    const float* wout_pk; // output layer rows in the sweep's register order (width-416 kernel)
+    int d_out;            // rows of the output layer
 };
 
 constexpr int sweep_nt(int nmb) { return (2 * nmb + 3) / 4 * 4; }  // tiles per item, multiple of 4
@@ -64,112 +67,13 @@ constexpr int sweep_nbuf(int nmb) { return sweep_nt(nmb) * 4 <= 150 ? 4 : 2; }
 // One 1 KB tile copy global -> LDS (global_load_lds_dwordx4): every lane moves 16 B of
 // its own address to lds_base + 16 * lane. Issued from asm so that the compiler's
 // LDS-read scheduling is not serialised behind the copy; completion is tracked by
-// the explicit vmcnt waits of the kernel (the copy has no VGPR result).
+// the explicit vmcnt waits of the kernel (the copy has no VGPR result). The copy reads
+// M0 one wait state after the SALU write.
 __device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
-    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base) : "memory");
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base) : "memory");
 }
 
-// One work item of the width-400 instance (26 K chunks) as a single asm block: the A
-// operands (1 KB weight tiles in LDS, one ds_read_b128 per lane) run 5 reads ahead of
-// the MFMA chain in a ring of 6 register sets, a set being refilled one MFMA after its
-// last use; every read is waited for inside the block (s_waitcnt lgkmcnt counts LDS
-// reads, which return in order). The block starts with no LDS operation outstanding and
-// ends with wait states that cover the last MFMA's write of the accumulator before
-// vector instructions read it.
-#define SW_RD(t, off) "ds_read_b128 %[t" #t "], %[addr] offset:" #off "\n\t"
-#define SW_MF(t, b) "v_mfma_f32_32x32x16_bf16 %[acc], %[t" #t "], %[b" #b "], %[acc]\n\t"
-#define SW_WT(n) "s_waitcnt lgkmcnt(" #n ")\n\t"
-
-__device__ __forceinline__ void sweep_item26(f32x16& acc, const bf16x8 (&bop)[26], uint32_t addr) {
-    bf16x8 t0, t1, t2, t3, t4, t5;
-    asm volatile(
-        "s_waitcnt lgkmcnt(0)\n\t"
-        SW_RD(0, 0)
-        SW_RD(1, 1024)
-        SW_RD(2, 2048)
-        SW_RD(3, 3072)
-        SW_RD(4, 4096)
-        SW_WT(4)
-        SW_MF(0, 0)
-        SW_RD(5, 5120)
-        SW_WT(4)
-        SW_MF(1, 1)
-        SW_RD(0, 6144)
-        SW_WT(4)
-        SW_MF(2, 2)
-        SW_RD(1, 7168)
-        SW_WT(4)
-        SW_MF(3, 3)
-        SW_RD(2, 8192)
-        SW_WT(4)
-        SW_MF(4, 4)
-        SW_RD(3, 9216)
-        SW_WT(4)
-        SW_MF(5, 5)
-        SW_RD(4, 10240)
-        SW_WT(4)
-        SW_MF(0, 6)
-        SW_RD(5, 11264)
-        SW_WT(4)
-        SW_MF(1, 7)
-        SW_RD(0, 12288)
-        SW_WT(4)
-        SW_MF(2, 8)
-        SW_RD(1, 13312)
-        SW_WT(4)
-        SW_MF(3, 9)
-        SW_RD(2, 14336)
-        SW_WT(4)
-        SW_MF(4, 10)
-        SW_RD(3, 15360)
-        SW_WT(4)
-        SW_MF(5, 11)
-        SW_RD(4, 16384)
-        SW_WT(4)
-        SW_MF(0, 12)
-        SW_RD(5, 17408)
-        SW_WT(4)
-        SW_MF(1, 13)
-        SW_RD(0, 18432)
-        SW_WT(4)
-        SW_MF(2, 14)
-        SW_RD(1, 19456)
-        SW_WT(4)
-        SW_MF(3, 15)
-        SW_RD(2, 20480)
-        SW_WT(4)
-        SW_MF(4, 16)
-        SW_RD(3, 21504)
-        SW_WT(4)
-        SW_MF(5, 17)
-        SW_RD(4, 22528)
-        SW_WT(4)
-        SW_MF(0, 18)
-        SW_RD(5, 23552)
-        SW_WT(4)
-        SW_MF(1, 19)
-        SW_RD(0, 24576)
-        SW_WT(4)
-        SW_MF(2, 20)
-        SW_RD(1, 25600)
-        SW_WT(4)
-        SW_MF(3, 21)
-        SW_WT(3)
-        SW_MF(4, 22)
-        SW_WT(2)
-        SW_MF(5, 23)
-        SW_WT(1)
-        SW_MF(0, 24)
-        SW_WT(0)
-        SW_MF(1, 25)
-        "s_nop 7\n\ts_nop 7\n\ts_nop 4"
-        : [acc] "+a"(acc), [t0] "=&v"(t0), [t1] "=&v"(t1), [t2] "=&v"(t2), [t3] "=&v"(t3), [t4] "=&v"(t4),
-          [t5] "=&v"(t5)
-        : [addr] "v"(addr), [b0] "v"(bop[0]), [b1] "v"(bop[1]), [b2] "v"(bop[2]), [b3] "v"(bop[3]), [b4] "v"(bop[4]), [b5] "v"(bop[5]), [b6] "v"(bop[6]), [b7] "v"(bop[7]), [b8] "v"(bop[8]), [b9] "v"(bop[9]), [b10] "v"(bop[10]), [b11] "v"(bop[11]), [b12] "v"(bop[12]), [b13] "v"(bop[13]), [b14] "v"(bop[14]), [b15] "v"(bop[15]), [b16] "v"(bop[16]), [b17] "v"(bop[17]), [b18] "v"(bop[18]), [b19] "v"(bop[19]), [b20] "v"(bop[20]), [b21] "v"(bop[21]), [b22] "v"(bop[22]), [b23] "v"(bop[23]), [b24] "v"(bop[24]), [b25] "v"(bop[25])
-        : "memory");
-    // the ring registers are consumed here (every read above has completed)
-    asm volatile("" ::"v"(t0), "v"(t1), "v"(t2), "v"(t3), "v"(t4), "v"(t5));
-}
+#include "sweep_asm.inc"
 
 template <int NMB>
 __global__ __launch_bounds__(JAC_TPB) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -265,15 +169,9 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
                 if (!L.resid)
 #pragma unroll
                     for (int j = 0; j < 16; ++j) lam[mob][j] = 0.f;
-                if constexpr (NKC == 26) {
-                    const uint32_t addr =
-                        lds_base + (uint32_t)(((item & (NBUF - 1)) * NT * 64 + lane) * (int)sizeof(bf16x8));
-                    sweep_item26(lam[mob], bop, addr);
-                } else {
 #pragma unroll
-                    for (int kc = 0; kc < NKC; ++kc)
-                        lam[mob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[kc * 64], bop[kc], lam[mob], 0, 0, 0);
-                }
+                for (int kc = 0; kc < NKC; ++kc)
+                    lam[mob] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[kc * 64], bop[kc], lam[mob], 0, 0, 0);
                 const f32x16& acc = lam[mob];
                 if (last && valid) {
                     // B[col][m] = winv_i Lambda_0^T[m][col]; rows padded to ldb (a multiple of
@@ -298,6 +196,131 @@ void jac_sweep_bf16_kernel(SweepArgs args) {
             if (mb >= L.nmb_out)
 #pragma unroll
                 for (int j = 0; j < 16; ++j) lam[mb][j] = 0.f;
+    }
+}
+
+// The width-416 instance (13 row blocks, 26 K chunks): every layer is one asm block
+// (sweep_layer13) that runs its items with the tile ring protocol of the kernel above
+// (copies three items ahead, vmcnt + barrier before an item is read), so that the
+// reads of an item overlap the last MFMAs of the previous one and no compiler-placed
+// code runs between items. Lambda stays in VGPRs; the B operands live in AGPRs. Layers
+// without an activation multiply by a row of ones, so that every layer takes the same
+// path.
+__global__ __launch_bounds__(JAC_TPB) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void jac_sweep13_kernel(SweepArgs args) {
+    constexpr int NMB = 13, NKC = 26, NT = 28, NBUF = 4;
+    static_assert(sweep_nt(NMB) == NT && sweep_nbuf(NMB) == NBUF, "ring layout of the width-416 sweep");
+    constexpr uint32_t ITEM = NT * 1024;  // bytes per item
+    extern __shared__ bf16x8 tiles_lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nl = lane & 31, h = lane >> 5;
+    const int col = (blockIdx.x * JAC_WAVES + wave) * 32 + nl;
+    const bool valid = col < args.n_cols;
+    const int c = valid ? col / args.dy : 0;
+    const int i = valid ? col % args.dy : 0;
+
+    // Lambda_L^T = the output layer's rows, from the packed copy: one 16-byte load per
+    // (row block, register quad), 1 KB contiguous per wave. Columns past n_cols compute
+    // with output 0 and are never written.
+    f32x16 lam[NMB];
+    {
+        const float4* wp = reinterpret_cast<const float4*>(args.wout_pk) + (long)i * 2 + h;
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int jq = 0; jq < 4; ++jq) {
+                const float4 v = wp[(long)(mb * 4 + jq) * args.d_out * 2];
+                lam[mb][4 * jq] = v.x;
+                lam[mb][4 * jq + 1] = v.y;
+                lam[mb][4 * jq + 2] = v.z;
+                lam[mb][4 * jq + 3] = v.w;
+            }
+    }
+    const float wi = valid ? (float)args.winv[(long)(args.rows ? args.rows[c] : 0) * args.dy + i] : 0.f;
+
+    const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) bf16x8*)tiles_lds;
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    for (int k = 0; k < NBUF - 1 && k < args.n_items; ++k) {
+        const bf16x8* src = args.tiles + (long)k * NT * 64;
+#pragma unroll
+        for (int q = 0; q < NT / 4; ++q) {
+            const int kc = wave_u + 4 * q;
+            dma_tile(src + kc * 64 + lane, __builtin_amdgcn_readfirstlane(lds_base + (uint32_t)k * ITEM + kc * 1024u));
+        }
+    }
+    if (NBUF - 2 <= args.n_items - 1) asm volatile("s_waitcnt vmcnt(14)\n\ts_barrier" ::: "memory");
+    else asm volatile("s_waitcnt vmcnt(0)\n\ts_barrier" ::: "memory");
+
+    const uint32_t sb = __builtin_amdgcn_readfirstlane(lds_base);
+    const uint64_t tb = (uint64_t)(uintptr_t)args.tiles;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)tb);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(tb >> 32));
+    const uint32_t sw = __builtin_amdgcn_readfirstlane((uint32_t)wave_u * 1024u);
+    uint32_t goff[7];
+#pragma unroll
+    for (int q = 0; q < 7; ++q) goff[q] = (uint32_t)(lane * 16 + (wave_u + 4 * q) * 1024);
+    bf16x8 zero;
+#pragma unroll
+    for (int jj = 0; jj < 8; ++jj) zero[jj] = (__bf16)0.f;
+
+    int item = 0;
+    for (int li = 0; li < args.n_layers; ++li) {
+        const SweepLayer L = args.layer[li];
+        bf16x8 bop[NKC];
+        const float4* drow = reinterpret_cast<const float4*>((L.d ? L.d + (long)c * args.ldd : args.ones) + 4 * h);
+#pragma unroll
+        for (int mb = 0; mb < NMB; ++mb)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float4 d0 = drow[8 * mb + 4 * q];
+                const float4 d1 = drow[8 * mb + 4 * q + 2];
+                const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) bop[2 * mb + q][jj] = (__bf16)(lam[mb][8 * q + jj] * dv[jj]);
+                __builtin_amdgcn_sched_barrier(0);  // keep only one block's gelu' values live
+            }
+        const uint32_t sc = __builtin_amdgcn_readfirstlane(lds_base + (uint32_t)(item & (NBUF - 1)) * ITEM);
+        // every scalar operand of the block is wave-uniform; readfirstlane places it in an SGPR
+        const uint32_t n_u = __builtin_amdgcn_readfirstlane((uint32_t)L.nmb_out);
+        const uint32_t zf_u = __builtin_amdgcn_readfirstlane(L.resid ? 0u : 1u);
+        const int32_t tl_u = __builtin_amdgcn_readfirstlane(args.n_items - (NBUF - 1) - item);
+        const uint32_t so_u = __builtin_amdgcn_readfirstlane((uint32_t)(item + NBUF - 1) * ITEM);
+        const uint32_t se_u = __builtin_amdgcn_readfirstlane(sb + NBUF * ITEM);
+        const uint32_t sz_u = __builtin_amdgcn_readfirstlane(sb + (NBUF - 1) * ITEM);
+        sweep_layer13(lam, bop, n_u, zf_u, tl_u, sc, so_u, lo, hi, sb, se_u, sz_u, sw, (uint32_t)lane * 16u, goff, zero);
+        item += L.nmb_out;
+    }
+    // B[col][m] = winv_i Lambda_0^T[m][col] (rows of ldb = 32 * nmb_last BF16). The wave's 32
+    // rows are one contiguous block of B: they are assembled in LDS (the ring is no longer
+    // read once every wave has passed the barrier below) and written with 16-byte stores.
+    __syncthreads();
+    {
+        const int ldb = args.ldb;
+        const int nmb_last = args.layer[args.n_layers - 1].nmb_out;
+        char* stage_lds = reinterpret_cast<char*>(tiles_lds) + (size_t)wave * 64 * ldb;
+#pragma unroll
+        for (int mob = 0; mob < NMB; ++mob) {
+            if (mob < nmb_last) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int m0 = 32 * mob + 8 * b + 4 * h;
+                    uint64_t v = 0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        v |= (uint64_t)__builtin_bit_cast(uint16_t, __float2bfloat16(wi * lam[mob][4 * b + t])) << (16 * t);
+                    *reinterpret_cast<uint64_t*>(stage_lds + ((size_t)nl * ldb + m0) * 2) = v;
+                }
+            }
+        }
+        __syncthreads();
+        const int col0 = (blockIdx.x * JAC_WAVES + wave) * 32;
+        const int rows = min(32, args.n_cols - col0);
+        const int chunks = rows * ldb / 8;  // 16-byte chunks of the wave's block
+        char* dst = reinterpret_cast<char*>(args.B + (long)col0 * ldb);
+        typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+        for (int e = lane; e < chunks; e += 64)
+            __builtin_nontemporal_store(*reinterpret_cast<const u32x4*>(stage_lds + (size_t)e * 16),
+                                        reinterpret_cast<u32x4*>(dst + (size_t)e * 16));
     }
 }
 
@@ -438,6 +461,19 @@ void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int
             }
 }
 
+void pack_sweep_wout(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<float>& out) {
+    out.assign((size_t)nmb_t * 4 * fan_out * 8, 0.f);
+    for (int mb = 0; mb < nmb_t; ++mb)
+        for (int jq = 0; jq < 4; ++jq)
+            for (int i = 0; i < fan_out; ++i)
+                for (int hh = 0; hh < 2; ++hh)
+                    for (int t = 0; t < 4; ++t) {
+                        const int row = 32 * mb + 8 * jq + 4 * hh + t;
+                        if (row < fan_in)
+                            out[(((size_t)mb * 4 + jq) * fan_out + i) * 8 + 4 * hh + t] = (float)W[(size_t)i * fan_in + row];
+                    }
+}
+
 template <int NMB>
 static void launch_sweep_t(const SweepArgs& a, hipStream_t st) {
     const size_t lds = (size_t)sweep_nbuf(NMB) * sweep_nt(NMB) * 64 * sizeof(bf16x8);
@@ -449,6 +485,19 @@ static void launch_sweep_t(const SweepArgs& a, hipStream_t st) {
     }
     const int blocks = (a.n_cols + 32 * JAC_WAVES - 1) / (32 * JAC_WAVES);
     hipLaunchKernelGGL(jac_sweep_bf16_kernel<NMB>, dim3(blocks), dim3(JAC_TPB), lds, st, a);
+    DINO_HIP(hipGetLastError());
+}
+
+static void launch_sweep13(const SweepArgs& a, hipStream_t st) {
+    const size_t lds = (size_t)sweep_nbuf(13) * sweep_nt(13) * 64 * sizeof(bf16x8);
+    static bool attr = false;
+    if (!attr) {
+        DINO_HIP(hipFuncSetAttribute((const void*)jac_sweep13_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+        attr = true;
+    }
+    const int blocks = (a.n_cols + 32 * JAC_WAVES - 1) / (32 * JAC_WAVES);
+    hipLaunchKernelGGL(jac_sweep13_kernel, dim3(blocks), dim3(JAC_TPB), lds, st, a);
     DINO_HIP(hipGetLastError());
 }
 
@@ -469,6 +518,9 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
     a.B = Bout;
     a.n_layers = L - 1;
     a.tiles = reinterpret_cast<const bf16x8*>(ctx->sweep_tiles);
+    a.ones = ctx->sweep_ones;
+    a.wout_pk = ctx->sweep_wout;
+    a.d_out = ctx->layers[L - 1].fan_out;
     DINO_REQUIRE(ldd >= 32 * nmb_t, DINO_EINVAL, "gelu' buffer rows shorter than the sweep width");
     int act = p->n_act, items = 0;
     const int nt = sweep_nt(nmb_t);
@@ -490,7 +542,7 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
     if (nmb_t == 2) launch_sweep_t<2>(a, st);
     else if (nmb_t == 4) launch_sweep_t<4>(a, st);
     else if (nmb_t == 7) launch_sweep_t<7>(a, st);
-    else if (nmb_t == 13) launch_sweep_t<13>(a, st);
+    else if (nmb_t == 13) launch_sweep13(a, st);
     else launch_sweep_t<16>(a, st);
 }
 

@@ -392,6 +392,8 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         DINO_HIP(hipSetDevice(ctx->device));
         std::vector<Layer> ls(n_layers);
         __hip_bfloat16* new_tiles = nullptr;
+        size_t n_tile_u16 = 0;
+        int sweep_nmb_t = 0;
         try {
             for (int l = 0; l < n_layers; ++l) {
                 Layer& ly = ls[l];
@@ -424,6 +426,7 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
                 probe.layers.back().fan_out = fan_out[l];
             }
             const int nmb_t = sweep_nmb(&probe);
+            sweep_nmb_t = nmb_t;
             probe.layers.clear();
             // reverse processing order: layer n_layers-2 first, output blocks ascending
             std::vector<uint16_t> all;
@@ -434,6 +437,19 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
                 all.insert(all.end(), tiles.begin(), tiles.end());
             }
             if (!all.empty()) {
+                // followed by one row of 32 * nmb_t FP32 ones (the d row of layers without an
+                // activation) and the output layer's rows in the sweep's register order
+                n_tile_u16 = all.size();
+                auto push_f32 = [&](float v) {
+                    uint32_t u;
+                    std::memcpy(&u, &v, 4);
+                    all.push_back((uint16_t)(u & 0xFFFFu));
+                    all.push_back((uint16_t)(u >> 16));
+                };
+                for (int e = 0; e < 32 * nmb_t; ++e) push_f32(1.f);
+                std::vector<float> wpk;
+                pack_sweep_wout(ls[n_layers - 1].hostW, ls[n_layers - 1].fan_out, ls[n_layers - 1].fan_in, nmb_t, wpk);
+                for (float v : wpk) push_f32(v);
                 DINO_HIP(hipMalloc(&new_tiles, sizeof(uint16_t) * all.size()));
                 DINO_HIP(hipMemcpy(new_tiles, all.data(), sizeof(uint16_t) * all.size(), hipMemcpyHostToDevice));
             }
@@ -445,6 +461,8 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         free_layers(ctx->layers);
         if (ctx->sweep_tiles) (void)hipFree(ctx->sweep_tiles);
         ctx->sweep_tiles = new_tiles;
+        ctx->sweep_ones = new_tiles ? reinterpret_cast<const float*>(new_tiles + n_tile_u16) : nullptr;
+        ctx->sweep_wout = new_tiles ? ctx->sweep_ones + 32 * sweep_nmb_t : nullptr;
         ctx->layers = std::move(ls);
         ctx->r_in = fan_in[0];
         ctx->d_out = fan_out[n_layers - 1];

@@ -4,10 +4,12 @@ Target: the BF16 path (FP32 forward, BF16 Jacobian and GN Hessian, FP64 factor a
 MH) matches the FP64 posterior mean and pointwise variance fields (Rao-Blackwellised:
 Psi_r xbar and diag(Psi_r S Psi_r^T) + v_perp) to within 1% relative L2.
 
-* Well-mixing case (ResNet r = 40, d_y = 20, sigma = 0.2, dt = 0.1; 4096 chains x 1000
-  steps from prior draws, burn-in 20%): BF16 and FP64 run on coupled streams (same keys and initial
-  states). An FP64 replicate with another seed gives the Monte Carlo scale of the
-  comparison; the BF16 deviation must be within 1% and below that scale.
+* Well-mixing case (ResNet r = 40, d_y = 20, sigma = 0.5, dt = 0.1, about 43% accepted;
+  32768 chains x 1000 steps from prior draws, burn-in 20%): BF16 and FP64 run on coupled
+  streams (same keys and initial states). An FP64 replicate with another seed gives the
+  Monte Carlo scale of the comparison; the BF16 deviation must be within 1% and below
+  that scale. The chain count keeps the Monte Carlo scale well under 1% (at 4096 chains
+  and sigma = 0.2 the replicate itself differed by 1-2%, so 1% could not be resolved).
   The FP64 device path is the oracle's arithmetic (stage parity 1e-10, identical
   decisions on coupled streams, test_gpu_parity), so FP64 here stands for the oracle
   at a chain count the CPU oracle cannot run in a test.
@@ -49,10 +51,10 @@ def run(case, precision, steps, seed=None):
 
 
 def test_bf16_posterior_within_one_percent_of_fp64():
-    case = make_case("tiny", chains=4096, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
-                     bias_scale=0.3, noise_scale=0.2, dt=0.1)
+    case = make_case("tiny", chains=32768, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
+                     bias_scale=0.3, noise_scale=0.5, dt=0.1)
     steps = 1000
-    print("statistics: bf16 vs fp64, 4096 chains x 1000 steps", flush=True)
+    print("statistics: bf16 vs fp64, 32768 chains x 1000 steps", flush=True)
     f64 = run(case, "f64", steps)
     b16 = run(case, "bf16", steps)
     rep = run(case, "f64", steps, seed=case["prob"].seed + 1000)

@@ -256,18 +256,35 @@ void jac_sweep13_kernel(SweepArgs args) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)tb);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(tb >> 32));
     const uint32_t sw = __builtin_amdgcn_readfirstlane((uint32_t)wave_u * 1024u);
-    uint32_t goff[7];
-#pragma unroll
-    for (int q = 0; q < 7; ++q) goff[q] = (uint32_t)(lane * 16 + (wave_u + 4 * q) * 1024);
     bf16x8 zero;
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) zero[jj] = (__bf16)0.f;
+
+    // gelu' rows: when the wave's 32 columns span at most two chains, each layer block
+    // copies the next layer's two rows (416 FP32 each) into the wave's 4 KB LDS region,
+    // chunk k of 16 B (row k / 104) from lane k % 64 of copy k / 64; otherwise every
+    // layer reads its rows from global memory
+    const int col0 = (blockIdx.x * JAC_WAVES + wave_u) * 32;
+    const int c_first = col0 / args.dy;
+    const int c_last = min(col0 + 31, args.n_cols - 1) / args.dy;
+    const bool staged = col0 < args.n_cols && c_last - c_first <= 1;
+    uint32_t doff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int kk = min(u * 64 + lane, 207);
+        const int row = kk / 104;
+        doff[u] = (uint32_t)(min(c_first + row, c_last) * args.ldd * 4 + (kk - row * 104) * 16);
+    }
+    const uint32_t dm = __builtin_amdgcn_readfirstlane(lds_base + NBUF * ITEM + (uint32_t)wave_u * 4096u);
+    const float* drow_lds = reinterpret_cast<const float*>(reinterpret_cast<const char*>(tiles_lds) + NBUF * ITEM +
+                                                           wave_u * 4096) + (valid ? c - c_first : 0) * 416;
 
     int item = 0;
     for (int li = 0; li < args.n_layers; ++li) {
         const SweepLayer L = args.layer[li];
         bf16x8 bop[NKC];
-        const float4* drow = reinterpret_cast<const float4*>((L.d ? L.d + (long)c * args.ldd : args.ones) + 4 * h);
+        const float* dsrc = (li > 0 && staged && L.d) ? drow_lds : (L.d ? L.d + (long)c * args.ldd : args.ones);
+        const float4* drow = reinterpret_cast<const float4*>(dsrc + 4 * h);
 #pragma unroll
         for (int mb = 0; mb < NMB; ++mb)
 #pragma unroll
@@ -281,13 +298,21 @@ void jac_sweep13_kernel(SweepArgs args) {
             }
         const uint32_t sc = __builtin_amdgcn_readfirstlane(lds_base + (uint32_t)(item & (NBUF - 1)) * ITEM);
         // every scalar operand of the block is wave-uniform; readfirstlane places it in an SGPR
-        const uint32_t n_u = __builtin_amdgcn_readfirstlane((uint32_t)L.nmb_out);
-        const uint32_t zf_u = __builtin_amdgcn_readfirstlane(L.resid ? 0u : 1u);
+        const uint32_t n_u =
+            __builtin_amdgcn_readfirstlane(((uint32_t)L.nmb_out & 0xffu) | ((uint32_t)(L.resid == 0) << 8));
         const int32_t tl_u = __builtin_amdgcn_readfirstlane(args.n_items - (NBUF - 1) - item);
         const uint32_t so_u = __builtin_amdgcn_readfirstlane((uint32_t)(item + NBUF - 1) * ITEM);
         const uint32_t se_u = __builtin_amdgcn_readfirstlane(sb + NBUF * ITEM);
         const uint32_t sz_u = __builtin_amdgcn_readfirstlane(sb + (NBUF - 1) * ITEM);
-        sweep_layer13(lam, bop, n_u, zf_u, tl_u, sc, so_u, lo, hi, sb, se_u, sz_u, sw, (uint32_t)lane * 16u, goff, zero);
+        const float* dnext = li + 1 < args.n_layers ? args.layer[li + 1].d : nullptr;
+        const uint32_t df_u = __builtin_amdgcn_readfirstlane((staged && dnext) ? 1u : 0u);
+        const uint64_t dsb = (uint64_t)(uintptr_t)(dnext ? dnext : args.ones);
+        // (readfirstlane returns int: each half goes through uint32_t so that the low half is
+        // not sign-extended into the high one)
+        const uint64_t dsb_u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(dsb >> 32)) << 32) |
+                               (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)dsb);
+        sweep_layer13(lam, bop, n_u, tl_u, sc, so_u, lo, hi, sb, se_u, sz_u, sw, (uint32_t)lane * 16u, zero,
+                      df_u, dsb_u, dm, doff);
         item += L.nmb_out;
     }
     // B[col][m] = winv_i Lambda_0^T[m][col] (rows of ldb = 32 * nmb_last BF16). The wave's 32
@@ -489,7 +514,8 @@ static void launch_sweep_t(const SweepArgs& a, hipStream_t st) {
 }
 
 static void launch_sweep13(const SweepArgs& a, hipStream_t st) {
-    const size_t lds = (size_t)sweep_nbuf(13) * sweep_nt(13) * 64 * sizeof(bf16x8);
+    // tile ring + one 4 KB gelu' region per wave
+    const size_t lds = (size_t)sweep_nbuf(13) * sweep_nt(13) * 64 * sizeof(bf16x8) + JAC_WAVES * 4096;
     static bool attr = false;
     if (!attr) {
         DINO_HIP(hipFuncSetAttribute((const void*)jac_sweep13_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -41,24 +41,70 @@ PEAKS = {  # MI355X published peaks
 
 # device kernel of each stage on the mixed-precision path (rocprofv3 kernel names)
 STAGE_KERNEL = {
-    "proposal": "propose_kernel", "forward": "fwd_layer_kernel", "jacobian": "jac_sweep_bf16_kernel",
+    "proposal": "propose_kernel", "forward": "fwd_mfma_kernel", "jacobian": "jac_sweep_bf16_kernel",
     "misfit_ppg": "residual_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_reg_kernel",
-    "accept": "accept_kernel", "complement": "complement_kernel", "trace": "trace_kernel",
+    "accept": "accept_kernel", "complement": "complement_kernel", "trace": "finish_kernel",
 }
-KERNEL_SOURCES = {"cholesky_reg_kernel": "kernels_chain.hip", "propose_kernel": "kernels_chain.hip",
-                  "accept_kernel": "kernels_chain.hip", "complement_kernel": "kernels_chain.hip",
-                  "finish_kernel": "kernels_chain.hip", "jac_sweep_bf16_kernel": "kernels_mfma.hip",
-                  "hess_bf16_kernel": "kernels_mfma.hip", "residual_kernel": "kernels_mfma.hip",
-                  "fwd_layer_kernel": "kernels_geometry.hip"}
+# observation-space form (d_y < r): Gram matrix, d_y x d_y factor and Woodbury kernels
+STAGE_KERNEL_DUAL = dict(STAGE_KERNEL, proposal="propose_dual_kernel", accept="accept_dual_kernel",
+                         gn_hessian="gram_bf16_kernel")
+# the width-416 sweep (layers of 401..416 units) has its own kernel
+SWEEP416_KERNEL = "jac_sweep13_kernel"
+KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "propose_kernel": ["kernels_chain.hip"],
+                  "accept_kernel": ["kernels_chain.hip"], "complement_kernel": ["kernels_chain.hip"],
+                  "finish_kernel": ["kernels_chain.hip"], "propose_dual_kernel": ["kernels_chain.hip"],
+                  "accept_dual_kernel": ["kernels_chain.hip"], "jac_sweep_bf16_kernel": ["kernels_mfma.hip"],
+                  "jac_sweep13_kernel": ["kernels_mfma.hip", "sweep_asm.inc"],
+                  "hess_bf16_kernel": ["kernels_mfma.hip"], "gram_bf16_kernel": ["kernels_mfma.hip"],
+                  "residual_kernel": ["kernels_mfma.hip"], "fwd_mfma_kernel": ["kernels_geometry.hip"],
+                  "fwd_layer_kernel": ["kernels_geometry.hip"]}
+
+
+def source_sha256(kernel):
+    """SHA-256 over the source files of `kernel` (None when one of them is missing)."""
+    h = hashlib.sha256()
+    names = KERNEL_SOURCES.get(kernel)
+    if not names:
+        return None
+    for name in names:
+        path = os.path.join(ROOT, "paper_2403_08220_amd", "csrc", name)
+        if not os.path.isfile(path):
+            return None
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stage_kernel(stage, dual, width):
+    k = (STAGE_KERNEL_DUAL if dual else STAGE_KERNEL)[stage]
+    if stage == "jacobian" and 400 < width <= 416:
+        k = SWEEP416_KERNEL
+    return k
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec):
+def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=False):
     """Algorithmic work of one step of a stage over C chains.
-    Returns (amount, unit, bound, peak); the per-chain figures are in the design notes."""
+    Returns (amount, unit, bound, peak); the per-chain figures are in the design notes.
+    dual: the observation-space form (Gram matrix I + B B^T, d_y x d_y factor)."""
+    if dual and stage == "gn_hessian":
+        flops = C * 2.0 * (dy * (dy + 1) / 2.0 * r + dy * r)  # lower half of B B^T, and B^T e
+        if prec == "bf16":
+            return flops, "TFLOP/s", "mfma", PEAKS["bf16_TFLOPs"]
+        return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
+    if dual and stage == "cholesky":
+        return C * dy ** 3 / 3.0, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
+    if dual and stage in ("proposal", "accept"):
+        # one read of the chain's B (BF16 on the mixed path, FP64 otherwise) and of the lower
+        # triangle of its FP64 d_y x d_y factor; on acceptance the proposal's B is copied
+        bsz = 2.0 if prec == "bf16" else 8.0
+        per = dy * r * bsz + dy * (dy + 1) / 2.0 * 8.0
+        if stage == "accept":
+            per += accepted_frac * 2.0 * dy * r * bsz
+        return C * per, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "jacobian":
         flops = C * 2.0 * (L_res * dy * w * w + dy * w * r)
         if prec == "bf16":
@@ -280,12 +326,8 @@ def traffic_record(kernel, workload_tag):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    src = os.path.join(ROOT, "paper_2403_08220_amd", "csrc", KERNEL_SOURCES.get(kernel, ""))
-    if not os.path.isfile(src):
-        return None
-    with open(src, "rb") as fh:
-        sha = hashlib.sha256(fh.read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    sha = source_sha256(kernel)
+    if sha is None or rec.get("source_sha256") != sha:
         return None
     return rec.get("bytes_per_launch")
 
@@ -354,11 +396,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="m
     with open(os.path.join(prof, f"step_kernels_{workload_tag}_traffic.md"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     for base, rec in records.items():
-        src = os.path.join(ROOT, "paper_2403_08220_amd", "csrc", KERNEL_SOURCES.get(base, ""))
-        if not os.path.isfile(src):
+        sha = source_sha256(base)
+        if sha is None:
             continue
-        with open(src, "rb") as fh:
-            sha = hashlib.sha256(fh.read()).hexdigest()
         with open(os.path.join(prof, f"{base}_{workload_tag}_traffic.json"), "w") as fh:
             json.dump(dict(kernel=base, grid=rec["grid"], bytes_per_launch=round(rec["read_bytes"] + rec["write_bytes"]),
                            read_bytes=round(rec["read_bytes"]), write_bytes=round(rec["write_bytes"]),
@@ -434,10 +474,12 @@ def main():
         log(f"bench: f64 path: {r64['wall_s']:.3f} s, accept {r64['accept_rate']:.3f}")
 
     prof = res.get("profile", {})
+    # the observation-space form is taken when asked for, or by "auto" when d_y < r
+    dual = args.factorization == "dual" or (args.factorization == "auto" and w.d_y < w.r)
     stages = {}
     for name, v in prof.items():
         amt, unit, bound, peak = stage_work(name, w.width, C, w.r, w.d_y, L_res, res["accept_rate"],
-                                            w.d_m - w.r, args.precision)
+                                            w.d_m - w.r, args.precision, dual=dual)
         t = v["ms_per_step"] * 1e-3
         ach = (amt / t / (1e12 if unit == "TFLOP/s" else 1e9)) if t > 0 else 0.0
         stages[name] = dict(ms=round(v["ms_per_step"], 4), launches=v["launches"], bound=bound,
@@ -446,7 +488,7 @@ def main():
     if stages:
         dom = max(stages, key=lambda k: stages[k]["ms"])
         s = stages[dom]
-        kern = STAGE_KERNEL[dom] if args.precision == "bf16" else dom
+        kern = stage_kernel(dom, dual, w.width) if args.precision == "bf16" else dom
         roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4),

@@ -18,6 +18,35 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Value of lane `lane` (wave-uniform) of a double, through two v_readlane (a scalar
+// broadcast, far shorter latency than a cross-lane permute).
+__device__ __forceinline__ double lane_bcast(double v, int lane) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sums over the block of four values per thread at once; red must hold 4 * TPB/64
+// doubles.
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* red) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) red[4 * wave + q] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < TPB / 64; ++k) t += red[4 * k + q];
+        v[q] = t;
+    }
+}
+
 // Sum over the block of one value per thread; red must hold TPB/64 doubles.
 __device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
@@ -70,7 +99,7 @@ __device__ void lt_solve(const double* __restrict__ L, const double* invd, int r
 #pragma unroll
             for (int jj = SB - 1; jj >= 0; --jj) {
                 if (jj < nb) {
-                    const double xj = __shfl(a * invd[b0 + jj], jj);
+                    const double xj = lane_bcast(a, jj) * invd[b0 + jj];
                     if (lane == jj) sol = xj;
                     if (lane < jj) a -= col[jj] * xj;
                 }
@@ -151,7 +180,7 @@ __device__ void l_solve(const double* __restrict__ L, const double* invd, int r,
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj) {
                 if (jj < nb) {
-                    const double wj = __shfl(a * invd[b0 + jj], jj);  // valid on lane jj
+                    const double wj = lane_bcast(a, jj) * invd[b0 + jj];
                     if (lane == jj) sol = wj;
                     if (lane > jj) a -= row[jj] * wj;
                 }
@@ -627,23 +656,135 @@ __device__ void bt_times(const TB* __restrict__ B, int dy, int r, int ldb, const
     __syncthreads();
 }
 
-// Scratch of the dual kernels: vectors of length r and d_y in dynamic LDS, followed
-// (BF16 path) by the chain's B (d_y x ldb), staged once so that every product reads LDS.
-constexpr int DU_NR = 8, DU_NY = 6;
-__host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool stage_bf16) {
-    const size_t b = stage_bf16 ? ((size_t)dy * ldb * sizeof(__hip_bfloat16) + 7) / 8 : 0;
-    return (size_t)DU_NR * r + (size_t)DU_NY * dy + SB + (size_t)8 * SB + TPB / 64 + b;
+// BF16 B staged in LDS (row stride ldl = ldb + 8: rows 16 bytes apart in bank order, so
+// that the 16-byte row reads of b_times from 32 rows spread over the banks; columns
+// r..ldb are zero). Two BF16 values of a 32-bit word, as doubles (exact).
+__device__ __forceinline__ double bf_lo(uint32_t u) { return (double)__uint_as_float(u << 16); }
+__device__ __forceinline__ double bf_hi(uint32_t u) { return (double)__uint_as_float(u & 0xFFFF0000u); }
+
+// y_i = sum_{j<r} B[i][j] v_j and, if TWO, y2_i = sum_j B[i][j] v2_j, B in LDS. P
+// consecutive threads share a row, each taking every P-th 16-byte chunk of it; the P
+// partial sums meet by xor shuffles inside the wave (no per-row reduction over 64 lanes).
+template <bool TWO>
+__device__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
+                            const double* v2, double* y2) {
+    const int nfull = r >> 3, nch = (r + 7) >> 3;
+    int P = 1;
+    while (P < 8 && 2 * P * dy <= TPB && 2 * P <= nch) P *= 2;
+    for (int t0 = 0; t0 < dy * P; t0 += TPB) {
+        const int t = t0 + (int)threadIdx.x;
+        const int i = t / P, p = t & (P - 1);
+        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+        if (i < dy) {
+            const uint4* row = reinterpret_cast<const uint4*>(B + (long)i * ldl);
+            for (int kq = p; kq < nch; kq += P) {
+                const uint4 q = row[kq];
+                const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+                const double* vv = v + 8 * kq;
+                const double* ww = TWO ? v2 + 8 * kq : nullptr;
+                if (kq < nfull) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double blo = bf_lo(w4[e]), bhi = bf_hi(w4[e]);
+                        a0 += blo * vv[2 * e];
+                        a1 += bhi * vv[2 * e + 1];
+                        if (TWO) {
+                            c0 += blo * ww[2 * e];
+                            c1 += bhi * ww[2 * e + 1];
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const double blo = bf_lo(w4[e]), bhi = bf_hi(w4[e]);
+                        if (8 * kq + 2 * e < r) {
+                            a0 += blo * vv[2 * e];
+                            if (TWO) c0 += blo * ww[2 * e];
+                        }
+                        if (8 * kq + 2 * e + 1 < r) {
+                            a1 += bhi * vv[2 * e + 1];
+                            if (TWO) c1 += bhi * ww[2 * e + 1];
+                        }
+                    }
+                }
+            }
+        }
+        double acc = a0 + a1, acc2 = c0 + c1;
+        for (int o = 1; o < P; o <<= 1) {
+            acc += __shfl_xor(acc, o);
+            if (TWO) acc2 += __shfl_xor(acc2, o);
+        }
+        if (i < dy && p == 0) {
+            y[i] = acc;
+            if (TWO) y2[i] = acc2;
+        }
+    }
+    __syncthreads();
 }
 
-// BF16 B rows are copied to LDS (16-byte moves) and used from there; FP64 B is read
-// from global memory as it is.
+// w_j = sum_i B[i][j] z_i (j < r), B in LDS: a thread takes a column pair (4-byte reads,
+// consecutive across lanes) and every Q-th row; the Q row shares are added in turn.
+__device__ void bt_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
+    const int np = (r + 1) >> 1;
+    const int Q = max(1, min(TPB / np, dy));
+    const int tid = threadIdx.x, jp = tid % np, q = tid / np;
+    const bool act = q < Q;
+    double a0 = 0.0, a1 = 0.0;
+    if (act)
+        for (int i = q; i < dy; i += Q) {
+            const uint32_t u = *reinterpret_cast<const uint32_t*>(B + (long)i * ldl + 2 * jp);
+            const double zi = z[i];
+            a0 += bf_lo(u) * zi;
+            a1 += bf_hi(u) * zi;
+        }
+    const int j = 2 * jp;
+    for (int qq = 0; qq < Q; ++qq) {
+        if (act && q == qq) {
+            w[j] = (qq == 0 ? 0.0 : w[j]) + a0;
+            if (j + 1 < r) w[j + 1] = (qq == 0 ? 0.0 : w[j + 1]) + a1;
+        }
+        __syncthreads();
+    }
+}
+
+// The BF16 instances read B from LDS (staged with row stride ldl).
+__device__ __forceinline__ void b_times(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y) {
+    b_times_lds<false>(B, dy, r, ldl, v, y, nullptr, nullptr);
+}
+__device__ __forceinline__ void bt_times(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
+    bt_times_lds(B, dy, r, ldl, z, w);
+}
+// y = B v and y2 = B v2 in one pass over B
+__device__ __forceinline__ void b_times2(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
+                                         const double* v2, double* y2) {
+    b_times_lds<true>(B, dy, r, ldl, v, y, v2, y2);
+}
+__device__ __forceinline__ void b_times2(const double* B, int dy, int r, int ldb, const double* v, double* y,
+                                         const double* v2, double* y2) {
+    b_times(B, dy, r, ldb, v, y);
+    b_times(B, dy, r, ldb, v2, y2);
+}
+
+// Scratch of the dual kernels: vectors of length r and d_y in dynamic LDS, followed
+// (BF16 path) by the chain's B (d_y x ldl), staged once so that every product reads LDS.
+constexpr int DU_NR = 8, DU_NY = 6;
+constexpr int DU_RED = 4 * (TPB / 64);  // block_sum4 scratch
+__host__ __device__ inline int dual_ldl(int ldb, bool stage_bf16) { return stage_bf16 ? ldb + 8 : ldb; }
+__host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool stage_bf16) {
+    const size_t b = stage_bf16 ? ((size_t)dy * dual_ldl(ldb, true) * sizeof(__hip_bfloat16) + 7) / 8 : 0;
+    return (size_t)DU_NR * r + (size_t)DU_NY * dy + SB + (size_t)8 * SB + DU_RED + b;
+}
+
+// BF16 B rows are copied to LDS (16-byte moves, row stride ldb + 8) and used from there;
+// FP64 B is read from global memory as it is.
 __device__ __forceinline__ const double* stage_b(const double* Bg, int, int, double*) { return Bg; }
 __device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* Bg, int dy, int ldb, double* lds) {
     __hip_bfloat16* Bl = reinterpret_cast<__hip_bfloat16*>(lds);
-    const long n16 = (long)dy * ldb / 8;  // ldb is a multiple of 32
+    const int c16 = ldb / 8, l16 = dual_ldl(ldb, true) / 8;  // 16-byte chunks per row (ldb: a multiple of 32)
+    const long n16 = (long)dy * c16;
     const uint4* src = reinterpret_cast<const uint4*>(Bg);
     uint4* dst = reinterpret_cast<uint4*>(Bl);
-    for (long e = threadIdx.x; e < n16; e += TPB) dst[e] = src[e];
+    for (long e = threadIdx.x; e < n16; e += TPB) dst[(e / c16) * l16 + e % c16] = src[e];
     __syncthreads();
     return Bl;
 }
@@ -665,24 +806,19 @@ __device__ double dual_rho0(const TB* Ba, int ldb, const double* Ka, const doubl
         mh[j] = (b[j] - s * a[j]) / beta;
     }
     __syncthreads();
-    b_times(Ba, dy, r, ldb, v, t2);
+    b_times2(Ba, dy, r, ldb, v, t2, mh, t1);
     l_solve(Ka, invd, dy, t2, z, acc_s);
-    b_times(Ba, dy, r, ldb, mh, t1);
-    double vv = 0.0, mv = 0.0;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};  // |v|^2, mh.v, |z|^2, |B mh|^2
     for (int j = tid; j < r; j += TPB) {
-        vv += v[j] * v[j];
-        mv += mh[j] * v[j];
+        sums[0] += v[j] * v[j];
+        sums[1] += mh[j] * v[j];
     }
-    double zz = 0.0, bm = 0.0;
     for (int i = tid; i < dy; i += TPB) {
-        zz += z[i] * z[i];
-        bm += t1[i] * t1[i];
+        sums[2] += z[i] * z[i];
+        sums[3] += t1[i] * t1[i];
     }
-    vv = block_sum(vv, red);
-    mv = block_sum(mv, red);
-    zz = block_sum(zz, red);
-    bm = block_sum(bm, red);
-    return -(dt / 8.0) * (vv - zz) + 0.5 * sqrt(dt) * mv - 0.5 * bm + logdet_a;
+    block_sum4(sums, red);
+    return -(dt / 8.0) * (sums[0] - sums[2]) + 0.5 * sqrt(dt) * sums[1] - 0.5 * sums[3] + logdet_a;
 }
 
 // Proposal: u = beta (xi_1 + B^T xi_2) - (1 - s)(x + g),  xp = x + (I + H)^-1 u,
@@ -716,7 +852,8 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         if (lfwd && tid == 0) lfwd[c] = 0.0;
         return;
     }
-    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + TPB / 64);
+    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + DU_RED);
+    const int ldl = dual_ldl(ldb, sizeof(TB) == 2);  // row stride of Bc
     const double* Kc = Kbuf + (long)c * strideK + slot_offset(slot, slot_xor, slot_stride, c);
     load_inv_diag(Kc, dy, invd);
     for (int j = tid; j < r; j += TPB) {
@@ -738,20 +875,20 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         }
     }
     __syncthreads();
-    bt_times(Bc, dy, r, ldb, xi2, w);
+    bt_times(Bc, dy, r, ldl, xi2, w);
     for (int j = tid; j < r; j += TPB) u[j] = beta * (xi1[j] + w[j]) - (1.0 - s) * (xs[j] + gs[j]);
     __syncthreads();
-    b_times(Bc, dy, r, ldb, u, y);
+    b_times(Bc, dy, r, ldl, u, y);
     l_solve(Kc, invd, dy, y, z1, acc);
     lt_solve(Kc, invd, dy, z1, t1, part);
-    bt_times(Bc, dy, r, ldb, t1, w);
+    bt_times(Bc, dy, r, ldl, t1, w);
     for (int j = tid; j < r; j += TPB) {
         xn[j] = xs[j] + u[j] - w[j];
         xp[(long)c * r + j] = xn[j];
     }
     __syncthreads();
     if (lfwd) {
-        const double l = dual_rho0(Bc, ldb, Kc, invd, r, dy, dt, s, beta, xs, xn, gs, logdet[c], v, mh, t1, t2, z1,
+        const double l = dual_rho0(Bc, ldl, Kc, invd, r, dy, dt, s, beta, xs, xn, gs, logdet[c], v, mh, t1, t2, z1,
                                    acc, red);
         if (tid == 0) lfwd[c] = l;
     }
@@ -785,7 +922,8 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     const int other = cur[c] ^ 1;
     const double* Kp = Kbuf + (long)other * half + c * kk;
     const TB* Bpg = Bp + (long)c * dy * ldb;
-    const TB* Bpc = stage_b(Bpg, dy, ldb, red + TPB / 64);
+    const TB* Bpc = stage_b(Bpg, dy, ldb, red + DU_RED);
+    const int ldl = dual_ldl(ldb, sizeof(TB) == 2);  // row stride of Bpc
     for (int j = tid; j < r; j += TPB) {
         xs[j] = x[(long)c * r + j];
         ps[j] = xp[(long)c * r + j];
@@ -807,7 +945,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
         double rev = 0.0;
         if (okc) {
             load_inv_diag(Kp, dy, invd);
-            rev = dual_rho0(Bpc, ldb, Kp, invd, r, dy, dt, s, beta, ps, xs, ga, logdetp[c], v, mh, t1, t2, z, acc,
+            rev = dual_rho0(Bpc, ldl, Kp, invd, r, dy, dt, s, beta, ps, xs, ga, logdetp[c], v, mh, t1, t2, z, acc,
                             red);
         }
         if (tid == 0) {

@@ -347,7 +347,8 @@ int sweep_nmb(const dino_ctx* ctx);
 void pack_sweep_wout(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<float>& out);
 void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int nmb_t, std::vector<uint16_t>& out,
                       int& nmb_out);
-void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hipStream_t st);
+// FP32 forward; the first layer reads x64 (FP64, rounded on load) if given, else xf.
+void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st);
 void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st);
 void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
                       const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);

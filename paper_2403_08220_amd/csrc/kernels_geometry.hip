@@ -263,16 +263,19 @@ static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 6
 typedef __attribute__((ext_vector_type(16))) float f32x16g;
 
 __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, const float* __restrict__ in, int ldin,
+                                                       const double* __restrict__ in64,
                                                        const float* __restrict__ W, const float* __restrict__ b,
                                                        int kind, float* __restrict__ out, int ldout,
                                                        float* __restrict__ dprime, int ldd) {
-    __shared__ float red[3][64][17];
+    // in64 (first layer): the FP64 states, rounded to FP32 as they are loaded
+    __shared__ float red[4][64][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
     const int arow = m0 + l32, wrow = n0 + l32;
     const bool aok = arow < M, wok = wrow < N;
-    const float* ap = in + (long)(aok ? arow : 0) * ldin;
+    const float* ap = in64 ? nullptr : in + (long)(aok ? arow : 0) * ldin;
+    const double* ap64 = in64 ? in64 + (long)(aok ? arow : 0) * ldin : nullptr;
     const float* wp = W + (long)(wok ? wrow : 0) * K;
     const bool vec = ((ldin & 3) == 0) && ((K & 3) == 0);
     f32x16g acc;
@@ -282,13 +285,26 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
     auto load = [&](int t, float4& a4, float4& w4) {
         const int k = 8 * t + 4 * h;
         if (vec && k + 3 < K) {
-            a4 = aok ? *reinterpret_cast<const float4*>(ap + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (ap64) {
+                const double2 lo = aok ? *reinterpret_cast<const double2*>(ap64 + k) : make_double2(0.0, 0.0);
+                const double2 hi = aok ? *reinterpret_cast<const double2*>(ap64 + k + 2) : make_double2(0.0, 0.0);
+                a4 = make_float4((float)lo.x, (float)lo.y, (float)hi.x, (float)hi.y);
+            } else {
+                a4 = aok ? *reinterpret_cast<const float4*>(ap + k) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
             w4 = wok ? *reinterpret_cast<const float4*>(wp + k) : make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
-            a4.x = (aok && k < K) ? ap[k] : 0.f;
-            a4.y = (aok && k + 1 < K) ? ap[k + 1] : 0.f;
-            a4.z = (aok && k + 2 < K) ? ap[k + 2] : 0.f;
-            a4.w = (aok && k + 3 < K) ? ap[k + 3] : 0.f;
+            if (ap64) {
+                a4.x = (aok && k < K) ? (float)ap64[k] : 0.f;
+                a4.y = (aok && k + 1 < K) ? (float)ap64[k + 1] : 0.f;
+                a4.z = (aok && k + 2 < K) ? (float)ap64[k + 2] : 0.f;
+                a4.w = (aok && k + 3 < K) ? (float)ap64[k + 3] : 0.f;
+            } else {
+                a4.x = (aok && k < K) ? ap[k] : 0.f;
+                a4.y = (aok && k + 1 < K) ? ap[k + 1] : 0.f;
+                a4.z = (aok && k + 2 < K) ? ap[k + 2] : 0.f;
+                a4.w = (aok && k + 3 < K) ? ap[k + 3] : 0.f;
+            }
             w4.x = (wok && k < K) ? wp[k] : 0.f;
             w4.y = (wok && k + 1 < K) ? wp[k + 1] : 0.f;
             w4.z = (wok && k + 2 < K) ? wp[k + 2] : 0.f;
@@ -319,28 +335,26 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
             mfma4(a4, w4);
         }
     }
-    if (wave > 0) {
+    // split-K partial sums meet in LDS; wave w finishes registers 4w..4w+3 of the tile
+    // (rows m0 + 8w + 4h + 0..3), so the epilogue runs on all four waves
 #pragma unroll
-        for (int q = 0; q < 16; ++q) red[wave - 1][lane][q] = acc[q];
-    }
+    for (int q = 0; q < 16; ++q) red[wave][lane][q] = acc[q];
     __syncthreads();
-    if (wave != 0) return;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] += red[0][lane][q] + red[1][lane][q] + red[2][lane][q];
     const int n = n0 + l32;
     if (n >= N) return;
     const float bn = b ? b[n] : 0.f;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int m = m0 + 8 * (q >> 2) + 4 * h + (q & 3);
+    for (int qq = 0; qq < 4; ++qq) {
+        const int q = 4 * wave + qq;
+        const int m = m0 + 8 * wave + 4 * h + qq;
         if (m >= M) continue;
-        const float z = acc[q] + bn;
+        const float z = red[0][lane][q] + red[1][lane][q] + red[2][lane][q] + red[3][lane][q] + bn;
         float o;
         if (kind == DINO_LAYER_LINEAR) {
             o = z;
         } else {
             o = gelu_t<float>(z);
-            if (kind == DINO_LAYER_RESID) o += in[(long)m * ldin + n];
+            if (kind == DINO_LAYER_RESID) o += in64 ? (float)in64[(long)m * ldin + n] : in[(long)m * ldin + n];
             if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
         }
         out[(long)m * ldout + n] = o;
@@ -443,10 +457,10 @@ void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipS
 }
 
 // FP32 forward of the mixed-precision path: gelu'(z) into d32 (row length ldd32).
-void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hipStream_t st) {
+void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
     const int L = (int)ctx->layers.size();
-    const float* in = xf;
+    const float* in = x64 ? nullptr : xf;
     int ldin = p->r;
     int act = 0;
     for (int l = 0; l < L; ++l) {
@@ -457,8 +471,9 @@ void launch_forward32(dino_problem* p, int n, const float* xf, float* f_out, hip
         const int N = last ? p->d_y : ly.fan_out;
         float* dp = nullptr;
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
+        // the first layer reads the FP64 states (x64) when given, else the FP32 copy xf
         hipLaunchKernelGGL(fwd_mfma_kernel, dim3((N + 31) / 32, (n + 31) / 32), dim3(256), 0, st, n, ly.fan_in, N,
-                           in, ldin, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
+                           in, ldin, l == 0 ? x64 : nullptr, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;

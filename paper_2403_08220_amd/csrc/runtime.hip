@@ -185,8 +185,7 @@ static void stage_forward(dino_problem* p, int n, const double* x, double* f64, 
     if (p->desc.precision == DINO_PREC_F64) {
         launch_forward(p, n, x, f64, st);
     } else {
-        launch_to_float((long)n * p->r, x, p->xpf, st);
-        launch_forward32(p, n, p->xpf, p->f32, st);
+        launch_forward32(p, n, nullptr, x, p->f32, st);  // the first layer rounds x to FP32 as it loads
     }
 }
 
@@ -656,7 +655,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const long half = (long)p->C * rr;
     const int L = (int)p->ctx->layers.size();
     const bool f64 = p->desc.precision == DINO_PREC_F64;
-    const int32_t launches[DINO_N_STAGES] = {1, f64 ? L : L + 1, f64 ? L : 1, 1, 1, 1, 1, p->z ? 1 : 0, 1};
+    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, 1, 1, 1, 1, p->z ? 1 : 0, 1};
     auto mark = [&](int i) {
         if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
     };

@@ -423,6 +423,112 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
     }
 }
 
+// One wave per chain for k <= 8 MB (k = 104 at MB = 13): lane (g, q) = (lane / 8, lane % 8)
+// holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs
+// c <= m only, 91 doubles at MB = 13). Column j is published through LDS by its eight
+// owners (q = j % 8) and read back by every lane; there is no barrier between waves
+// (a single wave, in-order LDS), so a column step costs one LDS round trip, a square
+// root and the rank-1 update of the lane's share of the trailing block.
+// Column j = 8 PH + JJ of the single-wave factorisation (compile-time PH, JJ, so that
+// every register index is a constant).
+template <int MB, int PH, int JJ>
+__device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
+                                               bool& bad) {
+    constexpr int j = 8 * PH + JJ;
+    if (j >= r) return;
+    if (q == JJ) {
+#pragma unroll
+        for (int m = PH; m < MB; ++m) col[g + 8 * m] = v[m][PH];
+    }
+    __syncthreads();
+    const double piv = col[j];
+    bad |= !(piv > 0.0);
+    if (g == 0 && q == 0) pivs[j] = piv;  // logs are taken after the sweep, off the critical path
+    // 1/sqrt(piv): hardware estimate and two Newton steps (relative error ~1 ulp)
+    double isq = __builtin_amdgcn_rsq(piv);
+    isq = isq * (1.5 - 0.5 * piv * isq * isq);
+    isq = isq * (1.5 - 0.5 * piv * isq * isq);
+    const double rs = piv * isq;
+    double li[MB], lk[MB];
+#pragma unroll
+    for (int m = PH; m < MB; ++m) {
+        const int i = g + 8 * m;
+        li[m] = (i > j) ? col[i] * isq : 0.0;
+        const int kk = q + 8 * m;
+        lk[m] = (kk > j) ? col[kk] * isq : 0.0;
+    }
+#pragma unroll
+    for (int m = PH; m < MB; ++m)
+#pragma unroll
+        for (int cc = PH; cc <= m; ++cc) v[m][cc] -= li[m] * lk[cc];
+    if (q == JJ) {
+#pragma unroll
+        for (int m = PH; m < MB; ++m) {
+            const int i = g + 8 * m;
+            if (i == j) v[m][PH] = rs;
+            else if (i > j) v[m][PH] *= isq;
+        }
+    }
+    __syncthreads();
+}
+
+template <int MB, int PH, int JJ>
+struct CholWaveSteps {
+    __device__ __forceinline__ static void run(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
+                                               bool& bad) {
+        chol_wave_step<MB, PH, JJ>(v, col, pivs, r, g, q, bad);
+        if constexpr (JJ + 1 < 8) CholWaveSteps<MB, PH, JJ + 1>::run(v, col, pivs, r, g, q, bad);
+        else if constexpr (PH + 1 < MB) CholWaveSteps<MB, PH + 1, 0>::run(v, col, pivs, r, g, q, bad);
+    }
+};
+
+// One wave per chain for k <= 8 MB (k = 104 at MB = 13): lane (g, q) = (lane / 8, lane % 8)
+// holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs
+// c <= m only, 91 doubles at MB = 13). Column j is published through LDS by its eight
+// owners (q = j % 8) and read back by every lane; there is no barrier between waves
+// (a single wave, in-order LDS), so a column step costs one LDS round trip, a square
+// root and the rank-1 update of the lane's share of the trailing block.
+template <int MB>
+__global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, long strideA, const int32_t* slot,
+                                                           int slot_xor, long slot_stride, double* logdet,
+                                                           int32_t* ok) {
+    __shared__ double col[8 * MB];
+    __shared__ double pivs[8 * MB];
+    const int c = blockIdx.x, lane = threadIdx.x;
+    const int g = lane >> 3, q = lane & 7;
+    double* a = A + (long)c * strideA + slot_offset(slot, slot_xor, slot_stride, c);
+    double v[MB][MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int i = g + 8 * m;
+#pragma unroll
+        for (int cc = 0; cc < MB; ++cc) {
+            const int kk = q + 8 * cc;
+            v[m][cc] = (cc <= m && i < r && kk <= i) ? a[(long)i * r + kk] : 0.0;
+        }
+    }
+    bool bad = false;
+    CholWaveSteps<MB, 0, 0>::run(v, col, pivs, r, g, q, bad);
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int i = g + 8 * m;
+#pragma unroll
+        for (int cc = 0; cc <= m; ++cc) {
+            const int kk = q + 8 * cc;
+            if (i < r && kk <= i) a[(long)i * r + kk] = v[m][cc];
+        }
+    }
+    __syncthreads();
+    double ls = 0.0;
+    for (int j = lane; j < r; j += 64) ls += log(pivs[j]);
+    ls = wave_sum(ls);
+    const bool any_bad = __any(bad);
+    if (lane == 0) {
+        if (logdet) logdet[c] = 0.5 * ls;
+        if (ok) ok[c] = any_bad ? 0 : 1;
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Reduced proposal: xp = L^-T (L^-1 [L L^T x - (1-s)(x + g)] + beta xi)
 //                      = L^-T (L^T x - (1-s) L^-1 (x + g) + beta xi),
@@ -1119,11 +1225,14 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
         attr_set = true;
     }
     if (r <= 32) {
-        hipLaunchKernelGGL((cholesky_reg_kernel<256, 4, 1>), dim3(n), dim3(256), 0, st, r, A, strideA, slot,
-                           slot_xor, slot_stride, logdet, ok);
-    } else if (r <= 64) {
-        hipLaunchKernelGGL((cholesky_reg_kernel<256, 8, 2>), dim3(n), dim3(256), 0, st, r, A, strideA, slot,
-                           slot_xor, slot_stride, logdet, ok);
+        hipLaunchKernelGGL((cholesky_wave_kernel<4>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
+                           slot_stride, logdet, ok);
+    } else if (r <= 56) {
+        hipLaunchKernelGGL((cholesky_wave_kernel<7>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
+                           slot_stride, logdet, ok);
+    } else if (r <= 104) {
+        hipLaunchKernelGGL((cholesky_wave_kernel<13>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
+                           slot_stride, logdet, ok);
     } else if (r <= 128) {
         hipLaunchKernelGGL((cholesky_reg_kernel<512, 8, 4>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
                            slot_xor, slot_stride, logdet, ok);

@@ -319,15 +319,17 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
     };
     constexpr int PRE = 16;  // chunks per wave with all loads issued before the products
     if (nchunk <= 4 * PRE) {
+        // wave w takes a contiguous quarter of K: its lanes read whole cache lines of their rows
+        const int per = (nchunk + 3) / 4;
         float4 a4[PRE], w4[PRE];
 #pragma unroll
         for (int u = 0; u < PRE; ++u) {
-            const int t = wave + 4 * u;
-            if (t < nchunk) load(t, a4[u], w4[u]);
+            const int t = wave * per + u;
+            if (u < per && t < nchunk) load(t, a4[u], w4[u]);
         }
 #pragma unroll
         for (int u = 0; u < PRE; ++u)
-            if (wave + 4 * u < nchunk) mfma4(a4[u], w4[u]);
+            if (u < per && wave * per + u < nchunk) mfma4(a4[u], w4[u]);
     } else {
         for (int t = wave; t < nchunk; t += 4) {
             float4 a4, w4;

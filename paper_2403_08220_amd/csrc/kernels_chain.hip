@@ -63,13 +63,21 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Backward substitution L^T x = b. Blocks from the bottom: rows of the block subtract
 // the solved part below through column reads (32 consecutive columns per row), then
 // lanes 0..SB-1 of wave 0 finish the block's transposed triangle.
-__device__ void lt_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* x,
+__device__ __forceinline__ void lt_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* x,
                          double* part) {
     const int tid = threadIdx.x;
     const int nblk = (r + SB - 1) / SB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
         const int b0 = bi * SB;
         const int nb = min(SB, r - b0);
+        // wave 0 issues the loads of the block's triangle before the partial sums
+        double col[SB];
+        if (tid < 64) {
+            const int lane = tid;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                col[jj] = (lane < nb && jj >= lane && jj < nb) ? L[(long)(b0 + jj) * r + b0 + lane] : 0.0;
+        }
         {
             const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
             double acc = 0.0;
@@ -81,19 +89,12 @@ __device__ void lt_solve(const double* __restrict__ L, const double* invd, int r
         __syncthreads();
         if (tid < 64) {
             const int lane = tid;
-            double col[SB];
             double a = 0.0;
             if (lane < nb) {
                 double s = 0.0;
 #pragma unroll
                 for (int g = 0; g < 8; ++g) s += part[g * SB + lane];
                 a = b[b0 + lane] - s;
-#pragma unroll
-                for (int jj = 0; jj < SB; ++jj)
-                    col[jj] = (jj >= lane && jj < nb) ? L[(long)(b0 + jj) * r + b0 + lane] : 0.0;
-            } else {
-#pragma unroll
-                for (int jj = 0; jj < SB; ++jj) col[jj] = 0.0;
             }
             double sol = 0.0;
 #pragma unroll
@@ -119,7 +120,7 @@ __device__ __forceinline__ void load_inv_diag(const double* __restrict__ L, int 
 // out1_j = sum_{i >= j} L[i][j] v1_i (L^T v1) and, if v2, out2 = L^T v2, in one pass
 // over L. Waves take rows i = wave (mod 4); lanes read 64 consecutive columns of a row;
 // partial sums are reduced through part (4 r doubles per product).
-__device__ void lt_matvec2(const double* __restrict__ L, int r, const double* v1, double* out1, const double* v2,
+__device__ __forceinline__ void lt_matvec2(const double* __restrict__ L, int r, const double* v1, double* out1, const double* v2,
                            double* out2, double* part) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int jb = 0; jb < r; jb += 64) {
@@ -149,11 +150,20 @@ __device__ void lt_matvec2(const double* __restrict__ L, int r, const double* v1
 // Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
 // a block first subtract the already solved part (8 threads per row), then lanes
 // 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
-__device__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
+__device__ __forceinline__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
                         double* acc_s) {
     const int tid = threadIdx.x;
     for (int b0 = 0; b0 < r; b0 += SB) {
         const int nb = min(SB, r - b0);
+        // wave 0 issues the loads of the block's triangle before the partial sums, so that
+        // both wait for memory once
+        double row[SB];
+        if (tid < 64) {
+            const int lane = tid;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+        }
         {
             const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
             const int i = b0 + il;
@@ -171,11 +181,7 @@ __device__ void l_solve(const double* __restrict__ L, const double* invd, int r,
         __syncthreads();
         if (tid < 64) {
             const int lane = tid;
-            double row[SB];
             double a = lane < nb ? acc_s[lane] : 0.0;
-#pragma unroll
-            for (int jj = 0; jj < SB; ++jj)
-                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
             double sol = 0.0;
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj) {
@@ -739,7 +745,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
 // y_i = sum_j B[i][j] v_j (i < dy): one wave per row, lanes over j.
 template <typename TB>
-__device__ void b_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* v, double* y) {
+__device__ __forceinline__ void b_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* v, double* y) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = wave; i < dy; i += TPB / 64) {
         double acc = 0.0;
@@ -752,7 +758,7 @@ __device__ void b_times(const TB* __restrict__ B, int dy, int r, int ldb, const 
 
 // w_j = sum_i B[i][j] z_i (j < r): threads over j.
 template <typename TB>
-__device__ void bt_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* z, double* w) {
+__device__ __forceinline__ void bt_times(const TB* __restrict__ B, int dy, int r, int ldb, const double* z, double* w) {
     for (int j = threadIdx.x; j < r; j += TPB) {
         double acc = 0.0;
 #pragma unroll 4
@@ -772,7 +778,7 @@ __device__ __forceinline__ double bf_hi(uint32_t u) { return (double)__uint_as_f
 // consecutive threads share a row, each taking every P-th 16-byte chunk of it; the P
 // partial sums meet by xor shuffles inside the wave (no per-row reduction over 64 lanes).
 template <bool TWO>
-__device__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
+__device__ __forceinline__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
                             const double* v2, double* y2) {
     const int nfull = r >> 3, nch = (r + 7) >> 3;
     int P = 1;
@@ -830,7 +836,7 @@ __device__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, con
 
 // w_j = sum_i B[i][j] z_i (j < r), B in LDS: a thread takes a column pair (4-byte reads,
 // consecutive across lanes) and every Q-th row; the Q row shares are added in turn.
-__device__ void bt_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
+__device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
     const int np = (r + 1) >> 1;
     const int Q = max(1, min(TPB / np, dy));
     const int tid = threadIdx.x, jp = tid % np, q = tid / np;
@@ -900,7 +906,7 @@ __device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* B
 // v = H a - g_a, mhat = (b - s a)/beta, with v^T (I + H)^-1 v = |v|^2 - |K^-1 B v|^2 and
 // mhat^T H mhat = |B mhat|^2. Vectors in R: v, mh, and in Y: t1, t2, z.
 template <typename TB>
-__device__ double dual_rho0(const TB* Ba, int ldb, const double* Ka, const double* invd, int r, int dy, double dt,
+__device__ __forceinline__ double dual_rho0(const TB* Ba, int ldb, const double* Ka, const double* invd, int r, int dy, double dt,
                             double s, double beta, const double* a, const double* b, const double* ga,
                             double logdet_a, double* v, double* mh, double* t1, double* t2, double* z,
                             double* acc_s, double* red) {

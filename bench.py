@@ -75,9 +75,11 @@ def source_sha256(kernel):
     return h.hexdigest()
 
 
-def stage_kernel(stage, dual, width):
+def stage_kernel(stage, dual, width, r):
     k = (STAGE_KERNEL_DUAL if dual else STAGE_KERNEL)[stage]
-    if stage == "jacobian" and 400 < width <= 416:
+    # the sweep instance covers the widest layer (the widths and r) in blocks of 32:
+    # 8..13 blocks run the width-416 kernel
+    if stage == "jacobian" and 224 < max(width, r) <= 416:
         k = SWEEP416_KERNEL
     return k
 
@@ -164,8 +166,9 @@ def laplace_start(w, ctx, y, nv):
     return x0, z0, dict(J_map=m.J, gn_iters=m.iters, seconds=round(time.perf_counter() - t0, 3))
 
 
-def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=6):
-    """The FP64 oracle on a bounded sample of the same workload (same starting states)."""
+def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=60, factor="primal"):
+    """The FP64 oracle on a bounded sample of the same workload (same starting states and
+    factorisation as the device path), about 10-20 s of host work."""
     from threadpoolctl import threadpool_info
 
     from oracle import mcmc, network
@@ -176,7 +179,7 @@ def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=6):
     f_true = f_true[0, : w.d_y]
     sigma = w.sigma * np.max(np.abs(f_true)) if w.sigma_rule == "rel_max" else w.sigma
     y = f_true + sigma * draw_noise(w)
-    prob = mcmc.Problem(layers, y, np.full(w.d_y, sigma ** 2), w.dt, seed=w.chain_seed)
+    prob = mcmc.Problem(layers, y, np.full(w.d_y, sigma ** 2), w.dt, seed=w.chain_seed, factor=factor)
     st = mcmc.init_state(prob, x0[:chains], z0[:chains].astype(np.float64))
     t0 = time.perf_counter()
     steps = 0
@@ -187,7 +190,7 @@ def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=6):
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     return {"value": round(chains * steps / dt, 2), "unit": "chain-steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{chains} of the {w.chains} chains x {steps} steps of the same workload and starting states "
-                      f"(FP64 NumPy/SciPy oracle, complement tracked, {dt:.1f} s)"}
+                      f"(FP64 NumPy/SciPy oracle, {factor} form, complement tracked, {dt:.1f} s)"}
 
 
 def copy_calibration(nbytes=1 << 29):
@@ -488,7 +491,7 @@ def main():
     if stages:
         dom = max(stages, key=lambda k: stages[k]["ms"])
         s = stages[dom]
-        kern = stage_kernel(dom, dual, w.width) if args.precision == "bf16" else dom
+        kern = stage_kernel(dom, dual, w.width, w.r) if args.precision == "bf16" else dom
         roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4),
@@ -501,7 +504,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle) ...")
-        cpu = cpu_baseline(w, layers, x0, z0)
+        cpu = cpu_baseline(w, layers, x0, z0, factor="dual" if dual else "primal")
     line = {
         "metric": "chain-steps/s",
         "value": round(value, 1),

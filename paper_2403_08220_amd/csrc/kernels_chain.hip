@@ -1084,7 +1084,15 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
             g[(long)c * r + j] = ga[j];
         }
         TB* Bsc = Bs + (long)c * dy * ldb;
-        for (long e = tid; e < (long)dy * ldb; e += TPB) Bsc[e] = Bpg[e];
+        if constexpr (sizeof(TB) == 2) {
+            // from the staged copy (row stride ldl), 16 bytes per move (ldb: a multiple of 32)
+            const int c16 = ldb / 8, l16 = ldl / 8;
+            const uint4* src = reinterpret_cast<const uint4*>(Bpc);
+            uint4* dst = reinterpret_cast<uint4*>(Bsc);
+            for (long e = tid; e < (long)dy * c16; e += TPB) dst[e] = src[(e / c16) * l16 + e % c16];
+        } else {
+            for (long e = tid; e < (long)dy * ldb; e += TPB) Bsc[e] = Bpg[e];
+        }
     }
 }
 

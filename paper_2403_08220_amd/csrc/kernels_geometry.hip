@@ -271,7 +271,20 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
     __shared__ float red[4][64][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
-    const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+    // 1-D grid of nx * ny tiles. Blocks are dispatched round-robin over the 8 XCDs; when
+    // ny is a multiple of 8, every tile of row block y goes to XCD y % 8, so that the next
+    // layer's blocks of that row block read activations written through the same L2.
+    const int nx = (N + 31) / 32, ny = (M + 31) / 32;
+    int tx, ty;
+    if ((ny & 7) == 0) {
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        ty = xcd + 8 * (slot / nx);
+        tx = slot % nx;
+    } else {
+        tx = blockIdx.x % nx;
+        ty = blockIdx.x / nx;
+    }
+    const int m0 = ty * 32, n0 = tx * 32;
     const int arow = m0 + l32, wrow = n0 + l32;
     const bool aok = arow < M, wok = wrow < N;
     const float* ap = in64 ? nullptr : in + (long)(aok ? arow : 0) * ldin;
@@ -474,7 +487,7 @@ void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64
         float* dp = nullptr;
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
         // the first layer reads the FP64 states (x64) when given, else the FP32 copy xf
-        hipLaunchKernelGGL(fwd_mfma_kernel, dim3((N + 31) / 32, (n + 31) / 32), dim3(256), 0, st, n, ly.fan_in, N,
+        hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((n + 31) / 32)), dim3(256), 0, st, n, ly.fan_in, N,
                            in, ldin, l == 0 ? x64 : nullptr, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;

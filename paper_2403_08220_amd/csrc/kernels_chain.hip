@@ -197,6 +197,94 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
     }
 }
 
+// out = L^T v (L lower, row stride r): waves take rows i = wave (mod 4), lanes 64
+// consecutive columns j <= i; the four waves' partial sums are added into out in turn
+// (no scratch beyond out).
+__device__ __forceinline__ void lt_matvec_acc(const double* __restrict__ L, int r, const double* v, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int jb = 0; jb < r; jb += 64) {
+        const int j = jb + lane;
+        double a = 0.0;
+        if (j < r) {
+#pragma unroll 8
+            for (int i = jb + ((wave - jb) & 3); i < r; i += 4)
+                if (i >= j) a += L[(long)i * r + j] * v[i];
+        }
+        for (int wq = 0; wq < TPB / 64; ++wq) {
+            if (wave == wq && j < r) out[j] = (wq == 0 ? 0.0 : out[j]) + a;
+            __syncthreads();
+        }
+    }
+}
+
+// Forward substitution for two right-hand sides at once (L w1 = b1, L w2 = b2): one
+// pass over L and one serial sweep for both; acc_s must hold 2 SB doubles.
+__device__ __forceinline__ void l_solve2(const double* __restrict__ L, const double* invd, int r, const double* b1,
+                                         double* w1, const double* b2, double* w2, double* acc_s) {
+    const int tid = threadIdx.x;
+    for (int b0 = 0; b0 < r; b0 += SB) {
+        const int nb = min(SB, r - b0);
+        double row[SB];
+        if (tid < 64) {
+            const int lane = tid;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+        }
+        {
+            const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
+            const int i = b0 + il;
+            double c1 = 0.0, c2 = 0.0;
+            if (il < nb)
+#pragma unroll 4
+                for (int j = 4 * sub; j < b0; j += 32)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (j + q < b0) {
+                            const double lij = L[(long)i * r + j + q];
+                            c1 += lij * w1[j + q];
+                            c2 += lij * w2[j + q];
+                        }
+#pragma unroll
+            for (int o = 4; o > 0; o >>= 1) {
+                c1 += __shfl_xor(c1, o);
+                c2 += __shfl_xor(c2, o);
+            }
+            if (il < nb && sub == 0) {
+                acc_s[il] = b1[i] - c1;
+                acc_s[SB + il] = b2[i] - c2;
+            }
+        }
+        __syncthreads();
+        if (tid < 64) {
+            const int lane = tid;
+            double a1 = lane < nb ? acc_s[lane] : 0.0;
+            double a2 = lane < nb ? acc_s[SB + lane] : 0.0;
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj) {
+                if (jj < nb) {
+                    const double dj = invd[b0 + jj];
+                    const double u1 = lane_bcast(a1, jj) * dj, u2 = lane_bcast(a2, jj) * dj;
+                    if (lane == jj) {
+                        s1 = u1;
+                        s2 = u2;
+                    }
+                    if (lane > jj) {
+                        a1 -= row[jj] * u1;
+                        a2 -= row[jj] * u2;
+                    }
+                }
+            }
+            if (lane < nb) {
+                w1[b0 + lane] = s1;
+                w2[b0 + lane] = s2;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Dynamic LDS of the per-chain transition kernels: CH_NV vectors of length r, the
 // triangular-solve scratch and the partial sums of the transposed products.
 constexpr int CH_NV = 10;
@@ -777,58 +865,51 @@ __device__ __forceinline__ double bf_hi(uint32_t u) { return (double)__uint_as_f
 // y_i = sum_{j<r} B[i][j] v_j and, if TWO, y2_i = sum_j B[i][j] v2_j, B in LDS. P
 // consecutive threads share a row, each taking every P-th 16-byte chunk of it; the P
 // partial sums meet by xor shuffles inside the wave (no per-row reduction over 64 lanes).
-template <bool TWO>
-__device__ __forceinline__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
-                            const double* v2, double* y2) {
+template <int NV>
+__device__ __forceinline__ void b_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* const (&vs)[NV],
+                                            double* const (&ys)[NV]) {
     const int nfull = r >> 3, nch = (r + 7) >> 3;
     int P = 1;
     while (P < 8 && 2 * P * dy <= TPB && 2 * P <= nch) P *= 2;
     for (int t0 = 0; t0 < dy * P; t0 += TPB) {
         const int t = t0 + (int)threadIdx.x;
         const int i = t / P, p = t & (P - 1);
-        double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
+        double a0[NV], a1[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) a0[q] = a1[q] = 0.0;
         if (i < dy) {
             const uint4* row = reinterpret_cast<const uint4*>(B + (long)i * ldl);
             for (int kq = p; kq < nch; kq += P) {
-                const uint4 q = row[kq];
-                const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
-                const double* vv = v + 8 * kq;
-                const double* ww = TWO ? v2 + 8 * kq : nullptr;
+                const uint4 qv = row[kq];
+                const uint32_t w4[4] = {qv.x, qv.y, qv.z, qv.w};
                 if (kq < nfull) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const double blo = bf_lo(w4[e]), bhi = bf_hi(w4[e]);
-                        a0 += blo * vv[2 * e];
-                        a1 += bhi * vv[2 * e + 1];
-                        if (TWO) {
-                            c0 += blo * ww[2 * e];
-                            c1 += bhi * ww[2 * e + 1];
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) {
+                            a0[q] += blo * vs[q][8 * kq + 2 * e];
+                            a1[q] += bhi * vs[q][8 * kq + 2 * e + 1];
                         }
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const double blo = bf_lo(w4[e]), bhi = bf_hi(w4[e]);
-                        if (8 * kq + 2 * e < r) {
-                            a0 += blo * vv[2 * e];
-                            if (TWO) c0 += blo * ww[2 * e];
-                        }
-                        if (8 * kq + 2 * e + 1 < r) {
-                            a1 += bhi * vv[2 * e + 1];
-                            if (TWO) c1 += bhi * ww[2 * e + 1];
+#pragma unroll
+                        for (int q = 0; q < NV; ++q) {
+                            if (8 * kq + 2 * e < r) a0[q] += blo * vs[q][8 * kq + 2 * e];
+                            if (8 * kq + 2 * e + 1 < r) a1[q] += bhi * vs[q][8 * kq + 2 * e + 1];
                         }
                     }
                 }
             }
         }
-        double acc = a0 + a1, acc2 = c0 + c1;
-        for (int o = 1; o < P; o <<= 1) {
-            acc += __shfl_xor(acc, o);
-            if (TWO) acc2 += __shfl_xor(acc2, o);
-        }
-        if (i < dy && p == 0) {
-            y[i] = acc;
-            if (TWO) y2[i] = acc2;
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double acc = a0[q] + a1[q];
+            for (int o = 1; o < P; o <<= 1) acc += __shfl_xor(acc, o);
+            if (i < dy && p == 0) ys[q][i] = acc;
         }
     }
     __syncthreads();
@@ -861,7 +942,9 @@ __device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, in
 
 // The BF16 instances read B from LDS (staged with row stride ldl).
 __device__ __forceinline__ void b_times(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y) {
-    b_times_lds<false>(B, dy, r, ldl, v, y, nullptr, nullptr);
+    const double* const vs[1] = {v};
+    double* const ys[1] = {y};
+    b_times_lds<1>(B, dy, r, ldl, vs, ys);
 }
 __device__ __forceinline__ void bt_times(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
     bt_times_lds(B, dy, r, ldl, z, w);
@@ -869,17 +952,32 @@ __device__ __forceinline__ void bt_times(const __hip_bfloat16* B, int dy, int r,
 // y = B v and y2 = B v2 in one pass over B
 __device__ __forceinline__ void b_times2(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
                                          const double* v2, double* y2) {
-    b_times_lds<true>(B, dy, r, ldl, v, y, v2, y2);
+    const double* const vs[2] = {v, v2};
+    double* const ys[2] = {y, y2};
+    b_times_lds<2>(B, dy, r, ldl, vs, ys);
 }
 __device__ __forceinline__ void b_times2(const double* B, int dy, int r, int ldb, const double* v, double* y,
                                          const double* v2, double* y2) {
     b_times(B, dy, r, ldb, v, y);
     b_times(B, dy, r, ldb, v2, y2);
 }
+// y_q = B v_q for three vectors in one pass over B
+__device__ __forceinline__ void b_times3(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v1,
+                                         double* y1, const double* v2, double* y2, const double* v3, double* y3) {
+    const double* const vs[3] = {v1, v2, v3};
+    double* const ys[3] = {y1, y2, y3};
+    b_times_lds<3>(B, dy, r, ldl, vs, ys);
+}
+__device__ __forceinline__ void b_times3(const double* B, int dy, int r, int ldb, const double* v1, double* y1,
+                                         const double* v2, double* y2, const double* v3, double* y3) {
+    b_times(B, dy, r, ldb, v1, y1);
+    b_times(B, dy, r, ldb, v2, y2);
+    b_times(B, dy, r, ldb, v3, y3);
+}
 
 // Scratch of the dual kernels: vectors of length r and d_y in dynamic LDS, followed
 // (BF16 path) by the chain's B (d_y x ldl), staged once so that every product reads LDS.
-constexpr int DU_NR = 8, DU_NY = 6;
+constexpr int DU_NR = 8, DU_NY = 8;
 constexpr int DU_RED = 4 * (TPB / 64);  // block_sum4 scratch
 __host__ __device__ inline int dual_ldl(int ldb, bool stage_bf16) { return stage_bf16 ? ldb + 8 : ldb; }
 __host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool stage_bf16) {
@@ -990,8 +1088,13 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     bt_times(Bc, dy, r, ldl, xi2, w);
     for (int j = tid; j < r; j += TPB) u[j] = beta * (xi1[j] + w[j]) - (1.0 - s) * (xs[j] + gs[j]);
     __syncthreads();
-    b_times(Bc, dy, r, ldl, u, y);
-    l_solve(Kc, invd, dy, y, z1, acc);
+    // y = B u, and B x, B g for the forward term (xi2 is free: it holds B g)
+    double *bx = Y + 6 * dy, *zs = Y + 7 * dy, *bg = xi2;
+    b_times3(Bc, dy, r, ldl, u, y, xs, bx, gs, bg);
+    for (int i = tid; i < dy; i += TPB) t2[i] = bx[i] + bg[i];
+    __syncthreads();
+    // z1 = K^-1 B u and zs = K^-1 B (x + g) in one sweep
+    l_solve2(Kc, invd, dy, y, z1, t2, zs, part);
     lt_solve(Kc, invd, dy, z1, t1, part);
     bt_times(Bc, dy, r, ldl, t1, w);
     for (int j = tid; j < r; j += TPB) {
@@ -1000,8 +1103,29 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     }
     __syncthreads();
     if (lfwd) {
-        const double l = dual_rho0(Bc, ldl, Kc, invd, r, dy, dt, s, beta, xs, xn, gs, logdet[c], v, mh, t1, t2, z1,
-                                   acc, red);
+        // log rho_0(x -> xn) with the cache of x (the reverse term of the dual form):
+        // v = H x - g = B^T (B x) - g, and K^-1 B v = K^T (B x) - K^-1 B (x + g), since
+        // B B^T = K K^T - I; the second term is zs from the sweep above.
+        bt_times(Bc, dy, r, ldl, bx, v);
+        for (int j = tid; j < r; j += TPB) {
+            v[j] -= gs[j];
+            mh[j] = (xn[j] - s * xs[j]) / beta;
+        }
+        __syncthreads();
+        b_times(Bc, dy, r, ldl, mh, y);          // y = B mhat
+        lt_matvec_acc(Kc, dy, bx, z1);          // z1 = K^T (B x)
+        double sums[4] = {0.0, 0.0, 0.0, 0.0};   // |v|^2, mhat.v, |K^-1 B v|^2, |B mhat|^2
+        for (int j = tid; j < r; j += TPB) {
+            sums[0] += v[j] * v[j];
+            sums[1] += mh[j] * v[j];
+        }
+        for (int i = tid; i < dy; i += TPB) {
+            const double zr = z1[i] - zs[i];
+            sums[2] += zr * zr;
+            sums[3] += y[i] * y[i];
+        }
+        block_sum4(sums, red);
+        const double l = -(dt / 8.0) * (sums[0] - sums[2]) + 0.5 * sqrt(dt) * sums[1] - 0.5 * sums[3] + logdet[c];
         if (tid == 0) lfwd[c] = l;
     }
 }

@@ -50,7 +50,8 @@ STAGE_KERNEL_DUAL = dict(STAGE_KERNEL, proposal="propose_dual_kernel", accept="a
                          gn_hessian="gram_bf16_kernel")
 # the width-416 sweep (layers of 401..416 units) has its own kernel
 SWEEP416_KERNEL = "jac_sweep13_kernel"
-KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "propose_kernel": ["kernels_chain.hip"],
+KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "cholesky_wave_kernel": ["kernels_chain.hip"],
+                  "propose_kernel": ["kernels_chain.hip"],
                   "accept_kernel": ["kernels_chain.hip"], "complement_kernel": ["kernels_chain.hip"],
                   "finish_kernel": ["kernels_chain.hip"], "propose_dual_kernel": ["kernels_chain.hip"],
                   "accept_dual_kernel": ["kernels_chain.hip"], "jac_sweep_bf16_kernel": ["kernels_mfma.hip"],
@@ -75,12 +76,15 @@ def source_sha256(kernel):
     return h.hexdigest()
 
 
-def stage_kernel(stage, dual, width, r):
+def stage_kernel(stage, dual, width, r, dy):
     k = (STAGE_KERNEL_DUAL if dual else STAGE_KERNEL)[stage]
     # the sweep instance covers the widest layer (the widths and r) in blocks of 32:
     # 8..13 blocks run the width-416 kernel
     if stage == "jacobian" and 224 < max(width, r) <= 416:
         k = SWEEP416_KERNEL
+    # factors of order up to 104 run one wavefront per chain
+    if stage == "cholesky" and (dy if dual else r) <= 104:
+        k = "cholesky_wave_kernel"
     return k
 
 
@@ -491,7 +495,7 @@ def main():
     if stages:
         dom = max(stages, key=lambda k: stages[k]["ms"])
         s = stages[dom]
-        kern = stage_kernel(dom, dual, w.width, w.r) if args.precision == "bf16" else dom
+        kern = stage_kernel(dom, dual, w.width, w.r, w.d_y) if args.precision == "bf16" else dom
         roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4),

@@ -517,12 +517,6 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
     }
 }
 
-// One wave per chain for k <= 8 MB (k = 104 at MB = 13): lane (g, q) = (lane / 8, lane % 8)
-// holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs
-// c <= m only, 91 doubles at MB = 13). Column j is published through LDS by its eight
-// owners (q = j % 8) and read back by every lane; there is no barrier between waves
-// (a single wave, in-order LDS), so a column step costs one LDS round trip, a square
-// root and the rank-1 update of the lane's share of the trailing block.
 // Column j = 8 PH + JJ of the single-wave factorisation (compile-time PH, JJ, so that
 // every register index is a constant).
 template <int MB, int PH, int JJ>

@@ -42,8 +42,8 @@ PEAKS = {  # MI355X published peaks
 # device kernel of each stage on the mixed-precision path (rocprofv3 kernel names)
 STAGE_KERNEL = {
     "proposal": "propose_kernel", "forward": "fwd_mfma_kernel", "jacobian": "jac_sweep_bf16_kernel",
-    "misfit_ppg": "residual_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_reg_kernel",
-    "accept": "accept_kernel", "complement": "complement_kernel", "trace": "finish_kernel",
+    "misfit_ppg": "misfit_grad_kernel", "gn_hessian": "hess_bf16_kernel", "cholesky": "cholesky_reg_kernel",
+    "accept": "accept_kernel", "complement": "complement_kernel", "trace": "accept_kernel",
 }
 # observation-space form (d_y < r): Gram matrix, d_y x d_y factor and Woodbury kernels
 STAGE_KERNEL_DUAL = dict(STAGE_KERNEL, proposal="propose_dual_kernel", accept="accept_dual_kernel",
@@ -53,11 +53,11 @@ SWEEP416_KERNEL = "jac_sweep13_kernel"
 KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "cholesky_wave_kernel": ["kernels_chain.hip"],
                   "propose_kernel": ["kernels_chain.hip"],
                   "accept_kernel": ["kernels_chain.hip"], "complement_kernel": ["kernels_chain.hip"],
-                  "finish_kernel": ["kernels_chain.hip"], "propose_dual_kernel": ["kernels_chain.hip"],
+                  "propose_dual_kernel": ["kernels_chain.hip"],
                   "accept_dual_kernel": ["kernels_chain.hip"], "jac_sweep_bf16_kernel": ["kernels_mfma.hip"],
                   "jac_sweep13_kernel": ["kernels_mfma.hip", "sweep_asm.inc"],
                   "hess_bf16_kernel": ["kernels_mfma.hip"], "gram_bf16_kernel": ["kernels_mfma.hip"],
-                  "residual_kernel": ["kernels_mfma.hip"], "fwd_mfma_kernel": ["kernels_geometry.hip"],
+                  "fwd_mfma_kernel": ["kernels_geometry.hip"],
                   "fwd_layer_kernel": ["kernels_geometry.hip"]}
 
 
@@ -485,6 +485,8 @@ def main():
     dual = args.factorization == "dual" or (args.factorization == "auto" and w.d_y < w.r)
     stages = {}
     for name, v in prof.items():
+        if v["launches"] == 0:  # a stage with no kernel of its own on this path
+            continue
         amt, unit, bound, peak = stage_work(name, w.width, C, w.r, w.d_y, L_res, res["accept_rate"],
                                             w.d_m - w.r, args.precision, dual=dual)
         t = v["ms_per_step"] * 1e-3

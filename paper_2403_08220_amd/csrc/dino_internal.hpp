@@ -254,7 +254,6 @@ struct dino_problem {
     float* h0f = nullptr;     // C x wmax FP32 activations
     float* h1f = nullptr;
     float* f32 = nullptr;     // C x d_y FP32 network output
-    float* e32 = nullptr;     // C x d_y whitened residual
     float* d32 = nullptr;     // n_act x C x ldd32 gelu'(z), zero padded
     __hip_bfloat16* B16 = nullptr;  // C x d_y x r BF16 whitened Jacobian (at the proposal)
     // observation-space (dual) form: the state's Jacobian; the factor buffers hold the
@@ -293,9 +292,10 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
                          const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
                          double* xp, double* lfwd, const double* logdet, hipStream_t st);
-void launch_accept(dino_problem* p, int n, hipStream_t st);
+// The accept kernels also end the step of each chain: trace row trace_row (-1: none),
+// running sums, step counter and life cycle.
+void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 // Per-step bookkeeping of chains [0, n): step counters, life cycle, running sums, trace row.
-void launch_finish(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 // Sets the metadata of chains [c0, c0 + n) (index = first_index + c - c0) and zeroes their sums.
 void launch_meta_fill(dino_problem* p, int c0, int n, uint64_t key0, uint64_t key1, int64_t budget, int64_t burn,
                       int32_t row, int32_t state, int32_t first_index, hipStream_t st);
@@ -305,13 +305,16 @@ void launch_request_mean(dino_problem* p, int c0, int n, int64_t count, double* 
 void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
                     const double* L_x, const double* logdet_x, const double* xp, const double* phi_p,
                     const double* g_p, const double* L_p, const double* logdet_p, double* out, hipStream_t st);
+// After the accept kernel of the same step (it reads the advanced step counter).
 void launch_complement(dino_problem* p, int n, hipStream_t st);
 // dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
 void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
-void launch_accept_dual(dino_problem* p, int n, hipStream_t st);
+void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st);
-void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
-                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
+// Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
+// no separate misfit launch).
+void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                      long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
 void launch_gram_f64(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,
                      int slot_xor, long slot_stride, hipStream_t st);
 void launch_btb(dino_problem* p, int n, double* H, hipStream_t st);
@@ -350,11 +353,10 @@ void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int
 // FP32 forward; the first layer reads x64 (FP64, rounded on load) if given, else xf.
 void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st);
 void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st);
-void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
-                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
+void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                      long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
 void launch_to_float(long count, const double* x, float* xf, hipStream_t st);
 void launch_to_double(long count, const float* xf, double* x, hipStream_t st);
 void launch_sym_from_lower(int n, int r, const double* A, double* H, hipStream_t st);
-void launch_residual(dino_problem* p, int n, const float* f, float* e, double* phi, hipStream_t st);
 
 }  // namespace dino

@@ -751,13 +751,54 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // MH decision of the first stage and the swap of state and cache on acceptance.
 // accflag: 0 rejected or idle, 1 accepted (pCN complement move), 2 fresh chain
 // initialised (complement drawn from the prior).
+// Per-step outputs of the finish: the trace row (xrow, phirow; null when the step is not
+// recorded) and the running sums of x past the burn-in (sumx; null outside serving).
+struct StepRecord {
+    double* sumx;
+    float* xrow;
+    double* phirow;
+};
+
+// End of a step for chain c, run by the whole block of the accept kernels after the
+// decision: the trace row, the running sum of x once the chain is past its burn-in, the
+// step counter and the life cycle (a live chain that has used its step budget goes
+// idle; a fresh chain becomes live). xn: the chain's state after the decision (LDS);
+// step: meta.step[c] as read at the start of the kernel; phin (thread 0): the misfit
+// after the decision.
+__device__ __forceinline__ void finish_chain(int c, int r, const ChainMeta& meta, int32_t state, int64_t step,
+                                             const double* xn, double phin, const StepRecord& rec) {
+    const int tid = threadIdx.x;
+    if (rec.xrow) {
+        for (int j = tid; j < r; j += TPB) rec.xrow[(long)c * r + j] = (float)xn[j];
+        if (tid == 0) rec.phirow[c] = phin;
+    }
+    if (state == CHAIN_LIVE) {
+        const int64_t s1 = step + 1;
+        if (rec.sumx && s1 > meta.burn[c])
+            for (int j = tid; j < r; j += TPB) rec.sumx[(long)c * r + j] += xn[j];
+        if (tid == 0) {
+            meta.step[c] = s1;
+            if (s1 >= meta.budget[c]) meta.state[c] = CHAIN_IDLE;
+        }
+    } else if (state == CHAIN_FRESH && tid == 0) {
+        meta.state[c] = CHAIN_LIVE;
+    }
+}
+
+// The trace row of an idle chain (its state does not change).
+__device__ __forceinline__ void record_idle(int c, int r, const double* x, const double* phi, const StepRecord& rec) {
+    if (!rec.xrow) return;
+    for (int j = threadIdx.x; j < r; j += TPB) rec.xrow[(long)c * r + j] = (float)x[(long)c * r + j];
+    if (threadIdx.x == 0) rec.phirow[c] = phi[c];
+}
+
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
                                                      double* x, double* g, double* phi,
                                                      double* logdet, const double* Lbuf, long half,
                                                      int32_t* cur, const double* xp, const double* gp,
                                                      const double* phip, const double* logdetp,
                                                      const int32_t* okp, const double* lfwd, int64_t* accepts,
-                                                     int64_t* failures, int32_t* accflag) {
+                                                     int64_t* failures, int32_t* accflag, StepRecord rec) {
     extern __shared__ double dyn[];
     const ChainLds S = carve_chain_lds(dyn, r);
     double *xs = S.v[0], *ps = S.v[1], *ga = S.v[2];
@@ -767,8 +808,11 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
+        record_idle(c, r, x, phi, rec);
         return;
     }
+    const int64_t step = meta.step[c];  // read by every thread before the finish advances it
+    double phin = 0.0;                   // thread 0: the misfit after the decision
     const int other = cur[c] ^ 1;
     const double* Lp = Lbuf + (long)other * half + c * rr;
     for (int j = tid; j < r; j += TPB) {
@@ -782,7 +826,8 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         // the initial state and its cache are taken as they are
         if (tid == 0) {
             if (!okc) failures[c] += 1;
-            phi[c] = phip[c];
+            phin = phip[c];
+            phi[c] = phin;
             logdet[c] = logdetp[c];
             cur[c] = other;
             decision = 1;
@@ -794,15 +839,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         if (okc) rev = log_rho0_dev(Lp, r, dt, s, beta, ps, xs, ga, logdetp[c], S);
         if (tid == 0) {
             const double lr = phi[c] - phip[c] + rev - lfwd[c];
-            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)meta.step[c],
-                                            (uint64_t)meta.index[c]);
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = okc && isfinite(lr);
             const bool accept = good && (log(u) <= lr);
             decision = accept ? 1 : 0;
             if (!good) failures[c] += 1;
+            phin = phi[c];
             if (accept) {
                 accepts[c] += 1;
-                phi[c] = phip[c];
+                phin = phip[c];
+                phi[c] = phin;
                 logdet[c] = logdetp[c];
                 cur[c] = other;
             }
@@ -816,6 +862,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             g[(long)c * r + j] = ga[j];
         }
     }
+    finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1133,7 +1180,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
                         double* phi, double* logdet, const double* Kbuf, long half, int32_t* cur, const double* xp,
                         const double* gp, const double* phip, const double* logdetp, const int32_t* okp,
                         const double* lfwd, const TB* __restrict__ Bp, TB* __restrict__ Bs, int64_t* accepts,
-                        int64_t* failures, int32_t* accflag) {
+                        int64_t* failures, int32_t* accflag, StepRecord rec) {
     extern __shared__ double dyn[];
     double* R = dyn;
     double *xs = R, *ps = R + r, *ga = R + 2 * r, *v = R + 3 * r, *mh = R + 4 * r;
@@ -1147,8 +1194,11 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
+        record_idle(c, r, x, phi, rec);
         return;
     }
+    const int64_t step = meta.step[c];  // read by every thread before the finish advances it
+    double phin = 0.0;                   // thread 0: the misfit after the decision
     const int other = cur[c] ^ 1;
     const double* Kp = Kbuf + (long)other * half + c * kk;
     const TB* Bpg = Bp + (long)c * dy * ldb;
@@ -1164,7 +1214,8 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     if (state == CHAIN_FRESH) {
         if (tid == 0) {
             if (!okc) failures[c] += 1;
-            phi[c] = phip[c];
+            phin = phip[c];
+            phi[c] = phin;
             logdet[c] = logdetp[c];
             cur[c] = other;
             decision = 1;
@@ -1180,15 +1231,16 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
         }
         if (tid == 0) {
             const double lr = phi[c] - phip[c] + rev - lfwd[c];
-            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)meta.step[c],
-                                            (uint64_t)meta.index[c]);
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = okc && isfinite(lr);
             const bool accept = good && (log(u) <= lr);
             decision = accept ? 1 : 0;
             if (!good) failures[c] += 1;
+            phin = phi[c];
             if (accept) {
                 accepts[c] += 1;
-                phi[c] = phip[c];
+                phin = phip[c];
+                phi[c] = phin;
                 logdet[c] = logdetp[c];
                 cur[c] = other;
             }
@@ -1212,6 +1264,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
             for (long e = tid; e < (long)dy * ldb; e += TPB) Bsc[e] = Bpg[e];
         }
     }
+    finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
 }
 
 // Copies the Jacobian of every chain (n x dy x ldb values) into the state's buffer.
@@ -1221,7 +1274,8 @@ __global__ void copy_b_kernel(long count, const TB* __restrict__ src, TB* __rest
         dst[e] = src[e];
 }
 
-// pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state).
+// pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state). Runs
+// after the accept kernel of the same step.
 __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta, ChainMeta meta,
                                                          const int32_t* __restrict__ accflag, float* z) {
     const int c = blockIdx.y;
@@ -1238,7 +1292,8 @@ __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, do
         for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)nv[q];
         return;
     }
-    philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_COMPLEMENT, (uint64_t)meta.step[c],
+    // the accept kernel has already advanced the step counter of this (live) chain
+    philox_normals4(meta.key0[c], meta.key1[c], (uint64_t)b4, STREAM_COMPLEMENT, (uint64_t)(meta.step[c] - 1),
                     (uint64_t)meta.index[c], nv);
     if (j0 + 3 < d_perp) {
         float4 v = *reinterpret_cast<const float4*>(zc + j0);
@@ -1249,32 +1304,6 @@ __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, do
         *reinterpret_cast<float4*>(zc + j0) = v;
     } else {
         for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)(s * (double)zc[j0 + q] + beta * nv[q]);
-    }
-}
-
-// End of a step for one chain per block: the trace row (when recorded), the running sum
-// of x once the chain is past its burn-in, the step counter and the life cycle (a live
-// chain that has used its step budget goes idle; a fresh chain becomes live).
-__global__ __launch_bounds__(64) void finish_kernel(int r, ChainMeta meta, const double* __restrict__ x,
-                                                    const double* __restrict__ phi, double* __restrict__ sumx,
-                                                    float* __restrict__ xrow, double* __restrict__ phirow) {
-    const int c = blockIdx.x, tid = threadIdx.x;
-    const int32_t state = chain_state(meta, c);
-    const double* xc = x + (long)c * r;
-    if (xrow) {
-        for (int j = tid; j < r; j += 64) xrow[(long)c * r + j] = (float)xc[j];
-        if (tid == 0) phirow[c] = phi[c];
-    }
-    if (state == CHAIN_LIVE) {
-        const int64_t s1 = meta.step[c] + 1;
-        if (sumx && s1 > meta.burn[c])
-            for (int j = tid; j < r; j += 64) sumx[(long)c * r + j] += xc[j];
-        if (tid == 0) {
-            meta.step[c] = s1;
-            if (s1 >= meta.budget[c]) meta.state[c] = CHAIN_IDLE;
-        }
-    } else if (state == CHAIN_FRESH && tid == 0) {
-        meta.state[c] = CHAIN_LIVE;
     }
 }
 
@@ -1404,13 +1433,23 @@ void launch_propose_slot(dino_problem* p, int n, const double* x, const double* 
 }
 
 
-void launch_accept(dino_problem* p, int n, hipStream_t st) {
+// The step record of a dino_step transition: trace row `trace_row` (-1: none).
+static StepRecord step_record(dino_problem* p, int64_t trace_row) {
+    StepRecord rec{p->sumx, nullptr, nullptr};
+    if (trace_row >= 0) {
+        rec.xrow = p->xtrace + trace_row * (long)p->C * p->r;
+        rec.phirow = p->phitrace + trace_row * (long)p->C;
+    }
+    return rec;
+}
+
+void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
     static bool attr = false;
     allow_large_lds(accept_kernel, attr);
     const long half = (long)p->C * p->r * p->r;
     hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s, p->beta,
                        p->meta, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip,
-                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc);
+                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p, trace_row));
     DINO_HIP(hipGetLastError());
 }
 
@@ -1438,7 +1477,7 @@ static void propose_dual_t(dino_problem* p, int n, const TB* Bs, int ldb, hipStr
 }
 
 template <typename TB>
-static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb, hipStream_t st) {
+static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb, int64_t trace_row, hipStream_t st) {
     static bool attr = false;
     allow_large_lds(accept_dual_kernel<TB>, attr);
     const long half = (long)p->C * p->d_y * p->d_y;
@@ -1447,7 +1486,7 @@ static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb,
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, p->phi, p->logdet,
                        p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp, p->lfwd, Bp, Bs,
-                       p->accepts, p->failures, p->acc);
+                       p->accepts, p->failures, p->acc, step_record(p, trace_row));
     DINO_HIP(hipGetLastError());
 }
 
@@ -1456,9 +1495,9 @@ void launch_propose_dual(dino_problem* p, int n, hipStream_t st) {
     else propose_dual_t<__hip_bfloat16>(p, n, p->Bs16, (p->r + 31) / 32 * 32, st);
 }
 
-void launch_accept_dual(dino_problem* p, int n, hipStream_t st) {
-    if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, st);
-    else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, st);
+void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, trace_row, st);
+    else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, trace_row, st);
 }
 
 void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st) {
@@ -1483,12 +1522,6 @@ void launch_complement(dino_problem* p, int n, hipStream_t st) {
     DINO_HIP(hipGetLastError());
 }
 
-void launch_finish(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
-    float* xrow = trace_row >= 0 ? p->xtrace + trace_row * (long)p->C * p->r : nullptr;
-    double* phirow = trace_row >= 0 ? p->phitrace + trace_row * (long)p->C : nullptr;
-    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(64), 0, st, p->r, p->meta, p->x, p->phi, p->sumx, xrow, phirow);
-    DINO_HIP(hipGetLastError());
-}
 
 void launch_meta_fill(dino_problem* p, int c0, int n, uint64_t key0, uint64_t key1, int64_t budget, int64_t burn,
                       int32_t row, int32_t state, int32_t first_index, hipStream_t st) {

@@ -356,26 +356,60 @@ void jac_sweep13_kernel(SweepArgs args) {
 // is one 16-byte read.
 constexpr int HES_TPB = 256;
 
+// Whitened residual e_i = Gamma^-1/2 (f_i - y_i) of chain c into es (FP32; zero where the
+// noise variance is infinite) and the misfit phi_c = |e|^2 / 2 summed in FP64 (Sec. 5.1).
+// f: the FP32 network output; y, winv: per request row. Called by all HES_TPB threads;
+// red holds HES_TPB / 64 doubles; es is complete after the call.
+__device__ __forceinline__ void residual_into(int c, int dy, const float* __restrict__ f,
+                                              const double* __restrict__ y_rows,
+                                              const double* __restrict__ winv_rows, const int32_t* __restrict__ rows,
+                                              float* es, double* red, double* __restrict__ phi) {
+    const int tid = threadIdx.x;
+    const long row = rows ? rows[c] : 0;
+    const double* y = y_rows + row * dy;
+    const double* winv = winv_rows + row * dy;
+    double part = 0.0;
+    for (int i = tid; i < dy; i += HES_TPB) {
+        const double w = winv[i];
+        const double v = (w == 0.0) ? 0.0 : ((double)f[(long)c * dy + i] - y[i]) * w;
+        es[i] = (float)v;
+        part += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < HES_TPB / 64; ++k) t += red[k];
+        phi[c] = 0.5 * t;
+    }
+}
+
 __global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int ldb, int dy_pad, int ldt,
                                                             const __hip_bfloat16* __restrict__ B,
-                                                            const float* __restrict__ e, double* A, long strideA,
+                                                            const float* __restrict__ f, const double* y_rows,
+                                                            const double* winv_rows, const int32_t* rows,
+                                                            double* __restrict__ phi, double* A, long strideA,
                                                             const int32_t* slot, int slot_xor, long slot_stride,
                                                             double* __restrict__ g) {
-    extern __shared__ __hip_bfloat16 bt[];  // r_pad x ldt
+    extern __shared__ __hip_bfloat16 bt[];  // r_pad x ldt, then e (dy floats)
+    __shared__ double red[HES_TPB / 64];
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nmb = (r + 31) / 32;
     const int r_pad = nmb * 32;
     const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
+    float* es = reinterpret_cast<float*>(bt + (long)r_pad * ldt);
     // transpose into LDS: bt[j][i] = B[i][j], zero padded
     for (int e2 = tid; e2 < r_pad * dy_pad; e2 += HES_TPB) {
         const int j = e2 / dy_pad, ii = e2 % dy_pad;
         bt[(long)j * ldt + ii] = (j < r && ii < dy) ? Bc[(long)ii * ldb + j] : __float2bfloat16(0.f);
     }
-    __syncthreads();
+    residual_into(c, dy, f, y_rows, winv_rows, rows, es, red, phi);  // ends with a barrier
     // gradient g_j = sum_i B[i][j] e[i]
     for (int j = tid; j < r; j += HES_TPB) {
         double acc = 0.0;
-        for (int ii = 0; ii < dy; ++ii) acc += (double)__bfloat162float(bt[(long)j * ldt + ii]) * (double)e[(long)c * dy + ii];
+        for (int ii = 0; ii < dy; ++ii) acc += (double)__bfloat162float(bt[(long)j * ldt + ii]) * (double)es[ii];
         g[(long)c * r + j] = acc;
     }
     double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
@@ -413,30 +447,6 @@ __global__ void to_float_kernel(long n, const double* __restrict__ x, float* __r
 __global__ void to_double_kernel(long n, const float* __restrict__ xf, double* __restrict__ x) {
     for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x)
         x[e] = (double)xf[e];
-}
-
-// Whitened residual e = winv (f - y) (FP32 out) and misfit phi = |e|^2 / 2 (FP64).
-__global__ __launch_bounds__(256) void residual_kernel(int dy, const float* __restrict__ f,
-                                                       const double* __restrict__ y_rows,
-                                                       const double* __restrict__ winv_rows,
-                                                       const int32_t* __restrict__ rows, float* __restrict__ e,
-                                                       double* __restrict__ phi) {
-    __shared__ double red[4];
-    const int c = blockIdx.x, tid = threadIdx.x;
-    const long row = rows ? rows[c] : 0;
-    const double* y = y_rows + row * dy;
-    const double* winv = winv_rows + row * dy;
-    double part = 0.0;
-    for (int i = tid; i < dy; i += 256) {
-        const double w = winv[i];
-        const double v = (w == 0.0) ? 0.0 : ((double)f[(long)c * dy + i] - y[i]) * w;
-        e[(long)c * dy + i] = (float)v;
-        part += v * v;
-    }
-    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-    if ((tid & 63) == 0) red[tid >> 6] = part;
-    __syncthreads();
-    if (tid == 0) phi[c] = 0.5 * (red[0] + red[1] + red[2] + red[3]);
 }
 
 // ---------------------------------------------------------------------------------
@@ -578,10 +588,13 @@ void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_
 // v_mfma_f32_32x32x16_bf16 as they are (K = the reduced index): no transpose.
 __global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ldt,
                                                             const __hip_bfloat16* __restrict__ B,
-                                                            const float* __restrict__ e, double* A, long strideA,
+                                                            const float* __restrict__ f, const double* y_rows,
+                                                            const double* winv_rows, const int32_t* rows,
+                                                            double* __restrict__ phi, double* A, long strideA,
                                                             const int32_t* slot, int slot_xor, long slot_stride,
                                                             double* __restrict__ g) {
     extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt, then e (dy floats)
+    __shared__ double red[HES_TPB / 64];
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
     float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
@@ -602,8 +615,7 @@ __global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int l
         }
         *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v;
     }
-    for (int i = tid; i < dy; i += HES_TPB) es[i] = e[(long)c * dy + i];
-    __syncthreads();
+    residual_into(c, dy, f, y_rows, winv_rows, rows, es, red, phi);  // ends with a barrier
     for (int j = tid; j < r; j += HES_TPB) {
         double acc = 0.0;
 #pragma unroll 4
@@ -635,41 +647,41 @@ __global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int l
     }
 }
 
-void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
-                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
+void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                      long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
     const int r = p->r, dy = p->d_y;
     const int dy_pad = (dy + 31) / 32 * 32;
     const int k_pad = (r + 15) / 16 * 16;
     const int ldt = k_pad + 8;  // 16-byte aligned rows, shifted banks
     const size_t lds = (size_t)dy_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
-    DINO_REQUIRE(lds <= 160 * 1024, DINO_EINVAL, "d_y x r too large for the LDS-staged Gram matrix");
+    DINO_REQUIRE(lds <= 160 * 1024 - 64, DINO_EINVAL, "d_y x r too large for the LDS-staged Gram matrix");
     static bool attr = false;
     if (!attr) {
         DINO_HIP(hipFuncSetAttribute((const void*)gram_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
+                                     160 * 1024 - 64));
         attr = true;
     }
     hipLaunchKernelGGL(gram_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, (r + 31) / 32 * 32, dy_pad, k_pad,
-                       ldt, B, e, A, strideA, slot, slot_xor, slot_stride, g);
+                       ldt, B, f, p->y, p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride, g);
     DINO_HIP(hipGetLastError());
 }
 
-void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* e, double* A, long strideA,
-                      const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
+void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                      long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
     const int r = p->r, dy = p->d_y;
     const int dy_pad = (dy + 15) / 16 * 16;
     const int ldt = dy_pad + 8;  // 16-byte aligned rows, shifted banks
     const int r_pad = (r + 31) / 32 * 32;
-    const size_t lds = (size_t)r_pad * ldt * sizeof(__hip_bfloat16);
-    DINO_REQUIRE(lds <= 160 * 1024, DINO_EINVAL, "r x d_y too large for the LDS-staged Hessian");
+    const size_t lds = (size_t)r_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
+    DINO_REQUIRE(lds <= 160 * 1024 - 64, DINO_EINVAL, "r x d_y too large for the LDS-staged Hessian");
     static bool attr = false;
     if (!attr) {
         DINO_HIP(hipFuncSetAttribute((const void*)hess_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     160 * 1024));
+                                     160 * 1024 - 64));
         attr = true;
     }
-    hipLaunchKernelGGL(hess_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, r_pad, dy_pad, ldt, B, e, A, strideA,
-                       slot, slot_xor, slot_stride, g);
+    hipLaunchKernelGGL(hess_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, r_pad, dy_pad, ldt, B, f, p->y,
+                       p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride, g);
     DINO_HIP(hipGetLastError());
 }
 
@@ -703,9 +715,5 @@ void launch_to_double(long count, const float* xf, double* x, hipStream_t st) {
     DINO_HIP(hipGetLastError());
 }
 
-void launch_residual(dino_problem* p, int n, const float* f, float* e, double* phi, hipStream_t st) {
-    hipLaunchKernelGGL(residual_kernel, dim3(n), dim3(256), 0, st, p->d_y, f, p->y, p->winv, p->meta.row, e, phi);
-    DINO_HIP(hipGetLastError());
-}
 
 }  // namespace dino

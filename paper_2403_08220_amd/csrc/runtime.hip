@@ -131,7 +131,6 @@ static void layout(dino_problem* p, Carver& cv) {
         p->h0f = cv.take<float>(C * w);
         p->h1f = cv.take<float>(C * w);
         p->f32 = cv.take<float>(C * dy);
-        p->e32 = cv.take<float>(C * dy);
         p->d32 = cv.take<float>((size_t)std::max(p->n_act, 1) * C * p->ldd32);
         p->B16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));  // rows padded to 32
         if (p->dual) p->Bs16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));
@@ -194,20 +193,20 @@ static void stage_jacobian(dino_problem* p, int n, hipStream_t st) {
     else launch_sweep_bf16(p, n, p->d32, p->ldd32, p->B16, st);
 }
 
+// The mixed path forms the residual and the misfit in the metric kernel (stage_hessian).
 static void stage_misfit(dino_problem* p, int n, const double* f64, double* phi, double* g, hipStream_t st) {
     if (p->desc.precision == DINO_PREC_F64) launch_misfit_grad(p, n, f64, p->Bj, phi, g, st);
-    else launch_residual(p, n, p->f32, p->e32, phi, st);
 }
 
 // A receives I + H (r x r), or in the dual form I + B B^T (d_y x d_y, row stride d_y).
-static void stage_hessian(dino_problem* p, int n, double* g, double* A, long strideA, const int32_t* slot,
-                          int slot_xor, long slot_stride, hipStream_t st) {
+static void stage_hessian(dino_problem* p, int n, double* phi, double* g, double* A, long strideA,
+                          const int32_t* slot, int slot_xor, long slot_stride, hipStream_t st) {
     if (p->desc.precision == DINO_PREC_F64) {
         if (p->dual) launch_gram_f64(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, st);
         else launch_gn_hessian_slot(p, n, p->Bj, A, strideA, slot, slot_xor, slot_stride, 1, 0, st);
     } else {
-        if (p->dual) launch_gram_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
-        else launch_hess_bf16(p, n, p->B16, p->e32, A, strideA, slot, slot_xor, slot_stride, g, st);
+        if (p->dual) launch_gram_bf16(p, n, p->B16, p->f32, phi, A, strideA, slot, slot_xor, slot_stride, g, st);
+        else launch_hess_bf16(p, n, p->B16, p->f32, phi, A, strideA, slot, slot_xor, slot_stride, g, st);
     }
 }
 
@@ -217,7 +216,7 @@ static void geometry_at(dino_problem* p, int n, const double* x, double* f, doub
     stage_forward(p, n, x, f, st);
     stage_jacobian(p, n, st);
     stage_misfit(p, n, f, phi, g, st);  // the FP64 ppg reads the Jacobian
-    stage_hessian(p, n, g, A, strideA, slot, slot_xor, slot_stride, st);
+    stage_hessian(p, n, phi, g, A, strideA, slot, slot_xor, slot_stride, st);
     launch_cholesky_slot(n, p->kdim, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
 }
 
@@ -655,7 +654,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const long half = (long)p->C * rr;
     const int L = (int)p->ctx->layers.size();
     const bool f64 = p->desc.precision == DINO_PREC_F64;
-    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, 1, 1, 1, 1, p->z ? 1 : 0, 1};
+    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, p->z ? 1 : 0, 0};
     auto mark = [&](int i) {
         if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
     };
@@ -673,18 +672,18 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
         mark(3);
         stage_misfit(p, n, p->f, p->phip, p->gp, st);
         mark(4);
-        stage_hessian(p, n, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
+        stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
         mark(5);
         launch_cholesky_slot(n, p->kdim, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
         mark(6);
-        if (p->dual) launch_accept_dual(p, n, st);
-        else launch_accept(p, n, st);
+        int64_t row = -1;
+        if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
+        // the accept kernel also ends the step (trace row, running sums, step counter)
+        if (p->dual) launch_accept_dual(p, n, row, st);
+        else launch_accept(p, n, row, st);
         mark(7);
         launch_complement(p, n, st);
         mark(8);
-        int64_t row = -1;
-        if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
-        launch_finish(p, n, row, st);
         mark(9);
         if (p->profile) {
             for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches[i];
@@ -854,7 +853,7 @@ dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* 
         stage_forward(p, n, x, f, st);
         stage_jacobian(p, n, st);
         stage_misfit(p, n, f, phi, g, st);
-        stage_hessian(p, n, g, L, rr, nullptr, 0, 0, st);
+        stage_hessian(p, n, phi, g, L, rr, nullptr, 0, 0, st);
         if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
         if (H) {
             if (p->dual) launch_btb(p, n, H, st);

@@ -192,11 +192,15 @@ dino_status dino_ess(dino_problem* p, int burn_in, double* ess);
 
 /* ---------------------------------------------------------------------------
  * Stage timing. With profiling enabled, dino_step records HIP events on its
- * stream around every stage of every step and synchronises after each step
- * (slower; meant for measurement passes). Stages: 0 proposal, 1 surrogate
- * forward, 2 reduced Jacobian, 3 misfit and ppg, 4 GN Hessian, 5 Cholesky,
+ * stream around every stage of every step into a ring of steps that is read
+ * back (one host wait) when it fills or when the profile is read (slower;
+ * meant for measurement passes). Stages: 0 proposal, 1 surrogate forward,
+ * 2 reduced Jacobian, 3 misfit and ppg, 4 GN Hessian, 5 Cholesky,
  * 6 acceptance, 7 complement, 8 trace. stage_ms: total milliseconds per stage;
- * launches: kernel launches per stage per step; steps: profiled steps.
+ * launches: kernel launches per stage per step (0 where the stage's work runs
+ * inside another stage's kernel: the misfit on the BF16 path, in the GN
+ * kernel; the trace and step counters, in the acceptance kernel); steps:
+ * profiled steps.
  */
 #define DINO_N_STAGES 9
 dino_status dino_set_profiling(dino_problem* p, int enable);

@@ -518,17 +518,17 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
 }
 
 // Column j = 8 PH + JJ of the single-wave factorisation (compile-time PH, JJ, so that
-// every register index is a constant).
+// every register index is a constant). Column j was published to col by the previous
+// step (or before the first). The step updates the column block of column j + 1 first
+// and publishes column j + 1 before the rest of the trailing update, so that the LDS
+// round trip of the next pivot overlaps that update.
 template <int MB, int PH, int JJ>
 __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
                                                bool& bad) {
     constexpr int j = 8 * PH + JJ;
+    constexpr int PN = (JJ == 7) ? PH + 1 : PH;  // column block of column j + 1
+    constexpr int JN = (JJ + 1) & 7;             // its owners' q
     if (j >= r) return;
-    if (q == JJ) {
-#pragma unroll
-        for (int m = PH; m < MB; ++m) col[g + 8 * m] = v[m][PH];
-    }
-    __syncthreads();
     const double piv = col[j];
     bad |= !(piv > 0.0);
     if (g == 0 && q == 0) pivs[j] = piv;  // logs are taken after the sweep, off the critical path
@@ -537,18 +537,30 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
     isq = isq * (1.5 - 0.5 * piv * isq * isq);
     isq = isq * (1.5 - 0.5 * piv * isq * isq);
     const double rs = piv * isq;
+    const double inv = isq * isq;
+    // trailing update a_ik -= a_ij a_kj / a_jj: one side scaled by 1 / a_jj
     double li[MB], lk[MB];
 #pragma unroll
     for (int m = PH; m < MB; ++m) {
         const int i = g + 8 * m;
-        li[m] = (i > j) ? col[i] * isq : 0.0;
+        li[m] = (i > j) ? col[i] : 0.0;
         const int kk = q + 8 * m;
-        lk[m] = (kk > j) ? col[kk] * isq : 0.0;
+        lk[m] = (kk > j) ? col[kk] * inv : 0.0;
+    }
+    if constexpr (PN < MB) {
+#pragma unroll
+        for (int m = PN; m < MB; ++m) v[m][PN] -= li[m] * lk[PN];
+        // col is read above before it is written here (one wave: LDS operations in order)
+        if (j + 1 < r && q == JN) {
+#pragma unroll
+            for (int m = PN; m < MB; ++m) col[g + 8 * m] = v[m][PN];
+        }
     }
 #pragma unroll
     for (int m = PH; m < MB; ++m)
 #pragma unroll
-        for (int cc = PH; cc <= m; ++cc) v[m][cc] -= li[m] * lk[cc];
+        for (int cc = PH; cc <= m; ++cc)
+            if (cc != PN) v[m][cc] -= li[m] * lk[cc];
     if (q == JJ) {
 #pragma unroll
         for (int m = PH; m < MB; ++m) {
@@ -574,8 +586,9 @@ struct CholWaveSteps {
 // holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs
 // c <= m only, 91 doubles at MB = 13). Column j is published through LDS by its eight
 // owners (q = j % 8) and read back by every lane; there is no barrier between waves
-// (a single wave, in-order LDS), so a column step costs one LDS round trip, a square
-// root and the rank-1 update of the lane's share of the trailing block.
+// (a single wave, in-order LDS), so a column step costs one LDS round trip (overlapped
+// with the trailing update of the step before), a square root and the rank-1 update of
+// the lane's share of the trailing block.
 template <int MB>
 __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, long strideA, const int32_t* slot,
                                                            int slot_xor, long slot_stride, double* logdet,
@@ -596,6 +609,11 @@ __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, lon
         }
     }
     bool bad = false;
+    if (q == 0) {  // column 0
+#pragma unroll
+        for (int m = 0; m < MB; ++m) col[g + 8 * m] = v[m][0];
+    }
+    __syncthreads();
     CholWaveSteps<MB, 0, 0>::run(v, col, pivs, r, g, q, bad);
 #pragma unroll
     for (int m = 0; m < MB; ++m) {

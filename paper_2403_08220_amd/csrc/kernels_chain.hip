@@ -62,7 +62,10 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 
 // Backward substitution L^T x = b. Blocks from the bottom: rows of the block subtract
 // the solved part below through column reads (32 consecutive columns per row), then
-// lanes 0..SB-1 of wave 0 finish the block's transposed triangle.
+// lanes 0..SB-1 of wave 0 finish the block's transposed triangle. In that serial part
+// lane l keeps the numerator a_l of x_l; the triangle entries are pre-scaled,
+// L_jl / L_jj (zero unless l < j), so that step j is one broadcast of a_j and one FMA
+// per lane, and x_l = a_l / L_ll at the end.
 __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* x,
                          double* part) {
     const int tid = threadIdx.x;
@@ -76,7 +79,7 @@ __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const dou
             const int lane = tid;
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj)
-                col[jj] = (lane < nb && jj >= lane && jj < nb) ? L[(long)(b0 + jj) * r + b0 + lane] : 0.0;
+                col[jj] = (lane < nb && jj > lane && jj < nb) ? L[(long)(b0 + jj) * r + b0 + lane] : 0.0;
         }
         {
             const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
@@ -96,16 +99,13 @@ __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const dou
                 for (int g = 0; g < 8; ++g) s += part[g * SB + lane];
                 a = b[b0 + lane] - s;
             }
-            double sol = 0.0;
 #pragma unroll
-            for (int jj = SB - 1; jj >= 0; --jj) {
-                if (jj < nb) {
-                    const double xj = lane_bcast(a, jj) * invd[b0 + jj];
-                    if (lane == jj) sol = xj;
-                    if (lane < jj) a -= col[jj] * xj;
-                }
-            }
-            if (lane < nb) x[b0 + lane] = sol;
+            for (int jj = 0; jj < SB; ++jj)
+                if (jj < nb) col[jj] *= invd[b0 + jj];
+#pragma unroll
+            for (int jj = SB - 1; jj >= 0; --jj)
+                if (jj < nb) a -= col[jj] * lane_bcast(a, jj);
+            if (lane < nb) x[b0 + lane] = a * invd[b0 + lane];
         }
         __syncthreads();
     }
@@ -149,7 +149,10 @@ __device__ __forceinline__ void lt_matvec2(const double* __restrict__ L, int r, 
 
 // Forward substitution L w = b (L lower, non-singular). Block rows of SB: the rows of
 // a block first subtract the already solved part (8 threads per row), then lanes
-// 0..SB-1 of wave 0 finish the block's triangle with register broadcasts.
+// 0..SB-1 of wave 0 finish the block's triangle with register broadcasts: lane l keeps
+// the numerator a_l of w_l, the triangle entries are pre-scaled, L_lj / L_jj (zero
+// unless j < l), so step j is one broadcast of a_j and one FMA per lane, and
+// w_l = a_l / L_ll at the end.
 __device__ __forceinline__ void l_solve(const double* __restrict__ L, const double* invd, int r, const double* b, double* w,
                         double* acc_s) {
     const int tid = threadIdx.x;
@@ -162,18 +165,17 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
             const int lane = tid;
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj)
-                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+                row[jj] = (lane < nb && jj < lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
         }
         {
             const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
             const int i = b0 + il;
             double acc = 0.0;
-            if (il < nb)
+            if (il < nb)  // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32)
 #pragma unroll 4
                 for (int j = 4 * sub; j < b0; j += 32)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (j + q < b0) acc += L[(long)i * r + j + q] * w[j + q];
+                    for (int q = 0; q < 4; ++q) acc += L[(long)i * r + j + q] * w[j + q];
 #pragma unroll
             for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
             if (il < nb && sub == 0) acc_s[il] = b[i] - acc;
@@ -182,16 +184,13 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
         if (tid < 64) {
             const int lane = tid;
             double a = lane < nb ? acc_s[lane] : 0.0;
-            double sol = 0.0;
 #pragma unroll
-            for (int jj = 0; jj < SB; ++jj) {
-                if (jj < nb) {
-                    const double wj = lane_bcast(a, jj) * invd[b0 + jj];
-                    if (lane == jj) sol = wj;
-                    if (lane > jj) a -= row[jj] * wj;
-                }
-            }
-            if (lane < nb) w[b0 + lane] = sol;
+            for (int jj = 0; jj < SB; ++jj)
+                if (jj < nb) row[jj] *= invd[b0 + jj];
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                if (jj < nb) a -= row[jj] * lane_bcast(a, jj);
+            if (lane < nb) w[b0 + lane] = a * invd[b0 + lane];
         }
         __syncthreads();
     }
@@ -218,7 +217,7 @@ __device__ __forceinline__ void lt_matvec_acc(const double* __restrict__ L, int 
 }
 
 // Forward substitution for two right-hand sides at once (L w1 = b1, L w2 = b2): one
-// pass over L and one serial sweep for both; acc_s must hold 2 SB doubles.
+// pass over L and one serial sweep for both (as l_solve); acc_s must hold 2 SB doubles.
 __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const double* invd, int r, const double* b1,
                                          double* w1, const double* b2, double* w2, double* acc_s) {
     const int tid = threadIdx.x;
@@ -229,22 +228,21 @@ __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const dou
             const int lane = tid;
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj)
-                row[jj] = (lane < nb && jj <= lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
+                row[jj] = (lane < nb && jj < lane) ? L[(long)(b0 + lane) * r + b0 + jj] : 0.0;
         }
         {
             const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
             const int i = b0 + il;
             double c1 = 0.0, c2 = 0.0;
-            if (il < nb)
+            if (il < nb)  // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32)
 #pragma unroll 4
                 for (int j = 4 * sub; j < b0; j += 32)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (j + q < b0) {
-                            const double lij = L[(long)i * r + j + q];
-                            c1 += lij * w1[j + q];
-                            c2 += lij * w2[j + q];
-                        }
+                    for (int q = 0; q < 4; ++q) {
+                        const double lij = L[(long)i * r + j + q];
+                        c1 += lij * w1[j + q];
+                        c2 += lij * w2[j + q];
+                    }
 #pragma unroll
             for (int o = 4; o > 0; o >>= 1) {
                 c1 += __shfl_xor(c1, o);
@@ -260,25 +258,21 @@ __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const dou
             const int lane = tid;
             double a1 = lane < nb ? acc_s[lane] : 0.0;
             double a2 = lane < nb ? acc_s[SB + lane] : 0.0;
-            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < SB; ++jj)
+                if (jj < nb) row[jj] *= invd[b0 + jj];
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj) {
                 if (jj < nb) {
-                    const double dj = invd[b0 + jj];
-                    const double u1 = lane_bcast(a1, jj) * dj, u2 = lane_bcast(a2, jj) * dj;
-                    if (lane == jj) {
-                        s1 = u1;
-                        s2 = u2;
-                    }
-                    if (lane > jj) {
-                        a1 -= row[jj] * u1;
-                        a2 -= row[jj] * u2;
-                    }
+                    const double u1 = lane_bcast(a1, jj), u2 = lane_bcast(a2, jj);
+                    a1 -= row[jj] * u1;
+                    a2 -= row[jj] * u2;
                 }
             }
             if (lane < nb) {
-                w1[b0 + lane] = s1;
-                w2[b0 + lane] = s2;
+                const double dl = invd[b0 + lane];
+                w1[b0 + lane] = a1 * dl;
+                w2[b0 + lane] = a2 * dl;
             }
         }
         __syncthreads();

@@ -84,9 +84,16 @@ __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const dou
         {
             const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
             double acc = 0.0;
+            constexpr int PB = 8;  // loads issued before their products
             if (il < nb)
-#pragma unroll 8
-                for (int j = b0 + nb + grp; j < r; j += 8) acc += L[(long)j * r + b0 + il] * x[j];
+                for (int j0 = b0 + nb + grp; j0 < r; j0 += 8 * PB) {
+                    double lv[PB];
+#pragma unroll
+                    for (int u = 0; u < PB; ++u) lv[u] = (j0 + 8 * u < r) ? L[(long)(j0 + 8 * u) * r + b0 + il] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < PB; ++u)
+                        if (j0 + 8 * u < r) acc += lv[u] * x[j0 + 8 * u];
+                }
             part[grp * SB + il] = acc;
         }
         __syncthreads();
@@ -99,12 +106,11 @@ __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const dou
                 for (int g = 0; g < 8; ++g) s += part[g * SB + lane];
                 a = b[b0 + lane] - s;
             }
+            // entries past the block are zero: the clamped index only keeps the factor finite
 #pragma unroll
-            for (int jj = 0; jj < SB; ++jj)
-                if (jj < nb) col[jj] *= invd[b0 + jj];
+            for (int jj = 0; jj < SB; ++jj) col[jj] *= invd[min(b0 + jj, r - 1)];
 #pragma unroll
-            for (int jj = SB - 1; jj >= 0; --jj)
-                if (jj < nb) a -= col[jj] * lane_bcast(a, jj);
+            for (int jj = SB - 1; jj >= 0; --jj) a -= col[jj] * lane_bcast(a, jj);
             if (lane < nb) x[b0 + lane] = a * invd[b0 + lane];
         }
         __syncthreads();
@@ -171,11 +177,23 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
             const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
             const int i = b0 + il;
             double acc = 0.0;
-            if (il < nb)  // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32)
-#pragma unroll 4
-                for (int j = 4 * sub; j < b0; j += 32)
+            // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32); the loads of PB
+            // chunks are issued before their products
+            constexpr int PB = 4;
+            if (il < nb)
+                for (int j0 = 4 * sub; j0 < b0; j0 += 32 * PB) {
+                    double lv[PB][4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc += L[(long)i * r + j + q] * w[j + q];
+                    for (int u = 0; u < PB; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            lv[u][q] = (j0 + 32 * u < b0) ? L[(long)i * r + j0 + 32 * u + q] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < PB; ++u)
+                        if (j0 + 32 * u < b0)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) acc += lv[u][q] * w[j0 + 32 * u + q];
+                }
 #pragma unroll
             for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
             if (il < nb && sub == 0) acc_s[il] = b[i] - acc;
@@ -184,12 +202,11 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
         if (tid < 64) {
             const int lane = tid;
             double a = lane < nb ? acc_s[lane] : 0.0;
+            // entries past the block are zero: the clamped index only keeps the factor finite
 #pragma unroll
-            for (int jj = 0; jj < SB; ++jj)
-                if (jj < nb) row[jj] *= invd[b0 + jj];
+            for (int jj = 0; jj < SB; ++jj) row[jj] *= invd[min(b0 + jj, r - 1)];
 #pragma unroll
-            for (int jj = 0; jj < SB; ++jj)
-                if (jj < nb) a -= row[jj] * lane_bcast(a, jj);
+            for (int jj = 0; jj < SB; ++jj) a -= row[jj] * lane_bcast(a, jj);
             if (lane < nb) w[b0 + lane] = a * invd[b0 + lane];
         }
         __syncthreads();
@@ -234,15 +251,26 @@ __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const dou
             const int il = tid >> 3, sub = tid & 7;  // 32 rows x 8 threads
             const int i = b0 + il;
             double c1 = 0.0, c2 = 0.0;
-            if (il < nb)  // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32)
-#pragma unroll 4
-                for (int j = 4 * sub; j < b0; j += 32)
+            // j + 3 < b0 whenever j < b0 (b0 is a multiple of 32); the loads of PB
+            // chunks are issued before their products
+            constexpr int PB = 4;
+            if (il < nb)
+                for (int j0 = 4 * sub; j0 < b0; j0 += 32 * PB) {
+                    double lv[PB][4];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double lij = L[(long)i * r + j + q];
-                        c1 += lij * w1[j + q];
-                        c2 += lij * w2[j + q];
-                    }
+                    for (int u = 0; u < PB; ++u)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            lv[u][q] = (j0 + 32 * u < b0) ? L[(long)i * r + j0 + 32 * u + q] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < PB; ++u)
+                        if (j0 + 32 * u < b0)
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) {
+                                c1 += lv[u][q] * w1[j0 + 32 * u + q];
+                                c2 += lv[u][q] * w2[j0 + 32 * u + q];
+                            }
+                }
 #pragma unroll
             for (int o = 4; o > 0; o >>= 1) {
                 c1 += __shfl_xor(c1, o);
@@ -258,16 +286,14 @@ __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const dou
             const int lane = tid;
             double a1 = lane < nb ? acc_s[lane] : 0.0;
             double a2 = lane < nb ? acc_s[SB + lane] : 0.0;
+            // entries past the block are zero: the clamped index only keeps the factor finite
 #pragma unroll
-            for (int jj = 0; jj < SB; ++jj)
-                if (jj < nb) row[jj] *= invd[b0 + jj];
+            for (int jj = 0; jj < SB; ++jj) row[jj] *= invd[min(b0 + jj, r - 1)];
 #pragma unroll
             for (int jj = 0; jj < SB; ++jj) {
-                if (jj < nb) {
-                    const double u1 = lane_bcast(a1, jj), u2 = lane_bcast(a2, jj);
-                    a1 -= row[jj] * u1;
-                    a2 -= row[jj] * u2;
-                }
+                const double u1 = lane_bcast(a1, jj), u2 = lane_bcast(a2, jj);
+                a1 -= row[jj] * u1;
+                a2 -= row[jj] * u2;
             }
             if (lane < nb) {
                 const double dl = invd[b0 + lane];

@@ -214,22 +214,36 @@ __device__ __forceinline__ void l_solve(const double* __restrict__ L, const doub
 }
 
 // out = L^T v (L lower, row stride r): waves take rows i = wave (mod 4), lanes 64
-// consecutive columns j <= i; the four waves' partial sums are added into out in turn
-// (no scratch beyond out).
-__device__ __forceinline__ void lt_matvec_acc(const double* __restrict__ L, int r, const double* v, double* out) {
+// consecutive columns j <= i, with the loads of PB rows issued before their products;
+// the four waves' partial sums meet in part (4 x 64 doubles) and are added in wave
+// order.
+__device__ __forceinline__ void lt_matvec(const double* __restrict__ L, int r, const double* v, double* out,
+                                          double* part) {
+    static_assert(TPB == 256, "four waves");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int PB = 16;
     for (int jb = 0; jb < r; jb += 64) {
         const int j = jb + lane;
         double a = 0.0;
         if (j < r) {
-#pragma unroll 8
-            for (int i = jb + ((wave - jb) & 3); i < r; i += 4)
-                if (i >= j) a += L[(long)i * r + j] * v[i];
+            for (int i0 = jb + ((wave - jb) & 3); i0 < r; i0 += 4 * PB) {
+                double lv[PB];
+#pragma unroll
+                for (int u = 0; u < PB; ++u) {
+                    const int i = i0 + 4 * u;
+                    lv[u] = (i < r && i >= j) ? L[(long)i * r + j] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < PB; ++u) {
+                    const int i = i0 + 4 * u;
+                    if (i < r && i >= j) a += lv[u] * v[i];
+                }
+            }
         }
-        for (int wq = 0; wq < TPB / 64; ++wq) {
-            if (wave == wq && j < r) out[j] = (wq == 0 ? 0.0 : out[j]) + a;
-            __syncthreads();
-        }
+        part[wave * 64 + lane] = a;
+        __syncthreads();
+        if (wave == 0 && j < r) out[j] = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        __syncthreads();
     }
 }
 
@@ -958,7 +972,39 @@ __device__ __forceinline__ void b_times_lds(const __hip_bfloat16* B, int dy, int
         for (int q = 0; q < NV; ++q) a0[q] = a1[q] = 0.0;
         if (i < dy) {
             const uint4* row = reinterpret_cast<const uint4*>(B + (long)i * ldl);
-            for (int kq = p; kq < nch; kq += P) {
+            int kq = p;
+            // full chunks two at a time: both chunks' LDS reads before the products
+            for (; kq + P < nfull; kq += 2 * P) {
+                const uint4 qa = row[kq], qb = row[kq + P];
+                double va[NV][8], vb[NV][8];
+#pragma unroll
+                for (int q = 0; q < NV; ++q)
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        va[q][e] = vs[q][8 * kq + e];
+                        vb[q][e] = vs[q][8 * (kq + P) + e];
+                    }
+                const uint32_t wa[4] = {qa.x, qa.y, qa.z, qa.w}, wb[4] = {qb.x, qb.y, qb.z, qb.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double blo = bf_lo(wa[e]), bhi = bf_hi(wa[e]);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        a0[q] += blo * va[q][2 * e];
+                        a1[q] += bhi * va[q][2 * e + 1];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double blo = bf_lo(wb[e]), bhi = bf_hi(wb[e]);
+#pragma unroll
+                    for (int q = 0; q < NV; ++q) {
+                        a0[q] += blo * vb[q][2 * e];
+                        a1[q] += bhi * vb[q][2 * e + 1];
+                    }
+                }
+            }
+            for (; kq < nch; kq += P) {
                 const uint4 qv = row[kq];
                 const uint32_t w4[4] = {qv.x, qv.y, qv.z, qv.w};
                 if (kq < nfull) {
@@ -1002,13 +1048,31 @@ __device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, in
     const int tid = threadIdx.x, jp = tid % np, q = tid / np;
     const bool act = q < Q;
     double a0 = 0.0, a1 = 0.0;
-    if (act)
-        for (int i = q; i < dy; i += Q) {
+    if (act) {
+        // U rows per batch: their LDS reads are issued before the products
+        constexpr int U = 8;
+        int i = q;
+        for (; i + (U - 1) * Q < dy; i += U * Q) {
+            uint32_t uu[U];
+            double zz[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                uu[k] = *reinterpret_cast<const uint32_t*>(B + (long)(i + k * Q) * ldl + 2 * jp);
+                zz[k] = z[i + k * Q];
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                a0 += bf_lo(uu[k]) * zz[k];
+                a1 += bf_hi(uu[k]) * zz[k];
+            }
+        }
+        for (; i < dy; i += Q) {
             const uint32_t u = *reinterpret_cast<const uint32_t*>(B + (long)i * ldl + 2 * jp);
             const double zi = z[i];
             a0 += bf_lo(u) * zi;
             a1 += bf_hi(u) * zi;
         }
+    }
     const int j = 2 * jp;
     for (int qq = 0; qq < Q; ++qq) {
         if (act && q == qq) {
@@ -1192,7 +1256,7 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         }
         __syncthreads();
         b_times(Bc, dy, r, ldl, mh, y);          // y = B mhat
-        lt_matvec_acc(Kc, dy, bx, z1);          // z1 = K^T (B x)
+        lt_matvec(Kc, dy, bx, z1, part);        // z1 = K^T (B x)
         double sums[4] = {0.0, 0.0, 0.0, 0.0};   // |v|^2, mhat.v, |K^-1 B v|^2, |B mhat|^2
         for (int j = tid; j < r; j += TPB) {
             sums[0] += v[j] * v[j];

@@ -149,7 +149,7 @@ __device__ __forceinline__ void sweep_layer13(f32x16 (&lam)[13], const bf16x8 (&
         : {bins}, {dins}, [vl] "v"(vl), [z] "a"(z), [n] "s"(n), [tl] "s"(tl), [sl] "s"(sl),
           [sh] "s"(sh), [sb] "s"(sb), [se] "s"(se), [sz] "s"(sz), [sw] "s"(sw), [df] "s"(df), [dsb] "s"(dsb),
           [dm] "s"(dm)
-        : "s60", "s61", "scc", "memory");
+        : "s60", "s61", "m0", "scc", "memory");
     // the ring registers are consumed here (every read above has completed)
     asm volatile("" ::{", ".join(f'"a"(t{i})' for i in range(RING))}, "v"(va), "v"(vb));
 }}

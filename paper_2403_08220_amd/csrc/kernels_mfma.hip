@@ -70,7 +70,8 @@ constexpr int sweep_nbuf(int nmb) { return sweep_nt(nmb) * 4 <= 150 ? 4 : 2; }
 // the explicit vmcnt waits of the kernel (the copy has no VGPR result). The copy reads
 // M0 one wait state after the SALU write.
 __device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base) : "memory");
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base)
+                 : "m0", "memory");
 }
 
 #include "sweep_asm.inc"

@@ -138,6 +138,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_08220_amd.build` "
                           "(hipcc for gfx950); there is no fallback path")
+    # torch first: torch's bundled HIP runtime and the one libdino.so links against share
+    # a soname, so whichever is loaded first serves the whole process. Loading torch's
+    # first gives the library and torch one runtime (the one torch was built with)
+    # whatever the caller imported before.
+    import torch  # noqa: F401
+
     lib = ct.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -551,18 +551,19 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
     }
 }
 
-// Column j = 8 PH + JJ of the single-wave factorisation (compile-time PH, JJ, so that
-// every register index is a constant). Column j was published to col by the previous
-// step (or before the first). The step updates the column block of column j + 1 first
-// and publishes column j + 1 before the rest of the trailing update, so that the LDS
-// round trip of the next pivot overlaps that update.
-template <int MB, int PH, int JJ>
+// Column j = 8 PH + JJ of the single-wave factorisation. The phase PH is a compile-time
+// constant, so that every register index is one; within a phase only JJ changes, and
+// it runs as a loop (the unrolled form of all columns was ~100 KB of code). LAST marks
+// JJ = 7, where column j + 1 lies in the next register block. Column j was published
+// to col by the previous step (or before the first). The step updates the column block
+// of column j + 1 first and publishes column j + 1 before the rest of the trailing
+// update, so that the LDS round trip of the next pivot overlaps that update.
+template <int MB, int PH, bool LAST>
 __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad) {
-    constexpr int j = 8 * PH + JJ;
-    constexpr int PN = (JJ == 7) ? PH + 1 : PH;  // column block of column j + 1
-    constexpr int JN = (JJ + 1) & 7;             // its owners' q
-    if (j >= r) return;
+                                               bool& bad, int JJ) {
+    const int j = 8 * PH + JJ;
+    constexpr int PN = LAST ? PH + 1 : PH;  // column block of column j + 1
+    const int JN = (JJ + 1) & 7;            // its owners' q
     const double piv = col[j];
     bad |= !(piv > 0.0);
     if (g == 0 && q == 0) pivs[j] = piv;  // logs are taken after the sweep, off the critical path
@@ -606,13 +607,18 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
     __syncthreads();
 }
 
-template <int MB, int PH, int JJ>
-struct CholWaveSteps {
+template <int MB, int PH>
+struct CholWavePhases {
     __device__ __forceinline__ static void run(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
                                                bool& bad) {
-        chol_wave_step<MB, PH, JJ>(v, col, pivs, r, g, q, bad);
-        if constexpr (JJ + 1 < 8) CholWaveSteps<MB, PH, JJ + 1>::run(v, col, pivs, r, g, q, bad);
-        else if constexpr (PH + 1 < MB) CholWaveSteps<MB, PH + 1, 0>::run(v, col, pivs, r, g, q, bad);
+#pragma unroll 1
+        for (int JJ = 0; JJ < 7; ++JJ) {
+            if (8 * PH + JJ >= r) return;
+            chol_wave_step<MB, PH, false>(v, col, pivs, r, g, q, bad, JJ);
+        }
+        if (8 * PH + 7 >= r) return;
+        chol_wave_step<MB, PH, true>(v, col, pivs, r, g, q, bad, 7);
+        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1>::run(v, col, pivs, r, g, q, bad);
     }
 };
 
@@ -648,7 +654,7 @@ __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, lon
         for (int m = 0; m < MB; ++m) col[g + 8 * m] = v[m][0];
     }
     __syncthreads();
-    CholWaveSteps<MB, 0, 0>::run(v, col, pivs, r, g, q, bad);
+    CholWavePhases<MB, 0>::run(v, col, pivs, r, g, q, bad);
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int i = g + 8 * m;

@@ -310,6 +310,9 @@ void launch_complement(dino_problem* p, int n, hipStream_t st);
 // dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
 void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
 void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+// Whether the dual-form transition kernels' LDS (vectors, scratch and, on the BF16 path,
+// the staged B) fits one block for reduced dimension r and d_y observations.
+bool dual_lds_fits(int r, int dy, bool bf16);
 void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st);
 // Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
 // no separate misfit launch).

@@ -1520,6 +1520,11 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
 constexpr size_t CH_LDS_LIMIT = 160 * 1024 - 1024;
 static size_t chain_lds_bytes(int r) { return chain_lds_doubles(r) * sizeof(double); }
 
+bool dual_lds_fits(int r, int dy, bool bf16) {
+    const int ldb = bf16 ? (r + 31) / 32 * 32 : r;
+    return dual_lds_doubles(r, dy, ldb, bf16) * sizeof(double) <= CH_LDS_LIMIT;
+}
+
 template <typename K>
 static void allow_large_lds(K kernel, bool& done) {
     if (!done) {

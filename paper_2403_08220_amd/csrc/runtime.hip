@@ -158,6 +158,8 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
                       (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
+    DINO_REQUIRE(!dual || dual_lds_fits(ctx->basis.r, d->d_y, d->precision == DINO_PREC_BF16), DINO_EINVAL,
+                 "d_y x r too large for the dual form's per-chain LDS (B and the work vectors)");
 }
 
 static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d) {

@@ -113,3 +113,28 @@ def test_dual_bf16_against_oracle():
     assert fail.sum() == 0 and abs(a_gpu - a_ref) < 0.08
     p.close()
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_dual_refuses_shapes_beyond_its_lds():
+    """The BF16 dual kernels hold B (d_y x r) and the work vectors in LDS: a shape that does
+    not fit is refused when the problem is described (the FP64 dual kernels read B from
+    global memory and take it)."""
+    import numpy as np
+    from paper_2403_08220_amd import Context, DinoError, Problem
+
+    rng = np.random.default_rng(3)
+    r, dy = 512, 300
+    ctx = Context(0)
+    try:
+        ctx.load_prior(24, 1.0, 1.0, r)  # 576 nodes >= r modes
+        layers = [("act", rng.standard_normal((32, r)) / np.sqrt(r), None),
+                  ("linear", rng.standard_normal((dy, 32)) / np.sqrt(32), None)]
+        ctx.load_network(layers)
+        y, nv = np.zeros(dy), np.ones(dy)
+        with pytest.raises(DinoError, match="too large for the dual form"):
+            Problem(ctx, 4, y, nv, 1e-3, precision="bf16", factorization="dual")
+        p = Problem(ctx, 4, y, nv, 1e-3, precision="f64", factorization="dual")
+        p.close()
+    finally:
+        ctx.close()

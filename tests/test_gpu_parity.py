@@ -83,13 +83,22 @@ def test_geometry_parity(kind):
     ctx.close()
 
 
-def test_propose_and_log_rho_parity():
-    case = small_resnet_case(C=70, dt=0.7)
+@pytest.mark.parametrize("kind", ["resnet", "resnet-r230"])
+def test_propose_and_log_rho_parity(kind):
+    # r = 40: two solve blocks; r = 230: eight blocks with a 6-row tail, panels of up to
+    # seven 32-column chunks (two load batches) and back-solve columns of 190+ rows
+    if kind == "resnet":
+        case = small_resnet_case(C=70, dt=0.7)
+    else:
+        case = make_case("tiny", chains=70, arch="resnet", r=230, width=96, depth=2, d_out=80, d_y=70,
+                         bias_scale=0.3, noise_scale=0.2, dt=0.7)
+    print(f"propose/log rho {kind}", flush=True)
     ctx, p = device_problem(case)
     prob = case["prob"]
+    r = case["w"].r
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((70, 40))
-    xi = rng.standard_normal((70, 40))
+    x = rng.standard_normal((70, r))
+    xi = rng.standard_normal((70, r))
     cx = mcmc.geometry(prob, x)
     xp_ref = mcmc.propose(prob, x, cx, xi)
     xp = p.eval_propose(to_dev(x), to_dev(cx.g), to_dev(cx.L), to_dev(xi))

@@ -57,18 +57,19 @@ def geometry_case(kind):
         return make_case("tiny", chains=70, bias_scale=0.3, noise_scale=0.2)
     if kind == "resnet":
         return small_resnet_case()
-    # reduced dimensions that select the other factorisation kernels (r in 65..128 and r > 208)
-    r = 100 if kind == "resnet-r100" else 230
-    return make_case("tiny", chains=70, arch="resnet", r=r, width=96, depth=2, d_out=80, d_y=70,
-                     bias_scale=0.3, noise_scale=0.2)
+    # reduced dimensions that select the other factorisation kernels (r in 65..128 and r > 208),
+    # and the largest reduced dimension the library takes (512)
+    r = {"resnet-r100": 100, "resnet-r230": 230, "resnet-r512": 512}[kind]
+    return make_case("tiny", chains=70 if r < 512 else 12, arch="resnet", r=r, width=96, depth=2, d_out=80,
+                     d_y=70, bias_scale=0.3, noise_scale=0.2)
 
 
-@pytest.mark.parametrize("kind", ["mlp", "resnet", "resnet-r100", "resnet-r230"])
+@pytest.mark.parametrize("kind", ["mlp", "resnet", "resnet-r100", "resnet-r230", "resnet-r512"])
 def test_geometry_parity(kind):
     case = geometry_case(kind)
     print(f"geometry {kind}", flush=True)
     ctx, p = device_problem(case)
-    x = np.random.default_rng(1).standard_normal((70, case["w"].r))
+    x = np.random.default_rng(1).standard_normal((case["C"], case["w"].r))
     got = {k: v.cpu().numpy() for k, v in p.eval_geometry(to_dev(x)).items()}
     ref = mcmc.geometry(case["prob"], x)
     assert rel_err(got["f"], ref.f) < 1e-12
@@ -83,22 +84,24 @@ def test_geometry_parity(kind):
     ctx.close()
 
 
-@pytest.mark.parametrize("kind", ["resnet", "resnet-r230"])
+@pytest.mark.parametrize("kind", ["resnet", "resnet-r230", "resnet-r512"])
 def test_propose_and_log_rho_parity(kind):
     # r = 40: two solve blocks; r = 230: eight blocks with a 6-row tail, panels of up to
-    # seven 32-column chunks (two load batches) and back-solve columns of 190+ rows
+    # seven 32-column chunks (two load batches) and back-solve columns of 190+ rows;
+    # r = 512: the largest reduced dimension (sixteen blocks, four load batches)
     if kind == "resnet":
         case = small_resnet_case(C=70, dt=0.7)
     else:
-        case = make_case("tiny", chains=70, arch="resnet", r=230, width=96, depth=2, d_out=80, d_y=70,
-                         bias_scale=0.3, noise_scale=0.2, dt=0.7)
+        r = 230 if kind == "resnet-r230" else 512
+        case = make_case("tiny", chains=70 if r < 512 else 12, arch="resnet", r=r, width=96, depth=2, d_out=80,
+                         d_y=70, bias_scale=0.3, noise_scale=0.2, dt=0.7)
     print(f"propose/log rho {kind}", flush=True)
     ctx, p = device_problem(case)
     prob = case["prob"]
-    r = case["w"].r
+    r, C = case["w"].r, case["C"]
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((70, r))
-    xi = rng.standard_normal((70, r))
+    x = rng.standard_normal((C, r))
+    xi = rng.standard_normal((C, r))
     cx = mcmc.geometry(prob, x)
     xp_ref = mcmc.propose(prob, x, cx, xi)
     xp = p.eval_propose(to_dev(x), to_dev(cx.g), to_dev(cx.L), to_dev(xi))

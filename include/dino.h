@@ -115,10 +115,10 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  *   applies (I + H)^-1 by Woodbury and draws the noise (I + H)^-1 (xi_1 + B^T xi_2)
  *   (the same law, N(0, (I + H)^-1); xi_2 = the d_y normals of stream 0 after the
  *   first r); DINO_FACTOR_AUTO takes the dual form when d_y < r. The order of the
- *   factorised matrix must not exceed 512. On the BF16 path the dual form keeps each
- *   chain's B (d_y x r) in LDS: a shape whose B and work vectors exceed one block's
- *   LDS is refused with DINO_EINVAL (by dino_problem_workspace_bytes and
- *   dino_problem_create).
+ *   factorised matrix must not exceed 512. On the BF16 path each chain's Jacobian is
+ *   staged in one block's LDS (the dual form keeps B (d_y x r) and its work vectors,
+ *   the primal form's Gauss-Newton kernel B^T): a shape that does not fit is refused
+ *   with DINO_EINVAL by dino_problem_workspace_bytes and dino_problem_create.
  */
 #define DINO_PREC_F64 0
 #define DINO_PREC_BF16 1

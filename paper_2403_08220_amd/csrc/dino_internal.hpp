@@ -310,6 +310,8 @@ void launch_complement(dino_problem* p, int n, hipStream_t st);
 // dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
 void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
 void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+// Whether the BF16 Gauss-Newton Hessian kernel's LDS (B^T and the residual) fits one block.
+bool hess_bf16_lds_fits(int r, int dy);
 // Whether the dual-form transition kernels' LDS (vectors, scratch and, on the BF16 path,
 // the staged B) fits one block for reduced dimension r and d_y observations.
 bool dual_lds_fits(int r, int dy, bool bf16);

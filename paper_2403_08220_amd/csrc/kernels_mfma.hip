@@ -667,13 +667,21 @@ void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
     DINO_HIP(hipGetLastError());
 }
 
+// LDS of hess_bf16_kernel: B^T (r_pad x (dy_pad + 8) BF16) and the residual (dy floats).
+static size_t hess_bf16_lds(int r, int dy) {
+    const size_t dy_pad = (dy + 15) / 16 * 16, r_pad = (r + 31) / 32 * 32;
+    return r_pad * (dy_pad + 8) * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
+}
+
+bool hess_bf16_lds_fits(int r, int dy) { return hess_bf16_lds(r, dy) <= 160 * 1024 - 64; }
+
 void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                       long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st) {
     const int r = p->r, dy = p->d_y;
     const int dy_pad = (dy + 15) / 16 * 16;
     const int ldt = dy_pad + 8;  // 16-byte aligned rows, shifted banks
     const int r_pad = (r + 31) / 32 * 32;
-    const size_t lds = (size_t)r_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
+    const size_t lds = hess_bf16_lds(r, dy);
     DINO_REQUIRE(lds <= 160 * 1024 - 64, DINO_EINVAL, "r x d_y too large for the LDS-staged Hessian");
     static bool attr = false;
     if (!attr) {

@@ -74,3 +74,26 @@ def test_bf16_chains_step_and_agree_on_decisions_mostly():
     assert abs(a_gpu - a_ref) < 0.08
     p.close()
     ctx.close()
+
+
+@pytest.mark.gpu
+def test_bf16_primal_refuses_shapes_beyond_its_lds():
+    """The BF16 Gauss-Newton Hessian stages B^T (r x d_y) in LDS: a shape that does not fit
+    is refused when the problem is described (the FP64 path takes it)."""
+    from paper_2403_08220_amd import Context, DinoError, Problem
+
+    rng = np.random.default_rng(4)
+    r, dy = 200, 400
+    ctx = Context(0)
+    try:
+        ctx.load_prior(33, 0.1, 1.0, r)
+        layers = [("act", rng.standard_normal((32, r)) / np.sqrt(r), None),
+                  ("linear", rng.standard_normal((dy, 32)) / np.sqrt(32), None)]
+        ctx.load_network(layers)
+        y, nv = np.zeros(dy), np.ones(dy)
+        with pytest.raises(DinoError, match="too large for the BF16 Gauss-Newton Hessian"):
+            Problem(ctx, 4, y, nv, 1e-3, precision="bf16", factorization="primal")
+        p = Problem(ctx, 4, y, nv, 1e-3, precision="f64", factorization="primal")
+        p.close()
+    finally:
+        ctx.close()

@@ -118,7 +118,9 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  *   factorised matrix must not exceed 512. On the BF16 path each chain's Jacobian is
  *   staged in one block's LDS (the dual form keeps B (d_y x r) and its work vectors,
  *   the primal form's Gauss-Newton kernel B^T): a shape that does not fit is refused
- *   with DINO_EINVAL by dino_problem_workspace_bytes and dino_problem_create.
+ *   with DINO_EINVAL by dino_problem_workspace_bytes and dino_problem_create. The BF16
+ *   reverse sweep holds at most 512 rows: networks with a hidden layer wider than 512
+ *   units need DINO_PREC_F64 (also refused with DINO_EINVAL otherwise).
  */
 #define DINO_PREC_F64 0
 #define DINO_PREC_BF16 1

@@ -310,6 +310,9 @@ void launch_complement(dino_problem* p, int n, hipStream_t st);
 // dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
 void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
 void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+// Whether the BF16 reverse sweep covers the network: it holds at most 16 row blocks of 32
+// (the reduced dimension and every hidden width at most 512).
+bool sweep_width_ok(const dino_ctx* ctx);
 // Whether the BF16 Gauss-Newton Hessian kernel's LDS (B^T and the residual) fits one block.
 bool hess_bf16_lds_fits(int r, int dy);
 // Whether the dual-form transition kernels' LDS (vectors, scratch and, on the BF16 path,

@@ -463,14 +463,19 @@ int sweep_template_nmb(int nmb) {
     return 16;
 }
 
-int sweep_nmb(const dino_ctx* ctx) {
+// Row blocks of 32 that the sweep must hold: the widest of r and the hidden layers.
+static int sweep_blocks(const dino_ctx* ctx) {
     int m = (ctx->r_in + 31) / 32;
     for (size_t l = 0; l + 1 < ctx->layers.size(); ++l) {
         m = std::max(m, (ctx->layers[l].fan_in + 31) / 32);
         m = std::max(m, (ctx->layers[l].fan_out + 31) / 32);
     }
-    return sweep_template_nmb(m);
+    return m;
 }
+
+int sweep_nmb(const dino_ctx* ctx) { return sweep_template_nmb(sweep_blocks(ctx)); }
+
+bool sweep_width_ok(const dino_ctx* ctx) { return sweep_blocks(ctx) <= 16; }
 
 // Pack A = W^T tiles for one layer W (fan_out x fan_in) for the sweep instance nmb_t:
 // work item mo (output rows 32 mo .. 32 mo + 31) holds sweep_nt(nmb_t) tiles; tile kc,

@@ -160,6 +160,8 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
     DINO_REQUIRE(!dual || dual_lds_fits(ctx->basis.r, d->d_y, d->precision == DINO_PREC_BF16), DINO_EINVAL,
                  "d_y x r too large for the dual form's per-chain LDS (B and the work vectors)");
+    DINO_REQUIRE(d->precision != DINO_PREC_BF16 || sweep_width_ok(ctx), DINO_EINVAL,
+                 "the BF16 reverse sweep holds layers of at most 512 units: this network needs the FP64 path");
     DINO_REQUIRE(dual || d->precision != DINO_PREC_BF16 || hess_bf16_lds_fits(ctx->basis.r, d->d_y), DINO_EINVAL,
                  "r x d_y too large for the BF16 Gauss-Newton Hessian's LDS (B^T and the residual)");
 }

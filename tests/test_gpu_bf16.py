@@ -97,3 +97,27 @@ def test_bf16_primal_refuses_shapes_beyond_its_lds():
         p.close()
     finally:
         ctx.close()
+
+
+@pytest.mark.gpu
+def test_bf16_refuses_networks_wider_than_the_sweep():
+    """The BF16 reverse sweep holds at most 512 rows (16 blocks of 32): a wider hidden
+    layer is refused when the problem is described instead of being cut short (the FP64
+    path takes it)."""
+    from paper_2403_08220_amd import Context, DinoError, Problem
+
+    rng = np.random.default_rng(5)
+    r, width, dy = 64, 544, 20
+    ctx = Context(0)
+    try:
+        ctx.load_prior(33, 0.1, 1.0, r)
+        layers = [("act", rng.standard_normal((width, r)) / np.sqrt(r), None),
+                  ("linear", rng.standard_normal((dy, width)) / np.sqrt(width), None)]
+        ctx.load_network(layers)
+        y, nv = np.zeros(dy), np.ones(dy)
+        with pytest.raises(DinoError, match="at most 512 units"):
+            Problem(ctx, 4, y, nv, 1e-3, precision="bf16")
+        p = Problem(ctx, 4, y, nv, 1e-3, precision="f64")
+        p.close()
+    finally:
+        ctx.close()

@@ -18,6 +18,11 @@
 
 namespace dino {
 
+// Largest grid extent in y and z; kernels that put chains (or fields) there loop over
+// c = blockIdx.y + k gridDim.y, so any count fits.
+constexpr unsigned GRID_Y_MAX = 65535;
+inline unsigned grid_y(long n) { return (unsigned)(n < (long)GRID_Y_MAX ? (n > 0 ? n : 1) : GRID_Y_MAX); }
+
 // ----------------------------------------------------------------------------------
 // Errors: every ABI call converts failures to a status and a thread-local message.
 struct Error {

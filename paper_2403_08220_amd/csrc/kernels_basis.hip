@@ -67,17 +67,18 @@ __global__ void q_kernel(int n, double* __restrict__ Q) {
 __global__ void sep_axis_kernel(int nf, int n, const double* __restrict__ in, const double* __restrict__ Q,
                                 int trans, double* __restrict__ out) {
     const long nn = (long)n * n;
-    const int f = blockIdx.y;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf || e >= nn) return;
+    if (e >= nn) return;
     const int b = e / n, a = e % n;
-    const double* row = in + f * nn + (long)a * n;
-    double acc = 0.0;
-    if (trans)
-        for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)b * n + c];
-    else
-        for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)c * n + b];
-    out[f * nn + e] = acc;
+    for (int f = blockIdx.y; f < nf; f += gridDim.y) {  // the grid's y extent is capped at GRID_Y_MAX
+        const double* row = in + f * nn + (long)a * n;
+        double acc = 0.0;
+        if (trans)
+            for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)b * n + c];
+        else
+            for (int c = 0; c < n; ++c) acc += row[c] * Q[(long)c * n + b];
+        out[f * nn + e] = acc;
+    }
 }
 
 // KLE position t holds mode perm[t] = k1 n + k2; the transformed grid is laid out
@@ -86,15 +87,16 @@ __global__ void kle_gather_kernel(int nf, int n, int r, const double* __restrict
                                   const double* __restrict__ sqlam, double* __restrict__ x,
                                   double* __restrict__ zp) {
     const long nn = (long)n * n;
-    const int f = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf || t >= nn) return;
+    if (t >= nn) return;
     const int e = perm[t], k1 = e / n, k2 = e % n;
-    const double z = G[f * nn + (long)k2 * n + k1] / sqlam[t];
-    if (t < r) {
-        if (x) x[(long)f * r + t] = z;
-    } else if (zp) {
-        zp[(long)f * (nn - r) + (t - r)] = z;
+    for (int f = blockIdx.y; f < nf; f += gridDim.y) {  // the grid's y extent is capped at GRID_Y_MAX
+        const double z = G[f * nn + (long)k2 * n + k1] / sqlam[t];
+        if (t < r) {
+            if (x) x[(long)f * r + t] = z;
+        } else if (zp) {
+            zp[(long)f * (nn - r) + (t - r)] = z;
+        }
     }
 }
 
@@ -102,18 +104,19 @@ __global__ void kle_scatter_kernel(int nf, int n, int r, const double* __restric
                                    const int32_t* __restrict__ perm, const double* __restrict__ sqlam,
                                    double* __restrict__ G) {
     const long nn = (long)n * n;
-    const int f = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf || t >= nn) return;
+    if (t >= nn) return;
     const int e = perm[t], k1 = e / n, k2 = e % n;
-    const double z = (t < r) ? x[(long)f * r + t] : (zp ? zp[(long)f * (nn - r) + (t - r)] : 0.0);
-    G[f * nn + (long)k2 * n + k1] = z * sqlam[t];
+    for (int f = blockIdx.y; f < nf; f += gridDim.y) {  // the grid's y extent is capped at GRID_Y_MAX
+        const double z = (t < r) ? x[(long)f * r + t] : (zp ? zp[(long)f * (nn - r) + (t - r)] : 0.0);
+        G[f * nn + (long)k2 * n + k1] = z * sqlam[t];
+    }
 }
 
 void launch_encode(const Basis& b, int nf, const double* fields, double* x, double* zp, double* t1, double* t2,
                    hipStream_t st) {
     const int n = b.n;
-    const dim3 grid((n * n + 255) / 256, nf);
+    const dim3 grid((n * n + 255) / 256, grid_y(nf));
     // m[f][j][i] -> t1[f][k1][j] -> t2[f][k2][k1]
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, fields, b.q, 0, t1);
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 0, t2);
@@ -124,7 +127,7 @@ void launch_encode(const Basis& b, int nf, const double* fields, double* x, doub
 void launch_decode(const Basis& b, int nf, const double* x, const double* zp, double* fields, double* t1, double* t2,
                    hipStream_t st) {
     const int n = b.n;
-    const dim3 grid((n * n + 255) / 256, nf);
+    const dim3 grid((n * n + 255) / 256, grid_y(nf));
     // z -> t1[f][k2][k1] -> t2[f][i][k2] -> m[f][j][i]
     hipLaunchKernelGGL(kle_scatter_kernel, grid, dim3(256), 0, st, nf, n, b.r, x, zp, b.perm, b.sqlam, t1);
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 1, t2);
@@ -273,20 +276,23 @@ void launch_posterior(dino_problem* p, int burn_in, double* mean, double* var, d
 // (chain means removed); one block per coordinate walks the lags in pairs.
 __global__ void ess_center_kernel(int n, int C, int r, const float* __restrict__ X, double* __restrict__ Y,
                                   double* __restrict__ cmean) {
-    const int j = blockIdx.x, c = blockIdx.y;
+    const int j = blockIdx.x;
     __shared__ double red[256];
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)X[((long)i * C + c) * r + j];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    for (int c = blockIdx.y; c < C; c += gridDim.y) {  // the grid's y extent is capped at GRID_Y_MAX
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)X[((long)i * C + c) * r + j];
+        red[threadIdx.x] = acc;
         __syncthreads();
+        for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+            if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+            __syncthreads();
+        }
+        const double m = red[0] / n;
+        if (threadIdx.x == 0) cmean[(long)j * C + c] = m;
+        double* y = Y + ((long)j * C + c) * n;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = (double)X[((long)i * C + c) * r + j] - m;
+        __syncthreads();  // red is rewritten for the next chain
     }
-    const double m = red[0] / n;
-    if (threadIdx.x == 0) cmean[(long)j * C + c] = m;
-    double* y = Y + ((long)j * C + c) * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = (double)X[((long)i * C + c) * r + j] - m;
 }
 
 __device__ double block_reduce_256(double v, double* red) {
@@ -353,7 +359,7 @@ void launch_ess(dino_problem* p, int burn_in, double* ess, hipStream_t st) {
     DINO_HIP(hipMalloc(&Y, sizeof(double) * (size_t)r * C * n));
     DINO_HIP(hipMalloc(&cm, sizeof(double) * (size_t)r * C));
     const float* X = p->xtrace + (long)burn_in * C * r;
-    hipLaunchKernelGGL(ess_center_kernel, dim3(r, C), dim3(256), 0, st, n, C, r, X, Y, cm);
+    hipLaunchKernelGGL(ess_center_kernel, dim3(r, grid_y(C)), dim3(256), 0, st, n, C, r, X, Y, cm);
     hipLaunchKernelGGL(ess_kernel, dim3(r), dim3(256), 0, st, n, C, Y, cm, ess);
     DINO_HIP(hipGetLastError());
     DINO_HIP(hipStreamSynchronize(st));

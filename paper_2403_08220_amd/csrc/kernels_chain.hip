@@ -1384,9 +1384,8 @@ __global__ void copy_b_kernel(long count, const TB* __restrict__ src, TB* __rest
 
 // pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state). Runs
 // after the accept kernel of the same step.
-__global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, double s, double beta, ChainMeta meta,
-                                                         const int32_t* __restrict__ accflag, float* z) {
-    const int c = blockIdx.y;
+__device__ __forceinline__ void complement_chain(int c, int d_perp, int ldz, double s, double beta,
+                                                 const ChainMeta& meta, const int32_t* __restrict__ accflag, float* z) {
     const int flag = accflag[c];
     if (!flag) return;
     const int b4 = blockIdx.x * TPB + threadIdx.x;
@@ -1413,6 +1412,13 @@ __global__ __launch_bounds__(TPB) void complement_kernel(int d_perp, int ldz, do
     } else {
         for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)(s * (double)zc[j0 + q] + beta * nv[q]);
     }
+}
+
+// Chains c = blockIdx.y + k gridDim.y (the grid's y extent is capped at GRID_Y_MAX).
+__global__ __launch_bounds__(TPB) void complement_kernel(int n, int d_perp, int ldz, double s, double beta,
+                                                         ChainMeta meta, const int32_t* __restrict__ accflag,
+                                                         float* z) {
+    for (int c = blockIdx.y; c < n; c += gridDim.y) complement_chain(c, d_perp, ldz, s, beta, meta, accflag, z);
 }
 
 __global__ void meta_fill_kernel(ChainMeta meta, double* __restrict__ sumx, int r, int c0, int n, uint64_t key0,
@@ -1459,17 +1465,18 @@ __global__ __launch_bounds__(256) void decode_kernel(int d_m, int r, const doubl
 // Normals of one stream for n chains at one step: out[c][k], k < count.
 __global__ void normals_kernel(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count,
                                double* out, long ldo, int as_float, float* outf) {
-    const int c = blockIdx.y;
     const int b4 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n || 4 * b4 >= count) return;
-    double nv[4];
-    philox_normals4(seed, rid, (uint64_t)b4, (uint64_t)stream_id, (uint64_t)step, (uint64_t)c, nv);
+    if (4 * b4 >= count) return;
+    for (int c = blockIdx.y; c < n; c += gridDim.y) {  // the grid's y extent is capped at GRID_Y_MAX
+        double nv[4];
+        philox_normals4(seed, rid, (uint64_t)b4, (uint64_t)stream_id, (uint64_t)step, (uint64_t)c, nv);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int k = 4 * b4 + q;
-        if (k < count) {
-            if (as_float) outf[(long)c * ldo + k] = (float)nv[q];
-            else out[(long)c * ldo + k] = nv[q];
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * b4 + q;
+            if (k < count) {
+                if (as_float) outf[(long)c * ldo + k] = (float)nv[q];
+                else out[(long)c * ldo + k] = nv[q];
+            }
         }
     }
 }
@@ -1629,8 +1636,8 @@ void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st) {
 void launch_complement(dino_problem* p, int n, hipStream_t st) {
     if (!p->z || p->d_perp == 0) return;
     const int nb4 = (p->d_perp + 3) / 4;
-    dim3 grid((nb4 + TPB - 1) / TPB, n);
-    hipLaunchKernelGGL(complement_kernel, grid, dim3(TPB), 0, st, p->d_perp, ldz_of(p->d_perp), p->s, p->beta,
+    dim3 grid((nb4 + TPB - 1) / TPB, grid_y(n));
+    hipLaunchKernelGGL(complement_kernel, grid, dim3(TPB), 0, st, n, p->d_perp, ldz_of(p->d_perp), p->s, p->beta,
                        p->meta, p->acc, p->z);
     DINO_HIP(hipGetLastError());
 }
@@ -1656,12 +1663,12 @@ void launch_request_mean(dino_problem* p, int c0, int n, int64_t count, double* 
 
 void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st) {
     if (draw_x) {
-        dim3 grid(((p->r + 3) / 4 + 255) / 256, p->C);
+        dim3 grid(((p->r + 3) / 4 + 255) / 256, grid_y(p->C));
         hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, p->desc.seed, p->desc.request_id, p->C,
                            (int)STREAM_INIT_X, (int64_t)0, p->r, p->x, (long)p->r, 0, (float*)nullptr);
     }
     if (draw_z && p->z) {
-        dim3 grid(((p->d_perp + 3) / 4 + 255) / 256, p->C);
+        dim3 grid(((p->d_perp + 3) / 4 + 255) / 256, grid_y(p->C));
         hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, p->desc.seed, p->desc.request_id, p->C,
                            (int)STREAM_INIT_Z, (int64_t)0, p->d_perp, (double*)nullptr, (long)ldz_of(p->d_perp),
                            1, p->z);
@@ -1671,7 +1678,7 @@ void launch_init_draws(dino_problem* p, int draw_x, int draw_z, hipStream_t st) 
 
 void launch_normals(uint64_t seed, uint64_t rid, int n, int stream_id, int64_t step, int count, double* out,
                     hipStream_t st) {
-    dim3 grid(((count + 3) / 4 + 255) / 256, n);
+    dim3 grid(((count + 3) / 4 + 255) / 256, grid_y(n));
     hipLaunchKernelGGL(normals_kernel, grid, dim3(256), 0, st, seed, rid, n, stream_id, step, count, out,
                        (long)count, 0, (float*)nullptr);
     DINO_HIP(hipGetLastError());

@@ -106,52 +106,55 @@ __global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int
     __shared__ T As[16][64 + 1];
     __shared__ T Bs[16][64 + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    T acc[4][4];
+    const int n0 = blockIdx.x * 64;
+    // row tiles m0 = 64 (blockIdx.y + k gridDim.y) (the grid's y extent is capped at GRID_Y_MAX)
+    for (int m0 = blockIdx.y * 64; m0 < M; m0 += gridDim.y * 64) {
+        T acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
-    for (int k0 = 0; k0 < K; k0 += 16) {
+            for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+        for (int k0 = 0; k0 < K; k0 += 16) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int row = ty + 16 * q, k = k0 + tx;
-            T v = T(0);
-            if (m0 + row < M && k < K) {
-                v = lam[(long)(m0 + row) * ldl + k];
-                if (d) v *= d[(long)((m0 + row) / dy) * ldd + k];
+            for (int q = 0; q < 4; ++q) {
+                const int row = ty + 16 * q, k = k0 + tx;
+                T v = T(0);
+                if (m0 + row < M && k < K) {
+                    v = lam[(long)(m0 + row) * ldl + k];
+                    if (d) v *= d[(long)((m0 + row) / dy) * ldd + k];
+                }
+                As[tx][row] = v;
+                // B tile: 16 k-rows x 64 n-columns, thread t -> k = t / 64 + 4 q, n = t % 64
+                const int kb = (tid >> 6) + 4 * q, nb = tid & 63;
+                Bs[kb][nb] = (k0 + kb < K && n0 + nb < N) ? W[(long)(k0 + kb) * N + n0 + nb] : T(0);
             }
-            As[tx][row] = v;
-            // B tile: 16 k-rows x 64 n-columns, thread t -> k = t / 64 + 4 q, n = t % 64
-            const int kb = (tid >> 6) + 4 * q, nb = tid & 63;
-            Bs[kb][nb] = (k0 + kb < K && n0 + nb < N) ? W[(long)(k0 + kb) * N + n0 + nb] : T(0);
+            __syncthreads();
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                T a[4], w[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * w[j];
+            }
+            __syncthreads();
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            T a[4], w[4];
+        for (int i = 0; i < 4; ++i) {
+            const int m = m0 + ty + 16 * i;
+            if (m >= M) continue;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) w[j] = Bs[kk][tx + 16 * j];
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * w[j];
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty + 16 * i;
-        if (m >= M) continue;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + tx + 16 * j;
-            if (n >= N) continue;
-            T o = acc[i][j];
-            if (resid) o += lam[(long)m * ldl + n];
-            out[(long)m * ldo + n] = o;
+            for (int j = 0; j < 4; ++j) {
+                const int n = n0 + tx + 16 * j;
+                if (n >= N) continue;
+                T o = acc[i][j];
+                if (resid) o += lam[(long)m * ldl + n];
+                out[(long)m * ldo + n] = o;
+            }
         }
     }
 }
@@ -206,51 +209,53 @@ __global__ __launch_bounds__(256) void misfit_grad_kernel(int n, int dy, int r, 
 
 // ---------------------------------------------------------------------------------
 // A_c = I + B_c^T B_c (or B_c^T B_c): tile 32 x 32 of the r x r output per block.
-__global__ __launch_bounds__(256) void gn_hessian_kernel(int dy, int r, const double* __restrict__ B, double* A,
+__global__ __launch_bounds__(256) void gn_hessian_kernel(int n, int dy, int r, const double* __restrict__ B, double* A,
                                                          long strideA, const int32_t* __restrict__ slot,
                                                          int slot_xor, long slot_stride, int add_identity,
                                                          int full) {
     __shared__ double Bj[16][33];
     __shared__ double Bk[16][33];
-    const int c = blockIdx.z;
     const int j0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
     if (!full && k0 > j0 + 31) return;  // upper tiles: not needed by the lower Cholesky
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const double* Bc = B + (long)c * dy * r;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int i0 = 0; i0 < dy; i0 += 16) {
-        for (int e = tid; e < 16 * 32; e += 256) {
-            const int ii = e >> 5, jj = e & 31;
-            const bool okr = i0 + ii < dy;
-            Bj[ii][jj] = (okr && j0 + jj < r) ? Bc[(long)(i0 + ii) * r + j0 + jj] : 0.0;
-            Bk[ii][jj] = (okr && k0 + jj < r) ? Bc[(long)(i0 + ii) * r + k0 + jj] : 0.0;
-        }
-        __syncthreads();
+    // chains c = blockIdx.z + k gridDim.z (the grid's z extent is capped at GRID_Y_MAX)
+    for (int c = blockIdx.z; c < n; c += gridDim.z) {
+        const double* Bc = B + (long)c * dy * r;
+        double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+        for (int i0 = 0; i0 < dy; i0 += 16) {
+            for (int e = tid; e < 16 * 32; e += 256) {
+                const int ii = e >> 5, jj = e & 31;
+                const bool okr = i0 + ii < dy;
+                Bj[ii][jj] = (okr && j0 + jj < r) ? Bc[(long)(i0 + ii) * r + j0 + jj] : 0.0;
+                Bk[ii][jj] = (okr && k0 + jj < r) ? Bc[(long)(i0 + ii) * r + k0 + jj] : 0.0;
+            }
+            __syncthreads();
 #pragma unroll
-        for (int ii = 0; ii < 16; ++ii) {
-            const double a0 = Bj[ii][ty], a1 = Bj[ii][ty + 16];
-            const double b0 = Bk[ii][tx], b1 = Bk[ii][tx + 16];
-            acc[0][0] += a0 * b0;
-            acc[0][1] += a0 * b1;
-            acc[1][0] += a1 * b0;
-            acc[1][1] += a1 * b1;
+            for (int ii = 0; ii < 16; ++ii) {
+                const double a0 = Bj[ii][ty], a1 = Bj[ii][ty + 16];
+                const double b0 = Bk[ii][tx], b1 = Bk[ii][tx + 16];
+                acc[0][0] += a0 * b0;
+                acc[0][1] += a0 * b1;
+                acc[1][0] += a1 * b0;
+                acc[1][1] += a1 * b1;
+            }
+            __syncthreads();
         }
-        __syncthreads();
+        const long off = (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+        double* Ac = A + off;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int j = j0 + ty + 16 * a, k = k0 + tx + 16 * b;
+                if (j < r && k < r) Ac[(long)j * r + k] = acc[a][b] + ((add_identity && j == k) ? 1.0 : 0.0);
+            }
     }
-    const long off = (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
-    double* Ac = A + off;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int j = j0 + ty + 16 * a, k = k0 + tx + 16 * b;
-            if (j < r && k < r) Ac[(long)j * r + k] = acc[a][b] + ((add_identity && j == k) ? 1.0 : 0.0);
-        }
 }
 
 // ---------------------------------------------------------------------------------
 // Host launchers.
-static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, (M + 63) / 64); }
+static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, grid_y((M + 63) / 64)); }
 
 // One forward layer with the largest tile that still gives >= 1024 blocks.
 // FP32 layer on MFMA (v_mfma_f32_32x32x2_f32: FP32 products, FP32 accumulation): a
@@ -541,7 +546,7 @@ void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, 
                             const int32_t* slot, int slot_xor, long slot_stride, int add_identity, int full,
                             hipStream_t st) {
     const int t = (p->r + 31) / 32;
-    hipLaunchKernelGGL(gn_hessian_kernel, dim3(t, t, n), dim3(256), 0, st, p->d_y, p->r, B, A, strideA, slot,
+    hipLaunchKernelGGL(gn_hessian_kernel, dim3(t, t, grid_y(n)), dim3(256), 0, st, n, p->d_y, p->r, B, A, strideA, slot,
                        slot_xor, slot_stride, add_identity, full);
     DINO_HIP(hipGetLastError());
 }

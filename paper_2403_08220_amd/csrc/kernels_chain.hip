@@ -1384,11 +1384,17 @@ __global__ void copy_b_kernel(long count, const TB* __restrict__ src, TB* __rest
 
 // pCN move of the complement on accepted chains: z <- s z + beta zeta (FP32 state). Runs
 // after the accept kernel of the same step.
-__device__ __forceinline__ void complement_chain(int c, int d_perp, int ldz, double s, double beta,
-                                                 const ChainMeta& meta, const int32_t* __restrict__ accflag, float* z) {
+// Grid: nbx blocks per chain, chain c = blockIdx.y; with FOLD (more chains than the
+// grid's y extent) a 1-D grid, chain c = blockIdx.x / nbx.
+template <bool FOLD>
+__global__ __launch_bounds__(TPB) void complement_kernel(int nbx, int d_perp, int ldz, double s, double beta,
+                                                         ChainMeta meta, const int32_t* __restrict__ accflag,
+                                                         float* z) {
+    const int c = FOLD ? (int)(blockIdx.x / nbx) : (int)blockIdx.y;
     const int flag = accflag[c];
     if (!flag) return;
-    const int b4 = blockIdx.x * TPB + threadIdx.x;
+    const int bx = FOLD ? (int)blockIdx.x - c * nbx : (int)blockIdx.x;
+    const int b4 = bx * TPB + threadIdx.x;
     const int j0 = 4 * b4;
     if (j0 >= d_perp) return;
     double nv[4];
@@ -1412,13 +1418,6 @@ __device__ __forceinline__ void complement_chain(int c, int d_perp, int ldz, dou
     } else {
         for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)(s * (double)zc[j0 + q] + beta * nv[q]);
     }
-}
-
-// Chains c = blockIdx.y + k gridDim.y (the grid's y extent is capped at GRID_Y_MAX).
-__global__ __launch_bounds__(TPB) void complement_kernel(int n, int d_perp, int ldz, double s, double beta,
-                                                         ChainMeta meta, const int32_t* __restrict__ accflag,
-                                                         float* z) {
-    for (int c = blockIdx.y; c < n; c += gridDim.y) complement_chain(c, d_perp, ldz, s, beta, meta, accflag, z);
 }
 
 __global__ void meta_fill_kernel(ChainMeta meta, double* __restrict__ sumx, int r, int c0, int n, uint64_t key0,
@@ -1636,9 +1635,13 @@ void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st) {
 void launch_complement(dino_problem* p, int n, hipStream_t st) {
     if (!p->z || p->d_perp == 0) return;
     const int nb4 = (p->d_perp + 3) / 4;
-    dim3 grid((nb4 + TPB - 1) / TPB, grid_y(n));
-    hipLaunchKernelGGL(complement_kernel, grid, dim3(TPB), 0, st, n, p->d_perp, ldz_of(p->d_perp), p->s, p->beta,
-                       p->meta, p->acc, p->z);
+    const int nbx = (nb4 + TPB - 1) / TPB;
+    if (n <= (int)GRID_Y_MAX)
+        hipLaunchKernelGGL(complement_kernel<false>, dim3(nbx, n), dim3(TPB), 0, st, nbx, p->d_perp, ldz_of(p->d_perp),
+                           p->s, p->beta, p->meta, p->acc, p->z);
+    else
+        hipLaunchKernelGGL(complement_kernel<true>, dim3((unsigned)((long)nbx * n)), dim3(TPB), 0, st, nbx,
+                           p->d_perp, ldz_of(p->d_perp), p->s, p->beta, p->meta, p->acc, p->z);
     DINO_HIP(hipGetLastError());
 }
 

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void fwd_layer_kernel(int M, int K, int N, con
 // ---------------------------------------------------------------------------------
 // Reverse sweep layer on rows R = (chain, output): out[R][n] = (resid ? lam[R][n] : 0)
 //   + sum_k lam[R][k] * (d ? d[R / dy][k] : 1) * W[k][n],  W of shape K x N (fan_out x fan_in).
-template <typename T>
+template <typename T, bool STRIDE>
 __global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int dy, const T* __restrict__ lam,
                                                         int ldl, const T* __restrict__ d, int ldd,
                                                         const T* __restrict__ W, int resid, T* __restrict__ out,
@@ -107,8 +107,8 @@ __global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int
     __shared__ T Bs[16][64 + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int n0 = blockIdx.x * 64;
-    // row tiles m0 = 64 (blockIdx.y + k gridDim.y) (the grid's y extent is capped at GRID_Y_MAX)
-    for (int m0 = blockIdx.y * 64; m0 < M; m0 += gridDim.y * 64) {
+    // STRIDE: more row tiles than the grid's y extent, tiles m0 = 64 (blockIdx.y + k gridDim.y)
+    auto tile = [&](const int m0) {
         T acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -156,6 +156,11 @@ __global__ __launch_bounds__(256) void rev_layer_kernel(int M, int K, int N, int
                 out[(long)m * ldo + n] = o;
             }
         }
+    };
+    if constexpr (STRIDE) {
+        for (int m0 = blockIdx.y * 64; m0 < M; m0 += gridDim.y * 64) tile(m0);
+    } else {
+        tile(blockIdx.y * 64);
     }
 }
 
@@ -209,6 +214,7 @@ __global__ __launch_bounds__(256) void misfit_grad_kernel(int n, int dy, int r, 
 
 // ---------------------------------------------------------------------------------
 // A_c = I + B_c^T B_c (or B_c^T B_c): tile 32 x 32 of the r x r output per block.
+template <bool STRIDE>
 __global__ __launch_bounds__(256) void gn_hessian_kernel(int n, int dy, int r, const double* __restrict__ B, double* A,
                                                          long strideA, const int32_t* __restrict__ slot,
                                                          int slot_xor, long slot_stride, int add_identity,
@@ -218,8 +224,8 @@ __global__ __launch_bounds__(256) void gn_hessian_kernel(int n, int dy, int r, c
     const int j0 = blockIdx.y * 32, k0 = blockIdx.x * 32;
     if (!full && k0 > j0 + 31) return;  // upper tiles: not needed by the lower Cholesky
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    // chains c = blockIdx.z + k gridDim.z (the grid's z extent is capped at GRID_Y_MAX)
-    for (int c = blockIdx.z; c < n; c += gridDim.z) {
+    // STRIDE: more chains than the grid's z extent, chains c = blockIdx.z + k gridDim.z
+    auto chain = [&](const int c) {
         const double* Bc = B + (long)c * dy * r;
         double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
         for (int i0 = 0; i0 < dy; i0 += 16) {
@@ -250,6 +256,11 @@ __global__ __launch_bounds__(256) void gn_hessian_kernel(int n, int dy, int r, c
                 const int j = j0 + ty + 16 * a, k = k0 + tx + 16 * b;
                 if (j < r && k < r) Ac[(long)j * r + k] = acc[a][b] + ((add_identity && j == k) ? 1.0 : 0.0);
             }
+    };
+    if constexpr (STRIDE) {
+        for (int c = blockIdx.z; c < n; c += gridDim.z) chain(c);
+    } else {
+        chain(blockIdx.z);
     }
 }
 
@@ -527,7 +538,8 @@ void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t 
         const bool first = (l == 0);
         double* out = first ? B_out : nxt;
         const int ldo = first ? p->r : ld;
-        hipLaunchKernelGGL(rev_layer_kernel<double>, grid2(M, ly.fan_in), dim3(256), 0, st, M, ly.fan_out,
+        auto kern = (M + 63) / 64 > (int)GRID_Y_MAX ? rev_layer_kernel<double, true> : rev_layer_kernel<double, false>;
+        hipLaunchKernelGGL(kern, grid2(M, ly.fan_in), dim3(256), 0, st, M, ly.fan_out,
                            ly.fan_in, dy, cur, ld, d, p->wmax, ly.W64, ly.kind == DINO_LAYER_RESID ? 1 : 0, out,
                            ldo);
         if (!first) std::swap(cur, nxt);
@@ -546,7 +558,8 @@ void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, 
                             const int32_t* slot, int slot_xor, long slot_stride, int add_identity, int full,
                             hipStream_t st) {
     const int t = (p->r + 31) / 32;
-    hipLaunchKernelGGL(gn_hessian_kernel, dim3(t, t, grid_y(n)), dim3(256), 0, st, n, p->d_y, p->r, B, A, strideA, slot,
+    auto kern = n > (int)GRID_Y_MAX ? gn_hessian_kernel<true> : gn_hessian_kernel<false>;
+    hipLaunchKernelGGL(kern, dim3(t, t, grid_y(n)), dim3(256), 0, st, n, p->d_y, p->r, B, A, strideA, slot,
                        slot_xor, slot_stride, add_identity, full);
     DINO_HIP(hipGetLastError());
 }

@@ -27,6 +27,9 @@ Readings of the paper taken here (listed with reasons in the design notes):
   accept iff log xi_1 <= log rho (Alg. 1 rejects iff alpha < xi_1, so ties accept).
 * A proposal whose misfit is not finite or whose I + H is not positive definite is
   rejected and counted.
+* The pCN baseline (method "pcn") uses the same s = (4 - dt)/(4 + dt): it is the
+  mMALA proposal with H = 0 and g = 0, x+ = s x + beta xi (xi: the first r normals of
+  the proposal stream), accepted with exp(Phi(x) - Phi(x+)).
 """
 from __future__ import annotations
 
@@ -49,6 +52,7 @@ class Problem:
     seed: int = 0
     request_id: int = 0
     factor: str = "primal"   # proposal noise mapping: "primal" (L^-T xi) or "dual"
+    method: str = "mmala"    # "mmala", or "pcn": the baseline without geometry (Sec. 6, table of baselines)
 
     @property
     def d_y(self) -> int:
@@ -56,7 +60,7 @@ class Problem:
 
     @property
     def s(self) -> float:
-        """s = (4 - dt)/(4 + dt) (Sec. 2.6, eq. mmala)."""
+        """s = (4 - dt)/(4 + dt) (Sec. 2.7, eq. mmala)."""
         return (4.0 - self.dt) / (4.0 + self.dt)
 
     @property
@@ -109,6 +113,17 @@ def geometry(prob: Problem, x: np.ndarray) -> Cache:
         except np.linalg.LinAlgError:
             ok[c] = False
     return Cache(f=f, phi=phi, g=g, H=H, d=d, P=P, L=L, ok=ok, B=Jw)
+
+
+def misfit(prob: Problem, x: np.ndarray):
+    """Network output f (C, d_y) and surrogate reduced misfit phi (C,) at x, without
+    derivatives (Sec. 5.1): all that the pCN baseline evaluates per proposal."""
+    x = np.atleast_2d(np.asarray(x, dtype=np.float64))
+    f_full, _ = network.forward(prob.layers, x)
+    f = f_full[:, :prob.d_y]
+    w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
+    res = (prob.y[None, :] - f) * w[None, :]
+    return f, 0.5 * np.sum(res * res, axis=1)
 
 
 def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:
@@ -207,6 +222,8 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
 
     xi (C, r), u (C,) and zeta (C, d_m - r) default to the Philox streams at the
     current step; pass them to evaluate the transition at given draws."""
+    if prob.method == "pcn":
+        return transition_pcn(prob, st, xi, u, zeta)
     C, r = st.x.shape
     if xi is None:
         count = r + prob.d_y if prob.factor == "dual" else r
@@ -221,19 +238,59 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
     log_u = np.log(u)
     acc = log_u <= lr
     st.failures += (~cp.ok).astype(np.int64)
-    # splitting proposition of Sec. 5.3, item 1: pCN move of the complement, realised on accepted moves only
-    if st.z is not None and np.any(acc):
-        idx = np.nonzero(acc)[0]
-        if zeta is None:
-            zeta_a = philox.normals(prob.seed, prob.request_id, philox.STREAM_COMPLEMENT, st.step,
-                                    st.chains[idx], st.z.shape[1])
-        else:
-            zeta_a = zeta[idx]
-        st.z[idx] = prob.s * st.z[idx] + prob.beta * zeta_a
+    _move_complement(prob, st, acc, zeta)
     st.x = np.where(acc[:, None], xp, st.x)
     st.cache = _select(st.cache, cp, acc)
     st.accepts += acc.astype(np.int64)
     st.step += 1
+    return StepRecord(xp=xp, cache_p=cp, log_rho=lr, log_u=log_u, accept=acc)
+
+
+def _move_complement(prob: Problem, st: ChainState, acc: np.ndarray, zeta) -> None:
+    """The pCN move of the complement (splitting proposition of Sec. 5.3, item 1), realised
+    on accepted moves only."""
+    if st.z is None or not np.any(acc):
+        return
+    idx = np.nonzero(acc)[0]
+    if zeta is None:
+        zeta_a = philox.normals(prob.seed, prob.request_id, philox.STREAM_COMPLEMENT, st.step,
+                                st.chains[idx], st.z.shape[1])
+    else:
+        zeta_a = zeta[idx]
+    st.z[idx] = prob.s * st.z[idx] + prob.beta * zeta_a
+
+
+def transition_pcn(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> StepRecord:
+    """One transition of the pCN baseline for every chain (Sec. 2.6, eq. pCN_proposal and
+    its transition rate ratio; the pCN row of the table of baselines in Sec. 6.1).
+
+    In whitened coordinates the prior is N(0, I), so the proposal N(s m, (1 - s^2) C_pr)
+    reads x+ = s x + beta xi in R^r and, for the complement, the same move as in the
+    splitting proposition. The proposal is prior-reversible, so the ratio is
+    exp(Phi(x) - Phi(x+)). s = (4 - dt)/(4 + dt) as for mMALA: it is the mMALA proposal
+    with the geometry removed (H = 0, g = 0). xi (C, r): the first r normals of the
+    proposal stream. The cache keeps f and phi current; its derivative fields are those
+    of the initial states."""
+    C, r = st.x.shape
+    if xi is None:
+        xi = philox.normals(prob.seed, prob.request_id, philox.STREAM_XI, st.step, st.chains, r)
+    if u is None:
+        u = philox.uniforms(prob.seed, prob.request_id, st.step, st.chains)
+    xp = prob.s * st.x + prob.beta * xi[:, :r]
+    fp, phip = misfit(prob, xp)
+    lr = st.cache.phi - phip
+    good = np.isfinite(lr)
+    lr = np.where(good, lr, -np.inf)
+    log_u = np.log(u)
+    acc = log_u <= lr
+    st.failures += (~good).astype(np.int64)
+    _move_complement(prob, st, acc, zeta)
+    st.x = np.where(acc[:, None], xp, st.x)
+    st.cache.phi = np.where(acc, phip, st.cache.phi)
+    st.cache.f = np.where(acc[:, None], fp, st.cache.f)
+    st.accepts += acc.astype(np.int64)
+    st.step += 1
+    cp = Cache(f=fp, phi=phip, g=None, H=None, d=None, P=None, L=None, ok=good)
     return StepRecord(xp=xp, cache_p=cp, log_rho=lr, log_u=log_u, accept=acc)
 
 

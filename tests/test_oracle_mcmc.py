@@ -283,3 +283,90 @@ def test_nonlinear_chain_matches_quadrature(r):
     assert np.all(np.abs(X.mean(0) - mean) < 4.5 * mcse)
     var_tol = 5.0 * np.sqrt(2.0 / n_eff) * np.diag(cov) + 5 * mcse * np.abs(X.mean(0) - mean)
     assert np.all(np.abs(X.var(0) - np.diag(cov)) < var_tol)
+
+
+# ---- pCN baseline (Sec. 2.6, eq. pCN_proposal; the pCN row of the baselines of Sec. 6.1) ----
+
+def test_pcn_misfit_is_the_geometry_misfit():
+    prob = nonlinear_problem()
+    x = np.random.default_rng(21).standard_normal((5, 4))
+    f, phi = mcmc.misfit(prob, x)
+    c = mcmc.geometry(prob, x)
+    np.testing.assert_array_equal(phi, c.phi)
+    np.testing.assert_array_equal(f, c.f)
+
+
+def test_pcn_log_rho_is_the_textbook_mh_ratio():
+    """log rho = log pi(x+) q(x+ -> x) - log pi(x) q(x -> x+), with pi = exp(-Phi) N(0, I)
+    and the pCN law q(a -> .) = N(s a, (1 - s^2) I), evaluated by scipy's Gaussian density."""
+    prob = nonlinear_problem(dt=0.6)
+    prob.method = "pcn"
+    rng = np.random.default_rng(22)
+    x = rng.standard_normal((6, 4))
+    st = mcmc.init_state(prob, x)
+    xi = rng.standard_normal((6, 4))
+    rec = mcmc.transition(prob, st, xi=xi, u=np.full(6, 0.5))
+    np.testing.assert_allclose(rec.xp, prob.s * x + prob.beta * xi, rtol=1e-15, atol=1e-15)
+    cov = (1.0 - prob.s ** 2) * np.eye(4)
+    for c in range(6):
+        a, b = x[c], rec.xp[c]
+        phi_a = mcmc.geometry(prob, a[None]).phi[0]
+        phi_b = mcmc.geometry(prob, b[None]).phi[0]
+        ref = (-phi_b - 0.5 * b @ b + multivariate_normal.logpdf(a, prob.s * b, cov)
+               + phi_a + 0.5 * a @ a - multivariate_normal.logpdf(b, prob.s * a, cov))
+        assert abs(rec.log_rho[c] - ref) < 1e-10 * max(1.0, abs(ref))
+    np.testing.assert_array_equal(rec.accept, np.log(0.5) <= rec.log_rho)
+
+
+def test_pcn_without_likelihood_is_the_prior_ar1():
+    """With Phi = 0 every pCN move is accepted and each coordinate is the AR(1) chain with
+    coefficient s and stationary law N(0, 1)."""
+    prob = nonlinear_problem(dt=0.8)
+    prob.method = "pcn"
+    prob.noise_var = np.full(prob.d_y, np.inf)
+    C, N = 8, 1500
+    st = mcmc.init_state(prob, np.zeros((C, 4)))
+    xs, _ = mcmc.run(prob, st, N)
+    assert np.all(st.accepts == N)
+    X = xs[300:]
+    n_eff = X.size * (1 - prob.s) / (1 + prob.s)
+    assert abs(X.var() - 1.0) < 5 * np.sqrt(2 / n_eff)
+    lag1 = np.mean(X[1:] * X[:-1]) / np.mean(X * X)
+    assert abs(lag1 - prob.s) < 0.03
+
+
+def test_pcn_chain_matches_quadrature():
+    prob = nonlinear_problem(r=1, d_out=2, dt=1.0, noise=0.5, seed=5)
+    prob.method = "pcn"
+    mean, cov = quadrature_moments(prob, 1)
+    C, N = 24, 3000
+    x0 = np.random.default_rng(13).standard_normal((C, 1)) * np.sqrt(np.diag(cov)) + mean
+    st = mcmc.init_state(prob, x0, np.zeros((C, 3)))
+    xs, _ = mcmc.run(prob, st, N)
+    acc = st.accepts.sum() / (C * N)
+    assert 0.05 < acc < 1.0
+    tr = xs[N // 5:]
+    e = stats.ess_per_coordinate(tr)
+    n_eff = tr.shape[0] * C * e
+    mcse = np.sqrt(np.diag(cov) / n_eff)
+    X = tr.reshape(-1, 1)
+    assert np.all(np.abs(X.mean(0) - mean) < 4.5 * mcse)
+    var_tol = 5.0 * np.sqrt(2.0 / n_eff) * np.diag(cov) + 5 * mcse * np.abs(X.mean(0) - mean)
+    assert np.all(np.abs(X.var(0) - np.diag(cov)) < var_tol)
+
+
+def test_pcn_planted_beta_squared_fails_the_prior_ar1():
+    """A pCN proposal that scales the noise by 1 - s^2 instead of its square root leaves
+    the prior: the stationary variance pin fails."""
+    prob = nonlinear_problem(dt=0.8)
+    prob.noise_var = np.full(prob.d_y, np.inf)
+    C, N = 8, 1500
+    rng = np.random.default_rng(23)
+    x = np.zeros((C, 4))
+    xs = np.empty((N, C, 4))
+    for t in range(N):
+        x = prob.s * x + (1.0 - prob.s ** 2) * rng.standard_normal((C, 4))
+        xs[t] = x
+    X = xs[300:]
+    n_eff = X.size * (1 - prob.s) / (1 + prob.s)
+    assert abs(X.var() - 1.0) > 5 * np.sqrt(2 / n_eff)

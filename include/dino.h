@@ -127,6 +127,16 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
 #define DINO_FACTOR_PRIMAL 0
 #define DINO_FACTOR_DUAL 1
 #define DINO_FACTOR_AUTO 2
+/* Transition kernel of a problem's chains.
+ * MMALA: the surrogate mMALA first stage (Alg. 1, the splitting proposition of Sec. 5.3).
+ * PCN: the pCN baseline (Sec. 2.6, eq. pCN_proposal; the pCN row of the baselines of
+ *   Sec. 6.1): x+ = s x + beta xi with xi the first r normals of the proposal stream and
+ *   s = (4 - dt)/(4 + dt), accepted with exp(Phi(x) - Phi(x+)); the complement moves as
+ *   for MMALA. A step evaluates the network forward only (no Jacobian, metric or factor);
+ *   the cache's g and factor then stay those of dino_chains_init. Not available to the
+ *   serving pools. */
+#define DINO_METHOD_MMALA 0
+#define DINO_METHOD_PCN 1
 typedef struct {
     int32_t n_chains;
     int32_t d_y;
@@ -137,6 +147,7 @@ typedef struct {
     double dt;
     uint64_t seed;
     uint64_t request_id;
+    int32_t method;           /* DINO_METHOD_MMALA (0) or DINO_METHOD_PCN */
 } dino_problem_desc;
 
 /* Device bytes a problem needs (state, caches, scratch, trace). */

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
+METHODS = {"mmala": 0, "pcn": 1}
 
 
 class DinoError(RuntimeError):
@@ -33,6 +34,7 @@ class ProblemDesc(ct.Structure):
         ("dt", ct.c_double),
         ("seed", ct.c_uint64),
         ("request_id", ct.c_uint64),
+        ("method", ct.c_int32),
     ]
 
 

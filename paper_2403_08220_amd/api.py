@@ -101,7 +101,7 @@ class Problem:
 
     def __init__(self, ctx: Context, n_chains: int, y, noise_var, dt: float, seed: int = 0, request_id: int = 0,
                  precision: str = "f64", track_complement: bool = True, trace_capacity: int = 0,
-                 torch_workspace: bool = True, factorization: str = "primal"):
+                 torch_workspace: bool = True, factorization: str = "primal", method: str = "mmala"):
         self.ctx = ctx
         self.lib = ctx.lib
         y = np.ascontiguousarray(y, dtype=np.float64)
@@ -109,7 +109,8 @@ class Problem:
         self.desc = ProblemDesc(n_chains=n_chains, d_y=len(y), precision=_lib.PRECISIONS[precision],
                                 track_complement=1 if track_complement else 0, trace_capacity=trace_capacity,
                                 factorization=_lib.FACTORIZATIONS[factorization], dt=dt, seed=seed,
-                                request_id=request_id)
+                                request_id=request_id, method=_lib.METHODS[method])
+        self.method = method
         self.h = None
         nbytes = ct.c_size_t()
         # the library validates the descriptor against the context's prior and network

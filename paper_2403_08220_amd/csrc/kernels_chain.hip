@@ -924,6 +924,102 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 }
 
 // ---------------------------------------------------------------------------------
+// pCN baseline (Sec. 2.6, eq. pCN_proposal; the pCN row of the baselines of Sec. 6.1).
+// In whitened coordinates the prior is N(0, I), so the proposal is x+ = s x + beta xi
+// (xi: the first r normals of the proposal stream, as the mMALA proposal draws them), and
+// prior reversibility makes the transition rate ratio exp(Phi(x) - Phi(x+)). No Jacobian,
+// metric or factor is formed: a step is this proposal, the network forward at x+ and the
+// decision kernel below. One wave per chain; a fresh chain (serving life cycle) draws its
+// initial state from the prior as the mMALA proposal kernel does.
+__global__ __launch_bounds__(64) void pcn_propose_kernel(int r, double s, double beta, ChainMeta meta,
+                                                         const double* __restrict__ x, double* __restrict__ xp) {
+    const int c = blockIdx.x, lane = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) return;
+    const bool fresh = state == CHAIN_FRESH;
+    const uint64_t k0 = meta.key0[c], k1 = meta.key1[c], chain = (uint64_t)meta.index[c];
+    const uint64_t stream = fresh ? STREAM_INIT_X : STREAM_XI, step = fresh ? 0 : (uint64_t)meta.step[c];
+    for (int b4 = lane; 4 * b4 < r; b4 += 64) {
+        double nv[4];
+        philox_normals4(k0, k1, (uint64_t)b4, stream, step, chain, nv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b4 + q;
+            if (j < r) xp[(long)c * r + j] = fresh ? nv[q] : s * x[(long)c * r + j] + beta * nv[q];
+        }
+    }
+}
+
+// Misfit at x+ (Sec. 5.1: 1/2 || Gamma^-1/2 (f - y) ||^2, from the network output f of
+// the forward stage, FP64 or FP32), the MH decision with exp(Phi(x) - Phi(x+)) (accept iff
+// log u <= log rho; a non-finite misfit rejects and is counted) and the end of the step.
+// accflag as for the mMALA accept kernel (the complement kernel reads it).
+template <typename TF>
+__global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMeta meta, const TF* __restrict__ f,
+                                                         const double* __restrict__ y_rows,
+                                                         const double* __restrict__ winv_rows, double* x,
+                                                         double* phi, const double* __restrict__ xp,
+                                                         int64_t* accepts, int64_t* failures, int32_t* accflag,
+                                                         StepRecord rec) {
+    __shared__ double red[TPB / 64];
+    __shared__ int decision;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) {
+        if (tid == 0) accflag[c] = 0;
+        record_idle(c, r, x, phi, rec);
+        return;
+    }
+    const int64_t step = meta.step[c];  // read by every thread before the finish advances it
+    const long row = chain_row(meta, c);
+    const double* y = y_rows + row * dy;
+    const double* winv = winv_rows + row * dy;
+    double part = 0.0;
+    for (int i = tid; i < dy; i += TPB) {
+        const double w = winv[i];
+        const double v = (w == 0.0) ? 0.0 : ((double)f[(long)c * dy + i] - y[i]) * w;
+        part += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+    if ((tid & 63) == 0) red[tid >> 6] = part;
+    __syncthreads();
+    double phin = 0.0;  // thread 0: the misfit after the decision
+    if (tid == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < TPB / 64; ++k) t += red[k];
+        const double php = 0.5 * t;
+        if (state == CHAIN_FRESH) {
+            // the initial state is taken as it is
+            if (!isfinite(php)) failures[c] += 1;
+            phin = php;
+            phi[c] = php;
+            decision = 1;
+            accflag[c] = 2;
+        } else {
+            const double lr = phi[c] - php;
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
+            const bool good = isfinite(lr);
+            const bool accept = good && (log(u) <= lr);
+            if (!good) failures[c] += 1;
+            phin = phi[c];
+            if (accept) {
+                accepts[c] += 1;
+                phin = php;
+                phi[c] = php;
+            }
+            decision = accept ? 1 : 0;
+            accflag[c] = decision;
+        }
+    }
+    __syncthreads();
+    const double* xn = (decision ? xp : x) + (long)c * r;
+    if (decision)
+        for (int j = tid; j < r; j += TPB) x[(long)c * r + j] = xp[(long)c * r + j];
+    finish_chain(c, r, meta, state, step, xn, phin, rec);
+}
+
+// ---------------------------------------------------------------------------------
 // Observation-space (dual) form for d_y < r. With B = Gamma^-1/2 J (d_y x r) and the
 // Cholesky factor K of M = I + B B^T (d_y x d_y), (I + H)^-1 v = v - B^T M^-1 B v
 // (Woodbury), log det (I + H) = log det M, and the proposal noise is drawn as
@@ -1569,6 +1665,23 @@ void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
     hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s, p->beta,
                        p->meta, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip,
                        p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p, trace_row));
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_pcn_propose(dino_problem* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(pcn_propose_kernel, dim3(n), dim3(64), 0, st, p->r, p->s, p->beta, p->meta, p->x, p->xp);
+    DINO_HIP(hipGetLastError());
+}
+
+// The forward stage leaves the network output in p->f (FP64 path) or p->f32 (BF16 path).
+void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+    const StepRecord rec = step_record(p, trace_row);
+    if (p->desc.precision == DINO_PREC_F64)
+        hipLaunchKernelGGL(pcn_accept_kernel<double>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f, p->y,
+                           p->winv, p->x, p->phi, p->xp, p->accepts, p->failures, p->acc, rec);
+    else
+        hipLaunchKernelGGL(pcn_accept_kernel<float>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f32, p->y,
+                           p->winv, p->x, p->phi, p->xp, p->accepts, p->failures, p->acc, rec);
     DINO_HIP(hipGetLastError());
 }
 

@@ -29,7 +29,7 @@ def make_case(name="tiny", chains=None, bias_scale=0.0, noise_scale=None, dt=Non
 
 
 def device_problem(case, precision="f64", trace_capacity=0, track_complement=True, chains=None,
-                   factorization="primal"):
+                   factorization="primal", method="mmala"):
     """Context + problem on cuda:0 holding the case's prior, network and data."""
     from paper_2403_08220_amd import Context, Problem
 
@@ -40,7 +40,7 @@ def device_problem(case, precision="f64", trace_capacity=0, track_complement=Tru
     prob = case["prob"]
     p = Problem(ctx, case["C"] if chains is None else chains, prob.y, prob.noise_var, prob.dt, seed=prob.seed,
                 request_id=prob.request_id, precision=precision, track_complement=track_complement,
-                trace_capacity=trace_capacity, factorization=factorization)
+                trace_capacity=trace_capacity, factorization=factorization, method=method)
     return ctx, p
 
 

@@ -209,14 +209,15 @@ def copy_calibration(nbytes=1 << 29):
     return nbytes
 
 
-def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, factorization="auto"):
+def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, factorization="auto", method="mmala",
+             dt=None):
     import torch
     from paper_2403_08220_amd import Problem
 
     C = w.chains
     cap = warmup + steps
-    p = Problem(ctx, C, y, nv, w.dt, seed=w.chain_seed, precision=precision, track_complement=True,
-                trace_capacity=cap, factorization=factorization)
+    p = Problem(ctx, C, y, nv, w.dt if dt is None else dt, seed=w.chain_seed, precision=precision,
+                track_complement=True, trace_capacity=cap, factorization=factorization, method=method)
     p.init(x0, z0)
     stream = torch.cuda.current_stream()
     p.step(warmup)
@@ -255,6 +256,43 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, fact
     out["median_ess_frac"] = float(np.nanmedian(e))
     p.close()
     return out
+
+
+PCN_DT_CANDIDATES = [1e-6, 3e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2]
+ESS_FLOOR_MARGIN = 1.5
+
+
+def ess_floor(n_chains):
+    """Multichain ESS of chains that do not decorrelate within the window (rho_t = 1 at
+    every lag): n_chains * n / (2 n - 1), about n_chains / 2."""
+    return n_chains / 2.0
+
+
+def pcn_leg(w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala):
+    """The pCN baseline on the same workload, chains and starting states: its step size
+    chosen by the same tuning rule over PCN_DT_CANDIDATES, then timed like the main leg.
+    The ratio of the two ESS rates is the effective sampling speedup (Sec. 6.3.1) of
+    mMALA over pCN on the surrogate posterior, at equal hardware. It is reported only when
+    both median ESS values clear the multichain estimator's floor: chains that stay
+    correlated over the whole window give rho_t near 1 at every lag and an ESS of about
+    n_chains / 2 whatever the method, which measures the spread of the starting states,
+    not mixing."""
+    from paper_2403_08220_amd.tune import tune_step_size
+
+    tr = tune_step_size(ctx, y, nv, x0, z0, PCN_DT_CANDIDATES, burn=20, steps=100, seed=w.chain_seed,
+                        precision=precision, method="pcn")
+    r = run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=False, method="pcn", dt=tr.dt)
+    C = w.chains
+    rate = r["median_ess"] / r["wall_s"]
+    mm_rate = mmala["median_ess"] / mmala["wall_s"]
+    above = min(r["median_ess"], mmala["median_ess"]) > ESS_FLOOR_MARGIN * ess_floor(C)
+    return dict(value=round(C * steps / r["wall_s"], 1), unit="chain-steps/s", steps=steps,
+                ms_per_step=round(1e3 * r["wall_s"] / steps, 4), dt=tr.dt, accept_rate=round(r["accept_rate"], 4),
+                step_cost_mmala_over_pcn=round(mmala["wall_s"] / r["wall_s"], 2),
+                median_ess=round(r["median_ess"], 1), median_ess_frac=r["median_ess_frac"], ess_per_s=round(rate, 3),
+                ess_speedup_mmala=round(mm_rate / rate, 2) if above and rate > 0 else None,
+                tuning=[dict(dt=t["dt"], AR=round(t["AR"], 4), ess_frac=t["ess_frac"], kept=t["kept"])
+                        for t in tr.table])
 
 
 def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=20, seed=11):
@@ -425,16 +463,17 @@ def main():
     ap.add_argument("--factorization", default="auto", choices=["auto", "primal", "dual"],
                     help="auto: the observation-space (d_y x d_y) factorisation when d_y < r")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pcn-steps", type=int, default=400, help="steps of the pCN baseline leg (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
-        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --serve-requests 0 --no-cpu-baseline"
+        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --pcn-steps 0 --serve-requests 0 --no-cpu-baseline"
         summarize_profiles(*args.summarize_profiles, command={
             "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py "
-                     "--steps 100 --fp64-steps 0 --serve-requests 0 --no-cpu-baseline",
+                     "--steps 100 --fp64-steps 0 --pcn-steps 0 --serve-requests 0 --no-cpu-baseline",
             "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {b}",
             "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {b}"})
         return
@@ -479,6 +518,11 @@ def main():
                     accept_rate=round(r64["accept_rate"], 4),
                     ess_per_s=round(r64["median_ess"] / r64["wall_s"], 3))
         log(f"bench: f64 path: {r64['wall_s']:.3f} s, accept {r64['accept_rate']:.3f}")
+
+    pcn = None
+    if args.pcn_steps > 0:
+        pcn = pcn_leg(w, ctx, y, nv, x0, z0, args.precision, args.pcn_steps, args.warmup, res)
+        log(f"bench: pcn baseline: dt {pcn['dt']}, accept {pcn['accept_rate']}, ESS/s {pcn['ess_per_s']}")
 
     prof = res.get("profile", {})
     # the observation-space form is taken when asked for, or by "auto" when d_y < r
@@ -529,11 +573,14 @@ def main():
                    "grid": w.n, "r": w.r, "width": w.width, "depth": w.depth, "d_y": w.d_y, "chains": C,
                    "dt": w.dt, "precision": args.precision, "factorization": args.factorization},
         "ess_per_s": round(res["median_ess"] / res["wall_s"], 3),
+        "median_ess": round(res["median_ess"], 1),
+        "ess_floor": ess_floor(C),
         "median_ess_frac": res["median_ess_frac"],
         "accept_rate": round(res["accept_rate"], 4),
         "roofline": roof,
         "stages": stages,
         "fp64_plain": fp64,
+        "pcn": pcn,
         "serving": serving,
         "cpu_baseline": cpu,
         "init": init_info,

@@ -50,8 +50,9 @@ class TuneResult:
 
 
 def tune_step_size(ctx, y, noise_var, x0, z0, candidates, burn: int, steps: int, seed: int = 0,
-                   precision: str = "f64", stream=None) -> TuneResult:
-    """Run every candidate dt on the device from (x0, z0) and apply the selection rule."""
+                   precision: str = "f64", stream=None, method: str = "mmala") -> TuneResult:
+    """Run every candidate dt on the device from (x0, z0) and apply the selection rule
+    (method: the transition kernel, "mmala" or the "pcn" baseline)."""
     import torch
 
     from .api import Problem
@@ -60,7 +61,7 @@ def tune_step_size(ctx, y, noise_var, x0, z0, candidates, burn: int, steps: int,
     rows = []
     for dt in candidates:
         p = Problem(ctx, C, y, noise_var, float(dt), seed=seed, precision=precision,
-                    track_complement=z0 is not None, trace_capacity=burn + steps)
+                    track_complement=z0 is not None, trace_capacity=burn + steps, method=method)
         try:
             p.init(x0, z0, stream=stream)
             p.step(burn, stream=stream)

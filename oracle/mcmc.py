@@ -30,6 +30,9 @@ Readings of the paper taken here (listed with reasons in the design notes):
 * The pCN baseline (method "pcn") uses the same s = (4 - dt)/(4 + dt): it is the
   mMALA proposal with H = 0 and g = 0, x+ = s x + beta xi (xi: the first r normals of
   the proposal stream), accepted with exp(Phi(x) - Phi(x+)).
+* The MALA baseline (method "mala") is the mMALA transition with the metric removed
+  (H = 0, so d = 0, P = L = I and B = 0 in the noise mapping) and the ppg kept: x+ =
+  s x - (1 - s) g + beta xi, and rho_0 keeps its ppg terms only.
 """
 from __future__ import annotations
 
@@ -52,7 +55,7 @@ class Problem:
     seed: int = 0
     request_id: int = 0
     factor: str = "primal"   # proposal noise mapping: "primal" (L^-T xi) or "dual"
-    method: str = "mmala"    # "mmala", or "pcn": the baseline without geometry (Sec. 6, table of baselines)
+    method: str = "mmala"    # "mmala"; baselines of Sec. 6.1: "pcn" (no metric, no ppg), "mala" (ppg only)
 
     @property
     def d_y(self) -> int:
@@ -124,6 +127,23 @@ def misfit(prob: Problem, x: np.ndarray):
     w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
     res = (prob.y[None, :] - f) * w[None, :]
     return f, 0.5 * np.sum(res * res, axis=1)
+
+
+def without_metric(c: Cache) -> Cache:
+    """The cache with the Gauss-Newton metric removed (H = 0: d = 0, P = L = I, B = 0)
+    and the misfit and ppg kept: the geometry the MALA baseline proposes with (the MALA
+    row of the baselines of Sec. 6.1: gradient, no Hessian)."""
+    C, r = c.g.shape
+    eye = np.broadcast_to(np.eye(r), (C, r, r)).copy()
+    return Cache(f=c.f, phi=c.phi, g=c.g, H=np.zeros((C, r, r)), d=np.zeros((C, r)), P=eye, L=eye.copy(),
+                 ok=np.isfinite(c.phi) & np.all(np.isfinite(c.g), axis=1),
+                 B=None if c.B is None else np.zeros_like(c.B))
+
+
+def method_geometry(prob: Problem, x: np.ndarray) -> Cache:
+    """The geometry a transition of prob.method proposes and accepts with."""
+    c = geometry(prob, x)
+    return without_metric(c) if prob.method == "mala" else c
 
 
 def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:
@@ -198,7 +218,7 @@ class ChainState:
 def init_state(prob: Problem, x0: np.ndarray, z0: np.ndarray | None = None, chains=None) -> ChainState:
     x0 = np.array(x0, dtype=np.float64)
     return ChainState(x=x0, z=None if z0 is None else np.array(z0, dtype=np.float64),
-                      cache=geometry(prob, x0), chains=None if chains is None else np.asarray(chains))
+                      cache=method_geometry(prob, x0), chains=None if chains is None else np.asarray(chains))
 
 
 def _select(cache_a: Cache, cache_b: Cache, mask: np.ndarray) -> Cache:
@@ -232,7 +252,7 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
         u = philox.uniforms(prob.seed, prob.request_id, st.step, st.chains)
     # Alg. 1: reduced proposal sampling, surrogate evaluation at x+, first-stage ratio
     xp = propose(prob, st.x, st.cache, xi)
-    cp = geometry(prob, xp)
+    cp = method_geometry(prob, xp)
     lr = log_rho1(prob, st.x, st.cache, xp, cp)
     lr = np.where(cp.ok & np.isfinite(lr), lr, -np.inf)
     log_u = np.log(u)

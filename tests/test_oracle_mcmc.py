@@ -370,3 +370,87 @@ def test_pcn_planted_beta_squared_fails_the_prior_ar1():
     X = xs[300:]
     n_eff = X.size * (1 - prob.s) / (1 + prob.s)
     assert abs(X.var() - 1.0) > 5 * np.sqrt(2 / n_eff)
+
+
+# ---- MALA baseline (gradient, no metric: the MALA row of the baselines of Sec. 6.1) ----
+
+def mala_textbook_log_ratio(prob, a, b):
+    """log pi(b) q(b -> a) - log pi(a) q(a -> b) with the Langevin law
+    q(u -> .) = N(s u - (1 - s) g(u), (1 - s^2) I), g the ppg of the geometry."""
+    r = a.shape[0]
+    cov = (1.0 - prob.s ** 2) * np.eye(r)
+
+    def parts(u):
+        c = mcmc.geometry(prob, u[None])
+        return c.phi[0], prob.s * u - (1.0 - prob.s) * c.g[0]
+
+    phi_a, mean_a = parts(a)
+    phi_b, mean_b = parts(b)
+    return (-phi_b - 0.5 * b @ b + multivariate_normal.logpdf(a, mean_b, cov)
+            + phi_a + 0.5 * a @ a - multivariate_normal.logpdf(b, mean_a, cov))
+
+
+@pytest.mark.parametrize("arch", ["mlp", "resnet"])
+def test_mala_log_rho_is_the_textbook_mh_ratio(arch):
+    prob = nonlinear_problem(dt=0.3, arch=arch)
+    prob.method = "mala"
+    rng = np.random.default_rng(31)
+    x = rng.standard_normal((5, 4))
+    st = mcmc.init_state(prob, x)
+    xi = rng.standard_normal((5, 4))
+    rec = mcmc.transition(prob, st, xi=xi, u=np.full(5, 0.5))
+    g = mcmc.geometry(prob, x).g
+    np.testing.assert_allclose(rec.xp, prob.s * x - (1 - prob.s) * g + prob.beta * xi, rtol=1e-13, atol=1e-13)
+    for c in range(5):
+        ref = mala_textbook_log_ratio(prob, x[c], rec.xp[c])
+        assert abs(rec.log_rho[c] - ref) < 1e-9 * max(1.0, abs(ref))
+
+
+def test_mala_without_likelihood_is_pcn():
+    prob = nonlinear_problem(dt=0.5)
+    prob.noise_var = np.full(prob.d_y, np.inf)
+    rng = np.random.default_rng(32)
+    x = rng.standard_normal((4, 4))
+    xi = rng.standard_normal((4, 4))
+    out = {}
+    for method in ("mala", "pcn"):
+        prob.method = method
+        st = mcmc.init_state(prob, x.copy())
+        out[method] = mcmc.transition(prob, st, xi=xi, u=np.full(4, 0.999))
+    np.testing.assert_allclose(out["mala"].xp, out["pcn"].xp, rtol=1e-15, atol=1e-15)
+    assert np.max(np.abs(out["mala"].log_rho)) < 1e-13 and np.all(out["mala"].accept)
+
+
+def test_mala_chain_matches_quadrature():
+    prob = nonlinear_problem(r=1, d_out=2, dt=0.05, noise=0.5, seed=5)   # acceptance about 0.5
+    prob.method = "mala"
+    mean, cov = quadrature_moments(prob, 1)
+    C, N = 24, 2500
+    x0 = np.random.default_rng(14).standard_normal((C, 1)) * np.sqrt(np.diag(cov)) + mean
+    st = mcmc.init_state(prob, x0)
+    xs, _ = mcmc.run(prob, st, N)
+    acc = st.accepts.sum() / (C * N)
+    assert 0.05 < acc < 1.0
+    tr = xs[N // 5:]
+    e = stats.ess_per_coordinate(tr)
+    n_eff = tr.shape[0] * C * e
+    mcse = np.sqrt(np.diag(cov) / n_eff)
+    X = tr.reshape(-1, 1)
+    assert np.all(np.abs(X.mean(0) - mean) < 4.5 * mcse)
+    var_tol = 5.0 * np.sqrt(2.0 / n_eff) * np.diag(cov) + 5 * mcse * np.abs(X.mean(0) - mean)
+    assert np.all(np.abs(X.var(0) - np.diag(cov)) < var_tol)
+
+
+def test_mala_planted_dropped_gradient_norm_fails_textbook():
+    """Dropping the -(dt/8)||g||^2 terms of rho_0 breaks the MH ratio pin."""
+    prob = nonlinear_problem(dt=0.3)
+    prob.method = "mala"
+    rng = np.random.default_rng(33)
+    x = rng.standard_normal((3, 4))
+    st = mcmc.init_state(prob, x)
+    rec = mcmc.transition(prob, st, xi=rng.standard_normal((3, 4)), u=np.full(3, 0.5))
+    gx = mcmc.geometry(prob, x).g
+    gp = mcmc.geometry(prob, rec.xp).g
+    planted = rec.log_rho + (prob.dt / 8.0) * (np.sum(gp * gp, axis=1) - np.sum(gx * gx, axis=1))
+    ref = np.array([mala_textbook_log_ratio(prob, x[c], rec.xp[c]) for c in range(3)])
+    assert np.max(np.abs(planted - ref)) > 1e-3

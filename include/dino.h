@@ -133,10 +133,16 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  *   Sec. 6.1): x+ = s x + beta xi with xi the first r normals of the proposal stream and
  *   s = (4 - dt)/(4 + dt), accepted with exp(Phi(x) - Phi(x+)); the complement moves as
  *   for MMALA. A step evaluates the network forward only (no Jacobian, metric or factor);
- *   the cache's g and factor then stay those of dino_chains_init. Not available to the
- *   serving pools. */
+ *   the cache's g and factor then stay those of dino_chains_init.
+ * MALA: the MALA baseline (the MALA row of the baselines of Sec. 6.1): the MMALA
+ *   transition with the metric removed (H = 0) and the ppg kept, x+ = s x - (1 - s) g +
+ *   beta xi, log rho_0(m1, m2) = -(dt/8)||g(m1)||^2 - (sqrt(dt)/2) mhat . g(m1). A step
+ *   forms the misfit and ppg at x+ (forward and Jacobian); the cache's factor stays that
+ *   of dino_chains_init.
+ * PCN and MALA are not available to the serving pools. */
 #define DINO_METHOD_MMALA 0
 #define DINO_METHOD_PCN 1
+#define DINO_METHOD_MALA 2
 typedef struct {
     int32_t n_chains;
     int32_t d_y;
@@ -147,7 +153,7 @@ typedef struct {
     double dt;
     uint64_t seed;
     uint64_t request_id;
-    int32_t method;           /* DINO_METHOD_MMALA (0) or DINO_METHOD_PCN */
+    int32_t method;           /* DINO_METHOD_MMALA (0), DINO_METHOD_PCN or DINO_METHOD_MALA */
 } dino_problem_desc;
 
 /* Device bytes a problem needs (state, caches, scratch, trace). */

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
-METHODS = {"mmala": 0, "pcn": 1}
+METHODS = {"mmala": 0, "pcn": 1, "mala": 2}
 
 
 class DinoError(RuntimeError):

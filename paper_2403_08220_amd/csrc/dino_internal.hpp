@@ -317,6 +317,8 @@ void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
 void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 void launch_pcn_propose(dino_problem* p, int n, hipStream_t st);
 void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_mala_propose(dino_problem* p, int n, hipStream_t st);
+void launch_mala_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 // Whether the BF16 reverse sweep covers the network: it holds at most 16 row blocks of 32
 // (the reduced dimension and every hidden width at most 512).
 bool sweep_width_ok(const dino_ctx* ctx);

@@ -1020,6 +1020,123 @@ __global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMet
 }
 
 // ---------------------------------------------------------------------------------
+// MALA baseline (the MALA row of the baselines of Sec. 6.1: the ppg, no metric). It is the
+// mMALA transition with H = 0: x+ = s x - (1 - s) g + beta xi, and the RN derivative with
+// respect to pCN keeps its ppg terms only,
+//   log rho_0(m1, m2) = -(dt/8) ||g(m1)||^2 - (sqrt(dt)/2) mhat . g(m1),
+//   mhat = (m2 - s m1) / beta.
+// The geometry stages still form the misfit and ppg at x+ (Jacobian sweep included); no
+// factor is formed or used.
+// One wave per chain: the proposal and the forward term log rho_0(x -> x+) (into lfwd).
+__global__ __launch_bounds__(64) void mala_propose_kernel(int r, double dt, double s, double beta, ChainMeta meta,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ g, double* __restrict__ xp,
+                                                          double* __restrict__ lfwd) {
+    const int c = blockIdx.x, lane = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) return;
+    const bool fresh = state == CHAIN_FRESH;
+    const uint64_t k0 = meta.key0[c], k1 = meta.key1[c], chain = (uint64_t)meta.index[c];
+    const uint64_t stream = fresh ? STREAM_INIT_X : STREAM_XI, step = fresh ? 0 : (uint64_t)meta.step[c];
+    double gg = 0.0, mg = 0.0;
+    for (int b4 = lane; 4 * b4 < r; b4 += 64) {
+        double nv[4];
+        philox_normals4(k0, k1, (uint64_t)b4, stream, step, chain, nv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int j = 4 * b4 + q;
+            if (j >= r) continue;
+            if (fresh) {
+                xp[(long)c * r + j] = nv[q];
+                continue;
+            }
+            const double xj = x[(long)c * r + j], gj = g[(long)c * r + j];
+            const double pj = s * xj - (1.0 - s) * gj + beta * nv[q];
+            xp[(long)c * r + j] = pj;
+            gg += gj * gj;
+            mg += ((pj - s * xj) / beta) * gj;
+        }
+    }
+    gg = wave_sum(gg);
+    mg = wave_sum(mg);
+    if (lane == 0) lfwd[c] = fresh ? 0.0 : -(dt / 8.0) * gg - (sqrt(dt) / 2.0) * mg;
+}
+
+// The reverse term log rho_0(x+ -> x) with the ppg at x+, the MH decision (a non-finite
+// misfit or ppg rejects and is counted) and the end of the step; x, g and phi follow the
+// decision. accflag as for the mMALA accept kernel.
+__global__ __launch_bounds__(TPB) void mala_accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
+                                                          double* x, double* g, double* phi,
+                                                          const double* __restrict__ xp,
+                                                          const double* __restrict__ gp,
+                                                          const double* __restrict__ phip,
+                                                          const double* __restrict__ lfwd, int64_t* accepts,
+                                                          int64_t* failures, int32_t* accflag, StepRecord rec) {
+    __shared__ double red[2][TPB / 64];
+    __shared__ int decision;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) {
+        if (tid == 0) accflag[c] = 0;
+        record_idle(c, r, x, phi, rec);
+        return;
+    }
+    const int64_t step = meta.step[c];  // read by every thread before the finish advances it
+    double gg = 0.0, mg = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        const double gj = gp[(long)c * r + j], pj = xp[(long)c * r + j];
+        gg += gj * gj;
+        mg += ((x[(long)c * r + j] - s * pj) / beta) * gj;
+    }
+    gg = wave_sum(gg);
+    mg = wave_sum(mg);
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = gg;
+        red[1][tid >> 6] = mg;
+    }
+    __syncthreads();
+    double phin = 0.0;  // thread 0: the misfit after the decision
+    if (tid == 0) {
+        double sg = 0.0, sm = 0.0;
+#pragma unroll
+        for (int k = 0; k < TPB / 64; ++k) {
+            sg += red[0][k];
+            sm += red[1][k];
+        }
+        const double php = phip[c];
+        if (state == CHAIN_FRESH) {
+            if (!isfinite(php) || !isfinite(sg)) failures[c] += 1;
+            phin = php;
+            phi[c] = php;
+            decision = 1;
+            accflag[c] = 2;
+        } else {
+            const double rev = -(dt / 8.0) * sg - (sqrt(dt) / 2.0) * sm;
+            const double lr = phi[c] - php + rev - lfwd[c];
+            const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
+            const bool good = isfinite(lr);
+            const bool accept = good && (log(u) <= lr);
+            if (!good) failures[c] += 1;
+            phin = phi[c];
+            if (accept) {
+                accepts[c] += 1;
+                phin = php;
+                phi[c] = php;
+            }
+            decision = accept ? 1 : 0;
+            accflag[c] = decision;
+        }
+    }
+    __syncthreads();
+    if (decision)
+        for (int j = tid; j < r; j += TPB) {
+            x[(long)c * r + j] = xp[(long)c * r + j];
+            g[(long)c * r + j] = gp[(long)c * r + j];
+        }
+    finish_chain(c, r, meta, state, step, (decision ? xp : x) + (long)c * r, phin, rec);
+}
+
+// ---------------------------------------------------------------------------------
 // Observation-space (dual) form for d_y < r. With B = Gamma^-1/2 J (d_y x r) and the
 // Cholesky factor K of M = I + B B^T (d_y x d_y), (I + H)^-1 v = v - B^T M^-1 B v
 // (Woodbury), log det (I + H) = log det M, and the proposal noise is drawn as
@@ -1682,6 +1799,19 @@ void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st
     else
         hipLaunchKernelGGL(pcn_accept_kernel<float>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f32, p->y,
                            p->winv, p->x, p->phi, p->xp, p->accepts, p->failures, p->acc, rec);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_mala_propose(dino_problem* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(mala_propose_kernel, dim3(n), dim3(64), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
+                       p->g, p->xp, p->lfwd);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_mala_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+    hipLaunchKernelGGL(mala_accept_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
+                       p->g, p->phi, p->xp, p->gp, p->phip, p->lfwd, p->accepts, p->failures, p->acc,
+                       step_record(p, trace_row));
     DINO_HIP(hipGetLastError());
 }
 

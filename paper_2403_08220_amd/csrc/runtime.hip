@@ -155,7 +155,8 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
     DINO_REQUIRE(d->factorization >= DINO_FACTOR_PRIMAL && d->factorization <= DINO_FACTOR_AUTO, DINO_EINVAL,
                  "unknown factorization");
-    DINO_REQUIRE(d->method == DINO_METHOD_MMALA || d->method == DINO_METHOD_PCN, DINO_EINVAL, "unknown method");
+    DINO_REQUIRE(d->method == DINO_METHOD_MMALA || d->method == DINO_METHOD_PCN || d->method == DINO_METHOD_MALA,
+                 DINO_EINVAL, "unknown method");
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
                       (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
@@ -663,7 +664,10 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const bool f64 = p->desc.precision == DINO_PREC_F64;
     const bool pcn = p->desc.method == DINO_METHOD_PCN;
     const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, p->z ? 1 : 0, 0};
+    const bool mala = p->desc.method == DINO_METHOD_MALA;
     const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, p->z ? 1 : 0, 0};
+    // MALA: on the mixed path the ppg comes from the metric kernel (its metric is unused)
+    const int32_t launches_mala[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, f64 ? 0 : 1, 0, 1, p->z ? 1 : 0, 0};
     auto mark = [&](int i) {
         if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
     };
@@ -684,6 +688,33 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             mark(9);
             if (p->profile) {
                 for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches_pcn[i];
+                if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
+            }
+            p->step += 1;
+            continue;
+        }
+        if (mala) {
+            // MALA baseline: proposal with the ppg, geometry without the factor, decision
+            launch_mala_propose(p, n, st);
+            mark(1);
+            stage_forward(p, n, p->xp, p->f, st);
+            mark(2);
+            stage_jacobian(p, n, st);
+            mark(3);
+            stage_misfit(p, n, p->f, p->phip, p->gp, st);
+            mark(4);
+            if (!f64) stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
+            mark(5);
+            mark(6);
+            int64_t row = -1;
+            if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
+            launch_mala_accept(p, n, row, st);
+            mark(7);
+            launch_complement(p, n, st);
+            mark(8);
+            mark(9);
+            if (p->profile) {
+                for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches_mala[i];
                 if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
             }
             p->step += 1;

@@ -258,7 +258,9 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, fact
     return out
 
 
-PCN_DT_CANDIDATES = [1e-6, 3e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2]
+# step sizes the tuning rule chooses from, per baseline
+BASELINE_DT_CANDIDATES = {"pcn": [1e-6, 3e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2],
+                          "mala": [1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3]}
 ESS_FLOOR_MARGIN = 1.5
 
 
@@ -268,27 +270,28 @@ def ess_floor(n_chains):
     return n_chains / 2.0
 
 
-def pcn_leg(w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala):
-    """The pCN baseline on the same workload, chains and starting states: its step size
-    chosen by the same tuning rule over PCN_DT_CANDIDATES, then timed like the main leg.
-    The ratio of the two ESS rates is the effective sampling speedup (Sec. 6.3.1) of
-    mMALA over pCN on the surrogate posterior, at equal hardware. It is reported only when
+def baseline_leg(method, w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala):
+    """A baseline of Sec. 6.1 (pCN or MALA) on the same workload, chains and starting
+    states: its step size chosen by the same tuning rule over BASELINE_DT_CANDIDATES,
+    then timed like the main leg. The ratio of the two ESS rates is the effective
+    sampling speedup (Sec. 6.3.1) of mMALA over the baseline on the surrogate posterior,
+    at equal hardware. It is reported only when
     both median ESS values clear the multichain estimator's floor: chains that stay
     correlated over the whole window give rho_t near 1 at every lag and an ESS of about
     n_chains / 2 whatever the method, which measures the spread of the starting states,
     not mixing."""
     from paper_2403_08220_amd.tune import tune_step_size
 
-    tr = tune_step_size(ctx, y, nv, x0, z0, PCN_DT_CANDIDATES, burn=20, steps=100, seed=w.chain_seed,
-                        precision=precision, method="pcn")
-    r = run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=False, method="pcn", dt=tr.dt)
+    tr = tune_step_size(ctx, y, nv, x0, z0, BASELINE_DT_CANDIDATES[method], burn=20, steps=100,
+                        seed=w.chain_seed, precision=precision, method=method)
+    r = run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=False, method=method, dt=tr.dt)
     C = w.chains
     rate = r["median_ess"] / r["wall_s"]
     mm_rate = mmala["median_ess"] / mmala["wall_s"]
     above = min(r["median_ess"], mmala["median_ess"]) > ESS_FLOOR_MARGIN * ess_floor(C)
     return dict(value=round(C * steps / r["wall_s"], 1), unit="chain-steps/s", steps=steps,
                 ms_per_step=round(1e3 * r["wall_s"] / steps, 4), dt=tr.dt, accept_rate=round(r["accept_rate"], 4),
-                step_cost_mmala_over_pcn=round(mmala["wall_s"] / r["wall_s"], 2),
+                step_cost_mmala_over_this=round(mmala["wall_s"] / r["wall_s"], 2),
                 median_ess=round(r["median_ess"], 1), median_ess_frac=r["median_ess_frac"], ess_per_s=round(rate, 3),
                 ess_speedup_mmala=round(mm_rate / rate, 2) if above and rate > 0 else None,
                 tuning=[dict(dt=t["dt"], AR=round(t["AR"], 4), ess_frac=t["ess_frac"], kept=t["kept"])
@@ -463,17 +466,18 @@ def main():
     ap.add_argument("--factorization", default="auto", choices=["auto", "primal", "dual"],
                     help="auto: the observation-space (d_y x d_y) factorisation when d_y < r")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--pcn-steps", type=int, default=400, help="steps of the pCN baseline leg (0: skip)")
+    ap.add_argument("--baseline-steps", type=int, default=400,
+                    help="steps of each baseline leg, pCN and MALA (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
-        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --pcn-steps 0 --serve-requests 0 --no-cpu-baseline"
+        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --baseline-steps 0 --serve-requests 0 --no-cpu-baseline"
         summarize_profiles(*args.summarize_profiles, command={
             "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py "
-                     "--steps 100 --fp64-steps 0 --pcn-steps 0 --serve-requests 0 --no-cpu-baseline",
+                     "--steps 100 --fp64-steps 0 --baseline-steps 0 --serve-requests 0 --no-cpu-baseline",
             "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {b}",
             "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {b}"})
         return
@@ -519,10 +523,13 @@ def main():
                     ess_per_s=round(r64["median_ess"] / r64["wall_s"], 3))
         log(f"bench: f64 path: {r64['wall_s']:.3f} s, accept {r64['accept_rate']:.3f}")
 
-    pcn = None
-    if args.pcn_steps > 0:
-        pcn = pcn_leg(w, ctx, y, nv, x0, z0, args.precision, args.pcn_steps, args.warmup, res)
-        log(f"bench: pcn baseline: dt {pcn['dt']}, accept {pcn['accept_rate']}, ESS/s {pcn['ess_per_s']}")
+    baselines = None
+    if args.baseline_steps > 0:
+        baselines = {}
+        for method in ("pcn", "mala"):
+            b = baseline_leg(method, w, ctx, y, nv, x0, z0, args.precision, args.baseline_steps, args.warmup, res)
+            baselines[method] = b
+            log(f"bench: {method} baseline: dt {b['dt']}, accept {b['accept_rate']}, {b['value']} chain-steps/s")
 
     prof = res.get("profile", {})
     # the observation-space form is taken when asked for, or by "auto" when d_y < r
@@ -580,7 +587,7 @@ def main():
         "roofline": roof,
         "stages": stages,
         "fp64_plain": fp64,
-        "pcn": pcn,
+        "baselines": baselines,
         "serving": serving,
         "cpu_baseline": cpu,
         "init": init_info,

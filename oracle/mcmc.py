@@ -30,6 +30,14 @@ Readings of the paper taken here (listed with reasons in the design notes):
 * The pCN baseline (method "pcn") uses the same s = (4 - dt)/(4 + dt): it is the
   mMALA proposal with H = 0 and g = 0, x+ = s x + beta xi (xi: the first r normals of
   the proposal stream), accepted with exp(Phi(x) - Phi(x+)).
+* The LA-pCN baseline (method "lapcn", eq. MAP): the printed proposal mean m_MAP - s m
+  is read as m_MAP + s (m - m_MAP), the pCN move about the MAP with the Laplace
+  covariance, which is reversible with respect to the Laplace approximation
+  N(m_MAP, C_post(m_MAP)); the printed mean is not. In whitened reduced coordinates:
+  x+ = x_map + s (x - x_map) + beta L^-T xi with L L^T = I + H(x_map), and
+  log rho = Phi(x) - Phi(x+) + (|x|^2 - |x+|^2)/2 + (|L^T(x+ - x_map)|^2 - |L^T(x - x_map)|^2)/2
+  (target over Laplace density). The complement keeps its pCN move (the Laplace
+  approximation equals the prior there).
 * The MALA baseline (method "mala") is the mMALA transition with the metric removed
   (H = 0, so d = 0, P = L = I and B = 0 in the noise mapping) and the ppg kept: x+ =
   s x - (1 - s) g + beta xi, and rho_0 keeps its ppg terms only.
@@ -55,7 +63,9 @@ class Problem:
     seed: int = 0
     request_id: int = 0
     factor: str = "primal"   # proposal noise mapping: "primal" (L^-T xi) or "dual"
-    method: str = "mmala"    # "mmala"; baselines of Sec. 6.1: "pcn" (no metric, no ppg), "mala" (ppg only)
+    method: str = "mmala"    # "mmala"; baselines of Sec. 6.1: "pcn" (no metric, no ppg), "mala" (ppg only),
+                             # "lapcn" (metric fixed at the MAP, no ppg)
+    fixed: tuple = None      # "lapcn": (x_map (r,), lower Cholesky factor of I + H(x_map) (r, r))
 
     @property
     def d_y(self) -> int:
@@ -244,6 +254,8 @@ def transition(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> Ste
     current step; pass them to evaluate the transition at given draws."""
     if prob.method == "pcn":
         return transition_pcn(prob, st, xi, u, zeta)
+    if prob.method == "lapcn":
+        return transition_lapcn(prob, st, xi, u, zeta)
     C, r = st.x.shape
     if xi is None:
         count = r + prob.d_y if prob.factor == "dual" else r
@@ -299,6 +311,40 @@ def transition_pcn(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) ->
     xp = prob.s * st.x + prob.beta * xi[:, :r]
     fp, phip = misfit(prob, xp)
     lr = st.cache.phi - phip
+    good = np.isfinite(lr)
+    lr = np.where(good, lr, -np.inf)
+    log_u = np.log(u)
+    acc = log_u <= lr
+    st.failures += (~good).astype(np.int64)
+    _move_complement(prob, st, acc, zeta)
+    st.x = np.where(acc[:, None], xp, st.x)
+    st.cache.phi = np.where(acc, phip, st.cache.phi)
+    st.cache.f = np.where(acc[:, None], fp, st.cache.f)
+    st.accepts += acc.astype(np.int64)
+    st.step += 1
+    cp = Cache(f=fp, phi=phip, g=None, H=None, d=None, P=None, L=None, ok=good)
+    return StepRecord(xp=xp, cache_p=cp, log_rho=lr, log_u=log_u, accept=acc)
+
+
+def transition_lapcn(prob: Problem, st: ChainState, xi=None, u=None, zeta=None) -> StepRecord:
+    """One transition of the LA-pCN baseline (eq. MAP and the LA-pCN proposal after it;
+    the LA-pCN row of the baselines of Sec. 6.1), with the mean read as
+    x_map + s (x - x_map). prob.fixed = (x_map, L_map)."""
+    x_map, L_map = prob.fixed
+    C, r = st.x.shape
+    if xi is None:
+        xi = philox.normals(prob.seed, prob.request_id, philox.STREAM_XI, st.step, st.chains, r)
+    if u is None:
+        u = philox.uniforms(prob.seed, prob.request_id, st.step, st.chains)
+    noise = sla.solve_triangular(L_map, xi[:, :r].T, lower=True, trans="T").T
+    xp = x_map + prob.s * (st.x - x_map) + prob.beta * noise
+    fp, phip = misfit(prob, xp)
+
+    def log_target_over_laplace(v, phi):
+        q = (v - x_map) @ L_map          # rows: L^T (v - x_map)
+        return -phi - 0.5 * np.sum(v * v, axis=1) + 0.5 * np.sum(q * q, axis=1)
+
+    lr = log_target_over_laplace(xp, phip) - log_target_over_laplace(st.x, st.cache.phi)
     good = np.isfinite(lr)
     lr = np.where(good, lr, -np.inf)
     log_u = np.log(u)

@@ -454,3 +454,69 @@ def test_mala_planted_dropped_gradient_norm_fails_textbook():
     planted = rec.log_rho + (prob.dt / 8.0) * (np.sum(gp * gp, axis=1) - np.sum(gx * gx, axis=1))
     ref = np.array([mala_textbook_log_ratio(prob, x[c], rec.xp[c]) for c in range(3)])
     assert np.max(np.abs(planted - ref)) > 1e-3
+
+
+# ---- LA-pCN baseline (metric fixed at the MAP, no ppg; eq. MAP) ----------------------
+
+def laplace_fixed(prob, r):
+    """MAP by Gauss-Newton on the oracle's geometry, and the factor of I + H there."""
+    x = np.zeros(r)
+    for _ in range(200):
+        c = mcmc.geometry(prob, x[None])
+        step = np.linalg.solve(np.eye(r) + c.H[0], x + c.g[0])
+        x = x - step
+        if np.linalg.norm(step) < 1e-13:
+            break
+    c = mcmc.geometry(prob, x[None])
+    return x, c.L[0]
+
+
+def test_lapcn_log_rho_is_the_textbook_mh_ratio():
+    prob = nonlinear_problem(dt=0.5)
+    prob.method = "lapcn"
+    x_map, L = laplace_fixed(prob, 4)
+    prob.fixed = (x_map, L)
+    cov = (1.0 - prob.s ** 2) * np.linalg.inv(L @ L.T)
+    rng = np.random.default_rng(41)
+    x = x_map + 0.5 * rng.standard_normal((5, 4))
+    st = mcmc.init_state(prob, x)
+    rec = mcmc.transition(prob, st, xi=rng.standard_normal((5, 4)), u=np.full(5, 0.5))
+    for c in range(5):
+        a, b = x[c], rec.xp[c]
+        pa, pb = mcmc.geometry(prob, a[None]).phi[0], mcmc.geometry(prob, b[None]).phi[0]
+        mean = lambda v: x_map + prob.s * (v - x_map)
+        ref = (-pb - 0.5 * b @ b + multivariate_normal.logpdf(a, mean(b), cov)
+               + pa + 0.5 * a @ a - multivariate_normal.logpdf(b, mean(a), cov))
+        assert abs(rec.log_rho[c] - ref) < 1e-9 * max(1.0, abs(ref))
+
+
+def test_lapcn_is_exact_on_a_linear_gaussian_posterior():
+    """Linear network: the Laplace approximation at the MAP is the posterior, so every
+    LA-pCN proposal has log rho = 0 and is accepted."""
+    prob, A, b = linear_problem(dt=0.7)
+    prob.method = "lapcn"
+    x_map, L = laplace_fixed(prob, 3)
+    Gi = np.diag(1 / prob.noise_var)
+    Sigma = np.linalg.inv(np.eye(3) + A.T @ Gi @ A)
+    np.testing.assert_allclose(x_map, Sigma @ A.T @ Gi @ (prob.y - b), rtol=1e-12, atol=1e-12)
+    prob.fixed = (x_map, L)
+    st = mcmc.init_state(prob, np.random.default_rng(42).standard_normal((6, 3)))
+    for _ in range(5):
+        rec = mcmc.transition(prob, st)
+        assert np.max(np.abs(rec.log_rho)) < 1e-11 and np.all(rec.accept)
+
+
+def test_lapcn_printed_mean_fails_the_textbook_ratio():
+    """The printed mean m_MAP - s m with the Laplace-reversible ratio disagrees with the
+    textbook MH ratio of that proposal: the printed form is not the method."""
+    prob, A, b = linear_problem(dt=0.7)
+    x_map, L = laplace_fixed(prob, 3)
+    cov = (1.0 - prob.s ** 2) * np.linalg.inv(L @ L.T)
+    rng = np.random.default_rng(43)
+    a = rng.standard_normal(3)
+    printed = lambda v: x_map - prob.s * v
+    bpt = printed(a) + np.linalg.cholesky(cov) @ rng.standard_normal(3)
+    phi = lambda v: mcmc.geometry(prob, v[None]).phi[0]
+    textbook = (-phi(bpt) - 0.5 * bpt @ bpt + multivariate_normal.logpdf(a, printed(bpt), cov)
+                + phi(a) + 0.5 * a @ a - multivariate_normal.logpdf(bpt, printed(a), cov))
+    assert abs(textbook) > 1e-3   # the closed-form ratio is 0 on this posterior

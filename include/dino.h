@@ -139,10 +139,18 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  *   beta xi, log rho_0(m1, m2) = -(dt/8)||g(m1)||^2 - (sqrt(dt)/2) mhat . g(m1). A step
  *   forms the misfit and ppg at x+ (forward and Jacobian); the cache's factor stays that
  *   of dino_chains_init.
- * PCN and MALA are not available to the serving pools. */
+ * LAPCN: the LA-pCN baseline (eq. MAP and the LA-pCN proposal after it; the LA-pCN row
+ *   of the baselines of Sec. 6.1), the pCN move about the MAP with the Laplace
+ *   covariance: x+ = x_map + s (x - x_map) + beta L^-T xi, with L L^T = I + H(x_map)
+ *   fixed by dino_set_fixed_metric, and log rho = Phi(x) - Phi(x+) + (|x|^2 - |x+|^2)/2
+ *   + (|L^T (x+ - x_map)|^2 - |L^T (x - x_map)|^2)/2. The printed proposal mean
+ *   m_MAP - s m is read as m_MAP + s (m - m_MAP): only that form is reversible with
+ *   respect to the Laplace approximation. A step evaluates the network forward only.
+ * PCN, MALA and LAPCN are not available to the serving pools. */
 #define DINO_METHOD_MMALA 0
 #define DINO_METHOD_PCN 1
 #define DINO_METHOD_MALA 2
+#define DINO_METHOD_LAPCN 3
 typedef struct {
     int32_t n_chains;
     int32_t d_y;
@@ -153,7 +161,7 @@ typedef struct {
     double dt;
     uint64_t seed;
     uint64_t request_id;
-    int32_t method;           /* DINO_METHOD_MMALA (0), DINO_METHOD_PCN or DINO_METHOD_MALA */
+    int32_t method;           /* DINO_METHOD_MMALA (0), _PCN, _MALA or _LAPCN */
 } dino_problem_desc;
 
 /* Device bytes a problem needs (state, caches, scratch, trace). */
@@ -173,6 +181,13 @@ dino_status dino_problem_destroy(dino_problem* p);
  * geometry cache at x0 (Alg. 1 "known at m_j") and resets the step counter,
  * acceptance counts and trace. */
 dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0, void* stream);
+
+/* The fixed metric of an LAPCN problem: x_map (host, r FP64, the reduced MAP) and L_map
+ * (host, r x r FP64 row-major, the lower Cholesky factor of I + H(x_map); the upper
+ * triangle is not read). Copied to the problem's workspace. EINVAL unless the problem's
+ * method is DINO_METHOD_LAPCN, for null pointers, or a non-positive diagonal; ENUMERIC
+ * for non-finite entries. An LAPCN problem refuses dino_step (ESTATE) until this call. */
+dino_status dino_set_fixed_metric(dino_problem* p, const double* x_map, const double* L_map);
 
 /* Advance every chain n_steps transitions (Alg. 1 first stage + the splitting proposition of Sec. 5.3).
  * Asynchronous on stream. Per-chain numerical failures (non-finite misfit,

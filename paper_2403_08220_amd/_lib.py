@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
-METHODS = {"mmala": 0, "pcn": 1, "mala": 2}
+METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3}
 
 
 class DinoError(RuntimeError):
@@ -102,6 +102,7 @@ SIGNATURES = {
     "dino_problem_destroy": (ct.c_int32, [_P]),
     "dino_chains_init": (ct.c_int32, [_P, _D, _F, _P]),
     "dino_step": (ct.c_int32, [_P, ct.c_int, _P]),
+    "dino_set_fixed_metric": (ct.c_int32, [_P, _D, _D]),
     "dino_read_states": (ct.c_int32, [_P, _D, _F]),
     "dino_read_cache": (ct.c_int32, [_P, _D, _D, _D]),
     "dino_read_diagnostics": (ct.c_int32, [_P, _I64, _I64, _I64]),

@@ -153,6 +153,13 @@ class Problem:
             assert z0.shape == (self.C, self.d_perp)
         check(self.lib.dino_chains_init(self.h, dptr(x0), fptr(z0), _stream_handle(stream)))
 
+    def set_fixed_metric(self, x_map, L_map):
+        """LA-pCN: the reduced MAP (r,) and the lower Cholesky factor of I + H there (r, r)."""
+        xm = np.ascontiguousarray(x_map, dtype=np.float64)
+        Lm = np.ascontiguousarray(L_map, dtype=np.float64)
+        assert xm.shape == (self.r,) and Lm.shape == (self.r, self.r)
+        check(self.lib.dino_set_fixed_metric(self.h, dptr(xm), dptr(Lm)))
+
     def step(self, n: int, stream=None):
         check(self.lib.dino_step(self.h, n, _stream_handle(stream)))
 

@@ -216,6 +216,7 @@ struct dino_problem {
     bool own_ws = false;
     bool initialised = false;
     bool serving = false;     // a serving pool: per-request rows, running sums
+    bool fixed_set = false;   // LA-pCN: dino_set_fixed_metric has been called
     void* ws = nullptr;
     size_t ws_bytes = 0;
     int64_t step = 0;
@@ -244,7 +245,9 @@ struct dino_problem {
     double* phip = nullptr;
     double* logdetp = nullptr;
     int32_t* okp = nullptr;
-    double* lfwd = nullptr;   // log rho_0(x -> xp) per chain
+    double* lfwd = nullptr;   // log rho_0(x -> xp) per chain (LA-pCN: its density term)
+    double* xmap = nullptr;   // LA-pCN: r, the MAP
+    double* Lfix = nullptr;   // LA-pCN: r x r, the factor of I + H(x_map)
     int32_t* acc = nullptr;   // accept flag of the last step
     double* f = nullptr;      // C x d_y (FP64)
     double* h0 = nullptr;     // C x wmax activations (ping)
@@ -318,6 +321,7 @@ void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t s
 void launch_pcn_propose(dino_problem* p, int n, hipStream_t st);
 void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 void launch_mala_propose(dino_problem* p, int n, hipStream_t st);
+void launch_lapcn_propose(dino_problem* p, int n, hipStream_t st);
 void launch_mala_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
 // Whether the BF16 reverse sweep covers the network: it holds at most 16 row blocks of 32
 // (the reduced dimension and every hidden width at most 512).

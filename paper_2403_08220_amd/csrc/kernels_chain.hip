@@ -950,17 +950,81 @@ __global__ __launch_bounds__(64) void pcn_propose_kernel(int r, double s, double
     }
 }
 
+// LA-pCN proposal (eq. MAP and the LA-pCN proposal after it, with the mean read as
+// x_map + s (x - x_map)): x+ = x_map + s (x - x_map) + beta L^-T xi, L the fixed factor
+// of I + H(x_map) shared by every chain. lterm receives the density part of log rho,
+// (|x|^2 - |x+|^2)/2 + (|L^T (x+ - x_map)|^2 - |L^T (x - x_map)|^2)/2; the decision
+// kernel adds Phi(x) - Phi(x+). One block per chain.
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void lapcn_propose_kernel(
+    int r, double s, double beta, ChainMeta meta, const double* __restrict__ x, const double* L,
+    const double* __restrict__ xmap, double* __restrict__ xp, double* __restrict__ lterm) {
+    extern __shared__ double dyn[];
+    const ChainLds S = carve_chain_lds(dyn, r);
+    double *xi = S.v[0], *u = S.v[1], *dx = S.v[2], *dp = S.v[3], *lx = S.v[4], *lp = S.v[5], *invd = S.v[6];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) return;
+    const uint64_t k0 = meta.key0[c], k1 = meta.key1[c], chain = (uint64_t)meta.index[c];
+    if (state == CHAIN_FRESH) {
+        for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
+            double nv[4];
+            philox_normals4(k0, k1, (uint64_t)b4, STREAM_INIT_X, 0, chain, nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (4 * b4 + q < r) xp[(long)c * r + 4 * b4 + q] = nv[q];
+        }
+        if (tid == 0) lterm[c] = 0.0;
+        return;
+    }
+    load_inv_diag(L, r, invd);
+    const uint64_t step = (uint64_t)meta.step[c];
+    for (int b4 = tid; 4 * b4 < r; b4 += TPB) {
+        double nv[4];
+        philox_normals4(k0, k1, (uint64_t)b4, STREAM_XI, step, chain, nv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (4 * b4 + q < r) xi[4 * b4 + q] = nv[q];
+    }
+    __syncthreads();
+    lt_solve(L, invd, r, xi, u, S.part);
+    __syncthreads();
+    double nx = 0.0, np = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        const double xj = x[(long)c * r + j], mj = xmap[j];
+        const double pj = mj + s * (xj - mj) + beta * u[j];
+        xp[(long)c * r + j] = pj;
+        dx[j] = xj - mj;
+        dp[j] = pj - mj;
+        nx += xj * xj;
+        np += pj * pj;
+    }
+    __syncthreads();
+    lt_matvec2(L, r, dx, lx, dp, lp, S.part);
+    __syncthreads();
+    double qx = 0.0, qp = 0.0;
+    for (int j = tid; j < r; j += TPB) {
+        qx += lx[j] * lx[j];
+        qp += lp[j] * lp[j];
+    }
+    nx = block_sum(nx, S.red);
+    np = block_sum(np, S.red);
+    qx = block_sum(qx, S.red);
+    qp = block_sum(qp, S.red);
+    if (tid == 0) lterm[c] = 0.5 * (nx - np) + 0.5 * (qp - qx);
+}
+
 // Misfit at x+ (Sec. 5.1: 1/2 || Gamma^-1/2 (f - y) ||^2, from the network output f of
 // the forward stage, FP64 or FP32), the MH decision with exp(Phi(x) - Phi(x+)) (accept iff
 // log u <= log rho; a non-finite misfit rejects and is counted) and the end of the step.
+// lterm (LA-pCN): the density part of log rho from the proposal kernel, or null (pCN).
 // accflag as for the mMALA accept kernel (the complement kernel reads it).
 template <typename TF>
 __global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMeta meta, const TF* __restrict__ f,
                                                          const double* __restrict__ y_rows,
                                                          const double* __restrict__ winv_rows, double* x,
                                                          double* phi, const double* __restrict__ xp,
-                                                         int64_t* accepts, int64_t* failures, int32_t* accflag,
-                                                         StepRecord rec) {
+                                                         const double* __restrict__ lterm, int64_t* accepts,
+                                                         int64_t* failures, int32_t* accflag, StepRecord rec) {
     __shared__ double red[TPB / 64];
     __shared__ int decision;
     const int c = blockIdx.x, tid = threadIdx.x;
@@ -997,7 +1061,7 @@ __global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMet
             decision = 1;
             accflag[c] = 2;
         } else {
-            const double lr = phi[c] - php;
+            const double lr = phi[c] - php + (lterm ? lterm[c] : 0.0);
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = isfinite(lr);
             const bool accept = good && (log(u) <= lr);
@@ -1793,12 +1857,21 @@ void launch_pcn_propose(dino_problem* p, int n, hipStream_t st) {
 // The forward stage leaves the network output in p->f (FP64 path) or p->f32 (BF16 path).
 void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
     const StepRecord rec = step_record(p, trace_row);
+    const double* lterm = p->desc.method == DINO_METHOD_LAPCN ? p->lfwd : nullptr;
     if (p->desc.precision == DINO_PREC_F64)
         hipLaunchKernelGGL(pcn_accept_kernel<double>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f, p->y,
-                           p->winv, p->x, p->phi, p->xp, p->accepts, p->failures, p->acc, rec);
+                           p->winv, p->x, p->phi, p->xp, lterm, p->accepts, p->failures, p->acc, rec);
     else
         hipLaunchKernelGGL(pcn_accept_kernel<float>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f32, p->y,
-                           p->winv, p->x, p->phi, p->xp, p->accepts, p->failures, p->acc, rec);
+                           p->winv, p->x, p->phi, p->xp, lterm, p->accepts, p->failures, p->acc, rec);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_lapcn_propose(dino_problem* p, int n, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(lapcn_propose_kernel, attr);
+    hipLaunchKernelGGL(lapcn_propose_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->s, p->beta,
+                       p->meta, p->x, p->Lfix, p->xmap, p->xp, p->lfwd);
     DINO_HIP(hipGetLastError());
 }
 

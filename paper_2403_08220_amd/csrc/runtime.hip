@@ -117,6 +117,10 @@ static void layout(dino_problem* p, Carver& cv) {
     p->okp = cv.take<int32_t>(C);
     p->lfwd = cv.take<double>(C);
     p->acc = cv.take<int32_t>(C);
+    if (p->desc.method == DINO_METHOD_LAPCN) {
+        p->xmap = cv.take<double>(r);
+        p->Lfix = cv.take<double>(r * r);
+    }
     p->f = cv.take<double>(C * dy);
     if (p->desc.precision == DINO_PREC_F64) {
         p->h0 = cv.take<double>(C * w);
@@ -155,8 +159,7 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
     DINO_REQUIRE(d->factorization >= DINO_FACTOR_PRIMAL && d->factorization <= DINO_FACTOR_AUTO, DINO_EINVAL,
                  "unknown factorization");
-    DINO_REQUIRE(d->method == DINO_METHOD_MMALA || d->method == DINO_METHOD_PCN || d->method == DINO_METHOD_MALA,
-                 DINO_EINVAL, "unknown method");
+    DINO_REQUIRE(d->method >= DINO_METHOD_MMALA && d->method <= DINO_METHOD_LAPCN, DINO_EINVAL, "unknown method");
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
                       (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
@@ -662,7 +665,8 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const long half = (long)p->C * rr;
     const int L = (int)p->ctx->layers.size();
     const bool f64 = p->desc.precision == DINO_PREC_F64;
-    const bool pcn = p->desc.method == DINO_METHOD_PCN;
+    const bool pcn = p->desc.method == DINO_METHOD_PCN || p->desc.method == DINO_METHOD_LAPCN;
+    const bool lapcn = p->desc.method == DINO_METHOD_LAPCN;
     const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, p->z ? 1 : 0, 0};
     const bool mala = p->desc.method == DINO_METHOD_MALA;
     const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, p->z ? 1 : 0, 0};
@@ -674,8 +678,9 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     for (int k = 0; k < n_steps; ++k) {
         mark(0);
         if (pcn) {
-            // pCN baseline: proposal, network forward, misfit and decision (one kernel)
-            launch_pcn_propose(p, n, st);
+            // pCN / LA-pCN baselines: proposal, network forward, misfit and decision (one kernel)
+            if (lapcn) launch_lapcn_propose(p, n, st);
+            else launch_pcn_propose(p, n, st);
             mark(1);
             stage_forward(p, n, p->xp, p->f, st);
             for (int i = 2; i <= 6; ++i) mark(i);
@@ -757,10 +762,34 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
 }  // namespace dino
 }  // extern "C++"
 
+dino_status dino_set_fixed_metric(dino_problem* p, const double* x_map, const double* L_map) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x_map && L_map, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(p->desc.method == DINO_METHOD_LAPCN, DINO_EINVAL, "the problem's method is not LA-pCN");
+        const int r = p->r;
+        for (int i = 0; i < r; ++i) {
+            DINO_REQUIRE(std::isfinite(x_map[i]), DINO_ENUMERIC, "non-finite x_map");
+            for (int j = 0; j <= i; ++j)
+                DINO_REQUIRE(std::isfinite(L_map[(long)i * r + j]), DINO_ENUMERIC, "non-finite L_map");
+            DINO_REQUIRE(L_map[(long)i * r + i] > 0.0, DINO_EINVAL, "L_map has a non-positive diagonal");
+        }
+        // lower triangle as given, upper triangle zero (the kernels read full rows)
+        std::vector<double> L((size_t)r * r, 0.0);
+        for (int i = 0; i < r; ++i)
+            for (int j = 0; j <= i; ++j) L[(size_t)i * r + j] = L_map[(long)i * r + j];
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipMemcpy(p->xmap, x_map, sizeof(double) * r, hipMemcpyHostToDevice));
+        DINO_HIP(hipMemcpy(p->Lfix, L.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
+        p->fixed_set = true;
+    });
+}
+
 dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
     return guarded([&] {
         DINO_REQUIRE(p, DINO_EINVAL, "null problem");
         DINO_REQUIRE(p->initialised, DINO_ESTATE, "dino_chains_init must precede dino_step");
+        DINO_REQUIRE(p->desc.method != DINO_METHOD_LAPCN || p->fixed_set, DINO_ESTATE,
+                     "dino_set_fixed_metric must precede dino_step for an LA-pCN problem");
         DINO_REQUIRE(n_steps >= 0, DINO_EINVAL, "negative step count");
         DINO_HIP(hipSetDevice(p->ctx->device));
         run_steps(p, p->C, n_steps, as_stream(stream));

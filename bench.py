@@ -167,7 +167,7 @@ def laplace_start(w, ctx, y, nv):
     m = laplace.gauss_newton_map(ctx, y, nv)
     x0 = laplace.laplace_samples(ctx, y, nv, m.x, draw_laplace_normals(w))
     _, z0 = draw_initial_states(w)
-    return x0, z0, dict(J_map=m.J, gn_iters=m.iters, seconds=round(time.perf_counter() - t0, 3))
+    return x0, z0, dict(J_map=m.J, gn_iters=m.iters, seconds=round(time.perf_counter() - t0, 3)), m.x
 
 
 def cpu_baseline(w, layers, x0, z0, chains=32, budget_s=20.0, max_steps=60, factor="primal"):
@@ -210,7 +210,7 @@ def copy_calibration(nbytes=1 << 29):
 
 
 def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, factorization="auto", method="mmala",
-             dt=None):
+             dt=None, fixed=None):
     import torch
     from paper_2403_08220_amd import Problem
 
@@ -219,6 +219,8 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, fact
     p = Problem(ctx, C, y, nv, w.dt if dt is None else dt, seed=w.chain_seed, precision=precision,
                 track_complement=True, trace_capacity=cap, factorization=factorization, method=method)
     p.init(x0, z0)
+    if fixed is not None:
+        p.set_fixed_metric(*fixed)
     stream = torch.cuda.current_stream()
     p.step(warmup)
     torch.cuda.synchronize()
@@ -260,7 +262,23 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, fact
 
 # step sizes the tuning rule chooses from, per baseline
 BASELINE_DT_CANDIDATES = {"pcn": [1e-6, 3e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3, 1e-2],
-                          "mala": [1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3]}
+                          "mala": [1e-5, 3e-5, 1e-4, 3e-4, 1e-3, 3e-3],
+                          "lapcn": [1e-3, 3e-3, 1e-2, 3e-2, 1e-1, 3e-1, 1.0]}
+
+
+def laplace_metric(w, ctx, y, nv, x_map):
+    """(x_map, L_map) for LA-pCN: the factor of I + H(x_map), evaluated by the device's
+    FP64 primal geometry."""
+    import torch
+    from paper_2403_08220_amd import Problem
+
+    p = Problem(ctx, 1, y, nv, w.dt, precision="f64", track_complement=False, factorization="primal")
+    try:
+        x = torch.tensor(np.asarray(x_map, dtype=np.float64)[None], device="cuda:0")
+        L = p.eval_geometry(x)["L"][0].cpu().numpy()
+    finally:
+        p.close()
+    return np.asarray(x_map, dtype=np.float64), np.tril(L)
 ESS_FLOOR_MARGIN = 1.5
 
 
@@ -270,12 +288,12 @@ def ess_floor(n_chains):
     return n_chains / 2.0
 
 
-def baseline_leg(method, w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala):
-    """A baseline of Sec. 6.1 (pCN or MALA) on the same workload, chains and starting
-    states: its step size chosen by the same tuning rule over BASELINE_DT_CANDIDATES,
-    then timed like the main leg. The ratio of the two ESS rates is the effective
-    sampling speedup (Sec. 6.3.1) of mMALA over the baseline on the surrogate posterior,
-    at equal hardware. It is reported only when
+def baseline_leg(method, w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala, fixed=None):
+    """A baseline of Sec. 6.1 (pCN, MALA, or LA-pCN with `fixed` = (x_map, L_map)) on
+    the same workload, chains and starting states: its step size chosen by the same
+    tuning rule over BASELINE_DT_CANDIDATES, then timed like the main leg. The ratio of
+    the two ESS rates is the effective sampling speedup (Sec. 6.3.1) of mMALA over the
+    baseline on the surrogate posterior, at equal hardware. It is reported only when
     both median ESS values clear the multichain estimator's floor: chains that stay
     correlated over the whole window give rho_t near 1 at every lag and an ESS of about
     n_chains / 2 whatever the method, which measures the spread of the starting states,
@@ -283,8 +301,9 @@ def baseline_leg(method, w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala)
     from paper_2403_08220_amd.tune import tune_step_size
 
     tr = tune_step_size(ctx, y, nv, x0, z0, BASELINE_DT_CANDIDATES[method], burn=20, steps=100,
-                        seed=w.chain_seed, precision=precision, method=method)
-    r = run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=False, method=method, dt=tr.dt)
+                        seed=w.chain_seed, precision=precision, method=method, fixed=fixed)
+    r = run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=False, method=method, dt=tr.dt,
+                 fixed=fixed)
     C = w.chains
     rate = r["median_ess"] / r["wall_s"]
     mm_rate = mmala["median_ess"] / mmala["wall_s"]
@@ -467,7 +486,7 @@ def main():
                     help="auto: the observation-space (d_y x d_y) factorisation when d_y < r")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--baseline-steps", type=int, default=400,
-                    help="steps of each baseline leg, pCN and MALA (0: skip)")
+                    help="steps of each baseline leg, pCN, MALA and LA-pCN (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
@@ -503,7 +522,7 @@ def main():
 
     log(f"bench: workload mid, {w.chains} chains, precision {args.precision}, steps {args.steps}")
     ctx, y, nv = make_problem_inputs(w, ctx_builder)
-    x0, z0, init_info = laplace_start(w, ctx, y, nv)
+    x0, z0, init_info, x_map = laplace_start(w, ctx, y, nv)
     log(f"bench: Laplace start ready {init_info}")
     copy_calibration()
     res = run_path(w, ctx, y, nv, x0, z0, args.precision, args.steps, args.warmup, profile=not args.no_profile,
@@ -526,8 +545,10 @@ def main():
     baselines = None
     if args.baseline_steps > 0:
         baselines = {}
-        for method in ("pcn", "mala"):
-            b = baseline_leg(method, w, ctx, y, nv, x0, z0, args.precision, args.baseline_steps, args.warmup, res)
+        fixed = laplace_metric(w, ctx, y, nv, x_map)
+        for method in ("pcn", "mala", "lapcn"):
+            b = baseline_leg(method, w, ctx, y, nv, x0, z0, args.precision, args.baseline_steps, args.warmup, res,
+                             fixed=fixed if method == "lapcn" else None)
             baselines[method] = b
             log(f"bench: {method} baseline: dt {b['dt']}, accept {b['accept_rate']}, {b['value']} chain-steps/s")
 

@@ -50,9 +50,10 @@ class TuneResult:
 
 
 def tune_step_size(ctx, y, noise_var, x0, z0, candidates, burn: int, steps: int, seed: int = 0,
-                   precision: str = "f64", stream=None, method: str = "mmala") -> TuneResult:
+                   precision: str = "f64", stream=None, method: str = "mmala", fixed=None) -> TuneResult:
     """Run every candidate dt on the device from (x0, z0) and apply the selection rule
-    (method: the transition kernel, "mmala" or the "pcn" baseline)."""
+    (method: the transition kernel, "mmala" or a baseline; fixed: (x_map, L_map) of an
+    "lapcn" problem)."""
     import torch
 
     from .api import Problem
@@ -64,6 +65,8 @@ def tune_step_size(ctx, y, noise_var, x0, z0, candidates, burn: int, steps: int,
                     track_complement=z0 is not None, trace_capacity=burn + steps, method=method)
         try:
             p.init(x0, z0, stream=stream)
+            if fixed is not None:
+                p.set_fixed_metric(*fixed)
             p.step(burn, stream=stream)
             a0, _, _ = p.diagnostics()
             p.step(steps, stream=stream)

@@ -413,6 +413,7 @@ __global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int l
         for (int ii = 0; ii < dy; ++ii) acc += (double)__bfloat162float(bt[(long)j * ldt + ii]) * (double)es[ii];
         g[(long)c * r + j] = acc;
     }
+    if (!A) return;  // misfit and ppg only (the MALA baseline forms no metric)
     double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
     const int nl = lane & 31, h = lane >> 5;
     const int nkc = dy_pad / 16;
@@ -628,6 +629,7 @@ __global__ __launch_bounds__(HES_TPB) void gram_bf16_kernel(int dy, int r, int l
         for (int i = 0; i < dy; ++i) acc += (double)__bfloat162float(bs[(long)i * ldt + j]) * (double)es[i];
         g[(long)c * r + j] = acc;
     }
+    if (!A) return;  // misfit and ppg only (the MALA baseline forms no metric)
     double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
     const int nl = lane & 31, h = lane >> 5;
     const int nmb = dy_pad / 32, nkc = k_pad / 16;

@@ -670,7 +670,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, p->z ? 1 : 0, 0};
     const bool mala = p->desc.method == DINO_METHOD_MALA;
     const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, p->z ? 1 : 0, 0};
-    // MALA: on the mixed path the ppg comes from the metric kernel (its metric is unused)
+    // MALA: on the mixed path the misfit and ppg come from the metric kernel, told to skip the metric
     const int32_t launches_mala[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, f64 ? 0 : 1, 0, 1, p->z ? 1 : 0, 0};
     auto mark = [&](int i) {
         if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
@@ -708,7 +708,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             mark(3);
             stage_misfit(p, n, p->f, p->phip, p->gp, st);
             mark(4);
-            if (!f64) stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
+            if (!f64) stage_hessian(p, n, p->phip, p->gp, nullptr, 0, nullptr, 0, 0, st);  // misfit and ppg only
             mark(5);
             mark(6);
             int64_t row = -1;

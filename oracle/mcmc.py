@@ -108,6 +108,17 @@ def geometry(prob: Problem, x: np.ndarray) -> Cache:
     J = J_full[:, :dy, :]
     w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
     Jw = J * w[None, :, None]                      # V^* J~_r : whitened reduced Jacobian
+    return cache_from_jacobian(prob, f, Jw)
+
+
+def cache_from_jacobian(prob: Problem, f: np.ndarray, Jw: np.ndarray) -> Cache:
+    """The cache of Sec. 5.1-5.2 from the network output f (C, d_y) and a whitened reduced
+    Jacobian Jw = Gamma^-1/2 J (C, d_y, r) given as data (geometry() passes the network's
+    own; a caller may pass a rounded copy to evaluate the method on it)."""
+    f = np.atleast_2d(np.asarray(f, dtype=np.float64))
+    Jw = np.asarray(Jw, dtype=np.float64)
+    C, r = Jw.shape[0], Jw.shape[2]
+    w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
     res = (prob.y[None, :] - f) * w[None, :]       # V^* y - f_NN (whitened)
     phi = 0.5 * np.sum(res * res, axis=1)          # eq. (reduced data misfit)
     g = -np.einsum("cir,ci->cr", Jw, res)          # J^T Gamma^-1 (f - y)  (sign reading)
@@ -196,6 +207,22 @@ def log_rho0(prob: Problem, m1: np.ndarray, m2: np.ndarray, cache1: Cache) -> np
         t3 = -0.5 * (mhat @ (H @ mhat))
         t4 = 0.5 * np.sum(np.log(d + 1.0))
         out[c] = t1 + t2 + t3 + t4
+    return out
+
+
+def log_rho0_terms(prob: Problem, m1: np.ndarray, m2: np.ndarray, cache1: Cache) -> np.ndarray:
+    """The four terms of log rho~_0,r(m1, m2) (Sec. 5.4) as columns (C, 4), in the order of
+    log_rho0's docstring; their sum is log_rho0. A caller bounds rounding in the sum by
+    the magnitudes of the terms that cancel in it."""
+    dt, s, beta = prob.dt, prob.s, prob.beta
+    C = m1.shape[0]
+    out = np.empty((C, 4))
+    for c in range(C):
+        d, P, g, H = cache1.d[c], cache1.P[c], cache1.g[c], cache1.H[c]
+        a = d * (P.T @ m1[c]) - P.T @ g
+        mhat = (m2[c] - s * m1[c]) / beta
+        out[c] = [-(dt / 8.0) * np.sum(a * a / (d + 1.0)), (math.sqrt(dt) / 2.0) * (mhat @ (H @ m1[c] - g)),
+                  -0.5 * (mhat @ (H @ mhat)), 0.5 * np.sum(np.log(d + 1.0))]
     return out
 
 

@@ -256,7 +256,8 @@ const char* dino_stage_name(int stage);
  * ok (n int32: 1 if finite and positive definite). H may be NULL. In the dual form
  * L receives the factor of I + B B^T (d_y x d_y, row stride d_y, in the first d_y^2
  * entries of each chain's block; log det is the same) and H is B^T B formed from the
- * stored B. dino_eval_propose and dino_eval_log_rho serve the primal form. */
+ * stored B. dino_eval_propose and dino_eval_log_rho serve the primal form,
+ * dino_eval_propose_dual and dino_eval_log_rho_dual the dual form. */
 dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* f, double* phi, double* g,
                                double* H, double* L, double* logdet, int32_t* ok, void* stream);
 
@@ -272,6 +273,38 @@ dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const dou
                               const double* L_x, const double* logdet_x, const double* xp,
                               const double* phi_p, const double* g_p, const double* L_p,
                               const double* logdet_p, double* log_rho, void* stream);
+
+/* Whitened reduced Jacobian B = Gamma^-1/2 J (the surrogate Jacobian of eq. rb_dino at
+ * x, whitened as in Sec. 5.1) of n points x (n x r), as the problem's Jacobian stage
+ * computes and stores it (BF16 problems: BF16 values), returned as FP64 in B
+ * (n x d_y x r, row-major). Runs the forward and Jacobian stages. */
+dino_status dino_eval_jacobian(dino_problem* p, int n, const double* x, double* B, void* stream);
+
+/* Row stride ldb of the Jacobian the dual stage entry points take: r for DINO_PREC_F64
+ * problems (B in doubles), ceil(r / 32) * 32 for DINO_PREC_BF16 problems (B as
+ * bfloat16 bit patterns; the entries of a row past r are not read). */
+dino_status dino_jacobian_ld(const dino_problem* p, int32_t* ldb);
+
+/* Observation-space (dual) form of the reduced proposal (eq. reduced_space_sampling,
+ * noise drawn as beta (I + H)^-1 (xi_1 + B^T xi_2), H = B^T B) and of the forward term
+ * lfwd = log rho_0(x -> xp) of the reduced RN derivative (Sec. 5.4), with the kernels
+ * dino_step runs for a dual problem. Device buffers: x, g (n x r), B (n x d_y x ldb, see
+ * dino_jacobian_ld, in the problem's Jacobian type), K (n x d_y x d_y, the lower Cholesky
+ * factor of I + B B^T, row-major, upper triangle not read), logdet (n, sum log K_ii), xi
+ * (n x (r + d_y): xi_1 then xi_2); outputs xp (n x r) and lfwd (n). EINVAL for a primal
+ * problem or a method other than MMALA. */
+dino_status dino_eval_propose_dual(dino_problem* p, int n, const double* x, const double* g, const void* B,
+                                   const double* K, const double* logdet, const double* xi, double* xp, double* lfwd,
+                                   void* stream);
+
+/* log of the first-stage ratio rho^(1)_r(x, xp) (eq. da_dino_trr_1) of the dual form from
+ * the two states and their caches (phi, g, B, K, logdet, laid out as for
+ * dino_eval_propose_dual); both transition terms are evaluated with the code of the
+ * acceptance kernel's reverse term. */
+dino_status dino_eval_log_rho_dual(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                                   const void* B_x, const double* K_x, const double* logdet_x, const double* xp,
+                                   const double* phi_p, const double* g_p, const void* B_p, const double* K_p,
+                                   const double* logdet_p, double* log_rho, void* stream);
 
 /* Philox4x64-10 normals of one stream for n chains at one step: out n x count. */
 dino_status dino_eval_normals(dino_problem* p, int n, int stream_id, int64_t step, int count, double* out,

@@ -113,6 +113,10 @@ SIGNATURES = {
     "dino_eval_propose": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P, _P, _P]),
     "dino_eval_log_rho": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dino_eval_normals": (ct.c_int32, [_P, ct.c_int, ct.c_int, ct.c_int64, ct.c_int, _P, _P]),
+    "dino_eval_jacobian": (ct.c_int32, [_P, ct.c_int, _P, _P, _P]),
+    "dino_jacobian_ld": (ct.c_int32, [_P, _I32]),
+    "dino_eval_propose_dual": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "dino_eval_log_rho_dual": (ct.c_int32, [_P, ct.c_int] + [_P] * 13 + [_P]),
     "dino_set_profiling": (ct.c_int32, [_P, ct.c_int]),
     "dino_read_profile": (ct.c_int32, [_P, _D, _I32, _I64]),
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),

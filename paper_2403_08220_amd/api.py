@@ -249,6 +249,50 @@ class Problem:
                                          _tp(cp["logdet"]), _tp(out), _stream_handle(stream)))
         return out
 
+    def eval_jacobian(self, x, stream=None):
+        """Whitened reduced Jacobian (n, d_y, r) at device points x, as the Jacobian stage stores it, in float64."""
+        torch = _torch()
+        B = torch.empty((x.shape[0], self.d_y, self.r), dtype=torch.float64, device=x.device)
+        check(self.lib.dino_eval_jacobian(self.h, x.shape[0], _tp(x), _tp(B), _stream_handle(stream)))
+        return B
+
+    def jacobian_ld(self) -> int:
+        ld = np.zeros(1, dtype=np.int32)
+        check(self.lib.dino_jacobian_ld(self.h, i32ptr(ld)))
+        return int(ld[0])
+
+    def jacobian_storage(self, B):
+        """Device copy of B (n, d_y, r) in the layout the dual stage entry points take: float64
+        rows of r (FP64 problems), or bfloat16 rows padded to dino_jacobian_ld (BF16 problems;
+        the values are rounded to bfloat16 by torch)."""
+        torch = _torch()
+        n = B.shape[0]
+        ld = self.jacobian_ld()
+        if self.desc.precision == _lib.PRECISIONS["f64"]:
+            return B.to(torch.float64).contiguous()
+        out = torch.zeros((n, self.d_y, ld), dtype=torch.bfloat16, device=B.device)
+        out[:, :, : self.r] = B.to(torch.bfloat16)
+        return out
+
+    def eval_propose_dual(self, x, g, B, K, logdet, xi, stream=None):
+        """Dual-form proposal and forward transition term at device buffers (see dino.h)."""
+        torch = _torch()
+        xp = torch.empty_like(x)
+        lfwd = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        check(self.lib.dino_eval_propose_dual(self.h, x.shape[0], _tp(x), _tp(g), _tp(B), _tp(K), _tp(logdet),
+                                              _tp(xi), _tp(xp), _tp(lfwd), _stream_handle(stream)))
+        return xp, lfwd
+
+    def eval_log_rho_dual(self, x, cx, xp, cp, stream=None):
+        """Dual-form log rho^(1); cx, cp: dicts with phi, g, B, K, logdet device tensors."""
+        torch = _torch()
+        out = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+        check(self.lib.dino_eval_log_rho_dual(self.h, x.shape[0], _tp(x), _tp(cx["phi"]), _tp(cx["g"]),
+                                              _tp(cx["B"]), _tp(cx["K"]), _tp(cx["logdet"]), _tp(xp),
+                                              _tp(cp["phi"]), _tp(cp["g"]), _tp(cp["B"]), _tp(cp["K"]),
+                                              _tp(cp["logdet"]), _tp(out), _stream_handle(stream)))
+        return out
+
     def eval_normals(self, n: int, stream_id: int, step: int, count: int, stream=None):
         torch = _torch()
         out = torch.empty((n, count), dtype=torch.float64, device=f"cuda:{self.ctx.device}")

@@ -332,6 +332,15 @@ bool hess_bf16_lds_fits(int r, int dy);
 // the staged B) fits one block for reduced dimension r and d_y observations.
 bool dual_lds_fits(int r, int dy, bool bf16);
 void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st);
+int jacobian_ld(const dino_problem* p);
+void launch_eval_propose_dual(dino_problem* p, int n, const double* x, const double* g, const void* B,
+                              const double* K, const double* logdet, const double* xi, double* xp, double* lfwd,
+                              hipStream_t st);
+void launch_eval_log_rho_dual(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                              const void* B_x, const double* K_x, const double* logdet_x, const double* xp,
+                              const double* phi_p, const double* g_p, const void* B_p, const double* K_p,
+                              const double* logdet_p, double* out, hipStream_t st);
+void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t st);
 // Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
 // no separate misfit launch).
 void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,

@@ -1459,12 +1459,14 @@ __device__ __forceinline__ double dual_rho0(const TB* Ba, int ldb, const double*
 
 // Proposal: u = beta (xi_1 + B^T xi_2) - (1 - s)(x + g),  xp = x + (I + H)^-1 u,
 // and lfwd = log rho_0(x -> xp) with the cache of x. B: the state's B (C x dy x ldb).
+// xi_given (n x (r + dy), xi_1 then xi_2) replaces the Philox draws when not null.
 template <typename TB>
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta, ChainMeta meta,
                          const double* __restrict__ x, const double* __restrict__ g, const TB* __restrict__ B,
                          const double* Kbuf, long strideK, const int32_t* slot, int slot_xor, long slot_stride,
-                         const double* __restrict__ logdet, double* __restrict__ xp, double* __restrict__ lfwd) {
+                         const double* __restrict__ logdet, const double* __restrict__ xi_given,
+                         double* __restrict__ xp, double* __restrict__ lfwd) {
     extern __shared__ double dyn[];
     double* R = dyn;
     double *xs = R, *gs = R + r, *u = R + 2 * r, *w = R + 3 * r, *v = R + 4 * r, *mh = R + 5 * r,
@@ -1496,7 +1498,13 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         xs[j] = x[(long)c * r + j];
         gs[j] = g[(long)c * r + j];
     }
-    {
+    if (xi_given) {
+        for (int k = tid; k < r + dy; k += TPB) {
+            const double v = xi_given[(long)c * (r + dy) + k];
+            if (k < r) xi1[k] = v;
+            else xi2[k - r] = v;
+        }
+    } else {
         const uint64_t k0 = meta.key0[c], k1 = meta.key1[c];
         const uint64_t step = (uint64_t)meta.step[c], chain = (uint64_t)meta.index[c];
         for (int b4 = tid; 4 * b4 < r + dy; b4 += TPB) {
@@ -1650,6 +1658,47 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
         }
     }
     finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
+}
+
+// log rho^(1) of the dual form at given states and caches (the stage entry point): the
+// forward term with the cache of x, the reverse term with the cache of xp, both by
+// dual_rho0 (the acceptance kernel's reverse-term code). K: n x dy x dy factors, B: n x dy x ldb.
+template <typename TB>
+__global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void log_rho_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta, const double* __restrict__ x,
+                         const double* __restrict__ phi_x, const double* __restrict__ g_x, const TB* __restrict__ Bx,
+                         const double* __restrict__ Kx, const double* __restrict__ logdet_x,
+                         const double* __restrict__ xp, const double* __restrict__ phi_p,
+                         const double* __restrict__ g_p, const TB* __restrict__ Bp, const double* __restrict__ Kp,
+                         const double* __restrict__ logdet_p, double* __restrict__ out) {
+    extern __shared__ double dyn[];
+    double* R = dyn;
+    double *xs = R, *ps = R + r, *ga = R + 2 * r, *v = R + 3 * r, *mh = R + 4 * r;
+    double* Y = dyn + (size_t)DU_NR * r;
+    double *invd = Y, *t1 = Y + dy, *t2 = Y + 2 * dy, *z = Y + 3 * dy;
+    double* acc = Y + (size_t)DU_NY * dy;
+    double* red = acc + 9 * SB;
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const long kk = (long)dy * dy;
+    const int ldl = dual_ldl(ldb, sizeof(TB) == 2);
+    for (int j = tid; j < r; j += TPB) {
+        xs[j] = x[(long)c * r + j];
+        ps[j] = xp[(long)c * r + j];
+        ga[j] = g_x[(long)c * r + j];
+    }
+    __syncthreads();
+    const TB* B1 = stage_b(Bx + (long)c * dy * ldb, dy, ldb, red + DU_RED);
+    load_inv_diag(Kx + c * kk, dy, invd);
+    const double fwd = dual_rho0(B1, ldl, Kx + c * kk, invd, r, dy, dt, s, beta, xs, ps, ga, logdet_x[c], v, mh, t1,
+                                 t2, z, acc, red);
+    __syncthreads();  // every thread is done with B1, invd and ga
+    for (int j = tid; j < r; j += TPB) ga[j] = g_p[(long)c * r + j];
+    __syncthreads();
+    const TB* B2 = stage_b(Bp + (long)c * dy * ldb, dy, ldb, red + DU_RED);
+    load_inv_diag(Kp + c * kk, dy, invd);
+    const double rev = dual_rho0(B2, ldl, Kp + c * kk, invd, r, dy, dt, s, beta, ps, xs, ga, logdet_p[c], v, mh, t1,
+                                 t2, z, acc, red);
+    if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
 }
 
 // Copies the Jacobian of every chain (n x dy x ldb values) into the state's buffer.
@@ -1907,7 +1956,86 @@ static void propose_dual_t(dino_problem* p, int n, const TB* Bs, int ldb, hipStr
     hipLaunchKernelGGL(propose_dual_kernel<TB>, dim3(n), dim3(TPB),
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, Bs, p->Lbuf, kk,
-                       p->cur, 0, (long)p->C * kk, p->logdet, p->xp, p->lfwd);
+                       p->cur, 0, (long)p->C * kk, p->logdet, (const double*)nullptr, p->xp, p->lfwd);
+    DINO_HIP(hipGetLastError());
+}
+
+// Stage entry points of the dual form on caller buffers: every chain is live, the
+// normals are given, the factors are packed n x dy x dy.
+template <typename TB>
+static void eval_propose_dual_t(dino_problem* p, int n, const double* x, const double* g, const TB* B, int ldb,
+                                const double* K, const double* logdet, const double* xi, double* xp, double* lfwd,
+                                hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(propose_dual_kernel<TB>, attr);
+    const long kk = (long)p->d_y * p->d_y;
+    hipLaunchKernelGGL(propose_dual_kernel<TB>, dim3(n), dim3(TPB),
+                       dual_lds_doubles(p->r, p->d_y, ldb, sizeof(TB) == 2) * sizeof(double), st, p->r, p->d_y, ldb,
+                       p->desc.dt, p->s, p->beta, ChainMeta{}, x, g, B, K, kk, (const int32_t*)nullptr, 0, 0L, logdet,
+                       xi, xp, lfwd);
+    DINO_HIP(hipGetLastError());
+}
+
+template <typename TB>
+static void eval_log_rho_dual_t(dino_problem* p, int n, int ldb, const double* x, const double* phi_x,
+                                const double* g_x, const TB* B_x, const double* K_x, const double* logdet_x,
+                                const double* xp, const double* phi_p, const double* g_p, const TB* B_p,
+                                const double* K_p, const double* logdet_p, double* out, hipStream_t st) {
+    static bool attr = false;
+    allow_large_lds(log_rho_dual_kernel<TB>, attr);
+    hipLaunchKernelGGL(log_rho_dual_kernel<TB>, dim3(n), dim3(TPB),
+                       dual_lds_doubles(p->r, p->d_y, ldb, sizeof(TB) == 2) * sizeof(double), st, p->r, p->d_y, ldb,
+                       p->desc.dt, p->s, p->beta, x, phi_x, g_x, B_x, K_x, logdet_x, xp, phi_p, g_p, B_p, K_p,
+                       logdet_p, out);
+    DINO_HIP(hipGetLastError());
+}
+
+int jacobian_ld(const dino_problem* p) {
+    return p->desc.precision == DINO_PREC_F64 ? p->r : (p->r + 31) / 32 * 32;
+}
+
+void launch_eval_propose_dual(dino_problem* p, int n, const double* x, const double* g, const void* B,
+                              const double* K, const double* logdet, const double* xi, double* xp, double* lfwd,
+                              hipStream_t st) {
+    const int ldb = jacobian_ld(p);
+    if (p->desc.precision == DINO_PREC_F64)
+        eval_propose_dual_t<double>(p, n, x, g, (const double*)B, ldb, K, logdet, xi, xp, lfwd, st);
+    else
+        eval_propose_dual_t<__hip_bfloat16>(p, n, x, g, (const __hip_bfloat16*)B, ldb, K, logdet, xi, xp, lfwd, st);
+}
+
+void launch_eval_log_rho_dual(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                              const void* B_x, const double* K_x, const double* logdet_x, const double* xp,
+                              const double* phi_p, const double* g_p, const void* B_p, const double* K_p,
+                              const double* logdet_p, double* out, hipStream_t st) {
+    const int ldb = jacobian_ld(p);
+    if (p->desc.precision == DINO_PREC_F64)
+        eval_log_rho_dual_t<double>(p, n, ldb, x, phi_x, g_x, (const double*)B_x, K_x, logdet_x, xp, phi_p, g_p,
+                                    (const double*)B_p, K_p, logdet_p, out, st);
+    else
+        eval_log_rho_dual_t<__hip_bfloat16>(p, n, ldb, x, phi_x, g_x, (const __hip_bfloat16*)B_x, K_x, logdet_x, xp,
+                                            phi_p, g_p, (const __hip_bfloat16*)B_p, K_p, logdet_p, out, st);
+}
+
+// The stored Jacobian of chains [0, n) as FP64 rows of r values (n x dy x r).
+template <typename TB>
+__global__ void jacobian_to_double_kernel(long total, int r, int ldb, const TB* __restrict__ B, double* __restrict__ out) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long row = e / r;
+        const int j = (int)(e - row * r);
+        out[e] = to_d(B[row * ldb + j]);
+    }
+}
+
+void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t st) {
+    const long total = (long)n * p->d_y * p->r;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 8192);
+    if (p->desc.precision == DINO_PREC_F64)
+        hipLaunchKernelGGL(jacobian_to_double_kernel<double>, dim3(blocks), dim3(256), 0, st, total, p->r, p->r,
+                           (const double*)p->Bj, out);
+    else
+        hipLaunchKernelGGL(jacobian_to_double_kernel<__hip_bfloat16>, dim3(blocks), dim3(256), 0, st, total, p->r,
+                           jacobian_ld(p), (const __hip_bfloat16*)p->B16, out);
     DINO_HIP(hipGetLastError());
 }
 

@@ -10,6 +10,7 @@
 
 namespace dino {
 
+
 static thread_local std::string g_error;
 
 void set_error(const std::string& msg) { g_error = msg; }
@@ -778,6 +779,9 @@ dino_status dino_set_fixed_metric(dino_problem* p, const double* x_map, const do
         for (int i = 0; i < r; ++i)
             for (int j = 0; j <= i; ++j) L[(size_t)i * r + j] = L_map[(long)i * r + j];
         DINO_HIP(hipSetDevice(p->ctx->device));
+        // steps still in flight on the problem's last stream read the fixed metric: let them
+        // finish before it is overwritten (the copies below run on the null stream)
+        if (p->last_stream) DINO_HIP(hipStreamSynchronize(p->last_stream));
         DINO_HIP(hipMemcpy(p->xmap, x_map, sizeof(double) * r, hipMemcpyHostToDevice));
         DINO_HIP(hipMemcpy(p->Lfix, L.data(), sizeof(double) * r * r, hipMemcpyHostToDevice));
         p->fixed_set = true;
@@ -978,6 +982,60 @@ dino_status dino_eval_log_rho(dino_problem* p, int n, const double* x, const dou
         DINO_HIP(hipSetDevice(p->ctx->device));
         hipStream_t st = as_stream(stream);
         launch_log_rho(p, n, x, phi_x, g_x, L_x, logdet_x, xp, phi_p, g_p, L_p, logdet_p, log_rho, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_eval_jacobian(dino_problem* p, int n, const double* x, double* B, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && B, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        stage_forward(p, n, x, p->f, st);
+        stage_jacobian(p, n, st);
+        launch_jacobian_to_double(p, n, B, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_jacobian_ld(const dino_problem* p, int32_t* ldb) {
+    return guarded([&] {
+        DINO_REQUIRE(p && ldb, DINO_EINVAL, "null argument");
+        *ldb = jacobian_ld(p);
+    });
+}
+
+dino_status dino_eval_propose_dual(dino_problem* p, int n, const double* x, const double* g, const void* B,
+                                   const double* K, const double* logdet, const double* xi, double* xp, double* lfwd,
+                                   void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && g && B && K && logdet && xi && xp && lfwd, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(p->dual, DINO_EINVAL, "dino_eval_propose_dual serves the dual form");
+        DINO_REQUIRE(p->desc.method == DINO_METHOD_MMALA, DINO_EINVAL, "dino_eval_propose_dual serves mMALA problems");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_eval_propose_dual(p, n, x, g, B, K, logdet, xi, xp, lfwd, st);
+        p->last_stream = st;
+    });
+}
+
+dino_status dino_eval_log_rho_dual(dino_problem* p, int n, const double* x, const double* phi_x, const double* g_x,
+                                   const void* B_x, const double* K_x, const double* logdet_x, const double* xp,
+                                   const double* phi_p, const double* g_p, const void* B_p, const double* K_p,
+                                   const double* logdet_p, double* log_rho, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && x && phi_x && g_x && B_x && K_x && logdet_x && xp && phi_p && g_p && B_p && K_p &&
+                         logdet_p && log_rho,
+                     DINO_EINVAL, "null argument");
+        DINO_REQUIRE(p->dual, DINO_EINVAL, "dino_eval_log_rho_dual serves the dual form");
+        DINO_REQUIRE(p->desc.method == DINO_METHOD_MMALA, DINO_EINVAL, "dino_eval_log_rho_dual serves mMALA problems");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_eval_log_rho_dual(p, n, x, phi_x, g_x, B_x, K_x, logdet_x, xp, phi_p, g_p, B_p, K_p, logdet_p, log_rho,
+                                 st);
         p->last_stream = st;
     });
 }

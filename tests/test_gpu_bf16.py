@@ -1,12 +1,15 @@
 """Mixed-precision path (FP32 forward, BF16 MFMA Jacobian / GN Hessian with FP32
-accumulation, FP64 factorisation and MH) against the FP64 oracle.
+accumulation, FP64 factorisation and MH) against the FP64 oracle, per chain.
 
-Tolerances derived from the arithmetic: the forward is FP32 (unit roundoff 6e-8, a
-few hundred accumulations: 1e-5 relative is generous); the Jacobian is a chain of
-BF16-operand products (unit roundoff 2^-8 = 3.9e-3 per rounded operand, random
-signs, a handful of layers), so B, g and H carry O(1e-2) relative error in
-Frobenius norm; 3e-2 is the bound used here and the measured values are printed.
-A wrong operand layout or permutation in the sweep gives O(1) errors.
+Bars derived from the arithmetic. The forward is FP32 (unit roundoff 6e-8, a few hundred
+accumulations: 1e-5 relative is generous). The Jacobian is a chain of about L + 2
+products whose operands are rounded to bfloat16 (unit roundoff u = 2^-8 = 3.9e-3): with
+randomly signed rounding errors each product adds ~0.8 u relative rms error to an output
+element, so a row of B, and g and H of a chain, carry ~sqrt(L + 2) * 0.8 u ~ 8e-3 rms at
+L = 4. Every row of B and every chain's g, H and factor is held to 3e-2 (about 4x that
+estimate): errors are compared per row or per chain, never through a norm over all
+chains, so an error confined to one wave's 32 Jacobian columns (one or two chains) shows
+at its own size. A wrong operand layout or permutation gives O(1) errors.
 """
 import numpy as np
 import pytest
@@ -18,8 +21,11 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def fro_rel(a, b):
-    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+def per_chain_rel(a, b):
+    """max over chains of |a_c - b_c| / |b_c| (Frobenius norms over each chain's entries)."""
+    a = np.asarray(a, dtype=np.float64).reshape(len(b), -1)
+    b = np.asarray(b, dtype=np.float64).reshape(len(b), -1)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
 
 
 def to_dev(a):
@@ -31,25 +37,40 @@ CASES = {
     "resnet-ragged": dict(name="tiny", chains=37, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
                           bias_scale=0.3, noise_scale=0.2),
     "mid": dict(name="mid", chains=64),
+    "mid-dual": dict(name="mid", chains=96, factorization="dual"),
 }
+
+BAR = 3e-2
 
 
 @pytest.mark.parametrize("key", list(CASES))
 def test_bf16_geometry_against_oracle(key):
     kw = dict(CASES[key])
+    fact = kw.pop("factorization", "primal")
     case = make_case(kw.pop("name"), **kw)
+    if fact == "dual":
+        case["prob"].factor = "dual"
     print(f"bf16 geometry {key}", flush=True)
-    ctx, p = device_problem(case, precision="bf16")
-    C, r = case["C"], case["w"].r
+    ctx, p = device_problem(case, precision="bf16", factorization=fact)
+    C, r, dy = case["C"], case["w"].r, case["prob"].d_y
     x = np.random.default_rng(3).standard_normal((C, r))
     got = {k: v.cpu().numpy() for k, v in p.eval_geometry(to_dev(x)).items()}
     ref = mcmc.geometry(case["prob"], x)
-    errs = dict(f=fro_rel(got["f"], ref.f), phi=float(np.max(np.abs(got["phi"] - ref.phi) / (1 + ref.phi))),
-                g=fro_rel(got["g"], ref.g), H=fro_rel(got["H"], ref.H),
-                L=fro_rel(np.tril(got["L"]), ref.L))
-    print(f"bf16 errors vs FP64 oracle ({key}): " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    if fact == "dual":
+        K = got["L"].reshape(C, -1)[:, : dy * dy].reshape(C, dy, dy)
+        Kref = np.linalg.cholesky(np.eye(dy)[None] + np.einsum("cir,ckr->cik", ref.B, ref.B))
+        e_fac = per_chain_rel(np.tril(K), Kref)
+    else:
+        e_fac = per_chain_rel(np.tril(got["L"]), ref.L)
+    B = p.eval_jacobian(to_dev(x)).cpu().numpy()
+    e_rows = np.linalg.norm(B - ref.B, axis=2) / np.linalg.norm(ref.B, axis=2)   # (C, d_y)
+    errs = dict(f=per_chain_rel(got["f"], ref.f), phi=float(np.max(np.abs(got["phi"] - ref.phi) / (1 + ref.phi))),
+                B_row=float(e_rows.max()), g=per_chain_rel(got["g"], ref.g), H=per_chain_rel(got["H"], ref.H),
+                factor=e_fac)
+    print(f"bf16 per-chain max errors vs FP64 oracle ({key}): " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items())
+          + f"; B row error rms {np.sqrt(np.mean(e_rows ** 2)):.2e}", flush=True)
     assert errs["f"] < 1e-5 and errs["phi"] < 1e-4
-    assert errs["g"] < 3e-2 and errs["H"] < 3e-2 and errs["L"] < 3e-2
+    assert errs["B_row"] < BAR and errs["g"] < BAR and errs["H"] < BAR and errs["factor"] < BAR
     assert np.all(got["ok"] == 1)
     p.close()
     ctx.close()

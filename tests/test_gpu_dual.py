@@ -100,9 +100,9 @@ def test_dual_bf16_against_oracle():
     dy = case["prob"].d_y
     K = got["L"].reshape(64, -1)[:, : dy * dy].reshape(64, dy, dy)
     Kref = np.linalg.cholesky(np.eye(dy)[None] + np.einsum("cir,ckr->cik", ref.B, ref.B))
-    eK = float(np.linalg.norm(np.tril(K) - Kref) / np.linalg.norm(Kref))
-    print(f"bf16 dual factor rel err {eK:.2e}", flush=True)
-    assert eK < 3e-2
+    eK = np.linalg.norm((np.tril(K) - Kref).reshape(64, -1), axis=1) / np.linalg.norm(Kref.reshape(64, -1), axis=1)
+    print(f"bf16 dual factor per-chain max rel err {eK.max():.2e}", flush=True)
+    assert eK.max() < 3e-2  # per chain; the bar is derived in test_gpu_bf16.py
     p.init(case["x0"], case["z0"])
     p.step(60)
     acc, fail, _ = p.diagnostics()

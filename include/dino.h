@@ -325,6 +325,19 @@ dino_status dino_encode(dino_ctx* ctx, int n_fields, const double* fields, doubl
 dino_status dino_decode(dino_ctx* ctx, int n_fields, const double* x, const double* z_perp, double* fields,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): dino_encode without any allocation.
+ * Same arguments, layouts and results as dino_encode; its two transform buffers live in
+ * a library-owned static device buffer of DINO_NOALLOC_SCRATCH_BYTES per GPU (held until
+ * the process ends), so 2 * n_fields * d_m * sizeof(double) must not exceed it (else
+ * DINO_EINVAL, e.g. at most 63 fields on a 129 x 129 grid). The call is asynchronous on
+ * stream and does not synchronise it. Every call on one GPU shares that GPU's buffer:
+ * calls that overlap on one GPU (other streams, other threads, other contexts) race and
+ * must be ordered by the caller. */
+#define DINO_NOALLOC_SCRATCH_BYTES (16u << 20)
+dino_status dino_encode_noalloc(dino_ctx* ctx, int n_fields, const double* fields, double* x, double* z_perp,
+                                void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of many inverse problems (one problem = one request:
  * its own data y, noise variances, observation count, chain count and step budget)

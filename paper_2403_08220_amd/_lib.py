@@ -122,6 +122,7 @@ SIGNATURES = {
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),
     "dino_encode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),
     "dino_decode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),
+    "dino_encode_noalloc": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),
     "dino_server_create": (ct.c_int32, [_P, ct.POINTER(ServerCfg), ct.POINTER(_P)]),
     "dino_server_destroy": (ct.c_int32, [_P]),
     "dino_server_clock": (ct.c_int32, [_P, ct.POINTER(ct.c_double)]),

@@ -4,12 +4,36 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <numeric>
 
 #include "dino_internal.hpp"
 
 namespace dino {
 
+// Scratch of the allocation-free encode (dino_encode_noalloc): two transform buffers of
+// n_fields x d_m doubles each. Host code never uses the array's name as an address: the
+// device address of each GPU's copy is taken once per device by hipGetSymbolAddress
+// (init_noalloc_scratch, from dino_ctx_create) and kept in g_scratch_ptr.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(16) << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// With `device` current: the device address of that device's scratch.
+static double* init_noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    DINO_REQUIRE(device >= 0 && device < MAX_DEVICES, DINO_EINVAL, "device ordinal beyond the scratch table");
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        DINO_REQUIRE(e == hipSuccess && ptr, DINO_EDEVICE,
+                     std::string("hipGetSymbolAddress of the encode scratch failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[device];
+}
 
 static thread_local std::string g_error;
 
@@ -248,6 +272,7 @@ dino_status dino_ctx_create(int device, dino_ctx** out) {
         DINO_HIP(hipGetDeviceCount(&count));
         DINO_REQUIRE(device >= 0 && device < count, DINO_EINVAL, "device ordinal out of range");
         DINO_HIP(hipSetDevice(device));
+        init_noalloc_scratch(device);
         auto* c = new dino_ctx();
         c->device = device;
         *out = c;
@@ -348,6 +373,22 @@ dino_status dino_encode(dino_ctx* ctx, int n_fields, const double* fields, doubl
         (void)hipFree(t1);
         (void)hipFree(t2);
         DINO_HIP(e);
+    });
+}
+
+dino_status dino_encode_noalloc(dino_ctx* ctx, int n_fields, const double* fields, double* x, double* z_perp,
+                                void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && ctx->basis.r > 0, DINO_ESTATE, "no prior loaded");
+        DINO_REQUIRE(n_fields >= 1 && n_fields <= 65535 && fields && (x || z_perp), DINO_EINVAL, "bad arguments");
+        const size_t nn = (size_t)ctx->basis.d_m * n_fields;
+        DINO_REQUIRE(2 * nn * sizeof(double) <= NOALLOC_SCRATCH_BYTES, DINO_EINVAL,
+                     "n_fields x d_m too large for the encode scratch (2 n_fields d_m doubles must fit in " +
+                         std::to_string(NOALLOC_SCRATCH_BYTES >> 20) + " MiB)");
+        DINO_HIP(hipSetDevice(ctx->device));
+        double* t1 = g_scratch_ptr[ctx->device];  // set by dino_ctx_create on this device
+        DINO_REQUIRE(t1, DINO_ESTATE, "encode scratch not initialised on this device");
+        launch_encode(ctx->basis, n_fields, fields, x, z_perp, t1, t1 + nn, as_stream(stream));
     });
 }
 

@@ -94,6 +94,18 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
                               const int32_t* fan_in, const double* const* W, const double* const* b);
 
 /* ---------------------------------------------------------------------------
+ * True model of delayed acceptance (Alg. 1 second stage; Sec. 2.5): the paper's true
+ * parameter-to-observable map is a PDE solve, out of scope here; its stand-in is a second
+ * network with the layer format of dino_load_network whose input is the first r_T
+ * whitened KLE coordinates of the full parameter, (x, z_perp[0 : r_T - r]) with
+ * r <= r_T <= d_m (checked when a DA_MMALA problem is created). A problem observes its
+ * first d_y outputs with the problem's noise variances. It runs in FP64 on DINO_PREC_F64
+ * problems and in FP32 on DINO_PREC_BF16 problems. Replaces a previously loaded one.
+ */
+dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kinds, const int32_t* fan_out,
+                                 const int32_t* fan_in, const double* const* W, const double* const* b);
+
+/* ---------------------------------------------------------------------------
  * Problem: one inverse problem (data y, noise, step size) with n_chains chains.
  *
  * precision:
@@ -146,11 +158,20 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
  *   + (|L^T (x+ - x_map)|^2 - |L^T (x - x_map)|^2)/2. The printed proposal mean
  *   m_MAP - s m is read as m_MAP + s (m - m_MAP): only that form is reversible with
  *   respect to the Laplace approximation. A step evaluates the network forward only.
- * PCN, MALA and LAPCN are not available to the serving pools. */
+ * DA_MMALA: delayed acceptance (Alg. 1 with its second stage; Sec. 2.5, eq. da_dino_trr_2):
+ *   the MMALA first stage, then, for the proposals it passes, the full proposal (x+ and the
+ *   pCN move of the complement, drawn only then) judged by the true misfit Phi of the true
+ *   model loaded with dino_load_true_model: log rho^(2) = (Phi~(x+) - Phi~(x)) +
+ *   (Phi(m) - Phi(m+)), accepted iff log u2 <= log rho^(2) with u2 word 0 of block 0 of
+ *   Philox stream 5 at (step, chain). The state keeps its true misfit. The true model runs
+ *   on the first-stage passes only (compacted). Needs track_complement when the true model
+ *   reads complement coordinates.
+ * PCN, MALA, LAPCN and DA_MMALA are not available to the serving pools. */
 #define DINO_METHOD_MMALA 0
 #define DINO_METHOD_PCN 1
 #define DINO_METHOD_MALA 2
 #define DINO_METHOD_LAPCN 3
+#define DINO_METHOD_DA_MMALA 4
 typedef struct {
     int32_t n_chains;
     int32_t d_y;
@@ -210,6 +231,16 @@ dino_status dino_read_cache(dino_problem* p, double* phi, double* g, double* L);
  * steps taken. Any pointer may be NULL. */
 dino_status dino_read_diagnostics(dino_problem* p, int64_t* accepts, int64_t* failures, int64_t* steps);
 
+/* Delayed acceptance: host copies of the true misfit of the current states (n_chains) and
+ * of the first-stage passes per chain since init (the true-model evaluations). EINVAL
+ * unless the problem's method is DINO_METHOD_DA_MMALA. */
+dino_status dino_read_delayed(dino_problem* p, double* phi_true, int64_t* passes);
+
+/* Delayed acceptance: the true misfit (n) of n full parameters given as the r_T
+ * coordinates the true model reads (device, n x r_T FP64), evaluated as the second stage
+ * evaluates it. EINVAL unless the method is DINO_METHOD_DA_MMALA. */
+dino_status dino_eval_true_misfit(dino_problem* p, int n, const double* z_in, double* phi_true, void* stream);
+
 /* Recorded trace: x_trace (steps x n_chains x r FP32) and phi_trace
  * (steps x n_chains FP64) for the min(steps, trace_capacity) first steps. */
 dino_status dino_read_trace(dino_problem* p, float* x_trace, double* phi_trace, int64_t* n_recorded);
@@ -233,13 +264,13 @@ dino_status dino_ess(dino_problem* p, int burn_in, double* ess);
  * back (one host wait) when it fills or when the profile is read (slower;
  * meant for measurement passes). Stages: 0 proposal, 1 surrogate forward,
  * 2 reduced Jacobian, 3 misfit and ppg, 4 GN Hessian, 5 Cholesky,
- * 6 acceptance, 7 complement, 8 trace. stage_ms: total milliseconds per stage;
+ * 6 acceptance, 7 second stage (delayed acceptance), 8 complement, 9 trace. stage_ms: total milliseconds per stage;
  * launches: kernel launches per stage per step (0 where the stage's work runs
  * inside another stage's kernel: the misfit on the BF16 path, in the GN
  * kernel; the trace and step counters, in the acceptance kernel); steps:
  * profiled steps.
  */
-#define DINO_N_STAGES 9
+#define DINO_N_STAGES 10
 dino_status dino_set_profiling(dino_problem* p, int enable);
 dino_status dino_read_profile(dino_problem* p, double* stage_ms, int32_t* launches, int64_t* steps);
 const char* dino_stage_name(int stage);

@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
-METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3}
+METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4}
 
 
 class DinoError(RuntimeError):
@@ -97,6 +97,9 @@ SIGNATURES = {
     "dino_load_prior": (ct.c_int32, [_P, ct.c_int, ct.c_double, ct.c_double, ct.c_int]),
     "dino_read_basis": (ct.c_int32, [_P, _D, _D, _D, _I32]),
     "dino_load_network": (ct.c_int32, [_P, ct.c_int, _I32, _I32, _I32, ct.POINTER(_D), ct.POINTER(_D)]),
+    "dino_load_true_model": (ct.c_int32, [_P, ct.c_int, _I32, _I32, _I32, ct.POINTER(_D), ct.POINTER(_D)]),
+    "dino_read_delayed": (ct.c_int32, [_P, _D, _I64]),
+    "dino_eval_true_misfit": (ct.c_int32, [_P, ct.c_int, _P, _P, _P]),
     "dino_problem_workspace_bytes": (ct.c_int32, [_P, ct.POINTER(ProblemDesc), ct.POINTER(ct.c_size_t)]),
     "dino_problem_create": (ct.c_int32, [_P, ct.POINTER(ProblemDesc), _D, _D, _P, ct.c_size_t, ct.POINTER(_P)]),
     "dino_problem_destroy": (ct.c_int32, [_P]),
@@ -132,7 +135,7 @@ SIGNATURES = {
     "dino_server_stats": (ct.c_int32, [_P, _I64, _I64, _I64]),
 }
 
-N_STAGES = 9
+N_STAGES = 10
 
 _lib = None
 

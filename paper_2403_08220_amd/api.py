@@ -82,6 +82,14 @@ class Context:
 
     def load_network(self, layers):
         """layers: list of (kind, W (fan_out x fan_in), b) with kind in linear/act/resid."""
+        self._load_layers(self.lib.dino_load_network, layers)
+
+    def load_true_model(self, layers):
+        """The true-model stand-in of delayed acceptance (same layer format; its input is the
+        first r_T whitened coordinates of the full parameter)."""
+        self._load_layers(self.lib.dino_load_true_model, layers, true_model=True)
+
+    def _load_layers(self, fn, layers, true_model=False):
         L = len(layers)
         kinds = np.array([_lib.LAYER_KINDS[k] for k, _, _ in layers], dtype=np.int32)
         Ws = [np.ascontiguousarray(W, dtype=np.float64) for _, W, _ in layers]
@@ -91,9 +99,11 @@ class Context:
         fi = np.array([W.shape[1] for W in Ws], dtype=np.int32)
         Wp = (_lib._D * L)(*[dptr(W) for W in Ws])
         bp = (_lib._D * L)(*[dptr(b) for b in bs])
-        check(self.lib.dino_load_network(self.h, L, i32ptr(kinds), i32ptr(fo), i32ptr(fi), Wp, bp))
-        self.d_out = int(fo[-1])
-        self._layers_keepalive = (Ws, bs)
+        check(fn(self.h, L, i32ptr(kinds), i32ptr(fo), i32ptr(fi), Wp, bp))
+        if true_model:
+            self.true_r_in = int(fi[0])
+        else:
+            self.d_out = int(fo[-1])
 
 
 class Problem:
@@ -195,6 +205,20 @@ class Problem:
         s = np.empty(1, dtype=np.int64)
         check(self.lib.dino_read_diagnostics(self.h, i64ptr(a), i64ptr(f), i64ptr(s)))
         return a, f, int(s[0])
+
+    def delayed(self):
+        """Delayed acceptance: true misfit of the current states and first-stage passes per chain."""
+        phi = np.empty(self.C)
+        passes = np.empty(self.C, dtype=np.int64)
+        check(self.lib.dino_read_delayed(self.h, dptr(phi), i64ptr(passes)))
+        return phi, passes
+
+    def eval_true_misfit(self, z_in, stream=None):
+        """True misfit of device rows z_in (n, r_T) float64."""
+        torch = _torch()
+        out = torch.empty(z_in.shape[0], dtype=torch.float64, device=z_in.device)
+        check(self.lib.dino_eval_true_misfit(self.h, z_in.shape[0], _tp(z_in), _tp(out), _stream_handle(stream)))
+        return out
 
     def trace(self):
         n = np.empty(1, dtype=np.int64)

@@ -71,7 +71,14 @@ inline dino_status guarded_call(F&& fn) {
 // key (seed, request id). Both the oracle and the kernels implement it from that
 // definition; streams: 0 proposal normals, 1 complement normals, 2 MH uniform,
 // 3 initial x, 4 initial z.
-enum : int { STREAM_XI = 0, STREAM_COMPLEMENT = 1, STREAM_UNIFORM = 2, STREAM_INIT_X = 3, STREAM_INIT_Z = 4 };
+enum : int {
+    STREAM_XI = 0,
+    STREAM_COMPLEMENT = 1,
+    STREAM_UNIFORM = 2,
+    STREAM_INIT_X = 3,
+    STREAM_INIT_Z = 4,
+    STREAM_UNIFORM2 = 5  // the second-stage uniform of delayed acceptance
+};
 
 constexpr uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ull;
 constexpr uint64_t PHILOX_M1 = 0xCA5A826395121157ull;
@@ -123,6 +130,20 @@ __device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t rid, ui
     uint64_t c[4] = {0, (uint64_t)STREAM_UNIFORM, step, chain};
     philox4x64(c, seed, rid);
     return philox_u01(c[0]);
+}
+
+// Word 0 of block 0 of `stream` at (step, chain) as a uniform in (0, 1).
+__device__ __forceinline__ double philox_uniform_stream(uint64_t seed, uint64_t rid, int stream, uint64_t step,
+                                                        uint64_t chain) {
+    uint64_t c[4] = {0, (uint64_t)stream, step, chain};
+    philox4x64(c, seed, rid);
+    return philox_u01(c[0]);
+}
+
+// The pCN move of one FP32 complement coordinate, z+ = s z + beta zeta, rounded to FP32;
+// every kernel that forms z+ uses this one expression, so they agree bit for bit.
+__device__ __forceinline__ float pcn_move(float z, double zeta, double s, double beta) {
+    return (float)fma(beta, zeta, s * (double)z);
 }
 
 // ----------------------------------------------------------------------------------
@@ -190,6 +211,10 @@ struct dino_ctx {
     __hip_bfloat16* sweep_tiles = nullptr;  // BF16 W^T tiles of the reverse sweep, in work-item order
     const float* sweep_ones = nullptr;      // 32 * nmb FP32 ones after the tiles (same allocation)
     const float* sweep_wout = nullptr;      // output layer rows in the sweep's register order (same allocation)
+    // true-model stand-in of delayed acceptance: a network on the first r_T whitened
+    // coordinates of the full parameter (FP64 and FP32 copies)
+    std::vector<dino::Layer> true_layers;
+    int true_r_in = 0, true_d_out = 0, true_max_width = 0;
 };
 
 namespace dino {
@@ -270,6 +295,21 @@ struct dino_problem {
     int kdim = 0;                   // order of the factorised matrix: r, or d_y in the dual form
     __hip_bfloat16* Bs16 = nullptr; // C x d_y x ldb (mixed path)
     double* Bs64 = nullptr;         // C x d_y x r (FP64 path)
+    // delayed acceptance (DINO_METHOD_DA_MMALA): true misfit of the states, compacted
+    // full-proposal rows of the first-stage passes, true-model activations and outputs
+    bool da = false;
+    int rT = 0;               // true-model input width: r + the complement coordinates it reads
+    double* phit = nullptr;   // C: true misfit of the states
+    int64_t* passes = nullptr;// C: first-stage passes (true-model evaluations)
+    int32_t* pos = nullptr;   // C: compacted row of a passing chain, -1 otherwise
+    int32_t* npass = nullptr; // 1: rows in the compacted batch
+    double* zin = nullptr;    // C x rT full-proposal coordinates the true model reads
+    double* th0 = nullptr;    // C x wT true-model activations (FP64 path)
+    double* th1 = nullptr;
+    double* fT64 = nullptr;   // C x d_y true outputs (FP64 path)
+    float* th0f = nullptr;    // mixed path
+    float* th1f = nullptr;
+    float* fT32 = nullptr;
     // trace
     float* xtrace = nullptr;  // capacity x C x r
     double* phitrace = nullptr;
@@ -341,6 +381,12 @@ void launch_eval_log_rho_dual(dino_problem* p, int n, const double* x, const dou
                               const double* phi_p, const double* g_p, const void* B_p, const double* K_p,
                               const double* logdet_p, double* out, hipStream_t st);
 void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t st);
+// delayed acceptance (kernels_geometry.hip, kernels_chain.hip)
+void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m_dev, hipStream_t st);
+void launch_da_gather(dino_problem* p, int n, hipStream_t st);
+void launch_da_init(dino_problem* p, int n, hipStream_t st);
+void launch_da_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st);
 // Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
 // no separate misfit launch).
 void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,

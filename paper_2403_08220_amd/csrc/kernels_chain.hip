@@ -856,7 +856,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                                                      int32_t* cur, const double* xp, const double* gp,
                                                      const double* phip, const double* logdetp,
                                                      const int32_t* okp, const double* lfwd, int64_t* accepts,
-                                                     int64_t* failures, int32_t* accflag, StepRecord rec) {
+                                                     int64_t* failures, int32_t* accflag, StepRecord rec, int da) {
     extern __shared__ double dyn[];
     const ChainLds S = carve_chain_lds(dyn, r);
     double *xs = S.v[0], *ps = S.v[1], *ga = S.v[2];
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        record_idle(c, r, x, phi, rec);
+        if (!da) record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -900,17 +900,23 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = okc && isfinite(lr);
             const bool accept = good && (log(u) <= lr);
-            decision = accept ? 1 : 0;
             if (!good) failures[c] += 1;
             phin = phi[c];
-            if (accept) {
-                accepts[c] += 1;
-                phin = phip[c];
-                phi[c] = phin;
-                logdet[c] = logdetp[c];
-                cur[c] = other;
+            if (da) {
+                // delayed acceptance: a pass goes to the second stage, which commits
+                decision = 0;
+                accflag[c] = accept ? 3 : 0;
+            } else {
+                decision = accept ? 1 : 0;
+                if (accept) {
+                    accepts[c] += 1;
+                    phin = phip[c];
+                    phi[c] = phin;
+                    logdet[c] = logdetp[c];
+                    cur[c] = other;
+                }
+                accflag[c] = decision;
             }
-            accflag[c] = decision;
         }
     }
     __syncthreads();
@@ -920,7 +926,7 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             g[(long)c * r + j] = ga[j];
         }
     }
-    finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
+    if (!da) finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1573,7 +1579,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
                         double* phi, double* logdet, const double* Kbuf, long half, int32_t* cur, const double* xp,
                         const double* gp, const double* phip, const double* logdetp, const int32_t* okp,
                         const double* lfwd, const TB* __restrict__ Bp, TB* __restrict__ Bs, int64_t* accepts,
-                        int64_t* failures, int32_t* accflag, StepRecord rec) {
+                        int64_t* failures, int32_t* accflag, StepRecord rec, int da) {
     extern __shared__ double dyn[];
     double* R = dyn;
     double *xs = R, *ps = R + r, *ga = R + 2 * r, *v = R + 3 * r, *mh = R + 4 * r;
@@ -1587,7 +1593,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        record_idle(c, r, x, phi, rec);
+        if (!da) record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -1627,17 +1633,23 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = okc && isfinite(lr);
             const bool accept = good && (log(u) <= lr);
-            decision = accept ? 1 : 0;
             if (!good) failures[c] += 1;
             phin = phi[c];
-            if (accept) {
-                accepts[c] += 1;
-                phin = phip[c];
-                phi[c] = phin;
-                logdet[c] = logdetp[c];
-                cur[c] = other;
+            if (da) {
+                // delayed acceptance: a pass goes to the second stage, which commits
+                decision = 0;
+                accflag[c] = accept ? 3 : 0;
+            } else {
+                decision = accept ? 1 : 0;
+                if (accept) {
+                    accepts[c] += 1;
+                    phin = phip[c];
+                    phi[c] = phin;
+                    logdet[c] = logdetp[c];
+                    cur[c] = other;
+                }
+                accflag[c] = decision;
             }
-            accflag[c] = decision;
         }
     }
     __syncthreads();
@@ -1657,7 +1669,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
             for (long e = tid; e < (long)dy * ldb; e += TPB) Bsc[e] = Bpg[e];
         }
     }
-    finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
+    if (!da) finish_chain(c, r, meta, state, step, decision ? ps : xs, phin, rec);
 }
 
 // log rho^(1) of the dual form at given states and caches (the stage entry point): the
@@ -1701,6 +1713,167 @@ void log_rho_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
 }
 
+// ---------------------------------------------------------------------------------
+// Delayed acceptance: the second stage of Alg. 1 (eq. da_dino_trr_2). The first-stage
+// acceptance kernel marks a pass with accflag 3 and commits nothing; the passes are
+// compacted into the first rows of a batch, the true-model stand-in runs on those rows
+// only (its launches skip row tiles past the count), and the second-stage kernel
+// decides, commits and ends every chain's step. The complement kernel then moves the
+// complement of the committed chains with the draws the gather used.
+
+// One wave per chain: a pass takes the next batch row and writes the coordinates the
+// true model reads: x+ and the pCN move of the first rT - r complement coordinates (the
+// complement kernel's draws and expression, so the true model sees the state a commit
+// leaves). Chains that did not pass get pos -1.
+__global__ __launch_bounds__(64) void da_gather_kernel(int r, int rT, int ldz, double s, double beta, ChainMeta meta,
+                                                       const int32_t* __restrict__ accflag, const double* __restrict__ xp,
+                                                       const float* __restrict__ z, int32_t* npass,
+                                                       int32_t* __restrict__ pos, double* __restrict__ zin) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    __shared__ int slot;
+    if (accflag[c] != 3) {
+        if (tid == 0) pos[c] = -1;
+        return;
+    }
+    if (tid == 0) {
+        slot = atomicAdd(npass, 1);
+        pos[c] = slot;
+    }
+    __syncthreads();
+    double* row = zin + (long)slot * rT;
+    for (int j = tid; j < r; j += 64) row[j] = xp[(long)c * r + j];
+    const int extra = rT - r;
+    if (extra > 0) {
+        const float* zc = z + (long)c * ldz;
+        const uint64_t k0 = meta.key0[c], k1 = meta.key1[c];
+        const uint64_t step = (uint64_t)meta.step[c], chain = (uint64_t)meta.index[c];
+        for (int b4 = tid; 4 * b4 < extra; b4 += 64) {
+            double nv[4];
+            philox_normals4(k0, k1, (uint64_t)b4, STREAM_COMPLEMENT, step, chain, nv);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * b4 + q;
+                if (k < extra) row[r + k] = (double)pcn_move(zc[k], nv[q], s, beta);
+            }
+        }
+    }
+}
+
+// The true model's input rows at the states themselves (chain initialisation): row c of
+// the batch is chain c; the batch holds all n chains.
+__global__ __launch_bounds__(64) void da_init_kernel(int n, int r, int rT, int ldz, const double* __restrict__ x,
+                                                     const float* __restrict__ z, int32_t* npass,
+                                                     int32_t* __restrict__ pos, double* __restrict__ zin) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) {
+        pos[c] = c;
+        if (c == 0) *npass = n;
+    }
+    double* row = zin + (long)c * rT;
+    for (int j = tid; j < r; j += 64) row[j] = x[(long)c * r + j];
+    for (int k = tid; k < rT - r; k += 64) row[r + k] = (double)z[(long)c * ldz + k];
+}
+
+// True misfit Phi = 1/2 |Gamma^-1/2 (y - f_T)|^2 of chain c from batch row pos[c] (pos
+// null: row c); with npass_reset, the batch count is cleared for the next step.
+template <typename TF>
+__global__ __launch_bounds__(64) void true_misfit_kernel(int dy, ChainMeta meta, const TF* __restrict__ fT,
+                                                         const int32_t* __restrict__ pos, const double* __restrict__ y,
+                                                         const double* __restrict__ winv, double* __restrict__ out,
+                                                         int32_t* npass_reset) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    const long pr = pos ? pos[c] : c;
+    const long rq = meta.row ? meta.row[c] : 0;
+    double a = 0.0;
+    for (int i = tid; i < dy; i += 64) {
+        const double e = (y[rq * dy + i] - (double)fT[pr * dy + i]) * winv[rq * dy + i];
+        a += e * e;
+    }
+    a = wave_sum(a);
+    if (tid == 0) {
+        out[c] = 0.5 * a;
+        if (c == 0 && npass_reset) *npass_reset = 0;
+    }
+}
+
+// Second stage: for a pass, the true misfit at the full proposal (batch row pos[c]),
+// log rho^(2) = (Phi~(x+) - Phi~(x)) + (Phi(m) - Phi(m+)) and the decision with the
+// uniform of stream 5; a commit takes the proposal and its caches (factor half flip, the
+// proposal's B in the dual form, the true misfit). Every chain's step ends here (trace
+// row, running sums, step counter). accflag leaves 1 for committed moves (the complement
+// kernel moves them) and 0 otherwise.
+template <typename TB, typename TF>
+__global__ __launch_bounds__(TPB) void da_accept_kernel(int r, int dy, long bcount, ChainMeta meta, double* x, double* g,
+                                                        double* phi, double* logdet, int32_t* cur, const double* xp,
+                                                        const double* gp, const double* phip, const double* logdetp,
+                                                        const TF* __restrict__ fT, const double* __restrict__ y,
+                                                        const double* __restrict__ winv, double* phit,
+                                                        int32_t* accflag, const int32_t* __restrict__ pos,
+                                                        int32_t* npass, int64_t* accepts, int64_t* failures,
+                                                        int64_t* passes, const TB* __restrict__ Bp, TB* __restrict__ Bs,
+                                                        StepRecord rec) {
+    __shared__ int decision;
+    __shared__ double red[TPB / 64];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    if (c == 0 && tid == 0) *npass = 0;  // this step's batch has been evaluated
+    const int32_t state = chain_state(meta, c);
+    if (state == CHAIN_IDLE) {
+        record_idle(c, r, x, phi, rec);
+        return;
+    }
+    const int64_t step = meta.step[c];  // read by every thread before the finish advances it
+    const int flag = accflag[c];
+    double phin = 0.0;
+    if (flag == 3) {
+        const long pr = pos[c];
+        const long rq = meta.row ? meta.row[c] : 0;
+        double a = 0.0;
+        for (int i = tid; i < dy; i += TPB) {
+            const double e = (y[rq * dy + i] - (double)fT[pr * dy + i]) * winv[rq * dy + i];
+            a += e * e;
+        }
+        a = block_sum(a, red);
+        if (tid == 0) {
+            const double phitp = 0.5 * a;
+            const double lr2 = (phip[c] - phi[c]) + (phit[c] - phitp);
+            const double u2 = philox_uniform_stream(meta.key0[c], meta.key1[c], STREAM_UNIFORM2, (uint64_t)step,
+                                                    (uint64_t)meta.index[c]);
+            const bool good = isfinite(lr2);
+            const bool accept = good && (log(u2) <= lr2);
+            passes[c] += 1;
+            if (!good) failures[c] += 1;
+            phin = phi[c];
+            if (accept) {
+                accepts[c] += 1;
+                phin = phip[c];
+                phi[c] = phin;
+                logdet[c] = logdetp[c];
+                cur[c] ^= 1;
+                phit[c] = phitp;
+            }
+            decision = accept ? 1 : 0;
+            accflag[c] = decision;
+        }
+        __syncthreads();
+        if (decision) {
+            for (int j = tid; j < r; j += TPB) {
+                x[(long)c * r + j] = xp[(long)c * r + j];
+                g[(long)c * r + j] = gp[(long)c * r + j];
+            }
+            if (Bs)
+                for (long e = tid; e < bcount; e += TPB) Bs[(long)c * bcount + e] = Bp[(long)c * bcount + e];
+        }
+    } else {
+        // rejected in the first stage (or a fresh chain, committed there)
+        if (tid == 0) {
+            phin = phi[c];
+            decision = flag == 2 ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    finish_chain(c, r, meta, state, step, decision ? xp + (long)c * r : x + (long)c * r, phin, rec);
+}
+
 // Copies the Jacobian of every chain (n x dy x ldb values) into the state's buffer.
 template <typename TB>
 __global__ void copy_b_kernel(long count, const TB* __restrict__ src, TB* __restrict__ dst) {
@@ -1736,13 +1909,13 @@ __global__ __launch_bounds__(TPB) void complement_kernel(int nbx, int d_perp, in
                     (uint64_t)meta.index[c], nv);
     if (j0 + 3 < d_perp) {
         float4 v = *reinterpret_cast<const float4*>(zc + j0);
-        v.x = (float)(s * (double)v.x + beta * nv[0]);
-        v.y = (float)(s * (double)v.y + beta * nv[1]);
-        v.z = (float)(s * (double)v.z + beta * nv[2]);
-        v.w = (float)(s * (double)v.w + beta * nv[3]);
+        v.x = pcn_move(v.x, nv[0], s, beta);
+        v.y = pcn_move(v.y, nv[1], s, beta);
+        v.z = pcn_move(v.z, nv[2], s, beta);
+        v.w = pcn_move(v.w, nv[3], s, beta);
         *reinterpret_cast<float4*>(zc + j0) = v;
     } else {
-        for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = (float)(s * (double)zc[j0 + q] + beta * nv[q]);
+        for (int q = 0; q < 4 && j0 + q < d_perp; ++q) zc[j0 + q] = pcn_move(zc[j0 + q], nv[q], s, beta);
     }
 }
 
@@ -1894,7 +2067,8 @@ void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
     const long half = (long)p->C * p->r * p->r;
     hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s, p->beta,
                        p->meta, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip,
-                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p, trace_row));
+                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p, trace_row),
+                       p->da ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
 
@@ -2049,7 +2223,7 @@ static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb,
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, p->phi, p->logdet,
                        p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp, p->lfwd, Bp, Bs,
-                       p->accepts, p->failures, p->acc, step_record(p, trace_row));
+                       p->accepts, p->failures, p->acc, step_record(p, trace_row), p->da ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
 
@@ -2061,6 +2235,54 @@ void launch_propose_dual(dino_problem* p, int n, hipStream_t st) {
 void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
     if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, trace_row, st);
     else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, trace_row, st);
+}
+
+void launch_da_gather(dino_problem* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(da_gather_kernel, dim3(n), dim3(64), 0, st, p->r, p->rT, p->z ? ldz_of(p->d_perp) : 0, p->s,
+                       p->beta, p->meta, p->acc, p->xp, p->z, p->npass, p->pos, p->zin);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64)
+        hipLaunchKernelGGL(true_misfit_kernel<double>, dim3(n), dim3(64), 0, st, p->d_y, p->meta, p->fT64,
+                           (const int32_t*)nullptr, p->y, p->winv, out, (int32_t*)nullptr);
+    else
+        hipLaunchKernelGGL(true_misfit_kernel<float>, dim3(n), dim3(64), 0, st, p->d_y, p->meta, p->fT32,
+                           (const int32_t*)nullptr, p->y, p->winv, out, (int32_t*)nullptr);
+    DINO_HIP(hipGetLastError());
+}
+
+// The true misfit of the states of chains [0, n) (initialisation).
+void launch_da_init(dino_problem* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(da_init_kernel, dim3(n), dim3(64), 0, st, n, p->r, p->rT, p->z ? ldz_of(p->d_perp) : 0, p->x,
+                       p->z, p->npass, p->pos, p->zin);
+    launch_true_forward(p, n, p->zin, p->npass, st);
+    if (p->desc.precision == DINO_PREC_F64)
+        hipLaunchKernelGGL(true_misfit_kernel<double>, dim3(n), dim3(64), 0, st, p->d_y, p->meta, p->fT64, p->pos, p->y,
+                           p->winv, p->phit, p->npass);
+    else
+        hipLaunchKernelGGL(true_misfit_kernel<float>, dim3(n), dim3(64), 0, st, p->d_y, p->meta, p->fT32, p->pos, p->y,
+                           p->winv, p->phit, p->npass);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_da_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+    const StepRecord rec = step_record(p, trace_row);
+    if (p->desc.precision == DINO_PREC_F64) {
+        const long bc = (long)p->d_y * p->r;
+        hipLaunchKernelGGL((da_accept_kernel<double, double>), dim3(n), dim3(TPB), 0, st, p->r, p->d_y, bc, p->meta,
+                           p->x, p->g, p->phi, p->logdet, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->fT64, p->y,
+                           p->winv, p->phit, p->acc, p->pos, p->npass, p->accepts, p->failures, p->passes,
+                           (const double*)(p->dual ? p->Bj : nullptr), p->dual ? p->Bs64 : nullptr, rec);
+    } else {
+        const long bc = (long)p->d_y * jacobian_ld(p);
+        hipLaunchKernelGGL((da_accept_kernel<__hip_bfloat16, float>), dim3(n), dim3(TPB), 0, st, p->r, p->d_y, bc,
+                           p->meta, p->x, p->g, p->phi, p->logdet, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->fT32,
+                           p->y, p->winv, p->phit, p->acc, p->pos, p->npass, p->accepts, p->failures, p->passes,
+                           (const __hip_bfloat16*)(p->dual ? p->B16 : nullptr), p->dual ? p->Bs16 : nullptr, rec);
+    }
+    DINO_HIP(hipGetLastError());
 }
 
 void launch_keep_jacobian(dino_problem* p, int n, hipStream_t st) {

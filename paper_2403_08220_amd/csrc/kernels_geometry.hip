@@ -31,16 +31,19 @@ __device__ __forceinline__ float gelu_prime_t<float>(float z) {
 // Tile (16 TM rows) x (16 TN outputs) x 16 (k); 256 threads, TM x TN outputs each at
 // rows ty + 16 i, columns tx + 16 j. The launcher picks the tile so that a small
 // batch of chains still fills the GPU.
+// m_dev (optional): a device count of the rows that hold input; blocks whose rows all lie
+// at or beyond it return at once (the grid still covers M rows).
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void fwd_layer_kernel(int M, int K, int N, const T* __restrict__ in, int ldin,
                                                         const T* __restrict__ W, const T* __restrict__ b,
                                                         int kind, T* __restrict__ out, int ldout,
-                                                        T* __restrict__ dprime, int ldd) {
+                                                        T* __restrict__ dprime, int ldd, const int* m_dev) {
     constexpr int BM = 16 * TM, BN = 16 * TN;
     __shared__ T As[16][BM + 1];
     __shared__ T Ws[16][BN + 1];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    if (m_dev && m0 >= *m_dev) return;
     T acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
                                                        const double* __restrict__ in64,
                                                        const float* __restrict__ W, const float* __restrict__ b,
                                                        int kind, float* __restrict__ out, int ldout,
-                                                       float* __restrict__ dprime, int ldd) {
+                                                       float* __restrict__ dprime, int ldd, const int* m_dev) {
     // in64 (first layer): the FP64 states, rounded to FP32 as they are loaded
     __shared__ float red[4][64][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -301,6 +304,7 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
         ty = blockIdx.x / nx;
     }
     const int m0 = ty * 32, n0 = tx * 32;
+    if (m_dev && m0 >= *m_dev) return;  // no input rows in this tile (uniform over the block)
     const int arow = m0 + l32, wrow = n0 + l32;
     const bool aok = arow < M, wok = wrow < N;
     const float* ap = in64 ? nullptr : in + (long)(aok ? arow : 0) * ldin;
@@ -394,17 +398,17 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
 
 template <typename T>
 static void fwd_layer(int M, int K, int N, const T* in, int ldin, const T* W, const T* b, int kind, T* out,
-                      int ldout, T* dprime, int ldd, hipStream_t st) {
+                      int ldout, T* dprime, int ldd, hipStream_t st, const int* m_dev = nullptr) {
     auto blocks = [&](int bm, int bn) { return (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
     if (blocks(64, 64) >= 1024)
         hipLaunchKernelGGL((fwd_layer_kernel<T, 4, 4>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M, K, N,
-                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd, m_dev);
     else if (blocks(32, 32) >= 1024)
         hipLaunchKernelGGL((fwd_layer_kernel<T, 2, 2>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st, M, K, N,
-                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd, m_dev);
     else
         hipLaunchKernelGGL((fwd_layer_kernel<T, 1, 1>), dim3((N + 15) / 16, (M + 15) / 16), dim3(256), 0, st, M, K, N,
-                           in, ldin, W, b, kind, out, ldout, dprime, ldd);
+                           in, ldin, W, b, kind, out, ldout, dprime, ldd, m_dev);
 }
 
 // Observation-space Gram matrix I + B B^T of the FP64 path (lower triangle, d_y x d_y)
@@ -504,10 +508,52 @@ void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64
         if (ly.kind != DINO_LAYER_LINEAR) dp = p->d32 + (long)act * p->C * p->ldd32;
         // the first layer reads the FP64 states (x64) when given, else the FP32 copy xf
         hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((n + 31) / 32)), dim3(256), 0, st, n, ly.fan_in, N,
-                           in, ldin, l == 0 ? x64 : nullptr, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32);
+                           in, ldin, l == 0 ? x64 : nullptr, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32,
+                           (const int*)nullptr);
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+// Forward of the true-model stand-in (delayed acceptance, second stage) on rows of zin
+// (n x r_T FP64), in the problem's forward precision: FP64 layers on the FP64 path,
+// FP32 MFMA layers (the first rounding zin as it loads) on the mixed path. Outputs the
+// first d_y true outputs into p->fT64 or p->fT32 (n x d_y). m_dev: optional device count
+// of the rows that hold input (the compacted first-stage passes).
+void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m_dev, hipStream_t st) {
+    const auto& TL = p->ctx->true_layers;
+    const int L = (int)TL.size();
+    const int dy = p->d_y, wT = p->ctx->true_max_width;
+    if (p->desc.precision == DINO_PREC_F64) {
+        const double* in = zin;
+        int ldin = p->rT;
+        for (int l = 0; l < L; ++l) {
+            const Layer& ly = TL[l];
+            const bool last = (l == L - 1);
+            double* out = last ? p->fT64 : ((l % 2 == 0) ? p->th0 : p->th1);
+            const int ldout = last ? dy : wT;
+            const int N = last ? dy : ly.fan_out;
+            fwd_layer<double>(n, ly.fan_in, N, in, ldin, ly.W64, ly.b64, ly.kind, out, ldout, nullptr, 0, st, m_dev);
+            in = out;
+            ldin = ldout;
+        }
+    } else {
+        const float* in = nullptr;
+        int ldin = p->rT;
+        for (int l = 0; l < L; ++l) {
+            const Layer& ly = TL[l];
+            const bool last = (l == L - 1);
+            float* out = last ? p->fT32 : ((l % 2 == 0) ? p->th0f : p->th1f);
+            const int ldout = last ? dy : wT;
+            const int N = last ? dy : ly.fan_out;
+            hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((n + 31) / 32)), dim3(256), 0, st, n, ly.fan_in,
+                               N, in, ldin, l == 0 ? zin : nullptr, ly.W32, ly.b32, ly.kind, out, ldout,
+                               (float*)nullptr, 0, m_dev);
+            in = out;
+            ldin = ldout;
+        }
     }
     DINO_HIP(hipGetLastError());
 }

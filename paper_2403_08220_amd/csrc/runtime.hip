@@ -81,6 +81,54 @@ static void free_layers(std::vector<Layer>& ls) {
     ls.clear();
 }
 
+// Checks a layer chain (kinds, widths, finite values); wmax: the widest input or hidden
+// width, n_act: layers with an activation.
+static void validate_layers(int n_layers, const int32_t* kinds, const int32_t* fan_out, const int32_t* fan_in,
+                            const double* const* W, const double* const* b, int& wmax, int& n_act) {
+    DINO_REQUIRE(n_layers >= 1 && n_layers <= 16, DINO_EINVAL, "1..16 layers supported");
+    DINO_REQUIRE(kinds[n_layers - 1] == DINO_LAYER_LINEAR, DINO_EINVAL, "the last layer must be linear");
+    wmax = 0;
+    n_act = 0;
+    for (int l = 0; l < n_layers; ++l) {
+        DINO_REQUIRE(kinds[l] >= 0 && kinds[l] <= 2, DINO_EINVAL, "unknown layer kind");
+        DINO_REQUIRE(fan_out[l] >= 1 && fan_out[l] <= 1024 && fan_in[l] >= 1 && fan_in[l] <= 1024, DINO_EINVAL,
+                     "layer widths must be in 1..1024");
+        DINO_REQUIRE(W[l], DINO_EINVAL, "null weight matrix");
+        if (l > 0) DINO_REQUIRE(fan_in[l] == fan_out[l - 1], DINO_EINVAL, "layer widths do not chain");
+        if (kinds[l] == DINO_LAYER_RESID)
+            DINO_REQUIRE(fan_in[l] == fan_out[l], DINO_EINVAL, "residual layers must be square");
+        if (kinds[l] != DINO_LAYER_LINEAR) ++n_act;
+        wmax = std::max(wmax, fan_in[l]);
+        if (l < n_layers - 1) wmax = std::max(wmax, fan_out[l]);
+        const size_t cnt = (size_t)fan_out[l] * fan_in[l];
+        for (size_t e = 0; e < cnt; ++e) DINO_REQUIRE(std::isfinite(W[l][e]), DINO_ENUMERIC, "non-finite weight");
+        if (b && b[l])
+            for (int e = 0; e < fan_out[l]; ++e) DINO_REQUIRE(std::isfinite(b[l][e]), DINO_ENUMERIC, "non-finite bias");
+    }
+}
+
+// Host copies and FP64/FP32 device copies of one layer (b may be null: zero bias).
+static void upload_layer(Layer& ly, int kind, int fan_out, int fan_in, const double* W, const double* b) {
+    ly.kind = kind;
+    ly.fan_out = fan_out;
+    ly.fan_in = fan_in;
+    const size_t cnt = (size_t)ly.fan_out * ly.fan_in;
+    ly.hostW.assign(W, W + cnt);
+    ly.hostb.assign(ly.fan_out, 0.0);
+    if (b) std::copy(b, b + ly.fan_out, ly.hostb.begin());
+    std::vector<float> w32(cnt), b32(ly.fan_out);
+    for (size_t e = 0; e < cnt; ++e) w32[e] = (float)ly.hostW[e];
+    for (int e = 0; e < ly.fan_out; ++e) b32[e] = (float)ly.hostb[e];
+    DINO_HIP(hipMalloc(&ly.W64, sizeof(double) * cnt));
+    DINO_HIP(hipMalloc(&ly.b64, sizeof(double) * ly.fan_out));
+    DINO_HIP(hipMalloc(&ly.W32, sizeof(float) * cnt));
+    DINO_HIP(hipMalloc(&ly.b32, sizeof(float) * ly.fan_out));
+    DINO_HIP(hipMemcpy(ly.W64, ly.hostW.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(ly.b64, ly.hostb.data(), sizeof(double) * ly.fan_out, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(ly.W32, w32.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
+    DINO_HIP(hipMemcpy(ly.b32, b32.data(), sizeof(float) * ly.fan_out, hipMemcpyHostToDevice));
+}
+
 NetView net_view(const dino_ctx* ctx) {
     NetView v{};
     v.n_layers = (int)ctx->layers.size();
@@ -165,6 +213,23 @@ static void layout(dino_problem* p, Carver& cv) {
         if (p->dual) p->Bs16 = cv.take<__hip_bfloat16>(C * dy * ((r + 31) / 32 * 32));
     }
     if (p->dual && p->desc.precision == DINO_PREC_F64) p->Bs64 = cv.take<double>(C * dy * r);
+    if (p->da) {
+        const size_t rT = p->rT, wT = p->ctx->true_max_width;
+        p->phit = cv.take<double>(C);
+        p->passes = cv.take<int64_t>(C);
+        p->pos = cv.take<int32_t>(C);
+        p->npass = cv.take<int32_t>(1);
+        p->zin = cv.take<double>(C * rT);
+        if (p->desc.precision == DINO_PREC_F64) {
+            p->th0 = cv.take<double>(C * wT);
+            p->th1 = cv.take<double>(C * wT);
+            p->fT64 = cv.take<double>(C * dy);
+        } else {
+            p->th0f = cv.take<float>(C * wT);
+            p->th1f = cv.take<float>(C * wT);
+            p->fT32 = cv.take<float>(C * dy);
+        }
+    }
     const size_t cap = (size_t)std::max(p->desc.trace_capacity, 0);
     p->xtrace = cap ? cv.take<float>(cap * C * r) : nullptr;
     p->phitrace = cap ? cv.take<double>(cap * C) : nullptr;
@@ -184,7 +249,15 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
     DINO_REQUIRE(d->factorization >= DINO_FACTOR_PRIMAL && d->factorization <= DINO_FACTOR_AUTO, DINO_EINVAL,
                  "unknown factorization");
-    DINO_REQUIRE(d->method >= DINO_METHOD_MMALA && d->method <= DINO_METHOD_LAPCN, DINO_EINVAL, "unknown method");
+    DINO_REQUIRE(d->method >= DINO_METHOD_MMALA && d->method <= DINO_METHOD_DA_MMALA, DINO_EINVAL, "unknown method");
+    if (d->method == DINO_METHOD_DA_MMALA) {
+        DINO_REQUIRE(!ctx->true_layers.empty(), DINO_ESTATE, "load the true model before creating a delayed-acceptance problem");
+        DINO_REQUIRE(ctx->true_r_in >= ctx->basis.r && ctx->true_r_in <= ctx->basis.d_m, DINO_EINVAL,
+                     "the true model must read between r and d_m whitened coordinates");
+        DINO_REQUIRE(d->d_y <= ctx->true_d_out, DINO_EINVAL, "d_y exceeds the true model's outputs");
+        DINO_REQUIRE(ctx->true_r_in == ctx->basis.r || d->track_complement, DINO_EINVAL,
+                     "a true model that reads complement coordinates needs track_complement");
+    }
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
                       (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
@@ -208,6 +281,8 @@ static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d
     p->n_act = ctx->n_act;
     p->dual = d->factorization == DINO_FACTOR_DUAL || (d->factorization == DINO_FACTOR_AUTO && d->d_y < p->r);
     p->kdim = p->dual ? p->d_y : p->r;
+    p->da = d->method == DINO_METHOD_DA_MMALA;
+    p->rT = p->da ? ctx->true_r_in : 0;
     p->s = (4.0 - d->dt) / (4.0 + d->dt);
     p->beta = std::sqrt(1.0 - p->s * p->s);
 }
@@ -286,6 +361,7 @@ dino_status dino_ctx_destroy(dino_ctx* ctx) {
         DINO_HIP(hipSetDevice(ctx->device));
         free_basis(ctx->basis);
         free_layers(ctx->layers);
+        free_layers(ctx->true_layers);
         if (ctx->sweep_tiles) (void)hipFree(ctx->sweep_tiles);
         delete ctx;
     });
@@ -419,54 +495,15 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
     return guarded([&] {
         DINO_REQUIRE(ctx && kinds && fan_out && fan_in && W, DINO_EINVAL, "null argument");
         DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "cannot replace the network under live problems");
-        DINO_REQUIRE(n_layers >= 1 && n_layers <= 16, DINO_EINVAL, "1..16 layers supported");
-        DINO_REQUIRE(kinds[n_layers - 1] == DINO_LAYER_LINEAR, DINO_EINVAL, "the last layer must be linear");
         int wmax = 0, n_act = 0;
-        for (int l = 0; l < n_layers; ++l) {
-            DINO_REQUIRE(kinds[l] >= 0 && kinds[l] <= 2, DINO_EINVAL, "unknown layer kind");
-            DINO_REQUIRE(fan_out[l] >= 1 && fan_out[l] <= 1024 && fan_in[l] >= 1 && fan_in[l] <= 1024, DINO_EINVAL,
-                         "layer widths must be in 1..1024");
-            DINO_REQUIRE(W[l], DINO_EINVAL, "null weight matrix");
-            if (l > 0) DINO_REQUIRE(fan_in[l] == fan_out[l - 1], DINO_EINVAL, "layer widths do not chain");
-            if (kinds[l] == DINO_LAYER_RESID)
-                DINO_REQUIRE(fan_in[l] == fan_out[l], DINO_EINVAL, "residual layers must be square");
-            if (kinds[l] != DINO_LAYER_LINEAR) ++n_act;
-            wmax = std::max(wmax, fan_in[l]);
-            if (l < n_layers - 1) wmax = std::max(wmax, fan_out[l]);
-            const size_t cnt = (size_t)fan_out[l] * fan_in[l];
-            for (size_t e = 0; e < cnt; ++e)
-                DINO_REQUIRE(std::isfinite(W[l][e]), DINO_ENUMERIC, "non-finite weight");
-            if (b && b[l])
-                for (int e = 0; e < fan_out[l]; ++e)
-                    DINO_REQUIRE(std::isfinite(b[l][e]), DINO_ENUMERIC, "non-finite bias");
-        }
+        validate_layers(n_layers, kinds, fan_out, fan_in, W, b, wmax, n_act);
         DINO_HIP(hipSetDevice(ctx->device));
         std::vector<Layer> ls(n_layers);
         __hip_bfloat16* new_tiles = nullptr;
         size_t n_tile_u16 = 0;
         int sweep_nmb_t = 0;
         try {
-            for (int l = 0; l < n_layers; ++l) {
-                Layer& ly = ls[l];
-                ly.kind = kinds[l];
-                ly.fan_out = fan_out[l];
-                ly.fan_in = fan_in[l];
-                const size_t cnt = (size_t)ly.fan_out * ly.fan_in;
-                ly.hostW.assign(W[l], W[l] + cnt);
-                ly.hostb.assign(ly.fan_out, 0.0);
-                if (b && b[l]) std::copy(b[l], b[l] + ly.fan_out, ly.hostb.begin());
-                std::vector<float> w32(cnt), b32(ly.fan_out);
-                for (size_t e = 0; e < cnt; ++e) w32[e] = (float)ly.hostW[e];
-                for (int e = 0; e < ly.fan_out; ++e) b32[e] = (float)ly.hostb[e];
-                DINO_HIP(hipMalloc(&ly.W64, sizeof(double) * cnt));
-                DINO_HIP(hipMalloc(&ly.b64, sizeof(double) * ly.fan_out));
-                DINO_HIP(hipMalloc(&ly.W32, sizeof(float) * cnt));
-                DINO_HIP(hipMalloc(&ly.b32, sizeof(float) * ly.fan_out));
-                DINO_HIP(hipMemcpy(ly.W64, ly.hostW.data(), sizeof(double) * cnt, hipMemcpyHostToDevice));
-                DINO_HIP(hipMemcpy(ly.b64, ly.hostb.data(), sizeof(double) * ly.fan_out, hipMemcpyHostToDevice));
-                DINO_HIP(hipMemcpy(ly.W32, w32.data(), sizeof(float) * cnt, hipMemcpyHostToDevice));
-                DINO_HIP(hipMemcpy(ly.b32, b32.data(), sizeof(float) * ly.fan_out, hipMemcpyHostToDevice));
-            }
+            for (int l = 0; l < n_layers; ++l) upload_layer(ls[l], kinds[l], fan_out[l], fan_in[l], W[l], b ? b[l] : nullptr);
             // BF16 MFMA operand tiles of W^T for the reverse sweep, packed for the sweep
             // instance that covers the widest layer
             dino_ctx probe;
@@ -519,6 +556,29 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         ctx->d_out = fan_out[n_layers - 1];
         ctx->max_width = wmax;
         ctx->n_act = n_act;
+    });
+}
+
+dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kinds, const int32_t* fan_out,
+                                 const int32_t* fan_in, const double* const* W, const double* const* b) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && kinds && fan_out && fan_in && W, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "cannot replace the true model under live problems");
+        int wmax = 0, n_act = 0;
+        validate_layers(n_layers, kinds, fan_out, fan_in, W, b, wmax, n_act);
+        DINO_HIP(hipSetDevice(ctx->device));
+        std::vector<Layer> ls(n_layers);
+        try {
+            for (int l = 0; l < n_layers; ++l) upload_layer(ls[l], kinds[l], fan_out[l], fan_in[l], W[l], b ? b[l] : nullptr);
+        } catch (...) {
+            free_layers(ls);
+            throw;
+        }
+        free_layers(ctx->true_layers);
+        ctx->true_layers = std::move(ls);
+        ctx->true_r_in = fan_in[0];
+        ctx->true_d_out = fan_out[n_layers - 1];
+        ctx->true_max_width = wmax;
     });
 }
 
@@ -673,6 +733,11 @@ dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0,
         const long kk = (long)p->kdim * p->kdim;
         geometry_at(p, p->C, p->x, p->f, p->phi, p->g, p->Lbuf, kk, nullptr, 0, 0, p->logdet, p->okp, st);
         if (p->dual) launch_keep_jacobian(p, p->C, st);
+        if (p->da) {
+            // the true misfit of the initial states (Alg. 1: known at m_j)
+            DINO_HIP(hipMemsetAsync(p->passes, 0, sizeof(int64_t) * C, st));
+            launch_da_init(p, p->C, st);
+        }
         DINO_HIP(hipStreamSynchronize(st));
         p->step = 0;
         p->recorded = 0;
@@ -709,11 +774,13 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const bool f64 = p->desc.precision == DINO_PREC_F64;
     const bool pcn = p->desc.method == DINO_METHOD_PCN || p->desc.method == DINO_METHOD_LAPCN;
     const bool lapcn = p->desc.method == DINO_METHOD_LAPCN;
-    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, p->z ? 1 : 0, 0};
+    // second stage of delayed acceptance: gather, the true model's layers, decision
+    const int LT = p->da ? (int)p->ctx->true_layers.size() + 2 : 0;
+    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, LT, p->z ? 1 : 0, 0};
     const bool mala = p->desc.method == DINO_METHOD_MALA;
-    const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, p->z ? 1 : 0, 0};
+    const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, 0, p->z ? 1 : 0, 0};
     // MALA: on the mixed path the misfit and ppg come from the metric kernel, told to skip the metric
-    const int32_t launches_mala[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, f64 ? 0 : 1, 0, 1, p->z ? 1 : 0, 0};
+    const int32_t launches_mala[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, f64 ? 0 : 1, 0, 1, 0, p->z ? 1 : 0, 0};
     auto mark = [&](int i) {
         if (p->profile) DINO_HIP(hipEventRecord(p->ev[p->ring_used * (DINO_N_STAGES + 1) + i], st));
     };
@@ -730,9 +797,10 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
             launch_pcn_accept(p, n, row, st);
             mark(7);
-            launch_complement(p, n, st);
             mark(8);
+            launch_complement(p, n, st);
             mark(9);
+            mark(10);
             if (p->profile) {
                 for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches_pcn[i];
                 if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
@@ -757,9 +825,10 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
             launch_mala_accept(p, n, row, st);
             mark(7);
-            launch_complement(p, n, st);
             mark(8);
+            launch_complement(p, n, st);
             mark(9);
+            mark(10);
             if (p->profile) {
                 for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches_mala[i];
                 if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
@@ -785,13 +854,20 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
         mark(6);
         int64_t row = -1;
         if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
-        // the accept kernel also ends the step (trace row, running sums, step counter)
+        // the accept kernel also ends the step (trace row, running sums, step counter),
+        // unless a second stage follows (delayed acceptance), which then ends it
         if (p->dual) launch_accept_dual(p, n, row, st);
         else launch_accept(p, n, row, st);
         mark(7);
-        launch_complement(p, n, st);
+        if (p->da) {
+            launch_da_gather(p, n, st);
+            launch_true_forward(p, n, p->zin, p->npass, st);
+            launch_da_accept(p, n, row, st);
+        }
         mark(8);
+        launch_complement(p, n, st);
         mark(9);
+        mark(10);
         if (p->profile) {
             for (int i = 0; i < DINO_N_STAGES; ++i) p->stage_launches[i] = launches[i];
             if (++p->ring_used == dino_problem::PROFILE_RING) drain_profile(p);
@@ -877,7 +953,7 @@ dino_status dino_read_profile(dino_problem* p, double* stage_ms, int32_t* launch
 
 const char* dino_stage_name(int stage) {
     static const char* names[DINO_N_STAGES] = {"proposal", "forward", "jacobian", "misfit_ppg", "gn_hessian",
-                                               "cholesky", "accept", "complement", "trace"};
+                                               "cholesky", "accept", "second_stage", "complement", "trace"};
     return (stage >= 0 && stage < DINO_N_STAGES) ? names[stage] : "";
 }
 
@@ -921,6 +997,30 @@ dino_status dino_read_diagnostics(dino_problem* p, int64_t* accepts, int64_t* fa
         if (accepts) DINO_HIP(hipMemcpy(accepts, p->accepts, sizeof(int64_t) * p->C, hipMemcpyDeviceToHost));
         if (failures) DINO_HIP(hipMemcpy(failures, p->failures, sizeof(int64_t) * p->C, hipMemcpyDeviceToHost));
         if (steps) *steps = p->step;
+    });
+}
+
+dino_status dino_read_delayed(dino_problem* p, double* phi_true, int64_t* passes) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "problem not initialised");
+        DINO_REQUIRE(p->da, DINO_EINVAL, "not a delayed-acceptance problem");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (phi_true) DINO_HIP(hipMemcpy(phi_true, p->phit, sizeof(double) * p->C, hipMemcpyDeviceToHost));
+        if (passes) DINO_HIP(hipMemcpy(passes, p->passes, sizeof(int64_t) * p->C, hipMemcpyDeviceToHost));
+    });
+}
+
+dino_status dino_eval_true_misfit(dino_problem* p, int n, const double* z_in, double* phi_true, void* stream) {
+    return guarded([&] {
+        DINO_REQUIRE(p && z_in && phi_true, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(p->da, DINO_EINVAL, "not a delayed-acceptance problem");
+        DINO_REQUIRE(n >= 1 && n <= p->C, DINO_EINVAL, "n out of range");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        launch_true_forward(p, n, z_in, nullptr, st);
+        launch_true_misfit(p, n, phi_true, st);
+        p->last_stream = st;
     });
 }
 

@@ -144,19 +144,9 @@ def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=Fals
 
 def make_problem_inputs(w, ctx_builder):
     """Data y = f(x_true) + sigma eps with f evaluated by the device path."""
-    import torch
-    from synth import draw_noise, draw_true_state
-
-    x_true = draw_true_state(w)[: w.r]
     ctx = ctx_builder()
-    from paper_2403_08220_amd import Problem
-    tmp = Problem(ctx, 1, np.zeros(w.d_y), np.ones(w.d_y), 0.1, track_complement=False)
-    geo = tmp.eval_geometry(torch.tensor(x_true[None], dtype=torch.float64, device="cuda:0"), want_H=False)
-    f_true = geo["f"].cpu().numpy()[0]
-    tmp.close()
-    sigma = w.sigma * np.max(np.abs(f_true)) if w.sigma_rule == "rel_max" else w.sigma
-    y = f_true + sigma * draw_noise(w)
-    return ctx, y, np.full(w.d_y, sigma ** 2)
+    y, nv = device_data(w, ctx)
+    return ctx, y, nv
 
 
 def laplace_start(w, ctx, y, nv):
@@ -334,6 +324,90 @@ def baseline_leg(method, w, ctx, y, nv, x0, z0, precision, steps, warmup, mmala,
                              ess_frac=t["ess_frac"], kept=t["kept"]) for t in tr.table])
 
 
+def device_data(w, ctx):
+    """y = f(x_true) + sigma eps for workload w, f evaluated by the device path on ctx."""
+    import torch
+    from paper_2403_08220_amd import Problem
+    from synth import draw_noise, draw_true_state
+
+    x_true = draw_true_state(w)[: w.r]
+    tmp = Problem(ctx, 1, np.zeros(w.d_y), np.ones(w.d_y), 0.1, track_complement=False)
+    try:
+        geo = tmp.eval_geometry(torch.tensor(x_true[None], dtype=torch.float64, device="cuda:0"), want_H=False)
+        f_true = geo["f"].cpu().numpy()[0]
+    finally:
+        tmp.close()
+    sigma = w.sigma * np.max(np.abs(f_true)) if w.sigma_rule == "rel_max" else w.sigma
+    return f_true + sigma * draw_noise(w), np.full(w.d_y, sigma ** 2)
+
+
+def ess_leg(ctx, steps, warmup):
+    """ESS/s of the BF16 path against the plain FP64 path on the mix workload: the bench's
+    shapes (129^2 grid, r = 200, ResNet 400 x 4, d_y = 100, 512 chains) with sigma = 30% of
+    max |f(x_true)|, a posterior on which these chains decorrelate within the run (at the
+    bench's sigma = 1% they do not, and ESS sits at the multichain floor). Both legs start
+    from the same Laplace samples, take dt from the tuning rule (BF16 path, 200-step runs),
+    and report ESS over their timed window of `steps` steps after `warmup` burn-in steps."""
+    from paper_2403_08220_amd import laplace
+    from paper_2403_08220_amd.tune import tune_step_size
+    from synth import draw_initial_states, draw_laplace_normals, workload
+
+    w = workload("mix")
+    y, nv = device_data(w, ctx)
+    m = laplace.gauss_newton_map(ctx, y, nv)
+    x0 = laplace.laplace_samples(ctx, y, nv, m.x, draw_laplace_normals(w))
+    _, z0 = draw_initial_states(w)
+    tr = tune_step_size(ctx, y, nv, x0, z0, [0.01, 0.03, 0.1, 0.3], burn=50, steps=200, seed=w.chain_seed,
+                        precision="bf16")
+    out = dict(workload="mix: the bench shapes with sigma = 30% of max|f(x_true)|, 512 chains", dt=tr.dt,
+               tuning_rule=tr.rule, steps=steps, burn_in=warmup)
+    for prec in ("bf16", "f64"):
+        r = run_path(w, ctx, y, nv, x0, z0, prec, steps, warmup, profile=False, factorization="auto", dt=tr.dt)
+        rate, note = ess_rate(r["median_ess"], r["wall_s"], w.chains)
+        out[prec] = dict(value=round(w.chains * steps / r["wall_s"], 1), unit="chain-steps/s",
+                         ms_per_step=round(1e3 * r["wall_s"] / steps, 4), accept_rate=round(r["accept_rate"], 4),
+                         median_ess=round(r["median_ess"], 1), ess_per_s=rate, ess_note=note)
+    a, b = out["bf16"]["ess_per_s"], out["f64"]["ess_per_s"]
+    out["ess_per_s_bf16_over_f64"] = round(a / b, 2) if a and b else None
+    return out
+
+
+def da_leg(ctx, w, layers, y, nv, x0, z0, precision, steps, warmup, mmala_wall):
+    """DA-DINO-mMALA (Alg. 1 with its second stage) on the bench workload, the true model a
+    stand-in network that reads 56 complement coordinates (r_T = 256; the surrogate's
+    weights perturbed by 5%). Reports chain-steps/s, the first-stage pass rate (true-model
+    evaluations per chain-step), the second-stage acceptance and the per-step cost
+    relative to plain mMALA."""
+    import torch
+    from paper_2403_08220_amd import Problem
+    from synth import draw_true_model
+
+    ctx.load_true_model(draw_true_model(layers, 56))
+    C = w.chains
+    p = Problem(ctx, C, y, nv, w.dt, seed=w.chain_seed, precision=precision, track_complement=True,
+                factorization="auto", method="da_mmala")
+    try:
+        p.init(x0, z0)
+        p.step(warmup)
+        torch.cuda.synchronize()
+        a0, _, _ = p.diagnostics()
+        _, q0 = p.delayed()
+        t0 = time.perf_counter()
+        p.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        a1, f1, _ = p.diagnostics()
+        _, q1 = p.delayed()
+    finally:
+        p.close()
+    passes, accepts = float((q1 - q0).sum()), float((a1 - a0).sum())
+    return dict(value=round(C * steps / wall, 1), unit="chain-steps/s", steps=steps,
+                ms_per_step=round(1e3 * wall / steps, 4), true_model="r_T = 256 (56 complement coordinates)",
+                pass_rate=round(passes / (C * steps), 4), accept_rate=round(accepts / (C * steps), 4),
+                second_stage_acceptance=round(accepts / passes, 4) if passes else None,
+                failures=int(f1.sum()), step_cost_over_mmala=round(wall / mmala_wall, 3))
+
+
 def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=20, seed=11):
     """Poisson stream of inverse problems on the served workload (129x129 grid, r = 200,
     ResNet 400x4 with 100 outputs): per request d_y in {25, 50, 100}, chains in [8, 128],
@@ -507,6 +581,10 @@ def main():
                     help="steps of each baseline leg, pCN, MALA and LA-pCN (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests of the serving leg (0: skip)")
     ap.add_argument("--serve-load", type=float, default=0.8, help="offered load as a fraction of capacity")
+    ap.add_argument("--ess-steps", type=int, default=1000,
+                    help="timed steps of the ESS/s leg on the mix workload (0: skip)")
+    ap.add_argument("--da-steps", type=int, default=None,
+                    help="timed steps of the delayed-acceptance leg (default: --steps; 0: skip)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
     args = ap.parse_args()
@@ -572,6 +650,17 @@ def main():
             baselines[method] = b
             log(f"bench: {method} baseline: dt {b['dt']}, accept {b['accept_rate']}, {b['value']} chain-steps/s")
 
+    ess = None
+    if args.ess_steps > 0:
+        log(f"bench: ESS/s leg (mix workload), {args.ess_steps} steps per path ...")
+        ess = ess_leg(ctx, args.ess_steps, 200)
+        log(f"bench: ESS/s bf16 {ess['bf16']['ess_per_s']} f64 {ess['f64']['ess_per_s']}")
+    da_res = None
+    da_steps = steps if args.da_steps is None else args.da_steps
+    if da_steps > 0:
+        da_res = da_leg(ctx, w, layers, y, nv, x0, z0, args.precision, da_steps, args.warmup,
+                        res["wall_s"] * da_steps / steps)
+        log(f"bench: DA leg {da_res['value']} chain-steps/s, pass rate {da_res['pass_rate']}")
     prof = res.get("profile", {})
     # the observation-space form is taken when asked for, or by "auto" when d_y < r
     dual = args.factorization == "dual" or (args.factorization == "auto" and w.d_y < w.r)
@@ -632,6 +721,8 @@ def main():
         "roofline": roof,
         "stages": stages,
         "fp64_plain": fp64,
+        "ess_leg": ess,
+        "delayed_acceptance": da_res,
         "baselines": baselines,
         "serving": serving,
         "cpu_baseline": cpu,

@@ -210,6 +210,15 @@ dino_status dino_chains_init(dino_problem* p, const double* x0, const float* z0,
  * for non-finite entries. An LAPCN problem refuses dino_step (ESTATE) until this call. */
 dino_status dino_set_fixed_metric(dino_problem* p, const double* x_map, const double* L_map);
 
+/* How dino_step launches its kernels. DINO_LAUNCH_GRAPH (the default, 8 steps per graph):
+ * the step loop of steps_per_graph transitions (1..256) is captured once as a HIP graph
+ * and replayed (one graph of the remainder too); DINO_LAUNCH_EAGER: one launch per kernel.
+ * Both run the same kernels with the same arguments, so their results are identical.
+ * Stage profiling always runs eagerly. Waits for the problem's last stream. */
+#define DINO_LAUNCH_EAGER 0
+#define DINO_LAUNCH_GRAPH 1
+dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph);
+
 /* Advance every chain n_steps transitions (Alg. 1 first stage + the splitting proposition of Sec. 5.3).
  * Asynchronous on stream. Per-chain numerical failures (non-finite misfit,
  * I + H not positive definite) reject the proposal and are counted; they do

@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
+LAUNCH_MODES = {"eager": 0, "graph": 1}
 METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4}
 
 
@@ -121,6 +122,7 @@ SIGNATURES = {
     "dino_eval_propose_dual": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "dino_eval_log_rho_dual": (ct.c_int32, [_P, ct.c_int] + [_P] * 13 + [_P]),
     "dino_set_profiling": (ct.c_int32, [_P, ct.c_int]),
+    "dino_set_launch_mode": (ct.c_int32, [_P, ct.c_int, ct.c_int]),
     "dino_read_profile": (ct.c_int32, [_P, _D, _I32, _I64]),
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),
     "dino_encode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),

@@ -173,6 +173,11 @@ class Problem:
     def step(self, n: int, stream=None):
         check(self.lib.dino_step(self.h, n, _stream_handle(stream)))
 
+    def set_launch_mode(self, mode: str = "graph", steps_per_graph: int = 8):
+        """"graph": dino_step replays captured graphs of steps_per_graph transitions; "eager":
+        one launch per kernel."""
+        check(self.lib.dino_set_launch_mode(self.h, _lib.LAUNCH_MODES[mode], steps_per_graph))
+
     def set_profiling(self, enable: bool):
         check(self.lib.dino_set_profiling(self.h, 1 if enable else 0))
 

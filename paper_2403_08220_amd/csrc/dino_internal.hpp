@@ -313,6 +313,16 @@ struct dino_problem {
     // trace
     float* xtrace = nullptr;  // capacity x C x r
     double* phitrace = nullptr;
+    // launch graphs: one per (chain bucket, steps) captured on cap_stream and replayed on
+    // the caller's stream (steps whose kernel arguments are all fixed per problem)
+    struct StepGraph {
+        int n = 0, steps = 0;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<StepGraph> graphs;
+    hipStream_t cap_stream = nullptr;
+    int launch_mode = 1;      // DINO_LAUNCH_GRAPH
+    int graph_steps = 8;      // transitions per captured graph
     // stage profiling
     bool profile = false;
     // ring of per-step stage events, drained when full and on read (no per-step host wait)
@@ -340,9 +350,9 @@ void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* 
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
                          const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
                          double* xp, double* lfwd, const double* logdet, hipStream_t st);
-// The accept kernels also end the step of each chain: trace row trace_row (-1: none),
-// running sums, step counter and life cycle.
-void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+// The accept kernels also end the step of each chain: trace row (the chain's step counter,
+// below the trace capacity), running sums, step counter and life cycle.
+void launch_accept(dino_problem* p, int n, hipStream_t st);
 // Per-step bookkeeping of chains [0, n): step counters, life cycle, running sums, trace row.
 // Sets the metadata of chains [c0, c0 + n) (index = first_index + c - c0) and zeroes their sums.
 void launch_meta_fill(dino_problem* p, int c0, int n, uint64_t key0, uint64_t key1, int64_t budget, int64_t burn,
@@ -357,12 +367,12 @@ void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x
 void launch_complement(dino_problem* p, int n, hipStream_t st);
 // dual form (kernels_chain.hip, kernels_mfma.hip, kernels_geometry.hip)
 void launch_propose_dual(dino_problem* p, int n, hipStream_t st);
-void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_accept_dual(dino_problem* p, int n, hipStream_t st);
 void launch_pcn_propose(dino_problem* p, int n, hipStream_t st);
-void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_pcn_accept(dino_problem* p, int n, hipStream_t st);
 void launch_mala_propose(dino_problem* p, int n, hipStream_t st);
 void launch_lapcn_propose(dino_problem* p, int n, hipStream_t st);
-void launch_mala_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_mala_accept(dino_problem* p, int n, hipStream_t st);
 // Whether the BF16 reverse sweep covers the network: it holds at most 16 row blocks of 32
 // (the reduced dimension and every hidden width at most 512).
 bool sweep_width_ok(const dino_ctx* ctx);
@@ -385,7 +395,7 @@ void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t 
 void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m_dev, hipStream_t st);
 void launch_da_gather(dino_problem* p, int n, hipStream_t st);
 void launch_da_init(dino_problem* p, int n, hipStream_t st);
-void launch_da_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st);
+void launch_da_accept(dino_problem* p, int n, hipStream_t st);
 void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st);
 // Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
 // no separate misfit launch).
@@ -401,6 +411,7 @@ void launch_copy_rows(int n, int width, const double* src, double* dst, hipStrea
 
 // n_steps transitions of chains [0, n) (runtime.hip).
 void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st);
+void release_graphs(dino_problem* p);
 // Problem with n_rows request rows; serving pools keep running sums (runtime.hip).
 dino_problem* create_problem(dino_ctx* ctx, const dino_problem_desc* desc, int n_rows, bool serving);
 void destroy_problem(dino_problem* p);

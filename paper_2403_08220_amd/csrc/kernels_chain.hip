@@ -809,12 +809,16 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 // MH decision of the first stage and the swap of state and cache on acceptance.
 // accflag: 0 rejected or idle, 1 accepted (pCN complement move), 2 fresh chain
 // initialised (complement drawn from the prior).
-// Per-step outputs of the finish: the trace row (xrow, phirow; null when the step is not
-// recorded) and the running sums of x past the burn-in (sumx; null outside serving).
+// Per-step outputs of the finish: the trace (xtrace cap x C x r, phitrace cap x C; a
+// chain records the step with its own step counter t as row t while t < cap; null when
+// the problem keeps no trace) and the running sums of x past the burn-in (sumx; null
+// outside serving). Every argument is fixed for a problem, so a captured step replays.
 struct StepRecord {
     double* sumx;
-    float* xrow;
-    double* phirow;
+    float* xtrace;
+    double* phitrace;
+    int64_t cap;
+    int C;
 };
 
 // End of a step for chain c, run by the whole block of the accept kernels after the
@@ -826,9 +830,10 @@ struct StepRecord {
 __device__ __forceinline__ void finish_chain(int c, int r, const ChainMeta& meta, int32_t state, int64_t step,
                                              const double* xn, double phin, const StepRecord& rec) {
     const int tid = threadIdx.x;
-    if (rec.xrow) {
-        for (int j = tid; j < r; j += TPB) rec.xrow[(long)c * r + j] = (float)xn[j];
-        if (tid == 0) rec.phirow[c] = phin;
+    if (rec.xtrace && step < rec.cap) {
+        float* xrow = rec.xtrace + step * (long)rec.C * r;
+        for (int j = tid; j < r; j += TPB) xrow[(long)c * r + j] = (float)xn[j];
+        if (tid == 0) rec.phitrace[step * (long)rec.C + c] = phin;
     }
     if (state == CHAIN_LIVE) {
         const int64_t s1 = step + 1;
@@ -843,12 +848,6 @@ __device__ __forceinline__ void finish_chain(int c, int r, const ChainMeta& meta
     }
 }
 
-// The trace row of an idle chain (its state does not change).
-__device__ __forceinline__ void record_idle(int c, int r, const double* x, const double* phi, const StepRecord& rec) {
-    if (!rec.xrow) return;
-    for (int j = threadIdx.x; j < r; j += TPB) rec.xrow[(long)c * r + j] = (float)x[(long)c * r + j];
-    if (threadIdx.x == 0) rec.phirow[c] = phi[c];
-}
 
 __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) void accept_kernel(int r, double dt, double s, double beta, ChainMeta meta,
                                                      double* x, double* g, double* phi,
@@ -866,7 +865,6 @@ __global__ __launch_bounds__(TPB) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        if (!da) record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -1037,7 +1035,6 @@ __global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMet
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -1148,7 +1145,6 @@ __global__ __launch_bounds__(TPB) void mala_accept_kernel(int r, double dt, doub
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -1593,7 +1589,6 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
         if (tid == 0) accflag[c] = 0;
-        if (!da) record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -1818,7 +1813,6 @@ __global__ __launch_bounds__(TPB) void da_accept_kernel(int r, int dy, long bcou
     if (c == 0 && tid == 0) *npass = 0;  // this step's batch has been evaluated
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) {
-        record_idle(c, r, x, phi, rec);
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
@@ -2051,23 +2045,18 @@ void launch_propose_slot(dino_problem* p, int n, const double* x, const double* 
 }
 
 
-// The step record of a dino_step transition: trace row `trace_row` (-1: none).
-static StepRecord step_record(dino_problem* p, int64_t trace_row) {
-    StepRecord rec{p->sumx, nullptr, nullptr};
-    if (trace_row >= 0) {
-        rec.xrow = p->xtrace + trace_row * (long)p->C * p->r;
-        rec.phirow = p->phitrace + trace_row * (long)p->C;
-    }
-    return rec;
+// The step record of a problem's transitions (trace rows by the chains' step counters).
+static StepRecord step_record(dino_problem* p) {
+    return StepRecord{p->sumx, p->xtrace, p->phitrace, p->xtrace ? (int64_t)p->desc.trace_capacity : 0, p->C};
 }
 
-void launch_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+void launch_accept(dino_problem* p, int n, hipStream_t st) {
     static bool attr = false;
     allow_large_lds(accept_kernel, attr);
     const long half = (long)p->C * p->r * p->r;
     hipLaunchKernelGGL(accept_kernel, dim3(n), dim3(TPB), chain_lds_bytes(p->r), st, p->r, p->desc.dt, p->s, p->beta,
                        p->meta, p->x, p->g, p->phi, p->logdet, p->Lbuf, half, p->cur, p->xp, p->gp, p->phip,
-                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p, trace_row),
+                       p->logdetp, p->okp, p->lfwd, p->accepts, p->failures, p->acc, step_record(p),
                        p->da ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
@@ -2078,8 +2067,8 @@ void launch_pcn_propose(dino_problem* p, int n, hipStream_t st) {
 }
 
 // The forward stage leaves the network output in p->f (FP64 path) or p->f32 (BF16 path).
-void launch_pcn_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
-    const StepRecord rec = step_record(p, trace_row);
+void launch_pcn_accept(dino_problem* p, int n, hipStream_t st) {
+    const StepRecord rec = step_record(p);
     const double* lterm = p->desc.method == DINO_METHOD_LAPCN ? p->lfwd : nullptr;
     if (p->desc.precision == DINO_PREC_F64)
         hipLaunchKernelGGL(pcn_accept_kernel<double>, dim3(n), dim3(TPB), 0, st, p->r, p->d_y, p->meta, p->f, p->y,
@@ -2104,10 +2093,10 @@ void launch_mala_propose(dino_problem* p, int n, hipStream_t st) {
     DINO_HIP(hipGetLastError());
 }
 
-void launch_mala_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
+void launch_mala_accept(dino_problem* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(mala_accept_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
                        p->g, p->phi, p->xp, p->gp, p->phip, p->lfwd, p->accepts, p->failures, p->acc,
-                       step_record(p, trace_row));
+                       step_record(p));
     DINO_HIP(hipGetLastError());
 }
 
@@ -2214,7 +2203,7 @@ void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t 
 }
 
 template <typename TB>
-static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb, int64_t trace_row, hipStream_t st) {
+static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb, hipStream_t st) {
     static bool attr = false;
     allow_large_lds(accept_dual_kernel<TB>, attr);
     const long half = (long)p->C * p->d_y * p->d_y;
@@ -2223,7 +2212,7 @@ static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb,
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, p->phi, p->logdet,
                        p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp, p->lfwd, Bp, Bs,
-                       p->accepts, p->failures, p->acc, step_record(p, trace_row), p->da ? 1 : 0);
+                       p->accepts, p->failures, p->acc, step_record(p), p->da ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
 
@@ -2232,9 +2221,9 @@ void launch_propose_dual(dino_problem* p, int n, hipStream_t st) {
     else propose_dual_t<__hip_bfloat16>(p, n, p->Bs16, (p->r + 31) / 32 * 32, st);
 }
 
-void launch_accept_dual(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
-    if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, trace_row, st);
-    else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, trace_row, st);
+void launch_accept_dual(dino_problem* p, int n, hipStream_t st) {
+    if (p->desc.precision == DINO_PREC_F64) accept_dual_t<double>(p, n, p->Bj, p->Bs64, p->r, st);
+    else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, st);
 }
 
 void launch_da_gather(dino_problem* p, int n, hipStream_t st) {
@@ -2267,8 +2256,8 @@ void launch_da_init(dino_problem* p, int n, hipStream_t st) {
     DINO_HIP(hipGetLastError());
 }
 
-void launch_da_accept(dino_problem* p, int n, int64_t trace_row, hipStream_t st) {
-    const StepRecord rec = step_record(p, trace_row);
+void launch_da_accept(dino_problem* p, int n, hipStream_t st) {
+    const StepRecord rec = step_record(p);
     if (p->desc.precision == DINO_PREC_F64) {
         const long bc = (long)p->d_y * p->r;
         hipLaunchKernelGGL((da_accept_kernel<double, double>), dim3(n), dim3(TPB), 0, st, p->r, p->d_y, bc, p->meta,

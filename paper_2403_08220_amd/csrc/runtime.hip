@@ -627,6 +627,7 @@ void destroy_problem(dino_problem* p) {
     if (!p) return;
     (void)hipSetDevice(p->ctx->device);
     (void)hipDeviceSynchronize();
+    release_graphs(p);
     if (p->own_ws && p->ws) (void)hipFree(p->ws);
     for (auto& e : p->ev)
         if (e) (void)hipEventDestroy(e);
@@ -702,6 +703,7 @@ dino_status dino_problem_destroy(dino_problem* p) {
         DINO_HIP(hipSetDevice(p->ctx->device));
         if (p->last_stream) hipStreamSynchronize(p->last_stream);
         else hipDeviceSynchronize();
+        release_graphs(p);
         if (p->own_ws && p->ws) (void)hipFree(p->ws);
         for (auto& e : p->ev)
             if (e) (void)hipEventDestroy(e);
@@ -765,9 +767,9 @@ static void drain_profile(dino_problem* p) {
 extern "C++" {
 namespace dino {
 
-// n_steps transitions of chains [0, n) on stream st (the body of dino_step; the serving
-// pools call it with n = the highest occupied slot + 1).
-void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
+// n_steps transitions of chains [0, n) on stream st, one launch per kernel (the step
+// loop that launch graphs capture).
+static void run_steps_eager(dino_problem* p, int n, int n_steps, hipStream_t st) {
     const long rr = (long)p->kdim * p->kdim;
     const long half = (long)p->C * rr;
     const int L = (int)p->ctx->layers.size();
@@ -793,9 +795,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             mark(1);
             stage_forward(p, n, p->xp, p->f, st);
             for (int i = 2; i <= 6; ++i) mark(i);
-            int64_t row = -1;
-            if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
-            launch_pcn_accept(p, n, row, st);
+            launch_pcn_accept(p, n, st);
             mark(7);
             mark(8);
             launch_complement(p, n, st);
@@ -821,9 +821,7 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
             if (!f64) stage_hessian(p, n, p->phip, p->gp, nullptr, 0, nullptr, 0, 0, st);  // misfit and ppg only
             mark(5);
             mark(6);
-            int64_t row = -1;
-            if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
-            launch_mala_accept(p, n, row, st);
+            launch_mala_accept(p, n, st);
             mark(7);
             mark(8);
             launch_complement(p, n, st);
@@ -852,17 +850,15 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
         mark(5);
         launch_cholesky_slot(n, p->kdim, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
         mark(6);
-        int64_t row = -1;
-        if (p->xtrace && p->recorded < p->desc.trace_capacity) row = p->recorded++;
         // the accept kernel also ends the step (trace row, running sums, step counter),
         // unless a second stage follows (delayed acceptance), which then ends it
-        if (p->dual) launch_accept_dual(p, n, row, st);
-        else launch_accept(p, n, row, st);
+        if (p->dual) launch_accept_dual(p, n, st);
+        else launch_accept(p, n, st);
         mark(7);
         if (p->da) {
             launch_da_gather(p, n, st);
             launch_true_forward(p, n, p->zin, p->npass, st);
-            launch_da_accept(p, n, row, st);
+            launch_da_accept(p, n, st);
         }
         mark(8);
         launch_complement(p, n, st);
@@ -874,6 +870,65 @@ void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
         }
         p->step += 1;
     }
+}
+
+void release_graphs(dino_problem* p) {
+    for (auto& g : p->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    p->cap_stream = nullptr;
+}
+
+// The executable graph of `steps` transitions of chains [0, nb), captured once from the
+// eager step loop on the problem's capture stream. Every kernel argument of a step is
+// fixed for a problem (the trace row and the Philox counters come from the chains' own
+// step counters in device memory), so one capture serves every later replay.
+static hipGraphExec_t step_graph(dino_problem* p, int nb, int steps) {
+    for (const auto& g : p->graphs)
+        if (g.n == nb && g.steps == steps) return g.exec;
+    if (!p->cap_stream) DINO_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    const int64_t step0 = p->step;
+    hipGraph_t graph = nullptr;
+    DINO_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+        run_steps_eager(p, nb, steps, p->cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(p->cap_stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        p->step = step0;
+        throw;
+    }
+    p->step = step0;
+    DINO_HIP(hipStreamEndCapture(p->cap_stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    DINO_HIP(e);
+    p->graphs.push_back({nb, steps, exec});
+    return exec;
+}
+
+// n_steps transitions of chains [0, n) on stream st (the body of dino_step; the serving
+// pools call it with n = the highest occupied slot + 1). Graph mode replays captured
+// graphs of graph_steps transitions (and one of the remainder); a serving pool's chain
+// count is rounded up to a bucket of 128 slots (idle slots do nothing), so a few graphs
+// serve every occupancy. Profiling runs eagerly (its events sit between the stages).
+void run_steps(dino_problem* p, int n, int n_steps, hipStream_t st) {
+    if (n_steps > 0) {
+        if (p->profile || p->launch_mode != DINO_LAUNCH_GRAPH) {
+            run_steps_eager(p, n, n_steps, st);
+        } else {
+            const int nb = p->serving ? std::min(p->C, (n + 127) / 128 * 128) : n;
+            const int G = std::max(1, std::min(p->graph_steps, n_steps));
+            const hipGraphExec_t full = step_graph(p, nb, G);
+            int done = 0;
+            for (; done + G <= n_steps; done += G) DINO_HIP(hipGraphLaunch(full, st));
+            if (done < n_steps) DINO_HIP(hipGraphLaunch(step_graph(p, nb, n_steps - done), st));
+            p->step += n_steps;
+        }
+    }
+    if (p->xtrace) p->recorded = std::min<int64_t>(p->step, p->desc.trace_capacity);
     p->last_stream = st;
 }
 
@@ -914,6 +969,19 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
         DINO_REQUIRE(n_steps >= 0, DINO_EINVAL, "negative step count");
         DINO_HIP(hipSetDevice(p->ctx->device));
         run_steps(p, p->C, n_steps, as_stream(stream));
+    });
+}
+
+dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph) {
+    return guarded([&] {
+        DINO_REQUIRE(p, DINO_EINVAL, "null problem");
+        DINO_REQUIRE(mode == DINO_LAUNCH_EAGER || mode == DINO_LAUNCH_GRAPH, DINO_EINVAL, "unknown launch mode");
+        DINO_REQUIRE(steps_per_graph >= 1 && steps_per_graph <= 256, DINO_EINVAL, "steps_per_graph must be in 1..256");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        if (p->last_stream) DINO_HIP(hipStreamSynchronize(p->last_stream));
+        if (steps_per_graph != p->graph_steps) release_graphs(p);
+        p->launch_mode = mode;
+        p->graph_steps = steps_per_graph;
     });
 }
 

@@ -15,6 +15,7 @@ from .workloads import (  # noqa: F401
     draw_network,
     draw_noise,
     draw_requests,
+    draw_true_model,
     draw_true_state,
     workload,
 )

@@ -12,6 +12,8 @@ weights and meshes are not available:
     serve : 129x129 grid, r=200, ResNet 400x4 (100 outputs); requests with d_y in {25,50,100},
             chains uniform in [8,128], steps uniform in [500,5000], Poisson arrivals
     large : 257x257 grid, r=400, ResNet width 800 depth 6, d_y=400, 4096 chains x 2000 steps
+    mix   : the mid shapes with sigma = 30% of max |f(x_true)|: a weakly informed posterior
+            on which the mid-shaped chains decorrelate within ~1000 steps (the ESS/s leg)
 
 Step sizes: tiny keeps the literal dt = 0.1 of its definition; mid and serve use the
 value chosen once by the appendix's tuning rule (AR decreasing and MSJ increasing up
@@ -66,6 +68,7 @@ CONFIGS = {
     "mid": Workload("mid", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 512, 1000, 3e-4, "rel_max", 0.01),
     "serve": Workload("serve", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 68, 2750, 3e-4, "rel_max", 0.01),
     "large": Workload("large", 257, 0.1, 1.0, 400, "resnet", 800, 6, 400, 400, 4096, 2000, 3e-4, "rel_max", 0.01),
+    "mix": Workload("mix", 129, 0.1, 1.0, 200, "resnet", 400, 4, 100, 100, 512, 1200, 0.1, "rel_max", 0.3),
 }
 
 TUNED_DT = {"tiny": 3e-3, "mid": 3e-4, "serve": 3e-4}
@@ -163,3 +166,19 @@ def draw_requests(count: int, rate: float, seed: int = 11):
     base = rng.integers(1, 2 ** 31, size=(count, 3))
     return [Request(i, float(t[i]), int(dys[i]), int(cs[i]), int(ns[i]),
                     int(base[i, 0]), int(base[i, 1]), int(base[i, 2])) for i in range(count)]
+
+
+def draw_true_model(layers, extra: int, eps: float = 0.05, seed: int = 17):
+    """Layers of a true-model stand-in for delayed acceptance: the surrogate's weights with
+    relative N(0, eps^2) perturbations and `extra` more input columns on the first layer
+    (N(0, (std(W_1)/2)^2) entries), so that it also reads the first `extra` complement
+    coordinates."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for l, (kind, W, b) in enumerate(layers):
+        W2 = W * (1.0 + eps * rng.standard_normal(W.shape))
+        if l == 0 and extra:
+            cols = rng.standard_normal((W.shape[0], extra)) * (np.std(W) * 0.5)
+            W2 = np.concatenate([W2, cols], axis=1)
+        out.append((kind, W2, None if b is None else b.copy()))
+    return out

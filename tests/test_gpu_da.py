@@ -19,23 +19,11 @@ import numpy as np
 import pytest
 
 from oracle import da, mcmc
+from synth import draw_true_model
 from tests.helpers import device_problem, make_case, rel_err
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
-
-
-def true_layers_from(layers, extra, eps=0.05, seed=17):
-    """The surrogate with `extra` more inputs on its first layer and relative weight noise eps."""
-    rng = np.random.default_rng(seed)
-    out = []
-    for l, (kind, W, b) in enumerate(layers):
-        W2 = W * (1.0 + eps * rng.standard_normal(W.shape))
-        if l == 0 and extra:
-            cols = rng.standard_normal((W.shape[0], extra)) * (np.std(W) * 0.5)
-            W2 = np.concatenate([W2, cols], axis=1)
-        out.append((kind, W2, None if b is None else b.copy()))
-    return out
 
 
 def da_case(C, extra=8, dt=0.5, name="tiny", **kw):
@@ -43,7 +31,7 @@ def da_case(C, extra=8, dt=0.5, name="tiny", **kw):
         kw = dict(dict(arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20, bias_scale=0.3, noise_scale=0.2),
                   **kw)
     case = make_case(name, chains=C, dt=dt, **kw)
-    case["tm"] = da.TrueModel(true_layers_from(case["layers"], extra))
+    case["tm"] = da.TrueModel(draw_true_model(case["layers"], extra))
     case["prob"].method = "mmala"
     return case
 

@@ -86,3 +86,58 @@ def test_configured_case_against_oracle():
     # the device trace holds FP32 states: 1e-6 relative on the moments
     assert dm64 < 1e-6 and dv64 < 1e-6
     assert np.isfinite(dm16) and np.isfinite(dv16)
+
+
+def test_bf16_dual_posterior_at_the_bench_shape():
+    """The bench's path (BF16, observation-space form) at its shapes: 129^2 grid, r = 200,
+    ResNet 400 x 4, d_y = 100, on the mix workload (sigma = 30% of max |f(x_true)|, dt = 0.1,
+    where these chains decorrelate within the run), 4096 chains x 600 steps from Laplace
+    samples, burn-in 20%. BF16 and FP64 run on coupled streams (same keys and starts); an
+    independent BF16 replicate (another seed) gives the Monte Carlo scale. Measured: coupled
+    deviation 1.5% (mean field) and 0.7% (variance) against a Monte Carlo scale of 2.8% and
+    1.4%. At 16384 chains the variance scale halves (0.63%, coupled 0.46%) but the mean
+    field's stays at 2.9% (coupled 1.8%): this weakly informed mean field has a Monte Carlo
+    component that more chains of this length do not reduce, so 1% is not resolvable here
+    at a test's cost; the 1% target is asserted on the well-mixing case above. Here the
+    BF16 deviation must lie below the Monte Carlo scale (no bias beyond sampling error) and
+    below 2%."""
+    from paper_2403_08220_amd import Context, Problem, laplace
+    from synth import draw_laplace_normals, draw_network, draw_noise, draw_true_state, workload
+
+    w = workload("mix")
+    C, steps = 4096, 600
+    ctx = Context(0)
+    try:
+        ctx.load_prior(w.n, w.gamma, w.delta, w.r)
+        ctx.load_network(draw_network(w))
+        x_true = draw_true_state(w)[: w.r]
+        tmp = Problem(ctx, 1, np.zeros(w.d_y), np.ones(w.d_y), 0.1, track_complement=False)
+        f_true = tmp.eval_geometry(torch.tensor(x_true[None], device="cuda:0"), want_H=False)["f"].cpu().numpy()[0]
+        tmp.close()
+        sigma = w.sigma * np.max(np.abs(f_true))
+        y, nv = f_true + sigma * draw_noise(w), np.full(w.d_y, sigma ** 2)
+        m = laplace.gauss_newton_map(ctx, y, nv)
+        x0 = laplace.laplace_samples(ctx, y, nv, m.x, draw_laplace_normals(w, chains=C))
+        out = {}
+        for tag, prec, seed in (("f64", "f64", w.chain_seed), ("bf16", "bf16", w.chain_seed),
+                                ("bf16_rep", "bf16", w.chain_seed + 1000)):
+            print(f"statistics at the bench shape: {tag}", flush=True)
+            p = Problem(ctx, C, y, nv, w.dt, seed=seed, precision=prec, track_complement=False,
+                        trace_capacity=steps, factorization="auto")
+            p.init(x0, None)
+            p.step(steps)
+            acc, fail, _ = p.diagnostics()
+            mean, var, _, _ = p.posterior(steps // 5)
+            out[tag] = dict(mean=mean, var=var, accept=acc.sum() / (C * steps), failures=int(fail.sum()))
+            p.close()
+    finally:
+        ctx.close()
+    f64, b16, rep = out["f64"], out["bf16"], out["bf16_rep"]
+    dm, dv = rel_l2(b16["mean"], f64["mean"]), rel_l2(b16["var"], f64["var"])
+    rm, rv = rel_l2(rep["mean"], b16["mean"]), rel_l2(rep["var"], b16["var"])
+    print(f"bench shape: accept fp64 {f64['accept']:.3f} bf16 {b16['accept']:.3f}; rel L2 bf16 vs fp64 (coupled): "
+          f"mean {dm:.2e} var {dv:.2e}; independent replicate: mean {rm:.2e} var {rv:.2e}", flush=True)
+    assert f64["failures"] == 0 and b16["failures"] == 0
+    assert abs(b16["accept"] - f64["accept"]) < 0.01
+    assert dm < rm and dv < rv
+    assert dm < 0.02 and dv < 0.02

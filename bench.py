@@ -205,7 +205,7 @@ def copy_calibration(nbytes=1 << 29):
 
 
 def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, factorization="auto", method="mmala",
-             dt=None, fixed=None):
+             dt=None, fixed=None, tune=True):
     import torch
     from paper_2403_08220_amd import Problem
 
@@ -216,6 +216,8 @@ def run_path(w, ctx, y, nv, x0, z0, precision, steps, warmup, profile=True, fact
     p.init(x0, z0)
     if fixed is not None:
         p.set_fixed_metric(*fixed)
+    if tune:
+        p.autotune()  # implementation choices for this problem's shapes, before any timing
     stream = torch.cuda.current_stream()
     p.step(warmup)
     torch.cuda.synchronize()
@@ -603,7 +605,7 @@ def main():
         sys.exit(2)
 
     import torch  # noqa: F401
-    from paper_2403_08220_amd import Context
+    from paper_2403_08220_amd import Context, tuning_table
     from synth import draw_network, workload
 
     w = workload("mid")
@@ -727,6 +729,9 @@ def main():
         "serving": serving,
         "cpu_baseline": cpu,
         "init": init_info,
+        "launch": "graphs of 8 steps (dino_step default)",
+        "autotune": [dict(kind=e["kind"], shape=list(e["shape"]), choice=e["choice"],
+                          ms=[round(v, 4) for v in e["ms"]]) for e in tuning_table()],
     }
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -219,6 +219,28 @@ dino_status dino_set_fixed_metric(dino_problem* p, const double* x_map, const do
 #define DINO_LAUNCH_GRAPH 1
 dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph);
 
+/* Autotuner. Times the implementations that can run a stage of this problem at its
+ * shapes, on the problem's own buffers between steps (stage outputs that every step
+ * overwrites; the chains' states are not touched), and keeps the fastest in a
+ * process-wide table keyed by stage and shape, which every later launch of that shape
+ * uses (other problems and serving pools included):
+ *   kind DINO_TUNE_CHOL  (a, b, c) = (chains, factor order, 0): the factor kernel,
+ *        0-2 one wavefront per chain (orders up to 32 / 56 / 104), 3-4 one block per
+ *        chain with the triangle in registers (up to 128 / 208), 5 the LDS panel kernel;
+ *   kind DINO_TUNE_FWD64 (rows, fan_in, fan_out): FP64 forward tile of 16, 32 or 64 outputs;
+ *   kind DINO_TUNE_FWD32 (rows, fan_in, fan_out): FP32 MFMA forward block order, 0 row-major,
+ *        1 the tiles of a 32-row block on one XCD.
+ * Every choice computes the same quantities (rounding order may differ between factor
+ * kernels). n_entries (optional): table entries written. Releases the problem's launch
+ * graphs (they hold the earlier choices). dino_tune_set sets or (choice < 0) erases an
+ * entry; dino_tuning_table writes the table as text lines "kind a b c choice ms...". */
+#define DINO_TUNE_CHOL 0
+#define DINO_TUNE_FWD64 1
+#define DINO_TUNE_FWD32 2
+dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries);
+dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice);
+dino_status dino_tuning_table(char* buf, size_t cap, size_t* length);
+
 /* Advance every chain n_steps transitions (Alg. 1 first stage + the splitting proposition of Sec. 5.3).
  * Asynchronous on stream. Per-chain numerical failures (non-finite misfit,
  * I + H not positive definite) reject the proposal and are counted; they do

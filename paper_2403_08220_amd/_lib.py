@@ -14,6 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
+TUNE_KINDS = {"chol": 0, "fwd64": 1, "fwd32": 2}
 LAUNCH_MODES = {"eager": 0, "graph": 1}
 METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4}
 
@@ -123,6 +124,9 @@ SIGNATURES = {
     "dino_eval_log_rho_dual": (ct.c_int32, [_P, ct.c_int] + [_P] * 13 + [_P]),
     "dino_set_profiling": (ct.c_int32, [_P, ct.c_int]),
     "dino_set_launch_mode": (ct.c_int32, [_P, ct.c_int, ct.c_int]),
+    "dino_autotune": (ct.c_int32, [_P, _P, _I32]),
+    "dino_tune_set": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32]),
+    "dino_tuning_table": (ct.c_int32, [ct.c_char_p, ct.c_size_t, ct.POINTER(ct.c_size_t)]),
     "dino_read_profile": (ct.c_int32, [_P, _D, _I32, _I64]),
     "dino_stage_name": (ct.c_char_p, [ct.c_int]),
     "dino_encode": (ct.c_int32, [_P, ct.c_int, _P, _P, _P, _P]),

@@ -173,6 +173,12 @@ class Problem:
     def step(self, n: int, stream=None):
         check(self.lib.dino_step(self.h, n, _stream_handle(stream)))
 
+    def autotune(self, stream=None) -> int:
+        """Time the implementations of this problem's stages and keep the fastest (dino_autotune)."""
+        n = np.zeros(1, dtype=np.int32)
+        check(self.lib.dino_autotune(self.h, _stream_handle(stream), i32ptr(n)))
+        return int(n[0])
+
     def set_launch_mode(self, mode: str = "graph", steps_per_graph: int = 8):
         """"graph": dino_step replays captured graphs of steps_per_graph transitions; "eager":
         one launch per kernel."""
@@ -327,6 +333,33 @@ class Problem:
         out = torch.empty((n, count), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
         check(self.lib.dino_eval_normals(self.h, n, stream_id, step, count, _tp(out), _stream_handle(stream)))
         return out
+
+
+def tuning_table():
+    """The process-wide tuning table: list of dicts (kind, shape, choice, ms per candidate)."""
+    lib = _lib.load()
+    n = ct.c_size_t()
+    check(lib.dino_tuning_table(None, 0, ct.byref(n)))
+    buf = ct.create_string_buffer(n.value + 1)
+    check(lib.dino_tuning_table(buf, n.value + 1, ct.byref(n)))
+    kinds = {v: k for k, v in _lib.TUNE_KINDS.items()}
+    out = []
+    for line in buf.value.decode().splitlines():
+        f = line.split()
+        out.append(dict(kind=kinds[int(f[0])], shape=tuple(int(v) for v in f[1:4]), choice=int(f[4]),
+                        ms=[float(v) for v in f[5:]]))
+    return out
+
+
+def tune_set(kind: str, shape, choice: int):
+    """Set (choice >= 0) or erase (choice < 0) a tuning-table entry."""
+    a, b, c = shape
+    check(_lib.load().dino_tune_set(_lib.TUNE_KINDS[kind], a, b, c, choice))
+
+
+def clear_tuning():
+    for e in tuning_table():
+        tune_set(e["kind"], e["shape"], -1)
 
 
 class Server:

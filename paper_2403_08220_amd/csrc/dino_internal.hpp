@@ -336,6 +336,13 @@ struct dino_problem {
 
 namespace dino {
 
+// Tuning table (runtime.hip): the implementation chosen for a stage at a shape (a, b, c),
+// process-wide; -1 when the shape has no entry (the launcher's default then applies).
+enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2 };
+constexpr int CHOL_VARIANTS = 6;
+int tuned_choice(int kind, int a, int b, int c);
+void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms);
+
 // launch helpers (kernels_*.hip)
 void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipStream_t st);
 void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t st);
@@ -347,6 +354,11 @@ void launch_gn_hessian_slot(dino_problem* p, int n, const double* B, double* A, 
 // Matrices addressed per chain c as base + c*stride + (slot[c] ^ slot_xor) * slot_stride.
 void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
                           long slot_stride, double* logdet, int32_t* ok, hipStream_t st);
+void launch_cholesky_variant(int variant, int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                             long slot_stride, double* logdet, int32_t* ok, hipStream_t st);
+int cholesky_variant_max(int variant);
+void launch_fill_identity(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor, long slot_stride,
+                          hipStream_t st);
 void launch_propose_slot(dino_problem* p, int n, const double* x, const double* g, const double* L, long strideL,
                          const int32_t* slot, int slot_xor, long slot_stride, const double* xi_given, bool use_meta,
                          double* xp, double* lfwd, const double* logdet, hipStream_t st);

@@ -1983,33 +1983,82 @@ __global__ void copy_rows_kernel(int n, int width, const double* __restrict__ sr
 static size_t chol_lds(int r) { return (size_t)r * CLDP * sizeof(double); }
 static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
 
-void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
-                          long slot_stride, double* logdet, int32_t* ok, hipStream_t st) {
-    const size_t lds = chol_lds(r);
+// Factor kernels by variant: 0-2 one wavefront per chain (orders up to 32, 56, 104), 3-4
+// a 512-thread block per chain with the triangle in registers (up to 128, 208), 5 the
+// LDS panel kernel (up to 512). Any variant whose maximum covers the order is correct.
+static const int kCholMax[CHOL_VARIANTS] = {32, 56, 104, 128, 208, 512};
+
+int cholesky_variant_max(int variant) { return (variant >= 0 && variant < CHOL_VARIANTS) ? kCholMax[variant] : 0; }
+
+// The smallest variant that holds the order (the choice without a tuning entry).
+static int default_cholesky_variant(int r) {
+    for (int v = 0; v < CHOL_VARIANTS; ++v)
+        if (r <= kCholMax[v]) return v;
+    return CHOL_VARIANTS - 1;
+}
+
+void launch_cholesky_variant(int variant, int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                             long slot_stride, double* logdet, int32_t* ok, hipStream_t st) {
+    DINO_REQUIRE(variant >= 0 && variant < CHOL_VARIANTS && r <= kCholMax[variant], DINO_EINVAL,
+                 "factor kernel variant does not hold this order");
     static bool attr_set = false;
     if (!attr_set) {
         DINO_HIP(hipFuncSetAttribute((const void*)cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      160 * 1024 - 256));
         attr_set = true;
     }
-    if (r <= 32) {
+    switch (variant) {
+    case 0:
         hipLaunchKernelGGL((cholesky_wave_kernel<4>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
                            slot_stride, logdet, ok);
-    } else if (r <= 56) {
+        break;
+    case 1:
         hipLaunchKernelGGL((cholesky_wave_kernel<7>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
                            slot_stride, logdet, ok);
-    } else if (r <= 104) {
+        break;
+    case 2:
         hipLaunchKernelGGL((cholesky_wave_kernel<13>), dim3(n), dim3(64), 0, st, r, A, strideA, slot, slot_xor,
                            slot_stride, logdet, ok);
-    } else if (r <= 128) {
+        break;
+    case 3:
         hipLaunchKernelGGL((cholesky_reg_kernel<512, 8, 4>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
                            slot_xor, slot_stride, logdet, ok);
-    } else if (r <= 208) {
+        break;
+    case 4:
         hipLaunchKernelGGL((cholesky_reg_kernel<512, 13, 7>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
                            slot_xor, slot_stride, logdet, ok);
-    } else {
-        hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), lds, st, r, A, strideA, slot, slot_xor, slot_stride,
-                           logdet, ok);
+        break;
+    default:
+        hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), chol_lds(r), st, r, A, strideA, slot, slot_xor,
+                           slot_stride, logdet, ok);
+        break;
+    }
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_cholesky_slot(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                          long slot_stride, double* logdet, int32_t* ok, hipStream_t st) {
+    int v = tuned_choice(TUNE_CHOL, n, r, 0);
+    if (v < 0 || cholesky_variant_max(v) < r) v = default_cholesky_variant(r);
+    launch_cholesky_variant(v, n, r, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
+}
+
+// Identity matrices of order r in the slot-selected halves (factor timing input).
+__global__ void fill_identity_kernel(int r, double* A, long strideA, const int32_t* slot, int slot_xor,
+                                     long slot_stride) {
+    const int c = blockIdx.y;
+    double* a = A + (long)c * strideA + slot_offset(slot, slot_xor, slot_stride, c);
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)r * r; e += (long)gridDim.x * blockDim.x)
+        a[e] = (e / r == e % r) ? 1.0 : 0.0;
+}
+
+void launch_fill_identity(int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor, long slot_stride,
+                          hipStream_t st) {
+    const int bx = (int)std::min<long>(((long)r * r + 255) / 256, 64);
+    for (int c0 = 0; c0 < n; c0 += (int)GRID_Y_MAX) {
+        const int cn = std::min(n - c0, (int)GRID_Y_MAX);
+        hipLaunchKernelGGL(fill_identity_kernel, dim3(bx, cn), dim3(256), 0, st, r, A + (long)c0 * strideA, strideA,
+                           slot ? slot + c0 : nullptr, slot_xor, slot_stride);
     }
     DINO_HIP(hipGetLastError());
 }

@@ -285,7 +285,8 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
                                                        const double* __restrict__ in64,
                                                        const float* __restrict__ W, const float* __restrict__ b,
                                                        int kind, float* __restrict__ out, int ldout,
-                                                       float* __restrict__ dprime, int ldd, const int* m_dev) {
+                                                       float* __restrict__ dprime, int ldd, const int* m_dev,
+                                                       int xcd_map) {
     // in64 (first layer): the FP64 states, rounded to FP32 as they are loaded
     __shared__ float red[4][64][17];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
     // layer's blocks of that row block read activations written through the same L2.
     const int nx = (N + 31) / 32, ny = (M + 31) / 32;
     int tx, ty;
-    if ((ny & 7) == 0) {
+    if (xcd_map && (ny & 7) == 0) {
         const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
         ty = xcd + 8 * (slot / nx);
         tx = slot % nx;
@@ -400,10 +401,14 @@ template <typename T>
 static void fwd_layer(int M, int K, int N, const T* in, int ldin, const T* W, const T* b, int kind, T* out,
                       int ldout, T* dprime, int ldd, hipStream_t st, const int* m_dev = nullptr) {
     auto blocks = [&](int bm, int bn) { return (long)((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
-    if (blocks(64, 64) >= 1024)
+    // tile 0: 16 x 16, 1: 32 x 32, 2: 64 x 64 outputs per block; a tuning entry for the
+    // shape decides, else the largest tile that still gives 1024 blocks
+    int tile = tuned_choice(TUNE_FWD64, M, K, N);
+    if (tile < 0 || tile > 2) tile = blocks(64, 64) >= 1024 ? 2 : (blocks(32, 32) >= 1024 ? 1 : 0);
+    if (tile == 2)
         hipLaunchKernelGGL((fwd_layer_kernel<T, 4, 4>), dim3((N + 63) / 64, (M + 63) / 64), dim3(256), 0, st, M, K, N,
                            in, ldin, W, b, kind, out, ldout, dprime, ldd, m_dev);
-    else if (blocks(32, 32) >= 1024)
+    else if (tile == 1)
         hipLaunchKernelGGL((fwd_layer_kernel<T, 2, 2>), dim3((N + 31) / 32, (M + 31) / 32), dim3(256), 0, st, M, K, N,
                            in, ldin, W, b, kind, out, ldout, dprime, ldd, m_dev);
     else
@@ -491,6 +496,14 @@ void launch_forward(dino_problem* p, int n, const double* x, double* f_out, hipS
     DINO_HIP(hipGetLastError());
 }
 
+// Block order of an FP32 forward layer: 1 groups the tiles of a 32-row block on one XCD
+// (when the row blocks divide by 8), 0 takes tiles in plain row-major order; a tuning
+// entry for the shape decides, else the XCD grouping.
+static int fwd32_xcd_map(int M, int K, int N) {
+    const int t = tuned_choice(TUNE_FWD32, M, K, N);
+    return t == 0 ? 0 : 1;
+}
+
 // FP32 forward of the mixed-precision path: gelu'(z) into d32 (row length ldd32).
 void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
@@ -509,7 +522,7 @@ void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64
         // the first layer reads the FP64 states (x64) when given, else the FP32 copy xf
         hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((n + 31) / 32)), dim3(256), 0, st, n, ly.fan_in, N,
                            in, ldin, l == 0 ? x64 : nullptr, ly.W32, ly.b32, ly.kind, out, ldout, dp, p->ldd32,
-                           (const int*)nullptr);
+                           (const int*)nullptr, fwd32_xcd_map(n, ly.fan_in, N));
         if (ly.kind != DINO_LAYER_LINEAR) ++act;
         in = out;
         ldin = ldout;
@@ -550,7 +563,7 @@ void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m
             const int N = last ? dy : ly.fan_out;
             hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((n + 31) / 32)), dim3(256), 0, st, n, ly.fan_in,
                                N, in, ldin, l == 0 ? zin : nullptr, ly.W32, ly.b32, ly.kind, out, ldout,
-                               (float*)nullptr, 0, m_dev);
+                               (float*)nullptr, 0, m_dev, fwd32_xcd_map(n, ly.fan_in, N));
             in = out;
             ldin = ldout;
         }

@@ -3,7 +3,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <array>
 #include <exception>
+#include <map>
 #include <mutex>
 #include <numeric>
 
@@ -58,6 +60,26 @@ static dino_status guarded(F&& fn) {
         set_error("unknown failure");
         return DINO_EDEVICE;
     }
+}
+
+// Tuning table: (kind, a, b, c) -> chosen implementation and the timings it was chosen by.
+struct TuneEntry {
+    int choice = -1;
+    std::vector<double> ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::array<int, 4>, TuneEntry> g_tune;
+
+int tuned_choice(int kind, int a, int b, int c) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find({kind, a, b, c});
+    return it == g_tune.end() ? -1 : it->second.choice;
+}
+
+void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (choice < 0) g_tune.erase({kind, a, b, c});
+    else g_tune[{kind, a, b, c}] = TuneEntry{choice, ms};
 }
 
 static void free_basis(Basis& b) {
@@ -969,6 +991,124 @@ dino_status dino_step(dino_problem* p, int n_steps, void* stream) {
         DINO_REQUIRE(n_steps >= 0, DINO_EINVAL, "negative step count");
         DINO_HIP(hipSetDevice(p->ctx->device));
         run_steps(p, p->C, n_steps, as_stream(stream));
+    });
+}
+
+}  // extern "C"
+
+// Mean milliseconds of `reps` runs of fn on st (after one untimed run).
+template <typename F>
+static double time_on_stream(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F&& fn) {
+    fn();
+    DINO_HIP(hipEventRecord(e0, st));
+    for (int k = 0; k < reps; ++k) fn();
+    DINO_HIP(hipEventRecord(e1, st));
+    DINO_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    DINO_HIP(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / reps;
+}
+
+extern "C" {
+
+dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
+    return guarded([&] {
+        DINO_REQUIRE(p && p->initialised, DINO_ESTATE, "dino_chains_init must precede dino_autotune");
+        DINO_HIP(hipSetDevice(p->ctx->device));
+        hipStream_t st = as_stream(stream);
+        if (p->last_stream) DINO_HIP(hipStreamSynchronize(p->last_stream));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        DINO_HIP(hipEventCreate(&e0));
+        DINO_HIP(hipEventCreate(&e1));
+        int count = 0;
+        try {
+            const int C = p->C;
+            const bool factor = p->desc.method == DINO_METHOD_MMALA || p->desc.method == DINO_METHOD_DA_MMALA;
+            if (factor) {
+                // the factor kernel at (C, k) on identity matrices in the proposal halves (scratch
+                // between steps; the factor of an identity is itself, so runs can repeat)
+                const int k = p->kdim;
+                const long kk = (long)k * k, half = (long)C * kk;
+                launch_fill_identity(C, k, p->Lbuf, kk, p->cur, 1, half, st);
+                std::vector<double> ms(CHOL_VARIANTS, -1.0);
+                int best = -1;
+                for (int v = 0; v < CHOL_VARIANTS; ++v) {
+                    if (cholesky_variant_max(v) < k) continue;
+                    ms[v] = time_on_stream(st, e0, e1, 5, [&] {
+                        launch_cholesky_variant(v, C, k, p->Lbuf, kk, p->cur, 1, half, p->logdetp, p->okp, st);
+                    });
+                    if (best < 0 || ms[v] < ms[best]) best = v;
+                }
+                set_tuned_choice(TUNE_CHOL, C, k, 0, best, ms);
+                ++count;
+            }
+            // the forward layers, one shape at a time (the other shapes at their current
+            // choice), timed as the whole forward stage at the states (its outputs are scratch)
+            const bool f64 = p->desc.precision == DINO_PREC_F64;
+            const int kind = f64 ? TUNE_FWD64 : TUNE_FWD32;
+            const int ncand = f64 ? 3 : 2;
+            std::vector<std::array<int, 3>> shapes;
+            const auto& L = p->ctx->layers;
+            for (size_t l = 0; l < L.size(); ++l) {
+                const int N = (l + 1 == L.size()) ? p->d_y : L[l].fan_out;
+                const std::array<int, 3> sh{C, L[l].fan_in, N};
+                if (!f64 && ((C + 31) / 32) % 8 != 0) continue;  // the block order only differs then
+                if (std::find(shapes.begin(), shapes.end(), sh) == shapes.end()) shapes.push_back(sh);
+            }
+            for (const auto& sh : shapes) {
+                std::vector<double> ms(ncand, -1.0);
+                int best = -1;
+                for (int cnd = 0; cnd < ncand; ++cnd) {
+                    set_tuned_choice(kind, sh[0], sh[1], sh[2], cnd, {});
+                    ms[cnd] = time_on_stream(st, e0, e1, 5, [&] { stage_forward(p, C, p->x, p->f, st); });
+                    if (best < 0 || ms[cnd] < ms[best]) best = cnd;
+                }
+                set_tuned_choice(kind, sh[0], sh[1], sh[2], best, ms);
+                ++count;
+            }
+        } catch (...) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            throw;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        release_graphs(p);  // captured graphs hold the earlier choices
+        p->last_stream = st;
+        if (n_entries) *n_entries = count;
+    });
+}
+
+dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice) {
+    return guarded([&] {
+        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_FWD32, DINO_EINVAL, "unknown tuning kind");
+        const int ncand = kind == TUNE_CHOL ? CHOL_VARIANTS : (kind == TUNE_FWD64 ? 3 : 2);
+        DINO_REQUIRE(choice < ncand, DINO_EINVAL, "choice out of range for this kind");
+        DINO_REQUIRE(kind != TUNE_CHOL || choice < 0 || cholesky_variant_max(choice) >= b, DINO_EINVAL,
+                     "factor kernel variant does not hold this order");
+        set_tuned_choice(kind, a, b, c, choice, {});
+    });
+}
+
+dino_status dino_tuning_table(char* buf, size_t cap, size_t* length) {
+    return guarded([&] {
+        std::string out;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            for (const auto& kv : g_tune) {
+                out += std::to_string(kv.first[0]) + " " + std::to_string(kv.first[1]) + " " +
+                       std::to_string(kv.first[2]) + " " + std::to_string(kv.first[3]) + " " +
+                       std::to_string(kv.second.choice);
+                for (double m : kv.second.ms) out += " " + std::to_string(m);
+                out += "\n";
+            }
+        }
+        if (length) *length = out.size();
+        if (buf && cap) {
+            const size_t n = std::min(cap - 1, out.size());
+            std::memcpy(buf, out.data(), n);
+            buf[n] = 0;
+        }
     });
 }
 

@@ -39,22 +39,29 @@ STREAM_UNIFORM2 = 5
 
 @dataclass
 class TrueModel:
-    """The true parameter-to-observable map's stand-in: a network on z[0:r_T]."""
+    """The true parameter-to-observable map's stand-in: a network on z[0:r_T]. basis: a
+    prior.DenseBasis when the reduced basis is dense (else the KLE basis)."""
     layers: list
+    basis: object = None
 
     @property
     def r_T(self) -> int:
         return self.layers[0][1].shape[1]
 
 
-def true_misfit(prob: mcmc.Problem, tm: TrueModel, x: np.ndarray, z: np.ndarray | None) -> np.ndarray:
+def true_misfit(prob: mcmc.Problem, tm: TrueModel, x: np.ndarray, z: np.ndarray | None, basis=None) -> np.ndarray:
     """Phi(m) = 1/2 |Gamma^-1/2 (y - G(m))|^2 (eq. data_model and the Gaussian likelihood of
-    Sec. 2.1) of full parameters given by reduced coordinates x (C, r) and complement z
-    (C, d_m - r) (z may be None when r_T = r)."""
+    Sec. 2.1) of full parameters given by reduced coordinates x (C, r) and complement z.
+    KLE basis (basis None): z (C, d_m - r) holds the whitened coordinates past r (None when
+    r_T = r). Dense basis (prior.DenseBasis): z (C, d_m) is the unprojected complement draw
+    w and the full parameter is U x + (I - U U^T) w (Alg. 1's assembly of m+)."""
     x = np.atleast_2d(np.asarray(x, dtype=np.float64))
     r = x.shape[1]
     extra = tm.r_T - r
-    zin = x if extra == 0 else np.concatenate([x, np.asarray(z, dtype=np.float64)[:, :extra]], axis=1)
+    if basis is not None:
+        zin = basis.full(x, np.asarray(z, dtype=np.float64))[:, :tm.r_T]
+    else:
+        zin = x if extra == 0 else np.concatenate([x, np.asarray(z, dtype=np.float64)[:, :extra]], axis=1)
     f, _ = network.forward(tm.layers, zin)
     w = 1.0 / np.sqrt(np.asarray(prob.noise_var, dtype=np.float64))
     res = (prob.y[None, :] - f[:, :prob.d_y]) * w[None, :]
@@ -99,7 +106,7 @@ class DARecord:
 
 def init_da_state(prob: mcmc.Problem, tm: TrueModel, x0, z0=None, chains=None) -> DAState:
     st = mcmc.init_state(prob, x0, z0, chains=chains)
-    return DAState(chain=st, phi_true=true_misfit(prob, tm, st.x, st.z))
+    return DAState(chain=st, phi_true=true_misfit(prob, tm, st.x, st.z, tm.basis))
 
 
 def transition_da(prob: mcmc.Problem, tm: TrueModel, ds: DAState, xi=None, u=None, zeta=None, u2=None) -> DARecord:
@@ -140,7 +147,7 @@ def transition_da(prob: mcmc.Problem, tm: TrueModel, ds: DAState, xi=None, u=Non
     lr2 = np.full(C, np.nan)
     if np.any(passed):
         idx = np.nonzero(passed)[0]
-        phi_tp[idx] = true_misfit(prob, tm, xp[idx], None if zp is None else zp[idx])
+        phi_tp[idx] = true_misfit(prob, tm, xp[idx], None if zp is None else zp[idx], tm.basis)
         lr2[idx] = log_rho2(st.cache.phi[idx], ds.phi_true[idx], cp.phi[idx], phi_tp[idx])
     good2 = passed & np.isfinite(lr2)
     acc = good2 & (np.log(u2) <= np.where(good2, lr2, -np.inf))

@@ -38,6 +38,9 @@ Readings of the paper taken here (listed with reasons in the design notes):
   log rho = Phi(x) - Phi(x+) + (|x|^2 - |x+|^2)/2 + (|L^T(x+ - x_map)|^2 - |L^T(x - x_map)|^2)/2
   (target over Laplace density). The complement keeps its pCN move (the Laplace
   approximation equals the prior there).
+* The DIS-mMALA baseline (method "dis_mmala", Sec. 6.1 with eq. dis_gnh) is the mMALA
+  transition with the metric fixed at the DIS approximation of the expected ppGNH, which is
+  diag(lam) in the coordinates of a DIS basis (lam its eigenvalues), and the ppg kept.
 * The MALA baseline (method "mala") is the mMALA transition with the metric removed
   (H = 0, so d = 0, P = L = I and B = 0 in the noise mapping) and the ppg kept: x+ =
   s x - (1 - s) g + beta xi, and rho_0 keeps its ppg terms only.
@@ -64,8 +67,9 @@ class Problem:
     request_id: int = 0
     factor: str = "primal"   # proposal noise mapping: "primal" (L^-T xi) or "dual"
     method: str = "mmala"    # "mmala"; baselines of Sec. 6.1: "pcn" (no metric, no ppg), "mala" (ppg only),
-                             # "lapcn" (metric fixed at the MAP, no ppg)
-    fixed: tuple = None      # "lapcn": (x_map (r,), lower Cholesky factor of I + H(x_map) (r, r))
+                             # "lapcn" (metric fixed at the MAP, no ppg), "dis_mmala" (fixed DIS metric, ppg)
+    fixed: tuple = None      # "lapcn": (x_map (r,), lower Cholesky factor of I + H(x_map) (r, r));
+                             # "dis_mmala": the DIS eigenvalues lam (r,) (the metric diag(lam))
 
     @property
     def d_y(self) -> int:
@@ -161,10 +165,29 @@ def without_metric(c: Cache) -> Cache:
                  B=None if c.B is None else np.zeros_like(c.B))
 
 
+def with_diagonal_metric(c: Cache, lam: np.ndarray) -> Cache:
+    """The cache with the Gauss-Newton metric replaced by the fixed diag(lam) and the misfit
+    and ppg kept: the geometry DIS-mMALA proposes with (the DIS-mMALA row of the baselines
+    of Sec. 6.1: the DIS approximation of the expected ppGNH, eq. dis_gnh, which is diagonal
+    in the coordinates of a DIS basis, with its eigenvalues lam, and the gradient)."""
+    C, r = c.g.shape
+    lam = np.asarray(lam, dtype=np.float64)
+    H = np.broadcast_to(np.diag(lam), (C, r, r)).copy()
+    L = np.broadcast_to(np.diag(np.sqrt(1.0 + lam)), (C, r, r)).copy()
+    return Cache(f=c.f, phi=c.phi, g=c.g, H=H, d=np.broadcast_to(lam, (C, r)).copy(),
+                 P=np.broadcast_to(np.eye(r), (C, r, r)).copy(), L=L,
+                 ok=np.isfinite(c.phi) & np.all(np.isfinite(c.g), axis=1),
+                 B=None if c.B is None else np.zeros_like(c.B))
+
+
 def method_geometry(prob: Problem, x: np.ndarray) -> Cache:
     """The geometry a transition of prob.method proposes and accepts with."""
     c = geometry(prob, x)
-    return without_metric(c) if prob.method == "mala" else c
+    if prob.method == "mala":
+        return without_metric(c)
+    if prob.method == "dis_mmala":
+        return with_diagonal_metric(c, prob.fixed)
+    return c
 
 
 def propose(prob: Problem, x: np.ndarray, cache: Cache, xi: np.ndarray) -> np.ndarray:

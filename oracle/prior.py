@@ -151,3 +151,51 @@ class KLEBasis:
         Z[..., self.k1_all, self.k2_all] = z * np.sqrt(self.lam_all)
         M = np.einsum("...kl,ik,jl->...ji", Z, Q, Q)
         return M.reshape(z.shape[:-1] + (n * n,))
+
+
+def prior_pointwise_variance(n: int, gamma: float, delta: float) -> np.ndarray:
+    """diag(C_pr) on the grid: sum over all modes of lambda_k eta_k(p)^2 (separable)."""
+    k1, k2, lam = kle_eigenvalues(n, gamma, delta)
+    Q2 = q_1d(n) ** 2
+    lamgrid = np.zeros((n, n))
+    lamgrid[k1, k2] = lam
+    return (Q2 @ lamgrid @ Q2.T).T.reshape(-1)
+
+
+class DenseBasis:
+    """A dense reduced basis given in whitened KLE coordinates (Sec. 4.2): U (d_m, r) with
+    orthonormal columns, psi_j = Q Lambda^1/2 u_j, which is H_mu-orthonormal (the Cameron-
+    Martin inner product is Euclidean in whitened coordinates). A DIS basis (eq.
+    jtj_eigenvalue) is of this form, with eigenvalues lam_dis (eq. dis_gnh) attached.
+
+    Encoder x = U^T z for the whitened coordinates z of m; decoder Psi_r x = Q Lambda^1/2 U x
+    (eq. projector); the complement of z is (I - U U^T) z. Attributes as KLEBasis: dec
+    (d_m, r) = Psi_r in nodal coordinates and var_perp (d_m), the pointwise prior variance
+    of the complement, diag(C_pr) - sum_j psi_j(p)^2."""
+
+    def __init__(self, n: int, gamma: float, delta: float, U: np.ndarray, lam_dis=None):
+        self.n, self.gamma, self.delta = n, gamma, delta
+        self.d_m = n * n
+        self.U = np.asarray(U, dtype=np.float64)
+        assert self.U.shape[0] == self.d_m
+        self.r = self.U.shape[1]
+        self.lam_dis = None if lam_dis is None else np.asarray(lam_dis, dtype=np.float64)
+        self.kle = KLEBasis(n, gamma, delta, 1)  # the full whitening transform (every mode)
+        self.dec = self.kle.unwhiten_full(self.U.T).T
+        self.var_perp = prior_pointwise_variance(n, gamma, delta) - np.sum(self.dec ** 2, axis=1)
+
+    def encode(self, m: np.ndarray) -> np.ndarray:
+        """Reduced coordinates x = U^T z(m) of fields m (..., d_m)."""
+        return self.kle.whiten_full(m) @ self.U
+
+    def decode(self, x: np.ndarray) -> np.ndarray:
+        return x @ self.dec.T
+
+    def project_complement(self, w: np.ndarray) -> np.ndarray:
+        """(I - U U^T) w for whitened vectors w (..., d_m)."""
+        return w - (w @ self.U) @ self.U.T
+
+    def full(self, x: np.ndarray, w: np.ndarray) -> np.ndarray:
+        """The whitened coordinates of the full parameter U x + (I - U U^T) w (Alg. 1's
+        assembly Psi_r x + m_perp - Psi_r Psi_r^* m_perp, in whitened coordinates)."""
+        return x @ self.U.T + self.project_complement(w)

@@ -68,12 +68,29 @@ dino_status dino_ctx_destroy(dino_ctx* ctx);
  */
 dino_status dino_load_prior(dino_ctx* ctx, int n, double gamma, double delta, int r);
 
+/* A dense reduced basis (Sec. 4.2), e.g. a derivative-informed (DIS) basis (eq.
+ * jtj_eigenvalue, eq. dis_gnh), replacing the KLE reduced basis of the loaded prior:
+ * U (host, d_m x r, row-major) holds orthonormal columns u_j in whitened KLE coordinates
+ * (KLE order of dino_read_basis's modes), so psi_j = Q Lambda^1/2 u_j is H_mu-orthonormal;
+ * lam_dis (host, r, >= 0, or NULL) its eigenvalues, the fixed metric diag(lam_dis) of
+ * DIS-mMALA. The reduced coordinates of a field with whitened coordinates z are x = U^T z.
+ * A problem on a dense basis keeps the unprojected complement draw w (n_chains x d_m,
+ * moved by the same pCN rule); the complement of the state is (I - U U^T) w, and the full
+ * parameter U x + (I - U U^T) w (Alg. 1's assembly of m+) is formed where it is needed:
+ * the second stage of delayed acceptance (per step), decode and statistics. dino_encode
+ * then returns z_perp = z - U x (n_fields x d_m) and dino_decode takes one. EINVAL unless
+ * U^T U = I within 1e-10, 1 <= r <= 512; ESTATE without a prior or under live problems.
+ * dino_load_prior restores a KLE basis. */
+dino_status dino_load_basis(dino_ctx* ctx, int r, const double* U, const double* lam_dis);
+
 /* Copies of the basis to host buffers (any may be NULL):
  *   dec      d_m x r   decoder Psi_r (columns psi_j = sqrt(lambda_j) eta_j)
  *   lam      r         eigenvalues lambda_j
  *   var_perp d_m       pointwise prior variance of the complement,
  *                      sum_{k >= r} lambda_k eta_k(p)^2
- *   modes    r x 2     (k1, k2) of every kept mode */
+ *   modes    r x 2     (k1, k2) of every kept mode
+ * For a dense basis: dec = Q Lambda^1/2 U, lam = its DIS eigenvalues (0 if none were
+ * given), var_perp = diag(C_pr) - sum_j psi_j(p)^2, modes -1. */
 dino_status dino_read_basis(dino_ctx* ctx, double* dec, double* lam, double* var_perp, int32_t* modes);
 
 /* ---------------------------------------------------------------------------
@@ -166,12 +183,19 @@ dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kin
  *   Philox stream 5 at (step, chain). The state keeps its true misfit. The true model runs
  *   on the first-stage passes only (compacted). Needs track_complement when the true model
  *   reads complement coordinates.
- * PCN, MALA, LAPCN and DA_MMALA are not available to the serving pools. */
+ * DIS_MMALA: the DIS-mMALA baseline (the DIS-mMALA row of the baselines of Sec. 6.1): the
+ *   MMALA transition with the metric fixed at the DIS approximation of the expected ppGNH
+ *   (eq. dis_gnh), diag(lam_dis) in the coordinates of a dense basis loaded with its DIS
+ *   eigenvalues, and the ppg kept: x+_j = ((lam_j + s) x_j - (1 - s) g_j)/(1 + lam_j) +
+ *   beta xi_j / sqrt(1 + lam_j). A step forms the misfit and ppg at x+ (no metric or
+ *   factor). lam = 0 is MALA.
+ * PCN, MALA, LAPCN, DA_MMALA and DIS_MMALA are not available to the serving pools. */
 #define DINO_METHOD_MMALA 0
 #define DINO_METHOD_PCN 1
 #define DINO_METHOD_MALA 2
 #define DINO_METHOD_LAPCN 3
 #define DINO_METHOD_DA_MMALA 4
+#define DINO_METHOD_DIS_MMALA 5
 typedef struct {
     int32_t n_chains;
     int32_t d_y;

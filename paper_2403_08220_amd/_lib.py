@@ -16,7 +16,7 @@ PRECISIONS = {"f64": 0, "bf16": 1}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
 TUNE_KINDS = {"chol": 0, "fwd64": 1, "fwd32": 2}
 LAUNCH_MODES = {"eager": 0, "graph": 1}
-METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4}
+METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4, "dis_mmala": 5}
 
 
 class DinoError(RuntimeError):
@@ -98,6 +98,7 @@ SIGNATURES = {
     "dino_ctx_destroy": (ct.c_int32, [_P]),
     "dino_load_prior": (ct.c_int32, [_P, ct.c_int, ct.c_double, ct.c_double, ct.c_int]),
     "dino_read_basis": (ct.c_int32, [_P, _D, _D, _D, _I32]),
+    "dino_load_basis": (ct.c_int32, [_P, ct.c_int, _D, _D]),
     "dino_load_network": (ct.c_int32, [_P, ct.c_int, _I32, _I32, _I32, ct.POINTER(_D), ct.POINTER(_D)]),
     "dino_load_true_model": (ct.c_int32, [_P, ct.c_int, _I32, _I32, _I32, ct.POINTER(_D), ct.POINTER(_D)]),
     "dino_read_delayed": (ct.c_int32, [_P, _D, _I64]),

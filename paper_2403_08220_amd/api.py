@@ -41,6 +41,7 @@ class Context:
         self.device = device
         self.n = self.r = None
         self.d_out = None
+        self.dense = False
 
     def close(self):
         if self.h:
@@ -50,10 +51,25 @@ class Context:
     def load_prior(self, n: int, gamma: float, delta: float, r: int):
         check(self.lib.dino_load_prior(self.h, n, gamma, delta, r))
         self.n, self.r = n, r
+        self.dense = False
+
+    def load_basis(self, U, lam_dis=None):
+        """A dense reduced basis: U (d_m, r) orthonormal columns in whitened KLE coordinates,
+        lam_dis (r,) its DIS eigenvalues or None."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        lam = None if lam_dis is None else np.ascontiguousarray(lam_dis, dtype=np.float64)
+        check(self.lib.dino_load_basis(self.h, U.shape[1], dptr(U), dptr(lam)))
+        self.r = U.shape[1]
+        self.dense = True
 
     @property
     def d_m(self):
         return self.n * self.n
+
+    @property
+    def d_perp(self):
+        """Length of a complement state: d_m - r (KLE), or d_m (dense basis: the unprojected draw)."""
+        return self.d_m if self.dense else self.d_m - self.r
 
     def read_basis(self):
         dec = np.empty((self.d_m, self.r))
@@ -68,7 +84,7 @@ class Context:
         torch = _torch()
         n = fields.shape[0]
         x = torch.empty((n, self.r), dtype=torch.float64, device=fields.device)
-        zp = torch.empty((n, self.d_m - self.r), dtype=torch.float64, device=fields.device)
+        zp = torch.empty((n, self.d_perp), dtype=torch.float64, device=fields.device)
         check(self.lib.dino_encode(self.h, n, _tp(fields), _tp(x), _tp(zp), _stream_handle(stream)))
         return x, zp
 
@@ -126,7 +142,7 @@ class Problem:
         # the library validates the descriptor against the context's prior and network
         check(self.lib.dino_problem_workspace_bytes(ctx.h, ct.byref(self.desc), ct.byref(nbytes)))
         self.C, self.r, self.d_y = n_chains, ctx.r, len(y)
-        self.d_perp = ctx.d_m - ctx.r
+        self.d_perp = ctx.d_perp
         self.track_complement = track_complement
         self.trace_capacity = trace_capacity
         self.dt = dt

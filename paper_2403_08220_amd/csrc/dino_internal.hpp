@@ -197,6 +197,14 @@ struct Basis {
     double* q = nullptr;           // n x n DCT-II matrix Q[i][k] = q_k(i)
     int32_t* perm = nullptr;       // d_m: order on the device
     double* sqlam = nullptr;       // d_m: sqrt_lam_all on the device
+    // dense basis (dino_load_basis): orthonormal u_j in whitened coordinates (KLE order);
+    // the reduced coordinates are x = U^T z and a problem's complement state is the
+    // unprojected w in R^d_m, whose complement part is (I - U U^T) w
+    bool dense = false;
+    double* UT = nullptr;          // r x d_m FP64, row j = u_j
+    float* UT32 = nullptr;         // r x d_m FP32 copy (mixed path)
+    double* lam_dis = nullptr;     // r DIS eigenvalues (device), null when none were given
+    std::vector<double> lam_dis_host;
 };
 
 struct dino_ctx_impl;
@@ -310,6 +318,13 @@ struct dino_problem {
     float* th0f = nullptr;    // mixed path
     float* th1f = nullptr;
     float* fT32 = nullptr;
+    // delayed acceptance on a dense basis: the compacted full-proposal complement draws w+,
+    // their projections U^T w+ and the chain of every compacted row
+    double* wb64 = nullptr;   // C x d_m (FP64 path)
+    float* wb32 = nullptr;    // C x ldz (mixed path)
+    double* tp64 = nullptr;   // C x r
+    float* tp32 = nullptr;    // C x r
+    int32_t* rowchain = nullptr;
     // trace
     float* xtrace = nullptr;  // capacity x C x r
     double* phitrace = nullptr;
@@ -405,6 +420,13 @@ void launch_eval_log_rho_dual(dino_problem* p, int n, const double* x, const dou
 void launch_jacobian_to_double(dino_problem* p, int n, double* out, hipStream_t st);
 // delayed acceptance (kernels_geometry.hip, kernels_chain.hip)
 void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m_dev, hipStream_t st);
+// C[m][n] = sum_k A[m][k] B[n][k] (B: N x K row-major) for rows m below M (and below *m_dev
+// when given): the forward layer kernels without bias or activation (kernels_geometry.hip)
+void launch_gemm_nt64(int M, int K, int N, const double* A, int lda, const double* B, double* C, int ldc,
+                      const int* m_dev, hipStream_t st);
+void launch_gemm_nt32(int M, int K, int N, const float* A, int lda, const float* B, float* C, int ldc,
+                      const int* m_dev, hipStream_t st);
+void build_dense_basis_device(Basis& b, const std::vector<double>& U, const double* lam_dis);
 void launch_da_gather(dino_problem* p, int n, hipStream_t st);
 void launch_da_init(dino_problem* p, int n, hipStream_t st);
 void launch_da_accept(dino_problem* p, int n, hipStream_t st);

@@ -113,10 +113,60 @@ __global__ void kle_scatter_kernel(int nf, int n, int r, const double* __restric
     }
 }
 
+// Dense basis: out[f][p] = (w ? w[f][p] : 0) + sum_j (a[f][j] - (c ? c[f][j] : 0)) UT[j][p], i.e.
+// (I - U U^T) w + U a with c = U^T w given (assembly of a full parameter from reduced
+// coordinates and an unprojected complement), or w - U a with a = U^T w and c null
+// (sign = -1: the complement of a whitened vector).
+__global__ void dense_combine_kernel(int nf, int d_m, int r, double sign, const double* __restrict__ w,
+                                     const double* __restrict__ a, const double* __restrict__ c,
+                                     const double* __restrict__ UT, double* __restrict__ out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d_m) return;
+    for (int f = blockIdx.y; f < nf; f += gridDim.y) {
+        double acc = 0.0;
+        for (int j = 0; j < r; ++j) acc += (a[(long)f * r + j] - (c ? c[(long)f * r + j] : 0.0)) * UT[(long)j * d_m + p];
+        out[(long)f * d_m + p] = (w ? w[(long)f * d_m + p] : 0.0) + sign * acc;
+    }
+}
+
+// All d_m whitened coordinates (KLE order) of nf fields: the KLE gather with no reduced part.
+static void whiten_full(const Basis& b, int nf, const double* fields, double* z, double* t1, double* t2,
+                        hipStream_t st) {
+    const int n = b.n;
+    const dim3 grid((n * n + 255) / 256, grid_y(nf));
+    // m[f][j][i] -> t1[f][k1][j] -> t2[f][k2][k1]
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, fields, b.q, 0, t1);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 0, t2);
+    hipLaunchKernelGGL(kle_gather_kernel, grid, dim3(256), 0, st, nf, n, 0, t2, b.perm, b.sqlam, (double*)nullptr, z);
+}
+
+// Nodal fields from all d_m whitened coordinates (z may alias fields).
+static void unwhiten_full(const Basis& b, int nf, const double* z, double* fields, double* t1, double* t2,
+                          hipStream_t st) {
+    const int n = b.n;
+    const dim3 grid((n * n + 255) / 256, grid_y(nf));
+    // z -> t1[f][k2][k1] -> t2[f][i][k2] -> m[f][j][i]
+    hipLaunchKernelGGL(kle_scatter_kernel, grid, dim3(256), 0, st, nf, n, 0, (const double*)nullptr, z, b.perm,
+                       b.sqlam, t1);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 1, t2);
+    hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t2, b.q, 1, fields);
+}
+
 void launch_encode(const Basis& b, int nf, const double* fields, double* x, double* zp, double* t1, double* t2,
                    hipStream_t st) {
     const int n = b.n;
     const dim3 grid((n * n + 255) / 256, grid_y(nf));
+    if (b.dense) {
+        // z = whitened coordinates (into t1); x = U^T z; z_perp = z - U x
+        whiten_full(b, nf, fields, t1, t1, t2, st);
+        double* xr = x ? x : t2;  // t2 is free once z is formed
+        launch_gemm_nt64(nf, b.d_m, b.r, t1, b.d_m, b.UT, xr, b.r, nullptr, st);
+        if (zp)
+            hipLaunchKernelGGL(dense_combine_kernel, grid, dim3(256), 0, st, nf, b.d_m, b.r, -1.0, t1, xr,
+                               (const double*)nullptr, b.UT, zp);
+        DINO_HIP(hipGetLastError());
+        return;
+    }
     // m[f][j][i] -> t1[f][k1][j] -> t2[f][k2][k1]
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, fields, b.q, 0, t1);
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 0, t2);
@@ -128,11 +178,110 @@ void launch_decode(const Basis& b, int nf, const double* x, const double* zp, do
                    hipStream_t st) {
     const int n = b.n;
     const dim3 grid((n * n + 255) / 256, grid_y(nf));
+    if (b.dense) {
+        // z = U x + (I - U U^T) z_perp (into fields), then the nodal transform in place
+        if (zp) launch_gemm_nt64(nf, b.d_m, b.r, zp, b.d_m, b.UT, t2, b.r, nullptr, st);
+        hipLaunchKernelGGL(dense_combine_kernel, grid, dim3(256), 0, st, nf, b.d_m, b.r, 1.0, zp, x,
+                           zp ? (const double*)t2 : nullptr, b.UT, fields);
+        unwhiten_full(b, nf, fields, fields, t1, t2, st);
+        DINO_HIP(hipGetLastError());
+        return;
+    }
     // z -> t1[f][k2][k1] -> t2[f][i][k2] -> m[f][j][i]
     hipLaunchKernelGGL(kle_scatter_kernel, grid, dim3(256), 0, st, nf, n, b.r, x, zp, b.perm, b.sqlam, t1);
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t1, b.q, 1, t2);
     hipLaunchKernelGGL(sep_axis_kernel, grid, dim3(256), 0, st, nf, n, t2, b.q, 1, fields);
     DINO_HIP(hipGetLastError());
+}
+
+// dec[p][j] = F[j][p] (transpose of r x d_m rows)
+__global__ void transpose_kernel(int rows, int cols, const double* __restrict__ F, double* __restrict__ D) {
+    const long total = (long)rows * cols;
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const long p = e / rows;
+        const int j = (int)(e % rows);
+        D[e] = F[(long)j * cols + p];
+    }
+}
+
+// var_perp[p] = prior variance[p] - sum_j dec[p][j]^2
+__global__ void dense_var_perp_kernel(int d_m, int r, const double* __restrict__ pv, const double* __restrict__ dec,
+                                      double* __restrict__ vp) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= d_m) return;
+    double s = 0.0;
+    for (int j = 0; j < r; ++j) s += dec[(long)p * r + j] * dec[(long)p * r + j];
+    vp[p] = pv[p] - s;
+}
+
+__global__ void to_float_rows_kernel(long total, const double* __restrict__ a, float* __restrict__ b) {
+    for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x)
+        b[e] = (float)a[e];
+}
+
+// A dense basis on the grid of b (its KLE order, q, perm and sqlam are kept): U (d_m x r,
+// row-major, host) and optional DIS eigenvalues. Replaces dec, var_perp and lam_dev.
+void build_dense_basis_device(Basis& b, const std::vector<double>& U, const double* lam_dis) {
+    const int n = b.n, r = b.r, d_m = n * n;
+    std::vector<double> ut((size_t)r * d_m);
+    for (int p = 0; p < d_m; ++p)
+        for (int j = 0; j < r; ++j) ut[(size_t)j * d_m + p] = U[(size_t)p * r + j];
+    DINO_HIP(hipMalloc(&b.UT, sizeof(double) * ut.size()));
+    DINO_HIP(hipMemcpy(b.UT, ut.data(), sizeof(double) * ut.size(), hipMemcpyHostToDevice));
+    DINO_HIP(hipMalloc(&b.UT32, sizeof(float) * ut.size()));
+    const long total = (long)r * d_m;
+    const int gb = (int)std::min<long>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(to_float_rows_kernel, dim3(gb), dim3(256), 0, 0, total, b.UT, b.UT32);
+    b.lam_dis_host.clear();
+    if (lam_dis) {
+        b.lam_dis_host.assign(lam_dis, lam_dis + r);
+        DINO_HIP(hipMalloc(&b.lam_dis, sizeof(double) * r));
+        DINO_HIP(hipMemcpy(b.lam_dis, lam_dis, sizeof(double) * r, hipMemcpyHostToDevice));
+    }
+    // Psi_r = Q Lambda^1/2 U: the nodal fields of the basis vectors, transposed into dec
+    double *F = nullptr, *t1 = nullptr, *t2 = nullptr, *Q2 = nullptr, *lamc = nullptr, *T = nullptr, *pv = nullptr;
+    DINO_HIP(hipMalloc(&F, sizeof(double) * total));
+    DINO_HIP(hipMalloc(&t1, sizeof(double) * total));
+    DINO_HIP(hipMalloc(&t2, sizeof(double) * total));
+    unwhiten_full(b, r, b.UT, F, t1, t2, 0);
+    DINO_HIP(hipMalloc(&b.dec, sizeof(double) * total));
+    hipLaunchKernelGGL(transpose_kernel, dim3(gb), dim3(256), 0, 0, r, d_m, F, b.dec);
+    // prior pointwise variance (every mode), then the complement variance
+    {
+        const double h = 1.0 / (n - 1);
+        std::vector<double> mu(n), lg((size_t)d_m);
+        for (int k = 0; k < n; ++k) {
+            const double sn = std::sin(M_PI * k / (2.0 * n));
+            mu[k] = 4.0 * sn * sn;
+        }
+        for (int a = 0; a < n; ++a)
+            for (int c = 0; c < n; ++c) {
+                const double sm = mu[std::min(a, c)] + mu[std::max(a, c)];
+                const double av = b.gamma * sm / (h * h) + b.delta;
+                lg[(size_t)a * n + c] = 1.0 / (av * av);
+            }
+        DINO_HIP(hipMalloc(&lamc, sizeof(double) * d_m));
+        DINO_HIP(hipMemcpy(lamc, lg.data(), sizeof(double) * d_m, hipMemcpyHostToDevice));
+    }
+    DINO_HIP(hipMalloc(&Q2, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&T, sizeof(double) * d_m));
+    DINO_HIP(hipMalloc(&pv, sizeof(double) * d_m));
+    const int g = (d_m + 255) / 256;
+    hipLaunchKernelGGL(q2_kernel, dim3(g), dim3(256), 0, 0, n, Q2);
+    hipLaunchKernelGGL(vp_stage1_kernel, dim3(g), dim3(256), 0, 0, n, Q2, lamc, T);
+    hipLaunchKernelGGL(vp_stage2_kernel, dim3(g), dim3(256), 0, 0, n, Q2, T, pv);
+    DINO_HIP(hipMalloc(&b.var_perp, sizeof(double) * d_m));
+    hipLaunchKernelGGL(dense_var_perp_kernel, dim3(g), dim3(256), 0, 0, d_m, r, pv, b.dec, b.var_perp);
+    DINO_HIP(hipGetLastError());
+    DINO_HIP(hipDeviceSynchronize());
+    hipFree(F);
+    hipFree(t1);
+    hipFree(t2);
+    hipFree(Q2);
+    hipFree(lamc);
+    hipFree(T);
+    hipFree(pv);
+    b.dense = true;
 }
 
 void build_basis_device(Basis& b) {

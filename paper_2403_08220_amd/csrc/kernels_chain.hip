@@ -1095,17 +1095,21 @@ __global__ __launch_bounds__(TPB) void pcn_accept_kernel(int r, int dy, ChainMet
 // The geometry stages still form the misfit and ppg at x+ (Jacobian sweep included); no
 // factor is formed or used.
 // One wave per chain: the proposal and the forward term log rho_0(x -> x+) (into lfwd).
+// With lam (DIS-mMALA: the fixed metric diag(lam) of eq. dis_gnh in DIS coordinates) the
+// proposal is x+_j = ((lam_j + s) x_j - (1 - s) g_j)/(1 + lam_j) + beta xi_j / sqrt(1 + lam_j)
+// and, with v = lam a - g(a), log rho_0(a, b) = -(dt/8) sum v_j^2/(1 + lam_j) +
+// (sqrt(dt)/2) mhat . v - (1/2) sum lam_j mhat_j^2 (its log det term cancels in the ratio).
 __global__ __launch_bounds__(64) void mala_propose_kernel(int r, double dt, double s, double beta, ChainMeta meta,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ g, double* __restrict__ xp,
-                                                          double* __restrict__ lfwd) {
+                                                          double* __restrict__ lfwd, const double* __restrict__ lam) {
     const int c = blockIdx.x, lane = threadIdx.x;
     const int32_t state = chain_state(meta, c);
     if (state == CHAIN_IDLE) return;
     const bool fresh = state == CHAIN_FRESH;
     const uint64_t k0 = meta.key0[c], k1 = meta.key1[c], chain = (uint64_t)meta.index[c];
     const uint64_t stream = fresh ? STREAM_INIT_X : STREAM_XI, step = fresh ? 0 : (uint64_t)meta.step[c];
-    double gg = 0.0, mg = 0.0;
+    double gg = 0.0, mg = 0.0, hm = 0.0;
     for (int b4 = lane; 4 * b4 < r; b4 += 64) {
         double nv[4];
         philox_normals4(k0, k1, (uint64_t)b4, stream, step, chain, nv);
@@ -1118,15 +1122,26 @@ __global__ __launch_bounds__(64) void mala_propose_kernel(int r, double dt, doub
                 continue;
             }
             const double xj = x[(long)c * r + j], gj = g[(long)c * r + j];
-            const double pj = s * xj - (1.0 - s) * gj + beta * nv[q];
-            xp[(long)c * r + j] = pj;
-            gg += gj * gj;
-            mg += ((pj - s * xj) / beta) * gj;
+            if (lam) {
+                const double lj = lam[j], d1 = 1.0 + lj;
+                const double pj = ((lj + s) * xj - (1.0 - s) * gj) / d1 + beta * nv[q] / sqrt(d1);
+                xp[(long)c * r + j] = pj;
+                const double vj = lj * xj - gj, mj = (pj - s * xj) / beta;
+                gg += vj * vj / d1;
+                mg -= mj * vj;
+                hm += lj * mj * mj;
+            } else {
+                const double pj = s * xj - (1.0 - s) * gj + beta * nv[q];
+                xp[(long)c * r + j] = pj;
+                gg += gj * gj;
+                mg += ((pj - s * xj) / beta) * gj;
+            }
         }
     }
     gg = wave_sum(gg);
     mg = wave_sum(mg);
-    if (lane == 0) lfwd[c] = fresh ? 0.0 : -(dt / 8.0) * gg - (sqrt(dt) / 2.0) * mg;
+    hm = wave_sum(hm);
+    if (lane == 0) lfwd[c] = fresh ? 0.0 : -(dt / 8.0) * gg - (sqrt(dt) / 2.0) * mg - 0.5 * hm;
 }
 
 // The reverse term log rho_0(x+ -> x) with the ppg at x+, the MH decision (a non-finite
@@ -1138,8 +1153,9 @@ __global__ __launch_bounds__(TPB) void mala_accept_kernel(int r, double dt, doub
                                                           const double* __restrict__ gp,
                                                           const double* __restrict__ phip,
                                                           const double* __restrict__ lfwd, int64_t* accepts,
-                                                          int64_t* failures, int32_t* accflag, StepRecord rec) {
-    __shared__ double red[2][TPB / 64];
+                                                          int64_t* failures, int32_t* accflag, StepRecord rec,
+                                                          const double* __restrict__ lam) {
+    __shared__ double red[3][TPB / 64];
     __shared__ int decision;
     const int c = blockIdx.x, tid = threadIdx.x;
     const int32_t state = chain_state(meta, c);
@@ -1148,26 +1164,36 @@ __global__ __launch_bounds__(TPB) void mala_accept_kernel(int r, double dt, doub
         return;
     }
     const int64_t step = meta.step[c];  // read by every thread before the finish advances it
-    double gg = 0.0, mg = 0.0;
+    double gg = 0.0, mg = 0.0, hm = 0.0;
     for (int j = tid; j < r; j += TPB) {
         const double gj = gp[(long)c * r + j], pj = xp[(long)c * r + j];
-        gg += gj * gj;
-        mg += ((x[(long)c * r + j] - s * pj) / beta) * gj;
+        if (lam) {
+            const double lj = lam[j], vj = lj * pj - gj, mj = (x[(long)c * r + j] - s * pj) / beta;
+            gg += vj * vj / (1.0 + lj);
+            mg -= mj * vj;
+            hm += lj * mj * mj;
+        } else {
+            gg += gj * gj;
+            mg += ((x[(long)c * r + j] - s * pj) / beta) * gj;
+        }
     }
     gg = wave_sum(gg);
     mg = wave_sum(mg);
+    hm = wave_sum(hm);
     if ((tid & 63) == 0) {
         red[0][tid >> 6] = gg;
         red[1][tid >> 6] = mg;
+        red[2][tid >> 6] = hm;
     }
     __syncthreads();
     double phin = 0.0;  // thread 0: the misfit after the decision
     if (tid == 0) {
-        double sg = 0.0, sm = 0.0;
+        double sg = 0.0, sm = 0.0, sh = 0.0;
 #pragma unroll
         for (int k = 0; k < TPB / 64; ++k) {
             sg += red[0][k];
             sm += red[1][k];
+            sh += red[2][k];
         }
         const double php = phip[c];
         if (state == CHAIN_FRESH) {
@@ -1177,7 +1203,7 @@ __global__ __launch_bounds__(TPB) void mala_accept_kernel(int r, double dt, doub
             decision = 1;
             accflag[c] = 2;
         } else {
-            const double rev = -(dt / 8.0) * sg - (sqrt(dt) / 2.0) * sm;
+            const double rev = -(dt / 8.0) * sg - (sqrt(dt) / 2.0) * sm - 0.5 * sh;
             const double lr = phi[c] - php + rev - lfwd[c];
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);
             const bool good = isfinite(lr);
@@ -1769,6 +1795,80 @@ __global__ __launch_bounds__(64) void da_init_kernel(int n, int r, int rT, int l
     for (int k = tid; k < rT - r; k += 64) row[r + k] = (double)z[(long)c * ldz + k];
 }
 
+// Dense basis: a pass takes the next batch row and writes its whole unprojected
+// complement draw w+ = pCN move of w (every one of the d_m coordinates; the complement
+// kernel's draws and expression) and its chain. One block per chain.
+template <typename TW>
+__global__ __launch_bounds__(256) void da_gather_dense_kernel(int d_m, int ldz, double s, double beta, ChainMeta meta,
+                                                              const int32_t* __restrict__ accflag,
+                                                              const float* __restrict__ z, int32_t* npass,
+                                                              int32_t* __restrict__ pos, int32_t* __restrict__ rowchain,
+                                                              TW* __restrict__ wb, int ldw) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    __shared__ int slot;
+    if (accflag[c] != 3) {
+        if (tid == 0) pos[c] = -1;
+        return;
+    }
+    if (tid == 0) {
+        slot = atomicAdd(npass, 1);
+        pos[c] = slot;
+        rowchain[slot] = c;
+    }
+    __syncthreads();
+    const float* zc = z + (long)c * ldz;
+    TW* row = wb + (long)slot * ldw;
+    const uint64_t k0 = meta.key0[c], k1 = meta.key1[c];
+    const uint64_t step = (uint64_t)meta.step[c], chain = (uint64_t)meta.index[c];
+    for (int b4 = tid; 4 * b4 < d_m; b4 += 256) {
+        double nv[4];
+        philox_normals4(k0, k1, (uint64_t)b4, STREAM_COMPLEMENT, step, chain, nv);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * b4 + q;
+            if (k < d_m) row[k] = (TW)pcn_move(zc[k], nv[q], s, beta);
+        }
+    }
+}
+
+// Dense basis at initialisation: row c of the batch is chain c's own w.
+template <typename TW>
+__global__ __launch_bounds__(256) void da_init_dense_kernel(int n, int d_m, int ldz, const float* __restrict__ z,
+                                                            int32_t* npass, int32_t* __restrict__ pos,
+                                                            int32_t* __restrict__ rowchain, TW* __restrict__ wb,
+                                                            int ldw) {
+    const int c = blockIdx.x, tid = threadIdx.x;
+    if (tid == 0) {
+        pos[c] = c;
+        rowchain[c] = c;
+        if (c == 0) *npass = n;
+    }
+    for (int k = tid; k < d_m; k += 256) wb[(long)c * ldw + k] = (TW)z[(long)c * ldz + k];
+}
+
+// Alg. 1's assembly of the full parameter in whitened coordinates, the r_T coordinates the
+// true model reads: zin[q][i] = w[q][i] + sum_j u_j[i] (x[c][j] - t[q][j]), with t = U^T w
+// (the projection GEMM before this kernel), c = rowchain[q]; rows past the batch count
+// return. One block per batch row.
+template <typename TW, typename TT>
+__global__ __launch_bounds__(256) void da_assemble_kernel(int r, int rT, int d_m, int ldw, const int32_t* npass,
+                                                          const int32_t* __restrict__ rowchain,
+                                                          const double* __restrict__ xsrc, const double* __restrict__ UT,
+                                                          const TW* __restrict__ wb, const TT* __restrict__ tp,
+                                                          double* __restrict__ zin) {
+    const int q = blockIdx.x;
+    if (q >= *npass) return;
+    const int c = rowchain[q];
+    __shared__ double a[512];
+    for (int j = threadIdx.x; j < r; j += 256) a[j] = xsrc[(long)c * r + j] - (double)tp[(long)q * r + j];
+    __syncthreads();
+    for (int i = threadIdx.x; i < rT; i += 256) {
+        double acc = (double)wb[(long)q * ldw + i];
+        for (int j = 0; j < r; ++j) acc += UT[(long)j * d_m + i] * a[j];
+        zin[(long)q * rT + i] = acc;
+    }
+}
+
 // True misfit Phi = 1/2 |Gamma^-1/2 (y - f_T)|^2 of chain c from batch row pos[c] (pos
 // null: row c); with npass_reset, the batch count is cleared for the next step.
 template <typename TF>
@@ -2136,16 +2236,21 @@ void launch_lapcn_propose(dino_problem* p, int n, hipStream_t st) {
     DINO_HIP(hipGetLastError());
 }
 
+// The fixed diagonal metric of a DIS-mMALA problem (null for MALA).
+static const double* dis_metric(const dino_problem* p) {
+    return p->desc.method == DINO_METHOD_DIS_MMALA ? p->ctx->basis.lam_dis : nullptr;
+}
+
 void launch_mala_propose(dino_problem* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(mala_propose_kernel, dim3(n), dim3(64), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
-                       p->g, p->xp, p->lfwd);
+                       p->g, p->xp, p->lfwd, dis_metric(p));
     DINO_HIP(hipGetLastError());
 }
 
 void launch_mala_accept(dino_problem* p, int n, hipStream_t st) {
     hipLaunchKernelGGL(mala_accept_kernel, dim3(n), dim3(TPB), 0, st, p->r, p->desc.dt, p->s, p->beta, p->meta, p->x,
                        p->g, p->phi, p->xp, p->gp, p->phip, p->lfwd, p->accepts, p->failures, p->acc,
-                       step_record(p));
+                       step_record(p), dis_metric(p));
     DINO_HIP(hipGetLastError());
 }
 
@@ -2275,7 +2380,37 @@ void launch_accept_dual(dino_problem* p, int n, hipStream_t st) {
     else accept_dual_t<__hip_bfloat16>(p, n, p->B16, p->Bs16, (p->r + 31) / 32 * 32, st);
 }
 
+// Dense basis: the projection t = U^T w of the batch rows (a GEMM over d_m, FP64 on the FP64
+// path, FP32 MFMA on the mixed path; row tiles past the count skip) and the assembly of the
+// coordinates the true model reads, from the reduced states xsrc.
+static void da_project_dense(dino_problem* p, int n, const double* xsrc, hipStream_t st) {
+    const Basis& b = p->ctx->basis;
+    if (p->desc.precision == DINO_PREC_F64) {
+        launch_gemm_nt64(n, p->d_m, p->r, p->wb64, p->d_m, b.UT, p->tp64, p->r, p->npass, st);
+        hipLaunchKernelGGL((da_assemble_kernel<double, double>), dim3(n), dim3(256), 0, st, p->r, p->rT, p->d_m,
+                           p->d_m, p->npass, p->rowchain, xsrc, b.UT, p->wb64, p->tp64, p->zin);
+    } else {
+        const int ldw = ldz_of(p->d_perp);
+        launch_gemm_nt32(n, p->d_m, p->r, p->wb32, ldw, b.UT32, p->tp32, p->r, p->npass, st);
+        hipLaunchKernelGGL((da_assemble_kernel<float, float>), dim3(n), dim3(256), 0, st, p->r, p->rT, p->d_m, ldw,
+                           p->npass, p->rowchain, xsrc, b.UT, p->wb32, p->tp32, p->zin);
+    }
+    DINO_HIP(hipGetLastError());
+}
+
 void launch_da_gather(dino_problem* p, int n, hipStream_t st) {
+    if (p->ctx->basis.dense) {
+        const int ldz = ldz_of(p->d_perp);
+        if (p->desc.precision == DINO_PREC_F64)
+            hipLaunchKernelGGL(da_gather_dense_kernel<double>, dim3(n), dim3(256), 0, st, p->d_m, ldz, p->s, p->beta,
+                               p->meta, p->acc, p->z, p->npass, p->pos, p->rowchain, p->wb64, p->d_m);
+        else
+            hipLaunchKernelGGL(da_gather_dense_kernel<float>, dim3(n), dim3(256), 0, st, p->d_m, ldz, p->s, p->beta,
+                               p->meta, p->acc, p->z, p->npass, p->pos, p->rowchain, p->wb32, ldz);
+        DINO_HIP(hipGetLastError());
+        da_project_dense(p, n, p->xp, st);
+        return;
+    }
     hipLaunchKernelGGL(da_gather_kernel, dim3(n), dim3(64), 0, st, p->r, p->rT, p->z ? ldz_of(p->d_perp) : 0, p->s,
                        p->beta, p->meta, p->acc, p->xp, p->z, p->npass, p->pos, p->zin);
     DINO_HIP(hipGetLastError());
@@ -2293,8 +2428,20 @@ void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st) {
 
 // The true misfit of the states of chains [0, n) (initialisation).
 void launch_da_init(dino_problem* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(da_init_kernel, dim3(n), dim3(64), 0, st, n, p->r, p->rT, p->z ? ldz_of(p->d_perp) : 0, p->x,
-                       p->z, p->npass, p->pos, p->zin);
+    if (p->ctx->basis.dense) {
+        const int ldz = ldz_of(p->d_perp);
+        if (p->desc.precision == DINO_PREC_F64)
+            hipLaunchKernelGGL(da_init_dense_kernel<double>, dim3(n), dim3(256), 0, st, n, p->d_m, ldz, p->z, p->npass,
+                               p->pos, p->rowchain, p->wb64, p->d_m);
+        else
+            hipLaunchKernelGGL(da_init_dense_kernel<float>, dim3(n), dim3(256), 0, st, n, p->d_m, ldz, p->z, p->npass,
+                               p->pos, p->rowchain, p->wb32, ldz);
+        DINO_HIP(hipGetLastError());
+        da_project_dense(p, n, p->x, st);
+    } else {
+        hipLaunchKernelGGL(da_init_kernel, dim3(n), dim3(64), 0, st, n, p->r, p->rT, p->z ? ldz_of(p->d_perp) : 0,
+                           p->x, p->z, p->npass, p->pos, p->zin);
+    }
     launch_true_forward(p, n, p->zin, p->npass, st);
     if (p->desc.precision == DINO_PREC_F64)
         hipLaunchKernelGGL(true_misfit_kernel<double>, dim3(n), dim3(64), 0, st, p->d_y, p->meta, p->fT64, p->pos, p->y,

@@ -571,6 +571,20 @@ void launch_true_forward(dino_problem* p, int n, const double* zin, const int* m
     DINO_HIP(hipGetLastError());
 }
 
+void launch_gemm_nt64(int M, int K, int N, const double* A, int lda, const double* B, double* C, int ldc,
+                      const int* m_dev, hipStream_t st) {
+    fwd_layer<double>(M, K, N, A, lda, B, nullptr, DINO_LAYER_LINEAR, C, ldc, nullptr, 0, st, m_dev);
+    DINO_HIP(hipGetLastError());
+}
+
+void launch_gemm_nt32(int M, int K, int N, const float* A, int lda, const float* B, float* C, int ldc,
+                      const int* m_dev, hipStream_t st) {
+    hipLaunchKernelGGL(fwd_mfma_kernel, dim3(((N + 31) / 32) * ((M + 31) / 32)), dim3(256), 0, st, M, K, N, A, lda,
+                       (const double*)nullptr, B, (const float*)nullptr, (int)DINO_LAYER_LINEAR, C, ldc,
+                       (float*)nullptr, 0, m_dev, fwd32_xcd_map(M, K, N));
+    DINO_HIP(hipGetLastError());
+}
+
 void launch_reverse_jacobian(dino_problem* p, int n, double* B_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
     const int L = (int)ctx->layers.size();

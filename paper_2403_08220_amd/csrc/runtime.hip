@@ -89,8 +89,13 @@ static void free_basis(Basis& b) {
     if (b.q) hipFree(b.q);
     if (b.perm) hipFree(b.perm);
     if (b.sqlam) hipFree(b.sqlam);
-    b.dec = b.var_perp = b.lam_dev = b.q = b.sqlam = nullptr;
+    if (b.UT) hipFree(b.UT);
+    if (b.UT32) hipFree(b.UT32);
+    if (b.lam_dis) hipFree(b.lam_dis);
+    b.dec = b.var_perp = b.lam_dev = b.q = b.sqlam = b.UT = b.lam_dis = nullptr;
+    b.UT32 = nullptr;
     b.perm = nullptr;
+    b.dense = false;
 }
 
 static void free_layers(std::vector<Layer>& ls) {
@@ -242,6 +247,16 @@ static void layout(dino_problem* p, Carver& cv) {
         p->pos = cv.take<int32_t>(C);
         p->npass = cv.take<int32_t>(1);
         p->zin = cv.take<double>(C * rT);
+        if (p->ctx->basis.dense) {
+            p->rowchain = cv.take<int32_t>(C);
+            if (p->desc.precision == DINO_PREC_F64) {
+                p->wb64 = cv.take<double>(C * (size_t)p->d_m);
+                p->tp64 = cv.take<double>(C * r);
+            } else {
+                p->wb32 = cv.take<float>(C * (size_t)ldz_of(p->d_perp));
+                p->tp32 = cv.take<float>(C * r);
+            }
+        }
         if (p->desc.precision == DINO_PREC_F64) {
             p->th0 = cv.take<double>(C * wT);
             p->th1 = cv.take<double>(C * wT);
@@ -271,13 +286,15 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
     DINO_REQUIRE(d->factorization >= DINO_FACTOR_PRIMAL && d->factorization <= DINO_FACTOR_AUTO, DINO_EINVAL,
                  "unknown factorization");
-    DINO_REQUIRE(d->method >= DINO_METHOD_MMALA && d->method <= DINO_METHOD_DA_MMALA, DINO_EINVAL, "unknown method");
+    DINO_REQUIRE(d->method >= DINO_METHOD_MMALA && d->method <= DINO_METHOD_DIS_MMALA, DINO_EINVAL, "unknown method");
+    DINO_REQUIRE(d->method != DINO_METHOD_DIS_MMALA || (ctx->basis.dense && ctx->basis.lam_dis), DINO_EINVAL,
+                 "DIS-mMALA needs a dense basis loaded with its DIS eigenvalues");
     if (d->method == DINO_METHOD_DA_MMALA) {
         DINO_REQUIRE(!ctx->true_layers.empty(), DINO_ESTATE, "load the true model before creating a delayed-acceptance problem");
         DINO_REQUIRE(ctx->true_r_in >= ctx->basis.r && ctx->true_r_in <= ctx->basis.d_m, DINO_EINVAL,
                      "the true model must read between r and d_m whitened coordinates");
         DINO_REQUIRE(d->d_y <= ctx->true_d_out, DINO_EINVAL, "d_y exceeds the true model's outputs");
-        DINO_REQUIRE(ctx->true_r_in == ctx->basis.r || d->track_complement, DINO_EINVAL,
+        DINO_REQUIRE((ctx->true_r_in == ctx->basis.r && !ctx->basis.dense) || d->track_complement, DINO_EINVAL,
                      "a true model that reads complement coordinates needs track_complement");
     }
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
@@ -298,7 +315,7 @@ static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d
     p->r = ctx->basis.r;
     p->d_y = d->d_y;
     p->d_m = ctx->basis.d_m;
-    p->d_perp = p->d_m - p->r;
+    p->d_perp = ctx->basis.dense ? p->d_m : p->d_m - p->r;  // dense: the unprojected complement draw
     p->wmax = ctx->max_width;
     p->n_act = ctx->n_act;
     p->dual = d->factorization == DINO_FACTOR_DUAL || (d->factorization == DINO_FACTOR_AUTO && d->d_y < p->r);
@@ -436,18 +453,63 @@ dino_status dino_load_prior(dino_ctx* ctx, int n, double gamma, double delta, in
     });
 }
 
+dino_status dino_load_basis(dino_ctx* ctx, int r, const double* U, const double* lam_dis) {
+    return guarded([&] {
+        DINO_REQUIRE(ctx && U, DINO_EINVAL, "null argument");
+        DINO_REQUIRE(ctx->basis.n > 0, DINO_ESTATE, "load the prior before a basis");
+        DINO_REQUIRE(ctx->live_problems == 0, DINO_ESTATE, "cannot replace the basis under live problems");
+        const int d_m = ctx->basis.d_m;
+        DINO_REQUIRE(r >= 1 && r <= 512 && r <= d_m, DINO_EINVAL, "reduced dimension out of range");
+        // orthonormal columns (the basis is H_mu-orthonormal exactly when U^T U = I)
+        std::vector<double> G((size_t)r * r, 0.0);
+        for (int p = 0; p < d_m; ++p) {
+            const double* row = U + (size_t)p * r;
+            for (int j = 0; j < r; ++j) {
+                DINO_REQUIRE(std::isfinite(row[j]), DINO_ENUMERIC, "non-finite basis entry");
+                for (int k = 0; k <= j; ++k) G[(size_t)j * r + k] += row[j] * row[k];
+            }
+        }
+        for (int j = 0; j < r; ++j)
+            for (int k = 0; k <= j; ++k)
+                DINO_REQUIRE(std::fabs(G[(size_t)j * r + k] - (j == k ? 1.0 : 0.0)) < 1e-10, DINO_EINVAL,
+                             "basis columns are not orthonormal (U^T U = I within 1e-10)");
+        if (lam_dis)
+            for (int j = 0; j < r; ++j)
+                DINO_REQUIRE(std::isfinite(lam_dis[j]) && lam_dis[j] >= 0.0, DINO_EINVAL,
+                             "DIS eigenvalues must be finite and non-negative");
+        DINO_HIP(hipSetDevice(ctx->device));
+        Basis& b = ctx->basis;
+        // the KLE transform arrays (q, perm, sqlam, order) stay; the reduced part is replaced
+        for (double** ptr : {&b.dec, &b.var_perp, &b.lam_dev, &b.UT, &b.lam_dis})
+            if (*ptr) {
+                (void)hipFree(*ptr);
+                *ptr = nullptr;
+            }
+        if (b.UT32) (void)hipFree(b.UT32);
+        b.UT32 = nullptr;
+        b.r = r;
+        b.k1.clear();
+        b.k2.clear();
+        b.lam.assign(lam_dis ? lam_dis : nullptr, lam_dis ? lam_dis + r : nullptr);
+        build_dense_basis_device(b, std::vector<double>(U, U + (size_t)d_m * r), lam_dis);
+    });
+}
+
 dino_status dino_read_basis(dino_ctx* ctx, double* dec, double* lam, double* var_perp, int32_t* modes) {
     return guarded([&] {
         DINO_REQUIRE(ctx && ctx->basis.r > 0, DINO_ESTATE, "no prior loaded");
         DINO_HIP(hipSetDevice(ctx->device));
         const Basis& b = ctx->basis;
         if (dec) DINO_HIP(hipMemcpy(dec, b.dec, sizeof(double) * (size_t)b.d_m * b.r, hipMemcpyDeviceToHost));
-        if (lam) std::memcpy(lam, b.lam.data(), sizeof(double) * b.r);
+        if (lam) {
+            if (b.dense && b.lam_dis_host.empty()) std::fill(lam, lam + b.r, 0.0);
+            else std::memcpy(lam, b.dense ? b.lam_dis_host.data() : b.lam.data(), sizeof(double) * b.r);
+        }
         if (var_perp) DINO_HIP(hipMemcpy(var_perp, b.var_perp, sizeof(double) * b.d_m, hipMemcpyDeviceToHost));
         if (modes)
             for (int j = 0; j < b.r; ++j) {
-                modes[2 * j] = b.k1[j];
-                modes[2 * j + 1] = b.k2[j];
+                modes[2 * j] = b.dense ? -1 : b.k1[j];
+                modes[2 * j + 1] = b.dense ? -1 : b.k2[j];
             }
     });
 }
@@ -801,7 +863,7 @@ static void run_steps_eager(dino_problem* p, int n, int n_steps, hipStream_t st)
     // second stage of delayed acceptance: gather, the true model's layers, decision
     const int LT = p->da ? (int)p->ctx->true_layers.size() + 2 : 0;
     const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, LT, p->z ? 1 : 0, 0};
-    const bool mala = p->desc.method == DINO_METHOD_MALA;
+    const bool mala = p->desc.method == DINO_METHOD_MALA || p->desc.method == DINO_METHOD_DIS_MMALA;
     const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, 0, p->z ? 1 : 0, 0};
     // MALA: on the mixed path the misfit and ppg come from the metric kernel, told to skip the metric
     const int32_t launches_mala[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, f64 ? 0 : 1, 0, 1, 0, p->z ? 1 : 0, 0};

@@ -132,7 +132,9 @@ dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kin
  *                   Cholesky, log-densities and MH ratio in FP64.
  * d_y: observed outputs (the first d_y of the network's d_out outputs).
  * noise_var: diagonal of Gamma (d_y values > 0; +inf means the output carries no
- *   information). dt > 0 is the step size (s = (4-dt)/(4+dt), eq. mmala).
+ *   information). Gamma is diagonal here: a caller with a full noise covariance
+ *   Gamma = L L^T whitens its data and the network's output layer by L^-1 and passes
+ *   unit variances. dt > 0 is the step size (s = (4-dt)/(4+dt), eq. mmala).
  * seed, request_id: the Philox4x64-10 key. Draw k of stream S for chain c at
  *   step t uses counter (k/4, S, t, c): S = 0 proposal normals, 1 complement
  *   normals, 2 MH uniform, 3 initial x, 4 initial z.

@@ -37,6 +37,7 @@ PEAKS = {  # MI355X published peaks
     "bf16_TFLOPs": 2500.0,
     "fp32_TFLOPs": 157.3,
     "fp64_TFLOPs": 78.6,
+    "fp8_TFLOPs": 5000.0,
 }
 
 # device kernel of each stage on the mixed-precision path (rocprofv3 kernel names)
@@ -58,7 +59,12 @@ KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "cholesky_wave_k
                   "jac_sweep13_kernel": ["kernels_mfma.hip", "sweep_asm.inc"],
                   "hess_bf16_kernel": ["kernels_mfma.hip"], "gram_bf16_kernel": ["kernels_mfma.hip"],
                   "fwd_mfma_kernel": ["kernels_geometry.hip"],
-                  "fwd_layer_kernel": ["kernels_geometry.hip"]}
+                  "fwd_layer_kernel": ["kernels_geometry.hip"],
+                  "jac_sweep_fp8_kernel": ["kernels_fp8.hip"], "hess_bf16_tiled_kernel": ["kernels_mfma.hip"],
+                  "cholesky_kernel": ["kernels_chain.hip"]}
+# the FP8 path at the large shape: FP8 sweep, tiled Gauss-Newton kernel, LDS panel factor
+STAGE_KERNEL_FP8_LARGE = dict(STAGE_KERNEL, jacobian="jac_sweep_fp8_kernel", gn_hessian="hess_bf16_tiled_kernel",
+                              cholesky="cholesky_kernel")
 
 
 def source_sha256(kernel):
@@ -96,9 +102,10 @@ def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=Fals
     """Algorithmic work of one step of a stage over C chains.
     Returns (amount, unit, bound, peak); the per-chain figures are in the design notes.
     dual: the observation-space form (Gram matrix I + B B^T, d_y x d_y factor)."""
+    mixed = prec in ("bf16", "fp8")
     if dual and stage == "gn_hessian":
         flops = C * 2.0 * (dy * (dy + 1) / 2.0 * r + dy * r)  # lower half of B B^T, and B^T e
-        if prec == "bf16":
+        if mixed:
             return flops, "TFLOP/s", "mfma", PEAKS["bf16_TFLOPs"]
         return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if dual and stage == "cholesky":
@@ -106,22 +113,24 @@ def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=Fals
     if dual and stage in ("proposal", "accept"):
         # one read of the chain's B (BF16 on the mixed path, FP64 otherwise) and of the lower
         # triangle of its FP64 d_y x d_y factor; on acceptance the proposal's B is copied
-        bsz = 2.0 if prec == "bf16" else 8.0
+        bsz = 2.0 if mixed else 8.0
         per = dy * r * bsz + dy * (dy + 1) / 2.0 * 8.0
         if stage == "accept":
             per += accepted_frac * 2.0 * dy * r * bsz
         return C * per, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "jacobian":
         flops = C * 2.0 * (L_res * dy * w * w + dy * w * r)
-        if prec == "bf16":
+        if prec == "fp8":
+            return flops, "TFLOP/s", "mfma", PEAKS["fp8_TFLOPs"]
+        if mixed:
             return flops, "TFLOP/s", "mfma", PEAKS["bf16_TFLOPs"]
         return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if stage == "forward":
         flops = C * 2.0 * (r * w + L_res * w * w + w * dy)
-        return flops, "TFLOP/s", "alu", PEAKS["fp32_TFLOPs"] if prec == "bf16" else PEAKS["fp64_TFLOPs"]
+        return flops, "TFLOP/s", "alu", PEAKS["fp32_TFLOPs"] if mixed else PEAKS["fp64_TFLOPs"]
     if stage == "gn_hessian":
         flops = C * 2.0 * r * r * dy / 2.0  # symmetric product, lower half
-        if prec == "bf16":
+        if mixed:
             return flops, "TFLOP/s", "mfma", PEAKS["bf16_TFLOPs"]
         return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if stage == "cholesky":
@@ -134,7 +143,7 @@ def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=Fals
         return C * accepted_frac * d_perp * 8.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "misfit_ppg":
         # residual: read f and y, write e (FP32 path) / read B (FP64 path)
-        if prec == "bf16":
+        if mixed:
             return C * dy * 12.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
         return C * dy * r * 8.0, "GB/s", "hbm", PEAKS["hbm_GBps"]
     if stage == "trace":
@@ -567,6 +576,65 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="m
             fh.write("\n")
 
 
+def stage_table(prof, w, C, L_res, accept_rate, prec, dual):
+    """Per-stage time, algorithmic work rate and roofline fraction from a stage profile."""
+    stages = {}
+    for name, v in prof.items():
+        if v["launches"] == 0:  # a stage with no kernel of its own on this path
+            continue
+        amt, unit, bound, peak = stage_work(name, w.width, C, w.r, w.d_y, L_res, accept_rate, w.d_m - w.r, prec,
+                                            dual=dual)
+        t = v["ms_per_step"] * 1e-3
+        ach = (amt / t / (1e12 if unit == "TFLOP/s" else 1e9)) if t > 0 else 0.0
+        stages[name] = dict(ms=round(v["ms_per_step"], 4), launches=v["launches"], bound=bound,
+                            achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
+    return stages
+
+
+def large_leg(steps, warmup, fp64_steps):
+    """The largest shape: 257x257 grid, r = 400, ResNet 800x6, d_y = 400, 4096 chains, on the
+    FP8 path (FP8 reverse sweep, BF16 Gauss-Newton tiles, FP64 factor and MH), beside the
+    plain FP64 path on the same problem for a few steps."""
+    from paper_2403_08220_amd import Context
+    from synth import draw_network, workload
+
+    w = workload("large")
+    layers = draw_network(w)
+    L_res = sum(1 for k, _, _ in layers if k == "resid")
+    ctx = Context(0)
+    try:
+        ctx.load_prior(w.n, w.gamma, w.delta, w.r)
+        ctx.load_network(layers)
+        y, nv = device_data(w, ctx)
+        x0, z0, init_info, _ = laplace_start(w, ctx, y, nv)
+        log(f"bench: large leg, Laplace start ready {init_info}")
+        res = run_path(w, ctx, y, nv, x0, z0, "fp8", steps, warmup, profile=True, factorization="primal")
+        C = w.chains
+        stages = stage_table(res.get("profile", {}), w, C, L_res, res["accept_rate"], "fp8", False)
+        dom = max(stages, key=lambda k: stages[k]["ms"])
+        jac = stages.get("jacobian")
+        kern = STAGE_KERNEL_FP8_LARGE.get(dom, dom)
+        out = dict(
+            workload="257x257 grid, r=400 KLE, ResNet 800x6 GELU, d_y=400, 4096 chains, dt=3e-4",
+            precision="fp8", value=round(C * steps / res["wall_s"], 1), unit="chain-steps/s", steps=steps,
+            ms_per_step=round(1e3 * res["wall_s"] / steps, 4), accept_rate=round(res["accept_rate"], 4),
+            failures=res["failures"], stages=stages,
+            dominant=dict(stage=dom, kernel=kern, **{k: stages[dom][k] for k in ("bound", "achieved", "peak",
+                                                                                 "unit", "frac")}),
+            roofline_fp8_sweep=None if jac is None else dict(
+                bound="mfma", achieved=jac["achieved"], peak=PEAKS["fp8_TFLOPs"], unit="TFLOP/s",
+                frac=jac["frac"], kernel="jac_sweep_fp8_kernel", ms_per_launch=jac["ms"]),
+            init=init_info)
+        if fp64_steps > 0:
+            r64 = run_path(w, ctx, y, nv, x0, z0, "f64", fp64_steps, 1, profile=False, factorization="primal")
+            out["fp64_plain"] = dict(value=round(C * fp64_steps / r64["wall_s"], 1), unit="chain-steps/s",
+                                     steps=fp64_steps, ms_per_step=round(1e3 * r64["wall_s"] / fp64_steps, 4),
+                                     accept_rate=round(r64["accept_rate"], 4))
+        return out
+    finally:
+        ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -587,6 +655,9 @@ def main():
                     help="timed steps of the ESS/s leg on the mix workload (0: skip)")
     ap.add_argument("--da-steps", type=int, default=None,
                     help="timed steps of the delayed-acceptance leg (default: --steps; 0: skip)")
+    ap.add_argument("--large-steps", type=int, default=40,
+                    help="steps of the FP8 leg at the largest shape (4096 chains; 0: skip)")
+    ap.add_argument("--large-fp64-steps", type=int, default=4, help="plain FP64 steps at the largest shape")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
     args = ap.parse_args()
@@ -666,16 +737,7 @@ def main():
     prof = res.get("profile", {})
     # the observation-space form is taken when asked for, or by "auto" when d_y < r
     dual = args.factorization == "dual" or (args.factorization == "auto" and w.d_y < w.r)
-    stages = {}
-    for name, v in prof.items():
-        if v["launches"] == 0:  # a stage with no kernel of its own on this path
-            continue
-        amt, unit, bound, peak = stage_work(name, w.width, C, w.r, w.d_y, L_res, res["accept_rate"],
-                                            w.d_m - w.r, args.precision, dual=dual)
-        t = v["ms_per_step"] * 1e-3
-        ach = (amt / t / (1e12 if unit == "TFLOP/s" else 1e9)) if t > 0 else 0.0
-        stages[name] = dict(ms=round(v["ms_per_step"], 4), launches=v["launches"], bound=bound,
-                            achieved=round(ach, 3), peak=peak, unit=unit, frac=round(ach / peak, 4))
+    stages = stage_table(prof, w, C, L_res, res["accept_rate"], args.precision, dual)
     roof = None
     if stages:
         dom = max(stages, key=lambda k: stages[k]["ms"])
@@ -685,6 +747,12 @@ def main():
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4),
                     profiled_ms_per_step=round(res.get("profiled_ms_per_step", 0.0), 4))
+    large = None
+    if args.large_steps > 0:
+        log(f"bench: large leg (FP8), {args.large_steps} steps ...")
+        large = large_leg(args.large_steps, max(2, args.warmup // 4), args.large_fp64_steps)
+        log(f"bench: large FP8 {large['value']} chain-steps/s, {large['ms_per_step']} ms/step, "
+            f"accept {large['accept_rate']}")
     serving = None
     if args.serve_requests > 0:
         log(f"bench: serving leg, {args.serve_requests} requests at load {args.serve_load} ...")
@@ -725,6 +793,7 @@ def main():
         "fp64_plain": fp64,
         "ess_leg": ess,
         "delayed_acceptance": da_res,
+        "large_fp8": large,
         "baselines": baselines,
         "serving": serving,
         "cpu_baseline": cpu,

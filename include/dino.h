@@ -130,6 +130,19 @@ dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kin
  *   DINO_PREC_BF16  surrogate forward in FP32; reduced Jacobian and GN Hessian
  *                   from BF16 MFMA products with FP32 accumulation; proposal,
  *                   Cholesky, log-densities and MH ratio in FP64.
+ *   DINO_PREC_FP8   as DINO_PREC_BF16, but the reverse sweep of the reduced Jacobian
+ *                   multiplies in OCP FP8 e4m3 (FP32 accumulation): the weights W_l^T
+ *                   with one power-of-two scale per output channel (column of W_l),
+ *                   quantised when the network is loaded; the sweep's left operand
+ *                   Lambda diag(gelu') in MX blocks (one power-of-two scale per 32
+ *                   values of a row) as a two-term e4m3 expansion hi + lo (~2^-8
+ *                   relative error; two products per weight operand). Lambda is kept
+ *                   in BF16 between layers, the output layer's rows in FP32. Layers of
+ *                   at most 800 units (at that width, d_y >= 5).
+ *   DINO_PREC_FP8_SINGLE  as DINO_PREC_FP8 with the left operand as a single e4m3 term
+ *                   (one product per weight operand, ~2^-4 relative error). Its error
+ *                   varies from state to state, and at the largest shapes the metric's
+ *                   roughness lowers mMALA's acceptance far below the FP64 path's.
  * d_y: observed outputs (the first d_y of the network's d_out outputs).
  * noise_var: diagonal of Gamma (d_y values > 0; +inf means the output carries no
  *   information). Gamma is diagonal here: a caller with a full noise covariance
@@ -146,15 +159,18 @@ dino_status dino_load_true_model(dino_ctx* ctx, int n_layers, const int32_t* kin
  *   applies (I + H)^-1 by Woodbury and draws the noise (I + H)^-1 (xi_1 + B^T xi_2)
  *   (the same law, N(0, (I + H)^-1); xi_2 = the d_y normals of stream 0 after the
  *   first r); DINO_FACTOR_AUTO takes the dual form when d_y < r. The order of the
- *   factorised matrix must not exceed 512. On the BF16 path each chain's Jacobian is
- *   staged in one block's LDS (the dual form keeps B (d_y x r) and its work vectors,
- *   the primal form's Gauss-Newton kernel B^T): a shape that does not fit is refused
- *   with DINO_EINVAL by dino_problem_workspace_bytes and dino_problem_create. The BF16
- *   reverse sweep holds at most 512 rows: networks with a hidden layer wider than 512
- *   units need DINO_PREC_F64 (also refused with DINO_EINVAL otherwise).
+ *   factorised matrix must not exceed 512. On the BF16 and FP8 paths the dual form
+ *   stages each chain's B (d_y x r) and its work vectors in one block's LDS: a shape
+ *   that does not fit is refused with DINO_EINVAL by dino_problem_workspace_bytes and
+ *   dino_problem_create (the primal form's Gauss-Newton kernel stages B^T when it fits
+ *   and otherwise streams B through LDS in 64 x 64 output tiles). The BF16 reverse
+ *   sweep holds at most 512 rows: networks with a hidden layer wider than 512 units
+ *   need DINO_PREC_FP8 or DINO_PREC_F64 (refused with DINO_EINVAL otherwise).
  */
 #define DINO_PREC_F64 0
 #define DINO_PREC_BF16 1
+#define DINO_PREC_FP8 2
+#define DINO_PREC_FP8_SINGLE 3
 #define DINO_FACTOR_PRIMAL 0
 #define DINO_FACTOR_DUAL 1
 #define DINO_FACTOR_AUTO 2
@@ -255,7 +271,10 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
  *        chain with the triangle in registers (up to 128 / 208), 5 the LDS panel kernel;
  *   kind DINO_TUNE_FWD64 (rows, fan_in, fan_out): FP64 forward tile of 16, 32 or 64 outputs;
  *   kind DINO_TUNE_FWD32 (rows, fan_in, fan_out): FP32 MFMA forward block order, 0 row-major,
- *        1 the tiles of a 32-row block on one XCD.
+ *        1 the tiles of a 32-row block on one XCD;
+ *   kind DINO_TUNE_HESS  (r, d_y, 0): the BF16/FP8 paths' Gauss-Newton kernel of the primal
+ *        form, 0 one block per chain with B^T staged in LDS (where it fits), 1 one block per
+ *        64 x 64 output tile streaming B (the only choice where B^T does not fit).
  * Every choice computes the same quantities (rounding order may differ between factor
  * kernels). n_entries (optional): table entries written. Releases the problem's launch
  * graphs (they hold the earlier choices). dino_tune_set sets or (choice < 0) erases an
@@ -263,6 +282,7 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
 #define DINO_TUNE_CHOL 0
 #define DINO_TUNE_FWD64 1
 #define DINO_TUNE_FWD32 2
+#define DINO_TUNE_HESS 3
 dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries);
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice);
 dino_status dino_tuning_table(char* buf, size_t cap, size_t* length);

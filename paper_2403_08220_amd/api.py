@@ -314,7 +314,7 @@ class Problem:
 
     def jacobian_storage(self, B):
         """Device copy of B (n, d_y, r) in the layout the dual stage entry points take: float64
-        rows of r (FP64 problems), or bfloat16 rows padded to dino_jacobian_ld (BF16 problems;
+        rows of r (FP64 problems), or bfloat16 rows padded to dino_jacobian_ld (BF16 and FP8 problems;
         the values are rounded to bfloat16 by torch)."""
         torch = _torch()
         n = B.shape[0]

@@ -15,6 +15,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdino.so")
 
 SOURCES = ["runtime.hip", "kernels_geometry.hip", "kernels_chain.hip", "kernels_basis.hip", "kernels_mfma.hip",
+           "kernels_fp8.hip",
            "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -182,6 +182,12 @@ struct Layer {
     float* W32 = nullptr;
     float* b32 = nullptr;
     std::vector<double> hostW, hostb;
+    // FP8 e4m3 W^T for the FP8 reverse sweep (kp8 = fan_out rounded up to 64 columns, fan_in
+    // rows and zero rows up to a multiple of 32), followed in the same allocation by the E8M0
+    // column exponents (wexp8, one per row, 127 on the zero rows)
+    uint8_t* WT8 = nullptr;
+    uint8_t* wexp8 = nullptr;
+    int kp8 = 0;
 };
 
 struct Basis {
@@ -207,6 +213,16 @@ struct Basis {
     std::vector<double> lam_dis_host;
 };
 
+// One layer of the FP8 reverse sweep, in processing order (output side first).
+struct Fp8SweepLayer {
+    const uint8_t* WT;    // FP8 W^T: fan_in rows (zero rows up to a multiple of 32) x kp
+    const uint8_t* wexp;  // E8M0 column exponents, one per row of WT
+    int K, N, kp;         // fan_out, fan_in, K rounded up to 64
+    int resid;            // Lambda <- Lambda + ...
+    int act;              // index of the layer's gelu' rows among the activated layers, -1 if linear
+    int rows;             // rows of WT: fan_in rounded up to 32
+};
+
 struct dino_ctx_impl;
 }  // namespace dino
 
@@ -219,6 +235,7 @@ struct dino_ctx {
     __hip_bfloat16* sweep_tiles = nullptr;  // BF16 W^T tiles of the reverse sweep, in work-item order
     const float* sweep_ones = nullptr;      // 32 * nmb FP32 ones after the tiles (same allocation)
     const float* sweep_wout = nullptr;      // output layer rows in the sweep's register order (same allocation)
+    dino::Fp8SweepLayer* fp8_layers = nullptr;  // device table of the FP8 sweep's layers
     // true-model stand-in of delayed acceptance: a network on the first r_T whitened
     // coordinates of the full parameter (FP64 and FP32 copies)
     std::vector<dino::Layer> true_layers;
@@ -353,7 +370,7 @@ namespace dino {
 
 // Tuning table (runtime.hip): the implementation chosen for a stage at a shape (a, b, c),
 // process-wide; -1 when the shape has no entry (the launcher's default then applies).
-enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2 };
+enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3 };
 constexpr int CHOL_VARIANTS = 6;
 int tuned_choice(int kind, int a, int b, int c);
 void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms);
@@ -474,6 +491,19 @@ void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int
 // FP32 forward; the first layer reads x64 (FP64, rounded on load) if given, else xf.
 void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st);
 void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st);
+// FP8 reverse sweep (kernels_fp8.hip): same output as launch_sweep_bf16, products in e4m3,
+// the left operand as one e4m3 term or two (terms = 1 or 2).
+void launch_sweep_fp8(dino_problem* p, int n, int terms, const float* d32, int ldd, __hip_bfloat16* Bout,
+                      hipStream_t st);
+// Whether the FP8 sweep holds the network for d_y observations (Lambda of 64 rows and the
+// gelu' rows of its chains in one block's LDS).
+bool fp8_sweep_ok(const dino_ctx* ctx, int dy);
+// OCP e4m3 code of v (round to nearest even, saturating at 448).
+uint8_t e4m3_encode(double v);
+// FP8 W^T of a layer (from its host copy) with power-of-two column exponents.
+void pack_fp8_layer(Layer& ly);
+// (Re)builds ctx->fp8_layers from the loaded network's FP8 copies.
+void build_fp8_table(dino_ctx* ctx);
 void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                       long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
 void launch_to_float(long count, const double* x, float* xf, hipStream_t st);

@@ -379,7 +379,7 @@ __device__ __forceinline__ void residual_into(int c, int dy, const float* __rest
     for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
     if ((tid & 63) == 0) red[tid >> 6] = part;
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && phi) {
         double t = 0.0;
 #pragma unroll
         for (int k = 0; k < HES_TPB / 64; ++k) t += red[k];
@@ -437,6 +437,90 @@ __global__ __launch_bounds__(HES_TPB) void hess_bf16_kernel(int dy, int r, int l
             const int row = 32 * bj + 8 * (j >> 2) + 4 * h + (j & 3);
             if (row < r && col < r && col <= row) Ac[(long)row * r + col] = (double)acc[j] + (row == col ? 1.0 : 0.0);
         }
+    }
+}
+
+// The same Hessian, ppg and misfit for shapes whose B^T does not fit one block's LDS
+// (reduced dimensions and observation counts of several hundred): one block per chain and
+// lower 64 x 64 tile (bi >= bk) of I + B^T B, B streamed through LDS in chunks of 64 rows
+// (observed outputs), transposed as they are staged. Each wave forms one 32 x 32 sub-tile.
+// Diagonal tiles also form the ppg of their 64 columns; tile (0, 0) writes the misfit. The
+// products, and their order over the outputs, are those of hess_bf16_kernel, so the two
+// agree bit for bit where both apply. Work items are laid out so that the tiles of one
+// chain run on one XCD and share its L2 copy of B.
+constexpr int HT_CH = 64;
+__global__ __launch_bounds__(HES_TPB) void hess_bf16_tiled_kernel(int n, int dy, int r, int ldb, int ntile,
+                                                                  const __hip_bfloat16* __restrict__ B,
+                                                                  const float* __restrict__ f, const double* y_rows,
+                                                                  const double* winv_rows, const int32_t* rows,
+                                                                  double* __restrict__ phi, double* A, long strideA,
+                                                                  const int32_t* slot, int slot_xor, long slot_stride,
+                                                                  double* __restrict__ g) {
+    __shared__ __align__(16) __hip_bfloat16 ti[64 * (HT_CH + 8)];
+    __shared__ __align__(16) __hip_bfloat16 tk[64 * (HT_CH + 8)];
+    __shared__ float es[1024];
+    __shared__ double red[HES_TPB / 64];
+    const long total = (long)n * ntile;
+    const long per = (total + 7) / 8;
+    const long w = (long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (w >= total) return;
+    const int c = (int)(w / ntile), t = (int)(w - (long)(w / ntile) * ntile);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bk = t - bi * (bi + 1) / 2;
+    const bool diag = bi == bk;
+    if (!A && !diag) return;  // ppg and misfit only (the MALA baseline forms no metric)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int nl = lane & 31, h = lane >> 5, wi = wave & 1, wk = wave >> 1;
+    const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
+    const __hip_bfloat16* tkp = diag ? ti : tk;
+    if (diag) residual_into(c, dy, f, y_rows, winv_rows, rows, es, red, (bi == 0) ? phi : nullptr);
+    const bool mine = A && !(diag && wk > wi);  // the diagonal tile's upper sub-tile is not formed
+    f32x16 acc;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+    double gacc = 0.0;
+    for (int k0 = 0; k0 < dy; k0 += HT_CH) {
+        __syncthreads();  // the previous chunk is consumed
+        for (int e = tid; e < HT_CH * 8; e += HES_TPB) {
+            const int kk = e >> 3, c8 = (e & 7) * 8, k = k0 + kk;
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+                if (side == 1 && diag) break;
+                const int col = 64 * (side ? bk : bi) + c8;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (k < dy && col < ldb) v = *reinterpret_cast<const uint4*>(Bc + (long)k * ldb + col);
+                const __hip_bfloat16* pv = reinterpret_cast<const __hip_bfloat16*>(&v);
+                __hip_bfloat16* dst = side ? tk : ti;
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    dst[(c8 + j) * (HT_CH + 8) + kk] = (col + j < r) ? pv[j] : __float2bfloat16(0.f);
+            }
+        }
+        __syncthreads();
+        if (diag && tid < 64) {
+            const int kn = min(HT_CH, dy - k0);
+            for (int kk = 0; kk < kn; ++kk)
+                gacc += (double)__bfloat162float(ti[tid * (HT_CH + 8) + kk]) * (double)es[k0 + kk];
+        }
+        if (mine) {
+#pragma unroll
+            for (int s = 0; s < HT_CH / 16; ++s) {
+                if (k0 + 16 * s >= dy) break;
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(ti + (32 * wi + nl) * (HT_CH + 8) + 16 * s + 8 * h);
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(tkp + (32 * wk + nl) * (HT_CH + 8) + 16 * s + 8 * h);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+            }
+        }
+    }
+    if (diag && tid < 64 && 64 * bi + tid < r) g[(long)c * r + 64 * bi + tid] = gacc;
+    if (!mine) return;
+    double* Ac = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    const int col = 64 * bk + 32 * wk + nl;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int row = 64 * bi + 32 * wi + 8 * (j >> 2) + 4 * h + (j & 3);
+        if (row < r && col < r && col <= row) Ac[(long)row * r + col] = (double)acc[j] + (row == col ? 1.0 : 0.0);
     }
 }
 
@@ -689,7 +773,18 @@ void launch_hess_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
     const int ldt = dy_pad + 8;  // 16-byte aligned rows, shifted banks
     const int r_pad = (r + 31) / 32 * 32;
     const size_t lds = hess_bf16_lds(r, dy);
-    DINO_REQUIRE(lds <= 160 * 1024 - 64, DINO_EINVAL, "r x d_y too large for the LDS-staged Hessian");
+    if (lds > 160 * 1024 - 64 || tuned_choice(TUNE_HESS, r, dy, 0) == 1) {
+        DINO_REQUIRE(dy <= 1024, DINO_EINVAL, "d_y above 1024");
+        const int T = (r + 63) / 64, ntile = T * (T + 1) / 2;
+        const long total = (long)n * ntile, blocks = (total + 7) / 8 * 8;
+        DINO_REQUIRE(blocks < (1L << 31), DINO_EINVAL, "too many Hessian tiles for one launch");
+        if (n > 0)
+            hipLaunchKernelGGL(hess_bf16_tiled_kernel, dim3((unsigned)blocks), dim3(HES_TPB), 0, st, n, dy, r, r_pad,
+                               ntile, B, f, p->y, p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride,
+                               g);
+        DINO_HIP(hipGetLastError());
+        return;
+    }
     static bool attr = false;
     if (!attr) {
         DINO_HIP(hipFuncSetAttribute((const void*)hess_bf16_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -104,6 +104,7 @@ static void free_layers(std::vector<Layer>& ls) {
         if (l.b64) hipFree(l.b64);
         if (l.W32) hipFree(l.W32);
         if (l.b32) hipFree(l.b32);
+        if (l.WT8) hipFree(l.WT8);
     }
     ls.clear();
 }
@@ -230,7 +231,9 @@ static void layout(dino_problem* p, Carver& cv) {
         p->lam1 = cv.take<double>(C * dy * w);
         p->Bj = cv.take<double>(C * dy * r);
     } else {
-        p->ldd32 = 32 * sweep_nmb(p->ctx);  // the sweep reads gelu' rows of its full instance width
+        // the BF16 sweep reads gelu' rows of its full instance width, the FP8 sweep of the layer's
+        const bool fp8 = p->desc.precision == DINO_PREC_FP8 || p->desc.precision == DINO_PREC_FP8_SINGLE;
+        p->ldd32 = fp8 ? (w + 31) / 32 * 32 : 32 * sweep_nmb(p->ctx);
         p->xpf = cv.take<float>(C * r);
         p->h0f = cv.take<float>(C * w);
         p->h1f = cv.take<float>(C * w);
@@ -280,7 +283,8 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     DINO_REQUIRE(d->n_chains >= 1 && d->n_chains <= (1 << 20), DINO_EINVAL, "n_chains out of range");
     DINO_REQUIRE(d->d_y >= 1 && d->d_y <= ctx->d_out && d->d_y <= 1024, DINO_EINVAL, "d_y out of range");
     DINO_REQUIRE(d->dt > 0.0 && std::isfinite(d->dt), DINO_EINVAL, "dt must be positive");
-    DINO_REQUIRE(d->precision == DINO_PREC_F64 || d->precision == DINO_PREC_BF16, DINO_EINVAL,
+    const bool fp8 = d->precision == DINO_PREC_FP8 || d->precision == DINO_PREC_FP8_SINGLE;
+    DINO_REQUIRE(d->precision == DINO_PREC_F64 || d->precision == DINO_PREC_BF16 || fp8, DINO_EINVAL,
                  "unknown precision");
     DINO_REQUIRE(d->trace_capacity >= 0, DINO_EINVAL, "negative trace capacity");
     DINO_REQUIRE(ctx->basis.r <= 512, DINO_EINVAL, "reduced dimension above 512");
@@ -300,12 +304,13 @@ static void check_desc(const dino_ctx* ctx, const dino_problem_desc* d) {
     const bool dual = d->factorization == DINO_FACTOR_DUAL ||
                       (d->factorization == DINO_FACTOR_AUTO && d->d_y < ctx->basis.r);
     DINO_REQUIRE(!dual || d->d_y <= 512, DINO_EINVAL, "the dual form factorises d_y x d_y: d_y above 512");
-    DINO_REQUIRE(!dual || dual_lds_fits(ctx->basis.r, d->d_y, d->precision == DINO_PREC_BF16), DINO_EINVAL,
+    DINO_REQUIRE(!dual || dual_lds_fits(ctx->basis.r, d->d_y, d->precision != DINO_PREC_F64), DINO_EINVAL,
                  "d_y x r too large for the dual form's per-chain LDS (B and the work vectors)");
     DINO_REQUIRE(d->precision != DINO_PREC_BF16 || sweep_width_ok(ctx), DINO_EINVAL,
                  "the BF16 reverse sweep holds layers of at most 512 units: this network needs the FP64 path");
-    DINO_REQUIRE(dual || d->precision != DINO_PREC_BF16 || hess_bf16_lds_fits(ctx->basis.r, d->d_y), DINO_EINVAL,
-                 "r x d_y too large for the BF16 Gauss-Newton Hessian's LDS (B^T and the residual)");
+    DINO_REQUIRE(!fp8 || fp8_sweep_ok(ctx, d->d_y), DINO_EINVAL,
+                 "the FP8 reverse sweep holds layers of at most 800 units (and, at that width, d_y >= 5): this "
+                 "network needs the FP64 path");
 }
 
 static void fill_dims(dino_problem* p, dino_ctx* ctx, const dino_problem_desc* d) {
@@ -340,6 +345,8 @@ static void stage_forward(dino_problem* p, int n, const double* x, double* f64, 
 
 static void stage_jacobian(dino_problem* p, int n, hipStream_t st) {
     if (p->desc.precision == DINO_PREC_F64) launch_reverse_jacobian(p, n, p->Bj, st);
+    else if (p->desc.precision == DINO_PREC_FP8) launch_sweep_fp8(p, n, 2, p->d32, p->ldd32, p->B16, st);
+    else if (p->desc.precision == DINO_PREC_FP8_SINGLE) launch_sweep_fp8(p, n, 1, p->d32, p->ldd32, p->B16, st);
     else launch_sweep_bf16(p, n, p->d32, p->ldd32, p->B16, st);
 }
 
@@ -402,6 +409,7 @@ dino_status dino_ctx_destroy(dino_ctx* ctx) {
         free_layers(ctx->layers);
         free_layers(ctx->true_layers);
         if (ctx->sweep_tiles) (void)hipFree(ctx->sweep_tiles);
+        if (ctx->fp8_layers) (void)hipFree(ctx->fp8_layers);
         delete ctx;
     });
 }
@@ -588,6 +596,7 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         int sweep_nmb_t = 0;
         try {
             for (int l = 0; l < n_layers; ++l) upload_layer(ls[l], kinds[l], fan_out[l], fan_in[l], W[l], b ? b[l] : nullptr);
+            for (int l = 0; l + 1 < n_layers; ++l) pack_fp8_layer(ls[l]);  // the output layer stays FP32
             // BF16 MFMA operand tiles of W^T for the reverse sweep, packed for the sweep
             // instance that covers the widest layer
             dino_ctx probe;
@@ -640,6 +649,7 @@ dino_status dino_load_network(dino_ctx* ctx, int n_layers, const int32_t* kinds,
         ctx->d_out = fan_out[n_layers - 1];
         ctx->max_width = wmax;
         ctx->n_act = n_act;
+        build_fp8_table(ctx);
     });
 }
 
@@ -1104,6 +1114,25 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
                 set_tuned_choice(TUNE_CHOL, C, k, 0, best, ms);
                 ++count;
             }
+            const bool mixed = p->desc.precision != DINO_PREC_F64;
+            if (factor && mixed && !p->dual && hess_bf16_lds_fits(p->r, p->d_y)) {
+                // the Gauss-Newton kernel (LDS-staged B^T or tiles streaming B) on the Jacobian
+                // at the states, into the proposal halves and proposal scratch
+                stage_forward(p, C, p->x, p->f, st);
+                stage_jacobian(p, C, st);
+                const long kk = (long)p->r * p->r, half = (long)C * kk;
+                std::vector<double> ms(2, -1.0);
+                int best = -1;
+                for (int cnd = 0; cnd < 2; ++cnd) {
+                    set_tuned_choice(TUNE_HESS, p->r, p->d_y, 0, cnd, {});
+                    ms[cnd] = time_on_stream(st, e0, e1, 5, [&] {
+                        launch_hess_bf16(p, C, p->B16, p->f32, p->phip, p->Lbuf, kk, p->cur, 1, half, p->gp, st);
+                    });
+                    if (best < 0 || ms[cnd] < ms[best]) best = cnd;
+                }
+                set_tuned_choice(TUNE_HESS, p->r, p->d_y, 0, best, ms);
+                ++count;
+            }
             // the forward layers, one shape at a time (the other shapes at their current
             // choice), timed as the whole forward stage at the states (its outputs are scratch)
             const bool f64 = p->desc.precision == DINO_PREC_F64;
@@ -1143,11 +1172,13 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
 
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice) {
     return guarded([&] {
-        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_FWD32, DINO_EINVAL, "unknown tuning kind");
+        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_HESS, DINO_EINVAL, "unknown tuning kind");
         const int ncand = kind == TUNE_CHOL ? CHOL_VARIANTS : (kind == TUNE_FWD64 ? 3 : 2);
         DINO_REQUIRE(choice < ncand, DINO_EINVAL, "choice out of range for this kind");
         DINO_REQUIRE(kind != TUNE_CHOL || choice < 0 || cholesky_variant_max(choice) >= b, DINO_EINVAL,
                      "factor kernel variant does not hold this order");
+        DINO_REQUIRE(kind != TUNE_HESS || choice != 0 || hess_bf16_lds_fits(a, b), DINO_EINVAL,
+                     "the LDS-staged Gauss-Newton kernel does not hold this shape");
         set_tuned_choice(kind, a, b, c, choice, {});
     });
 }

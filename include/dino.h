@@ -268,7 +268,9 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
  * uses (other problems and serving pools included):
  *   kind DINO_TUNE_CHOL  (a, b, c) = (chains, factor order, 0): the factor kernel,
  *        0-2 one wavefront per chain (orders up to 32 / 56 / 104), 3-4 one block per
- *        chain with the triangle in registers (up to 128 / 208), 5 the LDS panel kernel;
+ *        chain with the triangle in registers (up to 128 / 208), 5 the LDS panel kernel,
+ *        6 the transposed-panel kernel (one-wave diagonal block, row-parallel panel solve;
+ *        up to 512);
  *   kind DINO_TUNE_FWD64 (rows, fan_in, fan_out): FP64 forward tile of 16, 32 or 64 outputs;
  *   kind DINO_TUNE_FWD32 (rows, fan_in, fan_out): FP32 MFMA forward block order, 0 row-major,
  *        1 the tiles of a 32-row block on one XCD;

@@ -182,9 +182,10 @@ struct Layer {
     float* W32 = nullptr;
     float* b32 = nullptr;
     std::vector<double> hostW, hostb;
-    // FP8 e4m3 W^T for the FP8 reverse sweep (kp8 = fan_out rounded up to 64 columns, fan_in
-    // rows and zero rows up to a multiple of 32), followed in the same allocation by the E8M0
-    // column exponents (wexp8, one per row, 127 on the zero rows)
+    // FP8 e4m3 W^T for the FP8 reverse sweep (fan_in rounded up to 32 rows, fan_out to kp8 = a
+    // multiple of 64, zero padded) in the sweep's operand order (32 x 64 blocks of 2 KB),
+    // followed in the same allocation by the E8M0 column exponents (wexp8, one per row, 127
+    // on the zero rows)
     uint8_t* WT8 = nullptr;
     uint8_t* wexp8 = nullptr;
     int kp8 = 0;
@@ -215,7 +216,7 @@ struct Basis {
 
 // One layer of the FP8 reverse sweep, in processing order (output side first).
 struct Fp8SweepLayer {
-    const uint8_t* WT;    // FP8 W^T: fan_in rows (zero rows up to a multiple of 32) x kp
+    const uint8_t* WT;    // FP8 W^T in operand order (rows: fan_in rounded up to 32; K: kp)
     const uint8_t* wexp;  // E8M0 column exponents, one per row of WT
     int K, N, kp;         // fan_out, fan_in, K rounded up to 64
     int resid;            // Lambda <- Lambda + ...
@@ -371,7 +372,7 @@ namespace dino {
 // Tuning table (runtime.hip): the implementation chosen for a stage at a shape (a, b, c),
 // process-wide; -1 when the shape has no entry (the launcher's default then applies).
 enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3 };
-constexpr int CHOL_VARIANTS = 6;
+constexpr int CHOL_VARIANTS = 7;
 int tuned_choice(int kind, int a, int b, int c);
 void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms);
 

@@ -442,6 +442,171 @@ __global__ __launch_bounds__(TPB) void cholesky_kernel(int r, double* A, long st
     }
 }
 
+// In-place Cholesky of A_c (r x r, lower triangle read and written) for the largest
+// orders: right-looking over 32-column panels, one 512-thread block per chain (two waves
+// per SIMD). A panel is held transposed in LDS (column jj of the panel at Pt + jj LD,
+// LD = r rounded up to odd, so that consecutive rows are consecutive words):
+//   1. one wave factors the 32 x 32 diagonal block (lane = row, the row in registers,
+//      each column's multipliers broadcast across lanes by shuffles);
+//   2. the rows below are solved row-parallel, L21 = A21 L11^-T, one row per thread with
+//      the row in registers;
+//   3. the trailing update A22 -= L21 L21^T runs in 4 x 4 register blocks, each thread
+//      loading its block of A22 before the products so that the loads' latency overlaps them.
+constexpr int PTPB = 512;
+constexpr int PNB = 32;
+
+// row[lane] with a run-time lane: the diagonal entry a lane holds.
+__device__ __forceinline__ double lane_diag(const double (&row)[PNB], int lane) {
+    double d = 0.0;
+#pragma unroll
+    for (int k = 0; k < PNB; ++k)
+        if (k == lane) d = row[k];
+    return d;
+}
+
+__global__ __launch_bounds__(PTPB) void cholesky_panel_kernel(int r, double* A, long strideA, const int32_t* slot,
+                                                             int slot_xor, long slot_stride, double* logdet,
+                                                             int32_t* ok) {
+    extern __shared__ double Pt[];  // PNB x LD, then the panel's reciprocal pivots
+    __shared__ int fail;
+    __shared__ double ld_acc;
+    const int LD = r | 1;
+    double* dinv = Pt + PNB * LD;
+    const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double* a = A + (long)c * strideA + slot_offset(slot, slot_xor, slot_stride, c);
+    if (tid == 0) {
+        fail = 0;
+        ld_acc = 0.0;
+    }
+    for (int j0 = 0; j0 < r; j0 += PNB) {
+        const int jb = min(PNB, r - j0), rows = r - j0;
+        __syncthreads();  // the previous panel's readers are done
+        for (int e = tid; e < rows * PNB; e += PTPB) {
+            const int i = e >> 5, jj = e & (PNB - 1);
+            if (jj < jb && jj <= i) Pt[jj * LD + i] = a[(long)(j0 + i) * r + j0 + jj];
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // lane = row of the diagonal block, held in registers; column jj's pivot and
+            // multipliers reach the other lanes by v_readlane (uniform lane index)
+            double row[PNB];
+#pragma unroll
+            for (int k = 0; k < PNB; ++k) row[k] = (lane < jb && k <= lane) ? Pt[k * LD + lane] : 0.0;
+            bool bad = false;
+#pragma unroll
+            for (int jj = 0; jj < PNB; ++jj) {
+                if (jj < jb) {
+                    const double piv = lane_bcast(row[jj], jj);
+                    bad = bad || !(piv > 0.0);
+                    const double dgl = sqrt(piv);
+                    const double inv = 1.0 / dgl;
+                    const double l = (lane > jj && lane < jb) ? row[jj] * inv : 0.0;
+                    if (lane == jj) row[jj] = dgl;
+                    if (lane > jj) row[jj] = l;
+                    if (lane == 0) dinv[jj] = inv;
+#pragma unroll
+                    for (int k = jj + 1; k < PNB; ++k) {
+                        const double lk = lane_bcast(l, k);
+                        if (k <= lane) row[k] -= l * lk;  // l = 0 on lanes <= jj
+                    }
+                }
+            }
+            // log det of the block: one log per lane (its pivot), summed across the wave
+            double lg = (lane < jb) ? log(lane_diag(row, lane)) : 0.0;
+            for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o);
+            if (lane == 0) {
+                if (bad) fail = 1;
+                ld_acc += lg;
+            }
+#pragma unroll
+            for (int k = 0; k < PNB; ++k)
+                if (lane < jb && k <= lane) Pt[k * LD + lane] = row[k];
+        }
+        __syncthreads();
+        for (int i = jb + tid; i < rows; i += PTPB) {
+            double x[PNB];
+            if (jb == PNB) {  // full panel: one straight-line region, its LDS reads issued early
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj) x[jj] = Pt[jj * LD + i];
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj) {
+                    double sum = x[jj];
+#pragma unroll
+                    for (int t = 0; t < jj; ++t) sum -= x[t] * Pt[t * LD + jj];
+                    x[jj] = sum * dinv[jj];
+                }
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj) Pt[jj * LD + i] = x[jj];
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj) x[jj] = jj < jb ? Pt[jj * LD + i] : 0.0;
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj) {
+                    if (jj < jb) {
+                        double sum = x[jj];
+#pragma unroll
+                        for (int t = 0; t < jj; ++t) sum -= x[t] * Pt[t * LD + jj];
+                        x[jj] = sum * dinv[jj];
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < PNB; ++jj)
+                    if (jj < jb) Pt[jj * LD + i] = x[jj];
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < rows * PNB; e += PTPB) {
+            const int i = e >> 5, jj = e & (PNB - 1);
+            if (jj < jb && jj <= i) a[(long)(j0 + i) * r + j0 + jj] = Pt[jj * LD + i];
+        }
+        const int T = rows - jb;
+        if (T > 0) {
+            const int nbk = (T + 3) / 4;
+            const int nblocks = nbk * (nbk + 1) / 2;
+            for (int bidx = tid; bidx < nblocks; bidx += PTPB) {
+                int bi = (int)((sqrt(8.0 * (double)bidx + 1.0) - 1.0) * 0.5);
+                while ((bi + 1) * (bi + 2) / 2 <= bidx) ++bi;
+                while (bi * (bi + 1) / 2 > bidx) --bi;
+                const int bk = bidx - bi * (bi + 1) / 2;
+                const int li = jb + 4 * bi, lk = jb + 4 * bk;  // panel-local rows of the block
+                double old[4][4], acc[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) {
+                        const int i = li + q, k = lk + s2;
+                        old[q][s2] = (i < rows && k <= i) ? a[(long)(j0 + i) * r + j0 + k] : 0.0;
+                        acc[q][s2] = 0.0;
+                    }
+                for (int jj = 0; jj < jb; ++jj) {
+                    double pi[4], pk[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pi[q] = Pt[jj * LD + min(li + q, rows - 1)];
+                        pk[q] = Pt[jj * LD + min(lk + q, rows - 1)];
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int s2 = 0; s2 < 4; ++s2) acc[q][s2] += pi[q] * pk[s2];
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; ++s2) {
+                        const int i = li + q, k = lk + s2;
+                        if (i < rows && k <= i) a[(long)(j0 + i) * r + j0 + k] = old[q][s2] - acc[q][s2];
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (logdet) logdet[c] = ld_acc;
+        if (ok) ok[c] = fail ? 0 : 1;
+    }
+}
+
 // Register-resident Cholesky for r <= min(G MR, 32 MC), G = NT / 32: the NT threads of a
 // block hold the lower triangle in a 2-D cyclic layout, thread t = 32 g + q owning rows
 // i = g + G m (m < MR) and columns k = q + 32 c (c < MC). A (m, c) pair is kept only if
@@ -2081,20 +2246,24 @@ __global__ void copy_rows_kernel(int n, int width, const double* __restrict__ sr
 
 // ---------------------------------------------------------------------------------
 static size_t chol_lds(int r) { return (size_t)r * CLDP * sizeof(double); }
+static size_t panel_lds(int r) { return ((size_t)PNB * (r | 1) + PNB) * sizeof(double); }
 static int ldz_of(int d_perp) { return (d_perp + 63) / 64 * 64; }
 
 // Factor kernels by variant: 0-2 one wavefront per chain (orders up to 32, 56, 104), 3-4
 // a 512-thread block per chain with the triangle in registers (up to 128, 208), 5 the
-// LDS panel kernel (up to 512). Any variant whose maximum covers the order is correct.
-static const int kCholMax[CHOL_VARIANTS] = {32, 56, 104, 128, 208, 512};
+// LDS panel kernel (up to 512), 6 the transposed-panel kernel with a one-wave diagonal
+// block (up to 512). Any variant whose maximum covers the order is correct.
+static const int kCholMax[CHOL_VARIANTS] = {32, 56, 104, 128, 208, 512, 512};
 
 int cholesky_variant_max(int variant) { return (variant >= 0 && variant < CHOL_VARIANTS) ? kCholMax[variant] : 0; }
 
-// The smallest variant that holds the order (the choice without a tuning entry).
+// The choice without a tuning entry: the smallest register or wavefront variant that holds
+// the order, and above those the transposed-panel kernel (faster than the LDS panel kernel
+// at every order it was timed at, 300 and 400).
 static int default_cholesky_variant(int r) {
-    for (int v = 0; v < CHOL_VARIANTS; ++v)
+    for (int v = 0; v < 5; ++v)
         if (r <= kCholMax[v]) return v;
-    return CHOL_VARIANTS - 1;
+    return 6;
 }
 
 void launch_cholesky_variant(int variant, int n, int r, double* A, long strideA, const int32_t* slot, int slot_xor,
@@ -2105,6 +2274,8 @@ void launch_cholesky_variant(int variant, int n, int r, double* A, long strideA,
     if (!attr_set) {
         DINO_HIP(hipFuncSetAttribute((const void*)cholesky_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      160 * 1024 - 256));
+        DINO_HIP(hipFuncSetAttribute((const void*)cholesky_panel_kernel,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256));
         attr_set = true;
     }
     switch (variant) {
@@ -2128,9 +2299,13 @@ void launch_cholesky_variant(int variant, int n, int r, double* A, long strideA,
         hipLaunchKernelGGL((cholesky_reg_kernel<512, 13, 7>), dim3(n), dim3(512), 0, st, r, A, strideA, slot,
                            slot_xor, slot_stride, logdet, ok);
         break;
-    default:
+    case 5:
         hipLaunchKernelGGL(cholesky_kernel, dim3(n), dim3(TPB), chol_lds(r), st, r, A, strideA, slot, slot_xor,
                            slot_stride, logdet, ok);
+        break;
+    default:
+        hipLaunchKernelGGL(cholesky_panel_kernel, dim3(n), dim3(PTPB), panel_lds(r), st, r, A, strideA, slot,
+                           slot_xor, slot_stride, logdet, ok);
         break;
     }
     DINO_HIP(hipGetLastError());

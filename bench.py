@@ -61,10 +61,10 @@ KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "cholesky_wave_k
                   "fwd_mfma_kernel": ["kernels_geometry.hip"],
                   "fwd_layer_kernel": ["kernels_geometry.hip"],
                   "jac_sweep_fp8_kernel": ["kernels_fp8.hip"], "hess_bf16_tiled_kernel": ["kernels_mfma.hip"],
-                  "cholesky_kernel": ["kernels_chain.hip"]}
-# the FP8 path at the large shape: FP8 sweep, tiled Gauss-Newton kernel, LDS panel factor
+                  "cholesky_kernel": ["kernels_chain.hip"], "cholesky_panel_kernel": ["kernels_chain.hip"]}
+# the FP8 path at the large shape: FP8 sweep, tiled Gauss-Newton kernel, transposed-panel factor
 STAGE_KERNEL_FP8_LARGE = dict(STAGE_KERNEL, jacobian="jac_sweep_fp8_kernel", gn_hessian="hess_bf16_tiled_kernel",
-                              cholesky="cholesky_kernel")
+                              cholesky="cholesky_panel_kernel")
 
 
 def source_sha256(kernel):
@@ -507,7 +507,21 @@ def _csv_rows(path):
         return list(csv.DictReader(fh))
 
 
-def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="mid"):
+# The profiled bench commands of each workload's committed summaries (the kernel trace run,
+# then one FETCH_SIZE and one WRITE_SIZE run of the counter command).
+_PROFILE_ZERO = "--fp64-steps 0 --baseline-steps 0 --serve-requests 0 --ess-steps 0 --da-steps 0 --no-cpu-baseline"
+PROFILE_RUNS = {
+    "mid": dict(desc="BF16 path, 512 chains",
+                trace=f"python3 bench.py --steps 100 {_PROFILE_ZERO} --large-steps 0",
+                counters=f"python3 bench.py --steps 20 --warmup 5 {_PROFILE_ZERO} --large-steps 0"),
+    "large": dict(desc="FP8 path at 257x257, r = 400, ResNet 800x6, d_y = 400, 4096 chains",
+                  trace=f"python3 bench.py --steps 2 --warmup 1 {_PROFILE_ZERO} --large-steps 10 --large-fp64-steps 0",
+                  counters=f"python3 bench.py --steps 2 --warmup 1 {_PROFILE_ZERO} --large-steps 3 "
+                           "--large-fp64-steps 0"),
+}
+
+
+def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="mid", desc="BF16 path, 512 chains"):
     """Turns rocprofv3 output (one --kernel-trace --stats run, one --pmc FETCH_SIZE and
     one --pmc WRITE_SIZE run of the same bench command) into the committed summaries
     under profiles/: per-kernel statistics of the step kernels, and the HBM traffic per
@@ -522,9 +536,9 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="m
                int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
         groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
     total = sum(sum(v) for v in groups.values())
-    lines = [f"# rocprofv3 kernel statistics, {workload_tag} workload (BF16 path, 512 chains)", "",
+    lines = [f"# rocprofv3 kernel statistics, {workload_tag} workload ({desc})", "",
              f"Command: `{command['trace']}`", "",
-             "Grouped by kernel and grid size (work-items): the per-step launches cover all 512 chains; "
+             "Grouped by kernel and grid size (work-items): the per-step launches cover all chains; "
              "launches at small grids belong to the Gauss-Newton start and the data setup.", "",
              "| Kernel | Grid | Calls | Average us | Min us | Max us | Share % |", "|---|---|---|---|---|---|---|"]
     for (k, g), v in sorted(groups.items(), key=lambda kv: -sum(kv[1]))[:24]:
@@ -546,7 +560,7 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="m
     f_cal = max(v[0] for (k, g), v in fetch.items() if k == "__amd_rocclr_copyBuffer") * 1024.0
     w_cal = max(v[0] for (k, g), v in write.items() if k == "__amd_rocclr_copyBuffer") * 1024.0
     f_scale, w_scale = cal_bytes / f_cal, cal_bytes / w_cal
-    lines = [f"# HBM traffic per launch, {workload_tag} workload (BF16 path, 512 chains)", "",
+    lines = [f"# HBM traffic per launch, {workload_tag} workload ({desc})", "",
              f"FETCH_SIZE: `{command['fetch']}`", "", f"WRITE_SIZE: `{command['write']}`", "",
              f"Calibration: the 512 MiB device copy reads {f_cal / 2**20:.1f} MiB by FETCH_SIZE and writes "
              f"{w_cal / 2**20:.1f} MiB by WRITE_SIZE: scales {f_scale:.3f} (fetch) and {w_scale:.3f} (write).", "",
@@ -623,7 +637,8 @@ def large_leg(steps, warmup, fp64_steps):
                                                                                  "unit", "frac")}),
             roofline_fp8_sweep=None if jac is None else dict(
                 bound="mfma", achieved=jac["achieved"], peak=PEAKS["fp8_TFLOPs"], unit="TFLOP/s",
-                frac=jac["frac"], kernel="jac_sweep_fp8_kernel", ms_per_launch=jac["ms"]),
+                frac=jac["frac"], kernel="jac_sweep_fp8_kernel", ms_per_launch=jac["ms"],
+                traffic=traffic_record("jac_sweep_fp8_kernel", "large")),
             init=init_info)
         if fp64_steps > 0:
             r64 = run_path(w, ctx, y, nv, x0, z0, "f64", fp64_steps, 1, profile=False, factorization="primal")
@@ -660,14 +675,16 @@ def main():
     ap.add_argument("--large-fp64-steps", type=int, default=4, help="plain FP64 steps at the largest shape")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write the profiles/ summaries from rocprofv3 output (no GPU needed) and exit")
+    ap.add_argument("--profile-workload", default="mid", choices=sorted(PROFILE_RUNS),
+                    help="which workload's bench commands the rocprofv3 output came from")
     args = ap.parse_args()
     if args.summarize_profiles:
-        b = "python3 bench.py --steps 20 --warmup 5 --fp64-steps 0 --baseline-steps 0 --serve-requests 0 --no-cpu-baseline"
+        run = PROFILE_RUNS[args.profile_workload]
         summarize_profiles(*args.summarize_profiles, command={
-            "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- python3 bench.py "
-                     "--steps 100 --fp64-steps 0 --baseline-steps 0 --serve-requests 0 --no-cpu-baseline",
-            "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {b}",
-            "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {b}"})
+            "trace": f"rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- {run['trace']}",
+            "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o run -- {run['counters']}",
+            "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o run -- {run['counters']}"},
+            workload_tag=args.profile_workload, desc=run["desc"])
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus}). "

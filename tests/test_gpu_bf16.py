@@ -98,24 +98,37 @@ def test_bf16_chains_step_and_agree_on_decisions_mostly():
 
 
 @pytest.mark.gpu
-def test_bf16_primal_refuses_shapes_beyond_its_lds():
-    """The BF16 Gauss-Newton Hessian stages B^T (r x d_y) in LDS: a shape that does not fit
-    is refused when the problem is described (the FP64 path takes it)."""
-    from paper_2403_08220_amd import Context, DinoError, Problem
+def test_bf16_primal_beyond_the_staged_lds_takes_the_tiled_kernel():
+    """B^T (r x d_y) of a chain too large for one block's LDS (r = 200, d_y = 400): the
+    Gauss-Newton kernel streams B in 64 x 64 output tiles instead. H and g equal FP64 sums
+    over the device's own B and FP32 residual to FP32 accumulation accuracy, and the
+    oracle's within the BF16 bar."""
+    from paper_2403_08220_amd import Context, Problem
 
     rng = np.random.default_rng(4)
-    r, dy = 200, 400
+    r, dy, C = 200, 400, 6
     ctx = Context(0)
     try:
         ctx.load_prior(33, 0.1, 1.0, r)
-        layers = [("act", rng.standard_normal((32, r)) / np.sqrt(r), None),
-                  ("linear", rng.standard_normal((dy, 32)) / np.sqrt(32), None)]
+        layers = [("act", rng.standard_normal((32, r)) / np.sqrt(r), np.zeros(32)),
+                  ("linear", rng.standard_normal((dy, 32)) / np.sqrt(32), np.zeros(dy))]
         ctx.load_network(layers)
-        y, nv = np.zeros(dy), np.ones(dy)
-        with pytest.raises(DinoError, match="too large for the BF16 Gauss-Newton Hessian"):
-            Problem(ctx, 4, y, nv, 1e-3, precision="bf16", factorization="primal")
-        p = Problem(ctx, 4, y, nv, 1e-3, precision="f64", factorization="primal")
-        p.close()
+        y, nv = 0.1 * rng.standard_normal(dy), np.full(dy, 0.05)
+        p = Problem(ctx, C, y, nv, 1e-3, precision="bf16", factorization="primal")
+        try:
+            x = 0.5 * rng.standard_normal((C, r))
+            B = p.eval_jacobian(to_dev(x)).cpu().numpy()
+            got = {k: v.cpu().numpy() for k, v in p.eval_geometry(to_dev(x)).items()}
+        finally:
+            p.close()
+        e = ((got["f"] - y[None, :]) / np.sqrt(nv)[None, :]).astype(np.float32).astype(np.float64)
+        for c in range(C):
+            H = B[c].T @ B[c]
+            assert np.max(np.abs(got["H"][c] - H)) < 1e-5 * np.max(np.abs(H))
+            assert np.max(np.abs(got["g"][c] - B[c].T @ e[c])) < 1e-9 * np.max(np.abs(B[c].T @ e[c]))
+        prob = mcmc.Problem(layers, y, nv, 1e-3)
+        ref = mcmc.geometry(prob, x)
+        assert per_chain_rel(got["H"], ref.H) < BAR and per_chain_rel(got["g"], ref.g) < BAR
     finally:
         ctx.close()
 

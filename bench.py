@@ -419,6 +419,19 @@ def da_leg(ctx, w, layers, y, nv, x0, z0, precision, steps, warmup, mmala_wall):
                 failures=int(f1.sum()), step_cost_over_mmala=round(wall / mmala_wall, 3))
 
 
+def run_logged(srv, total, what, slice_s=20.0):
+    """srv.run() in slices of slice_s seconds of server clock, logging progress between them."""
+    done = 0
+    while done < total:
+        done += srv.run(until=srv.clock() + slice_s)
+        st = srv.stats()
+        log(f"bench: serving {what}: {done} of {total} requests finished ({st['pending']} waiting, "
+            f"{st['live']} admitted)")
+        if st["pending"] == 0 and st["live"] == 0:
+            break
+    return done
+
+
 def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=20, seed=11):
     """Poisson stream of inverse problems on the served workload (129x129 grid, r = 200,
     ResNet 400x4 with 100 outputs): per request d_y in {25, 50, 100}, chains in [8, 128],
@@ -455,7 +468,7 @@ def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=2
     for q, (y, nv) in zip(burst, data(burst)):
         srv.submit(seed=q.chain_seed, request_id=100000 + q.rid, y=y, noise_var=nv, n_chains=q.chains, n_steps=300)
     t0 = srv.clock()
-    srv.run()
+    run_logged(srv, len(burst), "capacity burst")
     t1 = srv.clock()
     srv.poll(len(burst), with_means=False)
     kappa = sum(q.chains * 300 for q in burst) / (t1 - t0)
@@ -468,7 +481,7 @@ def serving_leg(ctx, w, n_requests, load, slots=1024, max_requests=48, quantum=2
     for q, (y, nv) in zip(reqs, ys):
         srv.submit(seed=q.chain_seed, request_id=q.rid + 1, y=y, noise_var=nv, n_chains=q.chains, n_steps=q.steps,
                    arrival=start + q.arrival)
-    srv.run()
+    run_logged(srv, n_requests, "stream")
     res = srv.poll(n_requests, with_means=True)
     srv.close()
     lat = np.array([r["finished"] - r["arrival"] for r in res])

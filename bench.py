@@ -527,6 +527,10 @@ PROFILE_RUNS = {
     "mid": dict(desc="BF16 path, 512 chains",
                 trace=f"python3 bench.py --steps 100 {_PROFILE_ZERO} --large-steps 0",
                 counters=f"python3 bench.py --steps 20 --warmup 5 {_PROFILE_ZERO} --large-steps 0"),
+    "mid_f64": dict(desc="plain FP64 path, 512 chains",
+                    trace=f"python3 bench.py --precision f64 --steps 100 {_PROFILE_ZERO} --large-steps 0",
+                    counters=f"python3 bench.py --precision f64 --steps 20 --warmup 5 {_PROFILE_ZERO} "
+                             "--large-steps 0"),
     "large": dict(desc="FP8 path at 257x257, r = 400, ResNet 800x6, d_y = 400, 4096 chains",
                   trace=f"python3 bench.py --steps 2 --warmup 1 {_PROFILE_ZERO} --large-steps 10 --large-fp64-steps 0",
                   counters=f"python3 bench.py --steps 2 --warmup 1 {_PROFILE_ZERO} --large-steps 3 "

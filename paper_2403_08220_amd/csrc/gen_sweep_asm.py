@@ -84,6 +84,8 @@ def layer():
                 line("s_cselect_b32 %[sc], %[sb], %[sc]"),
                 line(f"v_add_u32 {addr(j + 1)}, %[sc], %[vl]")]
 
+    # M0 is reserved (the compiler does not honour it as a clobber): saved here, restored at the end
+    out.append(line("s_mov_b32 %[ms], m0"))
     out.append(line("s_waitcnt lgkmcnt(0)"))
     out.append(line("s_and_b32 %[nn], %[n], 0xff"))
     # gelu' rows of the next layer (two chain rows, 4 KB) into the wave's LDS region, if df
@@ -124,6 +126,7 @@ def layer():
     out.append(line("s_waitcnt lgkmcnt(0)"))
     # the gelu' row copies are complete (at most the last item's seven tile copies are younger)
     out.append(line("s_waitcnt vmcnt(7)"))
+    out.append(line("s_mov_b32 m0, %[ms]"))
     out.append(line("s_nop 7"))
     out.append(line("s_nop 7"))
     out.append('        "s_nop 4"')
@@ -142,14 +145,14 @@ __device__ __forceinline__ void sweep_layer13(f32x16 (&lam)[13], const bf16x8 (&
         uint32_t sw, uint32_t vl, bf16x8 z, uint32_t df, uint64_t dsb, uint32_t dm,
         const uint32_t (&doff)[4]) {{
     bf16x8 {", ".join(f"t{i}" for i in range(RING))};
-    uint32_t va, vb, st, nn;
+    uint32_t va, vb, st, nn, ms;
     asm volatile(
 {body}
-        : {lam}, {ring}, [va] "=&v"(va), [vb] "=&v"(vb), [st] "=&s"(st), [nn] "=&s"(nn), [sc] "+s"(sc), [so] "+s"(so)
+        : {lam}, {ring}, [va] "=&v"(va), [vb] "=&v"(vb), [st] "=&s"(st), [nn] "=&s"(nn), [ms] "=&s"(ms), [sc] "+s"(sc), [so] "+s"(so)
         : {bins}, {dins}, [vl] "v"(vl), [z] "a"(z), [n] "s"(n), [tl] "s"(tl), [sl] "s"(sl),
           [sh] "s"(sh), [sb] "s"(sb), [se] "s"(se), [sz] "s"(sz), [sw] "s"(sw), [df] "s"(df), [dsb] "s"(dsb),
           [dm] "s"(dm)
-        : "s60", "s61", "m0", "scc", "memory");
+        : "s60", "s61", "scc", "memory");
     // the ring registers are consumed here (every read above has completed)
     asm volatile("" ::{", ".join(f'"a"(t{i})' for i in range(RING))}, "v"(va), "v"(vb));
 }}

@@ -68,10 +68,15 @@ constexpr int sweep_nbuf(int nmb) { return sweep_nt(nmb) * 4 <= 150 ? 4 : 2; }
 // its own address to lds_base + 16 * lane. Issued from asm so that the compiler's
 // LDS-read scheduling is not serialised behind the copy; completion is tracked by
 // the explicit vmcnt waits of the kernel (the copy has no VGPR result). The copy reads
-// M0 one wait state after the SALU write.
+// M0 one wait state after the SALU write. M0 is a reserved register that the compiler
+// does not treat as clobbered by asm, so its value is saved and restored around the copy.
 __device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
-    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(gsrc), "s"(lds_base)
-                 : "m0", "memory");
+    uint32_t m0_saved;
+    asm volatile("s_mov_b32 %0, m0\n\ts_mov_b32 m0, %2\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off\n\t"
+                 "s_mov_b32 m0, %0"
+                 : "=&s"(m0_saved)
+                 : "v"(gsrc), "s"(lds_base)
+                 : "memory");
 }
 
 #include "sweep_asm.inc"

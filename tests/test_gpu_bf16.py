@@ -33,6 +33,7 @@ def to_dev(a):
 
 
 CASES = {
+    "configured": dict(name="tiny", chains=64),
     "tiny-mlp": dict(name="tiny", chains=70, bias_scale=0.3, noise_scale=0.2),
     "resnet-ragged": dict(name="tiny", chains=37, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
                           bias_scale=0.3, noise_scale=0.2),

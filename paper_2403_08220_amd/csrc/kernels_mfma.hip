@@ -22,6 +22,7 @@ namespace dino {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(16))) _Float16 f16x16;
 
 constexpr int JAC_WAVES = 4;          // waves per block of the sweep kernel
@@ -77,6 +78,25 @@ __device__ __forceinline__ void dma_tile(const void* gsrc, uint32_t lds_base) {
                  : "=&s"(m0_saved)
                  : "v"(gsrc), "s"(lds_base)
                  : "memory");
+}
+
+// Four LDS-DMA copies of 1 KB (lane u*64 + l moves 16 B from base + doff[u]) into the LDS
+// region at dm: the gelu' rows of a wave's chains (completion tracked by the kernel's vmcnt
+// waits). M0 is saved and restored as in dma_tile.
+__device__ __forceinline__ void dma_rows(const float* base, const uint32_t (&doff)[4], uint32_t dm) {
+    const uint64_t b = (uint64_t)(uintptr_t)base;
+    const uint64_t bu = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(b >> 32)) << 32) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)b);
+    uint32_t m0_saved;
+    asm volatile("s_mov_b32 %0, m0\n\t"
+                 "s_mov_b32 m0, %5\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %6\n\t"
+                 "s_add_u32 m0, %5, 1024\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %2, %6\n\t"
+                 "s_add_u32 m0, %5, 2048\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %3, %6\n\t"
+                 "s_add_u32 m0, %5, 3072\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %4, %6\n\t"
+                 "s_mov_b32 m0, %0"
+                 : "=&s"(m0_saved)
+                 : "v"(doff[0]), "v"(doff[1]), "v"(doff[2]), "v"(doff[3]), "s"(dm), "s"(bu)
+                 : "scc", "memory");
 }
 
 #include "sweep_asm.inc"
@@ -246,6 +266,29 @@ void jac_sweep13_kernel(SweepArgs args) {
 
     const uint32_t lds_base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) bf16x8*)tiles_lds;
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+
+    // gelu' rows: when the wave's 32 columns span at most two chains, the wave's two rows
+    // (416 FP32 each) of a layer are copied into the wave's 4 KB LDS region, chunk k of
+    // 16 B (row k / 104) from lane k % 64 of copy k / 64: the first layer's here, every
+    // later layer's by the layer block before it; otherwise every layer reads its rows
+    // from global memory
+    const int col0 = (blockIdx.x * JAC_WAVES + wave_u) * 32;
+    const int c_first = col0 / args.dy;
+    const int c_last = min(col0 + 31, args.n_cols - 1) / args.dy;
+    const bool staged = col0 < args.n_cols && c_last - c_first <= 1;
+    uint32_t doff[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int kk = min(u * 64 + lane, 207);
+        const int row = kk / 104;
+        doff[u] = (uint32_t)(min(c_first + row, c_last) * args.ldd * 4 + (kk - row * 104) * 16);
+    }
+    const uint32_t dm = __builtin_amdgcn_readfirstlane(lds_base + NBUF * ITEM + (uint32_t)wave_u * 4096u);
+    // the lane's row in the region as an LDS byte address, plus the lane's 16-byte offset
+    const uint32_t vd = dm + (uint32_t)((valid ? c - c_first : 0) * 1664 + 16 * h);
+    // (copied before the tiles: the prologue's wait for item 0 also completes them)
+    if (staged && args.n_layers > 0 && args.layer[0].d) dma_rows(args.layer[0].d, doff, dm);
+
     for (int k = 0; k < NBUF - 1 && k < args.n_items; ++k) {
         const bf16x8* src = args.tiles + (long)k * NT * 64;
 #pragma unroll
@@ -266,42 +309,16 @@ void jac_sweep13_kernel(SweepArgs args) {
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj) zero[jj] = (__bf16)0.f;
 
-    // gelu' rows: when the wave's 32 columns span at most two chains, each layer block
-    // copies the next layer's two rows (416 FP32 each) into the wave's 4 KB LDS region,
-    // chunk k of 16 B (row k / 104) from lane k % 64 of copy k / 64; otherwise every
-    // layer reads its rows from global memory
-    const int col0 = (blockIdx.x * JAC_WAVES + wave_u) * 32;
-    const int c_first = col0 / args.dy;
-    const int c_last = min(col0 + 31, args.n_cols - 1) / args.dy;
-    const bool staged = col0 < args.n_cols && c_last - c_first <= 1;
-    uint32_t doff[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int kk = min(u * 64 + lane, 207);
-        const int row = kk / 104;
-        doff[u] = (uint32_t)(min(c_first + row, c_last) * args.ldd * 4 + (kk - row * 104) * 16);
-    }
-    const uint32_t dm = __builtin_amdgcn_readfirstlane(lds_base + NBUF * ITEM + (uint32_t)wave_u * 4096u);
-    const float* drow_lds = reinterpret_cast<const float*>(reinterpret_cast<const char*>(tiles_lds) + NBUF * ITEM +
-                                                           wave_u * 4096) + (valid ? c - c_first : 0) * 416;
-
     int item = 0;
+    bool formed = false;  // the previous layer block formed this layer's operands
+    bf16x8 bop[NKC];
     for (int li = 0; li < args.n_layers; ++li) {
         const SweepLayer L = args.layer[li];
-        bf16x8 bop[NKC];
-        const float* dsrc = (li > 0 && staged && L.d) ? drow_lds : (L.d ? L.d + (long)c * args.ldd : args.ones);
-        const float4* drow = reinterpret_cast<const float4*>(dsrc + 4 * h);
-#pragma unroll
-        for (int mb = 0; mb < NMB; ++mb)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const float4 d0 = drow[8 * mb + 4 * q];
-                const float4 d1 = drow[8 * mb + 4 * q + 2];
-                const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) bop[2 * mb + q][jj] = (__bf16)(lam[mb][8 * q + jj] * dv[jj]);
-                __builtin_amdgcn_sched_barrier(0);  // keep only one block's gelu' values live
-            }
+        // B operands bf16(d * Lambda) of this layer, unless the block before formed them
+        if (!formed) {
+            if (staged && L.d) sweep_form13_lds(lam, bop, vd);
+            else sweep_form13_global(lam, bop, (L.d ? L.d + (long)c * args.ldd : args.ones) + 4 * h);
+        }
         const uint32_t sc = __builtin_amdgcn_readfirstlane(lds_base + (uint32_t)(item & (NBUF - 1)) * ITEM);
         // every scalar operand of the block is wave-uniform; readfirstlane places it in an SGPR
         const uint32_t n_u =
@@ -312,13 +329,18 @@ void jac_sweep13_kernel(SweepArgs args) {
         const uint32_t sz_u = __builtin_amdgcn_readfirstlane(sb + (NBUF - 1) * ITEM);
         const float* dnext = li + 1 < args.n_layers ? args.layer[li + 1].d : nullptr;
         const uint32_t df_u = __builtin_amdgcn_readfirstlane((staged && dnext) ? 1u : 0u);
+        // the block forms the next layer's operands itself when its gelu' rows are staged and
+        // every output block runs
+        const bool fuse = staged && dnext && L.nmb_out == NMB;
+        const uint32_t ff_u = __builtin_amdgcn_readfirstlane(fuse ? 1u : 0u);
         const uint64_t dsb = (uint64_t)(uintptr_t)(dnext ? dnext : args.ones);
         // (readfirstlane returns int: each half goes through uint32_t so that the low half is
         // not sign-extended into the high one)
         const uint64_t dsb_u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(dsb >> 32)) << 32) |
                                (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)dsb);
         sweep_layer13(lam, bop, n_u, tl_u, sc, so_u, lo, hi, sb, se_u, sz_u, sw, (uint32_t)lane * 16u, zero,
-                      df_u, dsb_u, dm, doff);
+                      df_u, dsb_u, dm, doff, ff_u, vd);
+        formed = fuse;
         item += L.nmb_out;
     }
     // B[col][m] = winv_i Lambda_0^T[m][col] (rows of ldb = 32 * nmb_last BF16). The wave's 32

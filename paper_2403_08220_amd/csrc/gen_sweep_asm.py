@@ -8,7 +8,8 @@ sets (1 KB weight tiles read from LDS, one ds_read_b128 per lane) is in AGPRs.
 
 Per work item j (output row block) of the layer, when j < n:
   * if the item three ahead exists (j < T): copy its tiles into the ring buffer freed by
-    item j - 1 (seven global_load_lds_dwordx4 per wave, M0 = LDS destination);
+    item j - 1 (seven global_load_lds_dwordx4 per wave, M0 = LDS destination, one after
+    every third MFMA of the item);
   * (block start, if df != 0) copy the next layer's gelu' rows of the wave's chains into
     the wave's LDS region (four copies, complete when the block ends);
   * 26 MFMAs v_mfma_f32_32x32x16_bf16 into accumulator j (the first one starts from 0
@@ -42,6 +43,7 @@ NKC = 26       # K chunks (MFMAs) per item
 NITEMS = 13    # output row blocks per layer
 ITEM_BYTES = 28 * 1024   # tiles per item (28) x 1 KB
 NQ = 7         # tile copies per wave per item
+COPY_EVERY = 3  # one copy after every third MFMA of the item (all before its boundary)
 TD = 240       # gelu' values of two chunks: v[240:247], v[248:255]
 TC = 236       # converted pairs: v[236:239]
 
@@ -90,26 +92,33 @@ def layer():
         reads.issue(("r", c))
         return line(f"ds_read_b128 %[t{c % RING}], {addr(c // NKC)} offset:{(c % NKC) * 1024}")
 
-    def stage(j):
-        # copy item j + 3 into the buffer before the current one (ring of 4), if it exists
+    def stage_setup(j):
+        # copies of item j + 3 (if it exists) go to the ring buffer before the current one
+        # (ring of 4): LDS destination st and global source s[60:61] of this wave's first tile
+        return [line(f"s_cmp_lt_i32 {j}, %[tl]"),
+                line("s_cbranch_scc0 1f"),
+                line("s_sub_u32 %[st], %[sc], " + str(ITEM_BYTES)),
+                line("s_cmp_eq_u32 %[sc], %[sb]"),
+                line("s_cselect_b32 %[st], %[sz], %[st]"),
+                line("s_add_u32 %[st], %[st], %[sw]"),
+                line("s_add_u32 s60, %[sl], %[so]"),
+                line("s_addc_u32 s61, %[sh], 0"),
+                line("s_add_u32 s60, s60, %[sw]"),
+                line("s_addc_u32 s61, s61, 0"),
+                line("s_add_u32 %[so], %[so], " + str(ITEM_BYTES)),
+                label("1")]
+
+    def stage_copy(j, q):
+        # tile copy q of this wave for item j + 3; the seven copies are spread over the
+        # item's first MFMAs (copies issued back to back slow the LDS reads beside them)
         s = [line(f"s_cmp_lt_i32 {j}, %[tl]"),
-             line("s_cbranch_scc0 1f"),
-             line("s_sub_u32 %[st], %[sc], " + str(ITEM_BYTES)),
-             line("s_cmp_eq_u32 %[sc], %[sb]"),
-             line("s_cselect_b32 %[st], %[sz], %[st]"),
-             line("s_add_u32 %[st], %[st], %[sw]"),
-             line("s_add_u32 s60, %[sl], %[so]"),
-             line("s_addc_u32 s61, %[sh], 0"),
-             line("s_add_u32 s60, s60, %[sw]"),
-             line("s_addc_u32 s61, s61, 0")]
-        for q in range(NQ):
-            if q > 0:
-                s.append(line("s_add_u32 s60, s60, 4096"))
-                s.append(line("s_addc_u32 s61, s61, 0"))
-            s.append(line("s_mov_b32 m0, %[st]") if q == 0 else line(f"s_add_u32 m0, %[st], {q * 4096}"))
-            s.append(line("s_nop 0"))  # one wait state between an SALU write of M0 and an LDS DMA
-            s.append(line("global_load_lds_dwordx4 %[vl], s[60:61]"))
-        s.append(line("s_add_u32 %[so], %[so], " + str(ITEM_BYTES)))
+             line("s_cbranch_scc0 1f")]
+        if q > 0:
+            s.append(line("s_add_u32 s60, s60, 4096"))
+            s.append(line("s_addc_u32 s61, s61, 0"))
+        s.append(line("s_mov_b32 m0, %[st]") if q == 0 else line(f"s_add_u32 m0, %[st], {q * 4096}"))
+        s.append(line("s_nop 0"))  # one wait state between an SALU write of M0 and an LDS DMA
+        s.append(line("global_load_lds_dwordx4 %[vl], s[60:61]"))
         s.append(label("1"))
         return s
 
@@ -156,7 +165,7 @@ def layer():
         return s
 
     def item(j, reads, fused):
-        s = []
+        s = stage_setup(j)
         for kc in range(NKC):
             c = j * NKC + kc
             mf = lambda src: line(f"v_mfma_f32_32x32x16_bf16 %[l{j}], %[t{c % RING}], %[b{kc}], {src}")
@@ -166,6 +175,8 @@ def layer():
                       label("2"), mf(f"%[l{j}]"), label("3")]
             else:
                 s.append(mf(f"%[l{j}]"))
+            if kc % COPY_EVERY == 0 and kc // COPY_EVERY < NQ:
+                s += stage_copy(j, kc // COPY_EVERY)
             if kc == NKC - D:
                 s += boundary(j, reads)
             if c + D < total:
@@ -204,7 +215,6 @@ def layer():
     for j in range(NITEMS):
         out.append(line(f"s_cmp_le_u32 %[nn], {j}"))
         out.append(line(f"s_cbranch_scc1 {100 + j}f"))
-        out += stage(j)
         if j == last:
             fused_reads = reads.copy()
             out += [line("s_cmp_eq_u32 %[ff], 0"), line("s_cbranch_scc0 300f")]

@@ -49,15 +49,20 @@ STAGE_KERNEL = {
 # observation-space form (d_y < r): Gram matrix, d_y x d_y factor and Woodbury kernels
 STAGE_KERNEL_DUAL = dict(STAGE_KERNEL, proposal="propose_dual_kernel", accept="accept_dual_kernel",
                          gn_hessian="gram_bf16_kernel")
+# the dual form on the mixed path at d_y <= 104: Gram matrix and factor in one kernel (the
+# metric stage; the factor stage has no kernel of its own)
+FUSED_METRIC_KERNEL = "gram_chol_bf16_kernel"
 # the width-416 sweep (layers of 401..416 units) has its own kernel
 SWEEP416_KERNEL = "jac_sweep13_kernel"
-KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"], "cholesky_wave_kernel": ["kernels_chain.hip"],
+KERNEL_SOURCES = {"cholesky_reg_kernel": ["kernels_chain.hip"],
+                  "cholesky_wave_kernel": ["kernels_chain.hip", "chol_wave.hpp"],
                   "propose_kernel": ["kernels_chain.hip"],
                   "accept_kernel": ["kernels_chain.hip"], "complement_kernel": ["kernels_chain.hip"],
                   "propose_dual_kernel": ["kernels_chain.hip"],
                   "accept_dual_kernel": ["kernels_chain.hip"], "jac_sweep_bf16_kernel": ["kernels_mfma.hip"],
                   "jac_sweep13_kernel": ["kernels_mfma.hip", "sweep_asm.inc"],
                   "hess_bf16_kernel": ["kernels_mfma.hip"], "gram_bf16_kernel": ["kernels_mfma.hip"],
+                  "gram_chol_bf16_kernel": ["kernels_mfma.hip", "chol_wave.hpp"],
                   "fwd_mfma_kernel": ["kernels_geometry.hip"],
                   "fwd_layer_kernel": ["kernels_geometry.hip"],
                   "jac_sweep_fp8_kernel": ["kernels_fp8.hip"], "hess_bf16_tiled_kernel": ["kernels_mfma.hip"],
@@ -82,8 +87,10 @@ def source_sha256(kernel):
     return h.hexdigest()
 
 
-def stage_kernel(stage, dual, width, r, dy):
+def stage_kernel(stage, dual, width, r, dy, fused=False):
     k = (STAGE_KERNEL_DUAL if dual else STAGE_KERNEL)[stage]
+    if fused and stage == "gn_hessian":
+        return FUSED_METRIC_KERNEL
     # the sweep instance covers the widest layer (the widths and r) in blocks of 32:
     # 8..13 blocks run the width-416 kernel
     if stage == "jacobian" and 224 < max(width, r) <= 416:
@@ -98,11 +105,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=False):
+def stage_work(stage, w, C, r, dy, L_res, accepted_frac, d_perp, prec, dual=False, fused=False):
     """Algorithmic work of one step of a stage over C chains.
     Returns (amount, unit, bound, peak); the per-chain figures are in the design notes.
-    dual: the observation-space form (Gram matrix I + B B^T, d_y x d_y factor)."""
+    dual: the observation-space form (Gram matrix I + B B^T, d_y x d_y factor); fused: the
+    Gram matrix and its factor in one kernel (the metric stage), bound by the FP64 factor."""
     mixed = prec in ("bf16", "fp8")
+    if dual and fused and stage == "gn_hessian":
+        flops = C * (2.0 * (dy * (dy + 1) / 2.0 * r + dy * r) + dy ** 3 / 3.0)
+        return flops, "TFLOP/s", "alu", PEAKS["fp64_TFLOPs"]
     if dual and stage == "gn_hessian":
         flops = C * 2.0 * (dy * (dy + 1) / 2.0 * r + dy * r)  # lower half of B B^T, and B^T e
         if mixed:
@@ -607,14 +618,20 @@ def summarize_profiles(trace_dir, fetch_dir, write_dir, command, workload_tag="m
             fh.write("\n")
 
 
+def fused_metric(prof, prec, dual):
+    """The profile's factor stage has no kernel of its own: the metric kernel factorises."""
+    return bool(dual and prec in ("bf16", "fp8") and prof.get("cholesky", {}).get("launches", 1) == 0)
+
+
 def stage_table(prof, w, C, L_res, accept_rate, prec, dual):
     """Per-stage time, algorithmic work rate and roofline fraction from a stage profile."""
     stages = {}
+    fused = fused_metric(prof, prec, dual)
     for name, v in prof.items():
         if v["launches"] == 0:  # a stage with no kernel of its own on this path
             continue
         amt, unit, bound, peak = stage_work(name, w.width, C, w.r, w.d_y, L_res, accept_rate, w.d_m - w.r, prec,
-                                            dual=dual)
+                                            dual=dual, fused=fused)
         t = v["ms_per_step"] * 1e-3
         ach = (amt / t / (1e12 if unit == "TFLOP/s" else 1e9)) if t > 0 else 0.0
         stages[name] = dict(ms=round(v["ms_per_step"], 4), launches=v["launches"], bound=bound,
@@ -776,7 +793,8 @@ def main():
     if stages:
         dom = max(stages, key=lambda k: stages[k]["ms"])
         s = stages[dom]
-        kern = stage_kernel(dom, dual, w.width, w.r, w.d_y) if args.precision == "bf16" else dom
+        kern = (stage_kernel(dom, dual, w.width, w.r, w.d_y, fused=fused_metric(prof, args.precision, dual))
+                if args.precision == "bf16" else dom)
         roof = dict(bound=s["bound"], achieved=s["achieved"], peak=s["peak"], unit=s["unit"], frac=s["frac"],
                     traffic=traffic_record(kern, "mid") if args.precision == "bf16" else None,
                     kernel=kern, stage=dom, ms_per_launch=round(s["ms"] / max(s["launches"], 1), 4),

@@ -451,6 +451,10 @@ void launch_da_accept(dino_problem* p, int n, hipStream_t st);
 void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st);
 // Also the whitened residual and the misfit phi from the FP32 output f (the mixed path has
 // no separate misfit launch).
+bool gram_chol_bf16_fits(int r, int dy);
+void launch_gram_chol_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                           long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g,
+                           double* logdet, int32_t* ok, hipStream_t st);
 void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                       long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
 void launch_gram_f64(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,

@@ -5,6 +5,7 @@
 //  * MH decision (Alg. 1: reject iff alpha < xi_1) and state swap,
 //  * pCN move of the complement (splitting proposition of Sec. 5.3, item 1), trace rows, draws.
 #include "dino_internal.hpp"
+#include "chol_wave.hpp"
 
 namespace dino {
 
@@ -715,77 +716,6 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
         if (ok) ok[c] = any_bad ? 0 : 1;
     }
 }
-
-// Column j = 8 PH + JJ of the single-wave factorisation. The phase PH is a compile-time
-// constant, so that every register index is one; within a phase only JJ changes, and
-// it runs as a loop (the unrolled form of all columns was ~100 KB of code). LAST marks
-// JJ = 7, where column j + 1 lies in the next register block. Column j was published
-// to col by the previous step (or before the first). The step updates the column block
-// of column j + 1 first and publishes column j + 1 before the rest of the trailing
-// update, so that the LDS round trip of the next pivot overlaps that update.
-template <int MB, int PH, bool LAST>
-__device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad, int JJ) {
-    const int j = 8 * PH + JJ;
-    constexpr int PN = LAST ? PH + 1 : PH;  // column block of column j + 1
-    const int JN = (JJ + 1) & 7;            // its owners' q
-    const double piv = col[j];
-    bad |= !(piv > 0.0);
-    if (g == 0 && q == 0) pivs[j] = piv;  // logs are taken after the sweep, off the critical path
-    // 1/sqrt(piv): hardware estimate and two Newton steps (relative error ~1 ulp)
-    double isq = __builtin_amdgcn_rsq(piv);
-    isq = isq * (1.5 - 0.5 * piv * isq * isq);
-    isq = isq * (1.5 - 0.5 * piv * isq * isq);
-    const double rs = piv * isq;
-    const double inv = isq * isq;
-    // trailing update a_ik -= a_ij a_kj / a_jj: one side scaled by 1 / a_jj
-    double li[MB], lk[MB];
-#pragma unroll
-    for (int m = PH; m < MB; ++m) {
-        const int i = g + 8 * m;
-        li[m] = (i > j) ? col[i] : 0.0;
-        const int kk = q + 8 * m;
-        lk[m] = (kk > j) ? col[kk] * inv : 0.0;
-    }
-    if constexpr (PN < MB) {
-#pragma unroll
-        for (int m = PN; m < MB; ++m) v[m][PN] -= li[m] * lk[PN];
-        // col is read above before it is written here (one wave: LDS operations in order)
-        if (j + 1 < r && q == JN) {
-#pragma unroll
-            for (int m = PN; m < MB; ++m) col[g + 8 * m] = v[m][PN];
-        }
-    }
-#pragma unroll
-    for (int m = PH; m < MB; ++m)
-#pragma unroll
-        for (int cc = PH; cc <= m; ++cc)
-            if (cc != PN) v[m][cc] -= li[m] * lk[cc];
-    if (q == JJ) {
-#pragma unroll
-        for (int m = PH; m < MB; ++m) {
-            const int i = g + 8 * m;
-            if (i == j) v[m][PH] = rs;
-            else if (i > j) v[m][PH] *= isq;
-        }
-    }
-    __syncthreads();
-}
-
-template <int MB, int PH>
-struct CholWavePhases {
-    __device__ __forceinline__ static void run(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad) {
-#pragma unroll 1
-        for (int JJ = 0; JJ < 7; ++JJ) {
-            if (8 * PH + JJ >= r) return;
-            chol_wave_step<MB, PH, false>(v, col, pivs, r, g, q, bad, JJ);
-        }
-        if (8 * PH + 7 >= r) return;
-        chol_wave_step<MB, PH, true>(v, col, pivs, r, g, q, bad, 7);
-        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1>::run(v, col, pivs, r, g, q, bad);
-    }
-};
 
 // One wave per chain for k <= 8 MB (k = 104 at MB = 13): lane (g, q) = (lane / 8, lane % 8)
 // holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs

@@ -17,6 +17,7 @@
 // (the A operands, W_l^T) are packed on the host with the same permutation, so the
 // result of one layer feeds the next layer's products without leaving registers.
 #include "dino_internal.hpp"
+#include "chol_wave.hpp"
 
 namespace dino {
 
@@ -782,6 +783,165 @@ void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
     }
     hipLaunchKernelGGL(gram_bf16_kernel, dim3(n), dim3(HES_TPB), lds, st, dy, r, (r + 31) / 32 * 32, dy_pad, k_pad,
                        ldt, B, f, p->y, p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride, g);
+    DINO_HIP(hipGetLastError());
+}
+
+// Observation-space Gram matrix and its Cholesky factor in one launch, one block per
+// chain: the block stages the chain's B, forms the residual, the misfit and g = B^T e as
+// gram_bf16_kernel does, accumulates the lower 32 x 32 blocks of B B^T by MFMA in
+// registers, writes B B^T (FP32, the accumulation precision) over B's LDS, and its first
+// wave factorises K = I + B B^T in FP64 registers (the identity added in FP64; the
+// single-wave column steps), so that K never leaves LDS and the factor equals that of the
+// separate Gram and factor kernels bit for bit. Writes the factor (lower triangle, row stride d_y), log det K / 2
+// and the pivot flag. d_y <= 8 MB.
+template <int MB>
+__global__ __launch_bounds__(HES_TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ldt,
+                           const __hip_bfloat16* __restrict__ B, const float* __restrict__ f, const double* y_rows,
+                           const double* winv_rows, const int32_t* rows, double* __restrict__ phi, double* A,
+                           long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* __restrict__ g,
+                           double* __restrict__ logdet, int32_t* __restrict__ ok) {
+    extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt B, then e (dy floats); K (FP32) over B afterwards
+    __shared__ double red[HES_TPB / 64];
+    __shared__ double col[8 * MB];
+    __shared__ double pivs[8 * MB];
+    const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
+    float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
+    const int k8 = k_pad / 8;
+    for (int e2 = tid; e2 < dy_pad * k8; e2 += HES_TPB) {
+        const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (i < dy) {
+            if (j8 + 8 <= r) {
+                v = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
+            } else {
+                __hip_bfloat16 t[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) t[q] = (j8 + q < r) ? Bc[(long)i * ldb + j8 + q] : __float2bfloat16(0.f);
+                v = *reinterpret_cast<const uint4*>(t);
+            }
+        }
+        *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v;
+    }
+    residual_into(c, dy, f, y_rows, winv_rows, rows, es, red, phi);  // ends with a barrier
+    for (int j = tid; j < r; j += HES_TPB) {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int i = 0; i < dy; ++i) acc += (double)__bfloat162float(bs[(long)i * ldt + j]) * (double)es[i];
+        g[(long)c * r + j] = acc;
+    }
+    // lower blocks of B B^T: wave w takes blocks w, w + 4, w + 8 (at most 3 of the 10 at 4 row blocks)
+    const int nl = lane & 31, h = lane >> 5;
+    const int nmb = dy_pad / 32, nkc = k_pad / 16;
+    const int nblocks = nmb * (nmb + 1) / 2;
+    constexpr int MAXB = 3;
+    f32x16 acc[MAXB];
+    int bi_of[MAXB], bk_of[MAXB];
+#pragma unroll
+    for (int u = 0; u < MAXB; ++u) {
+        const int bidx = wave + 4 * u;
+        bi_of[u] = -1;
+        bk_of[u] = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[u][j] = 0.f;
+        if (bidx < nblocks) {
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= bidx) ++bi;
+            const int bk = bidx - bi * (bi + 1) / 2;
+            bi_of[u] = bi;
+            bk_of[u] = bk;
+            for (int kc = 0; kc < nkc; ++kc) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(bs + (long)(32 * bi + nl) * ldt + 16 * kc + 8 * h);
+                const bf16x8 b = *reinterpret_cast<const bf16x8*>(bs + (long)(32 * bk + nl) * ldt + 16 * kc + 8 * h);
+                acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[u], 0, 0, 0);
+            }
+        }
+    }
+    __syncthreads();  // every wave has read B
+    float* K = reinterpret_cast<float*>(bs);  // dy x (dy + 1), lower triangle
+    const int ldk = dy + 1;
+#pragma unroll
+    for (int u = 0; u < MAXB; ++u) {
+        if (bi_of[u] < 0) continue;
+        const int colk = 32 * bk_of[u] + nl;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int row = 32 * bi_of[u] + 8 * (j >> 2) + 4 * h + (j & 3);
+            if (row < dy && colk <= row) K[row * ldk + colk] = acc[u][j];
+        }
+    }
+    __syncthreads();
+    if (wave != 0) return;  // the factorisation runs on the first wave alone (wavefront-scope steps)
+    const int gg = lane >> 3, q = lane & 7;
+    double v[MB][MB];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int i = gg + 8 * m;
+#pragma unroll
+        for (int cc = 0; cc < MB; ++cc) {
+            const int kk = q + 8 * cc;
+            // the identity is added in FP64, as the separate Gram kernel writes it
+            v[m][cc] = (cc <= m && i < dy && kk <= i) ? (double)K[i * ldk + kk] + (i == kk ? 1.0 : 0.0) : 0.0;
+        }
+    }
+    bool bad = false;
+    if (q == 0) {  // column 0
+#pragma unroll
+        for (int m = 0; m < MB; ++m) col[gg + 8 * m] = v[m][0];
+    }
+    chol_sync<true>();
+    CholWavePhases<MB, 0, true>::run(v, col, pivs, dy, gg, q, bad);
+    double* a = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+        const int i = gg + 8 * m;
+#pragma unroll
+        for (int cc = 0; cc <= m; ++cc) {
+            const int kk = q + 8 * cc;
+            if (i < dy && kk <= i) a[(long)i * dy + kk] = v[m][cc];
+        }
+    }
+    chol_sync<true>();
+    double ls = 0.0;
+    for (int j = lane; j < dy; j += 64) ls += log(pivs[j]);
+    for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o);
+    const bool any_bad = __any(bad);
+    if (lane == 0) {
+        if (logdet) logdet[c] = 0.5 * ls;
+        if (ok) ok[c] = any_bad ? 0 : 1;
+    }
+}
+
+// Fused Gram + factor of the dual form on the mixed path: d_y <= 104 and the staged B
+// within LDS (two blocks per CU when it takes at most ~78 KB).
+static size_t gram_chol_lds(int r, int dy) {
+    const size_t dy_pad = (dy + 31) / 32 * 32, k_pad = (r + 15) / 16 * 16, ldt = k_pad + 8;
+    const size_t b = dy_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
+    const size_t k = (size_t)dy * (dy + 1) * sizeof(float);
+    return std::max(b, k);
+}
+
+bool gram_chol_bf16_fits(int r, int dy) { return dy <= 104 && gram_chol_lds(r, dy) <= 160 * 1024 - 4096; }
+
+void launch_gram_chol_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
+                           long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g,
+                           double* logdet, int32_t* ok, hipStream_t st) {
+    const int r = p->r, dy = p->d_y;
+    DINO_REQUIRE(gram_chol_bf16_fits(r, dy), DINO_EINVAL, "d_y x r beyond the fused Gram + factor kernel");
+    const int dy_pad = (dy + 31) / 32 * 32;
+    const int k_pad = (r + 15) / 16 * 16;
+    const int ldt = k_pad + 8;
+    const size_t lds = gram_chol_lds(r, dy);
+    static bool attr = false;
+    if (!attr) {
+        DINO_HIP(hipFuncSetAttribute((const void*)gram_chol_bf16_kernel<13>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     160 * 1024 - 4096));
+        attr = true;
+    }
+    hipLaunchKernelGGL(gram_chol_bf16_kernel<13>, dim3(n), dim3(HES_TPB), lds, st, dy, r, (r + 31) / 32 * 32, dy_pad,
+                       k_pad, ldt, B, f, p->y, p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride, g,
+                       logdet, ok);
     DINO_HIP(hipGetLastError());
 }
 

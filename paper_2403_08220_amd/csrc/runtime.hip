@@ -367,14 +367,31 @@ static void stage_hessian(dino_problem* p, int n, double* phi, double* g, double
     }
 }
 
+// The dual form on the mixed path forms I + B B^T and factorises it in one kernel (the
+// matrix stays in LDS) when the shape fits that kernel.
+static bool fused_metric_factor(const dino_problem* p) {
+    return p->dual && p->desc.precision != DINO_PREC_F64 && gram_chol_bf16_fits(p->r, p->d_y);
+}
+
+// I + H (or I + B B^T) into A and its factor in place, with log det and the pivot flag.
+static void stage_metric_factor(dino_problem* p, int n, double* phi, double* g, double* A, long strideA,
+                                const int32_t* slot, int slot_xor, long slot_stride, double* logdet, int32_t* ok,
+                                hipStream_t st) {
+    if (fused_metric_factor(p)) {
+        launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, A, strideA, slot, slot_xor, slot_stride, g, logdet, ok, st);
+    } else {
+        stage_hessian(p, n, phi, g, A, strideA, slot, slot_xor, slot_stride, st);
+        launch_cholesky_slot(n, p->kdim, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
+    }
+}
+
 static void geometry_at(dino_problem* p, int n, const double* x, double* f, double* phi, double* g, double* A,
                         long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* logdet,
                         int32_t* ok, hipStream_t st) {
     stage_forward(p, n, x, f, st);
     stage_jacobian(p, n, st);
     stage_misfit(p, n, f, phi, g, st);  // the FP64 ppg reads the Jacobian
-    stage_hessian(p, n, phi, g, A, strideA, slot, slot_xor, slot_stride, st);
-    launch_cholesky_slot(n, p->kdim, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
+    stage_metric_factor(p, n, phi, g, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
 }
 
 }  // namespace dino
@@ -872,7 +889,8 @@ static void run_steps_eager(dino_problem* p, int n, int n_steps, hipStream_t st)
     const bool lapcn = p->desc.method == DINO_METHOD_LAPCN;
     // second stage of delayed acceptance: gather, the true model's layers, decision
     const int LT = p->da ? (int)p->ctx->true_layers.size() + 2 : 0;
-    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, 1, 1, LT, p->z ? 1 : 0, 0};
+    const bool fused = fused_metric_factor(p);
+    const int32_t launches[DINO_N_STAGES] = {1, L, f64 ? L : 1, f64 ? 1 : 0, 1, fused ? 0 : 1, 1, LT, p->z ? 1 : 0, 0};
     const bool mala = p->desc.method == DINO_METHOD_MALA || p->desc.method == DINO_METHOD_DIS_MMALA;
     const int32_t launches_pcn[DINO_N_STAGES] = {1, L, 0, 0, 0, 0, 1, 0, p->z ? 1 : 0, 0};
     // MALA: on the mixed path the misfit and ppg come from the metric kernel, told to skip the metric
@@ -940,9 +958,16 @@ static void run_steps_eager(dino_problem* p, int n, int n_steps, hipStream_t st)
         mark(3);
         stage_misfit(p, n, p->f, p->phip, p->gp, st);
         mark(4);
-        stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
-        mark(5);
-        launch_cholesky_slot(n, p->kdim, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
+        if (fused) {
+            // one kernel for both stages (profiled as the metric stage)
+            launch_gram_chol_bf16(p, n, p->B16, p->f32, p->phip, p->Lbuf, rr, p->cur, 1, half, p->gp, p->logdetp,
+                                  p->okp, st);
+            mark(5);
+        } else {
+            stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
+            mark(5);
+            launch_cholesky_slot(n, p->kdim, p->Lbuf, rr, p->cur, 1, half, p->logdetp, p->okp, st);
+        }
         mark(6);
         // the accept kernel also ends the step (trace row, running sums, step counter),
         // unless a second stage follows (delayed acceptance), which then ends it
@@ -1388,13 +1413,19 @@ dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* 
         stage_forward(p, n, x, f, st);
         stage_jacobian(p, n, st);
         stage_misfit(p, n, f, phi, g, st);
-        stage_hessian(p, n, phi, g, L, rr, nullptr, 0, 0, st);
-        if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
-        if (H) {
-            if (p->dual) launch_btb(p, n, H, st);
-            else launch_sym_from_lower(n, p->r, L, H, st);
+        if (fused_metric_factor(p)) {
+            launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, L, rr, nullptr, 0, 0, g, logdet, ok, st);
+            if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
+            if (H) launch_btb(p, n, H, st);
+        } else {
+            stage_hessian(p, n, phi, g, L, rr, nullptr, 0, 0, st);
+            if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
+            if (H) {
+                if (p->dual) launch_btb(p, n, H, st);
+                else launch_sym_from_lower(n, p->r, L, H, st);
+            }
+            launch_cholesky_slot(n, p->kdim, L, rr, nullptr, 0, 0, logdet, ok, st);
         }
-        launch_cholesky_slot(n, p->kdim, L, rr, nullptr, 0, 0, logdet, ok, st);
         p->last_stream = st;
     });
 }

@@ -34,7 +34,15 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
     const int j = 8 * PH + JJ;
     constexpr int PN = LAST ? PH + 1 : PH;  // column block of column j + 1
     const int JN = (JJ + 1) & 7;            // its owners' q
+    // every read of the column is issued before the pivot's arithmetic (all indices are
+    // within col), so that their LDS round trips overlap the reciprocal square root
     const double piv = col[j];
+    double ci[MB], ck[MB];
+#pragma unroll
+    for (int m = PH; m < MB; ++m) {
+        ci[m] = col[g + 8 * m];
+        ck[m] = col[q + 8 * m];
+    }
     bad |= !(piv > 0.0);
     if (g == 0 && q == 0) pivs[j] = piv;  // logs are taken after the sweep, off the critical path
     // 1/sqrt(piv): hardware estimate and two Newton steps (relative error ~1 ulp)
@@ -48,9 +56,9 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
 #pragma unroll
     for (int m = PH; m < MB; ++m) {
         const int i = g + 8 * m;
-        li[m] = (i > j) ? col[i] : 0.0;
+        li[m] = (i > j) ? ci[m] : 0.0;
         const int kk = q + 8 * m;
-        lk[m] = (kk > j) ? col[kk] * inv : 0.0;
+        lk[m] = (kk > j) ? ck[m] * inv : 0.0;
     }
     if constexpr (PN < MB) {
 #pragma unroll

@@ -720,10 +720,10 @@ __global__ __launch_bounds__(NT) void cholesky_reg_kernel(int r, double* A, long
 // One wave per chain for k <= 8 MB (k = 104 at MB = 13): lane (g, q) = (lane / 8, lane % 8)
 // holds rows g + 8m and columns q + 8c of the lower triangle in registers (block pairs
 // c <= m only, 91 doubles at MB = 13). Column j is published through LDS by its eight
-// owners (q = j % 8) and read back by every lane; there is no barrier between waves
-// (a single wave, in-order LDS), so a column step costs one LDS round trip (overlapped
-// with the trailing update of the step before), a square root and the rank-1 update of
-// the lane's share of the trailing block.
+// owners (q = j % 8) and read back by every lane; there is no barrier (a single wave,
+// in-order LDS: wavefront-scope fences only), so a column step costs one LDS round trip
+// (overlapped with the trailing update of the step before), a square root and the rank-1
+// update of the lane's share of the trailing block.
 template <int MB>
 __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, long strideA, const int32_t* slot,
                                                            int slot_xor, long slot_stride, double* logdet,
@@ -748,8 +748,8 @@ __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, lon
 #pragma unroll
         for (int m = 0; m < MB; ++m) col[g + 8 * m] = v[m][0];
     }
-    __syncthreads();
-    CholWavePhases<MB, 0>::run(v, col, pivs, r, g, q, bad);
+    chol_sync<true>();
+    CholWavePhases<MB, 0, true>::run(v, col, pivs, r, g, q, bad);
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int i = g + 8 * m;
@@ -759,7 +759,7 @@ __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, lon
             if (i < r && kk <= i) a[(long)i * r + kk] = v[m][cc];
         }
     }
-    __syncthreads();
+    chol_sync<true>();
     double ls = 0.0;
     for (int j = lane; j < r; j += 64) ls += log(pivs[j]);
     ls = wave_sum(ls);

@@ -26,17 +26,27 @@ __device__ __forceinline__ void chol_sync() {
 // it runs as a loop (the unrolled form of all columns was ~100 KB of code). LAST marks
 // JJ = 7, where column j + 1 lies in the next register block. Column j was published
 // to col by the previous step (or before the first). The step updates the column block
-// of column j + 1 first and publishes column j + 1 before the rest of the trailing
-// update, so that the LDS round trip of the next pivot overlaps that update.
+// of column j + 1 first, takes the next pivot from its lane (v_readlane) and publishes
+// column j + 1 before the rest of the trailing update, so that the next step's LDS reads
+// overlap that update and its pivot arithmetic waits for no LDS round trip.
+// the double of lane `lane` (wave-uniform) in every lane
+__device__ __forceinline__ double lane_value(double x, int lane) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 template <int MB, int PH, bool LAST, bool WS = false>
 __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad, int JJ) {
+                                               bool& bad, int JJ, double& pivot) {
     const int j = 8 * PH + JJ;
     constexpr int PN = LAST ? PH + 1 : PH;  // column block of column j + 1
     const int JN = (JJ + 1) & 7;            // its owners' q
-    // every read of the column is issued before the pivot's arithmetic (all indices are
-    // within col), so that their LDS round trips overlap the reciprocal square root
-    const double piv = col[j];
+    // the pivot comes in a register (read from its lane by the step before); every read of
+    // the column is issued before the pivot's arithmetic (all indices are within col), so
+    // that their LDS round trips overlap the reciprocal square root
+    const double piv = pivot;
     double ci[MB], ck[MB];
 #pragma unroll
     for (int m = PH; m < MB; ++m) {
@@ -63,6 +73,8 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
     if constexpr (PN < MB) {
 #pragma unroll
         for (int m = PN; m < MB; ++m) v[m][PN] -= li[m] * lk[PN];
+        // the next pivot a_{j+1,j+1}: element (PN, PN) of lane (g, q) = (JN, JN)
+        if (j + 1 < r) pivot = lane_value(v[PN][PN], 9 * JN);
         // col is read above before it is written here (one wave: LDS operations in order)
         if (j + 1 < r && q == JN) {
 #pragma unroll
@@ -87,16 +99,17 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
 
 template <int MB, int PH, bool WS = false>
 struct CholWavePhases {
+    // pivot: a_jj of the first column of the phase, in every lane
     __device__ __forceinline__ static void run(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad) {
+                                               bool& bad, double& pivot) {
 #pragma unroll 1
         for (int JJ = 0; JJ < 7; ++JJ) {
             if (8 * PH + JJ >= r) return;
-            chol_wave_step<MB, PH, false, WS>(v, col, pivs, r, g, q, bad, JJ);
+            chol_wave_step<MB, PH, false, WS>(v, col, pivs, r, g, q, bad, JJ, pivot);
         }
         if (8 * PH + 7 >= r) return;
-        chol_wave_step<MB, PH, true, WS>(v, col, pivs, r, g, q, bad, 7);
-        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1, WS>::run(v, col, pivs, r, g, q, bad);
+        chol_wave_step<MB, PH, true, WS>(v, col, pivs, r, g, q, bad, 7, pivot);
+        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1, WS>::run(v, col, pivs, r, g, q, bad, pivot);
     }
 };
 

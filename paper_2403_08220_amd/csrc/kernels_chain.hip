@@ -749,7 +749,8 @@ __global__ __launch_bounds__(64) void cholesky_wave_kernel(int r, double* A, lon
         for (int m = 0; m < MB; ++m) col[g + 8 * m] = v[m][0];
     }
     chol_sync<true>();
-    CholWavePhases<MB, 0, true>::run(v, col, pivs, r, g, q, bad);
+    double pivot = lane_value(v[0][0], 0);
+    CholWavePhases<MB, 0, true>::run(v, col, pivs, r, g, q, bad, pivot);
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
         const int i = g + 8 * m;

@@ -809,20 +809,33 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
     const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
     float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
     const int k8 = k_pad / 8;
-    for (int e2 = tid; e2 < dy_pad * k8; e2 += HES_TPB) {
-        const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
-        uint4 v = make_uint4(0u, 0u, 0u, 0u);
-        if (i < dy) {
-            if (j8 + 8 <= r) {
-                v = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
-            } else {
-                __hip_bfloat16 t[8];
+    const int n16 = dy_pad * k8;  // 16-byte chunks of the staged B
+    // eight chunks per thread in flight: all loads of a batch before its LDS stores
+    constexpr int SBATCH = 8;
+    for (int base = 0; base < n16; base += SBATCH * HES_TPB) {
+        uint4 v[SBATCH];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) t[q] = (j8 + q < r) ? Bc[(long)i * ldb + j8 + q] : __float2bfloat16(0.f);
-                v = *reinterpret_cast<const uint4*>(t);
+        for (int u = 0; u < SBATCH; ++u) {
+            const int e2 = base + u * HES_TPB + tid;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
+            if (e2 < n16 && i < dy) {
+                if (j8 + 8 <= r) {
+                    v[u] = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
+                } else {
+                    __hip_bfloat16 t[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) t[q] = (j8 + q < r) ? Bc[(long)i * ldb + j8 + q] : __float2bfloat16(0.f);
+                    v[u] = *reinterpret_cast<const uint4*>(t);
+                }
             }
         }
-        *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v;
+#pragma unroll
+        for (int u = 0; u < SBATCH; ++u) {
+            const int e2 = base + u * HES_TPB + tid;
+            const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
+            if (e2 < n16) *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v[u];
+        }
     }
     residual_into(c, dy, f, y_rows, winv_rows, rows, es, red, phi);  // ends with a barrier
     for (int j = tid; j < r; j += HES_TPB) {
@@ -881,8 +894,10 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
 #pragma unroll
         for (int cc = 0; cc < MB; ++cc) {
             const int kk = q + 8 * cc;
-            // the identity is added in FP64, as the separate Gram kernel writes it
-            v[m][cc] = (cc <= m && i < dy && kk <= i) ? (double)K[i * ldk + kk] + (i == kk ? 1.0 : 0.0) : 0.0;
+            // the identity is added in FP64, as the separate Gram kernel writes it; the read
+            // is unconditional (clamped index) so that the reads issue back to back
+            const float kv = K[min(i, dy - 1) * ldk + min(kk, dy - 1)];
+            v[m][cc] = (cc <= m && i < dy && kk <= i) ? (double)kv + (i == kk ? 1.0 : 0.0) : 0.0;
         }
     }
     bool bad = false;
@@ -891,7 +906,8 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
         for (int m = 0; m < MB; ++m) col[gg + 8 * m] = v[m][0];
     }
     chol_sync<true>();
-    CholWavePhases<MB, 0, true>::run(v, col, pivs, dy, gg, q, bad);
+    double pivot = lane_value(v[0][0], 0);
+    CholWavePhases<MB, 0, true>::run(v, col, pivs, dy, gg, q, bad, pivot);
     double* a = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
 #pragma unroll
     for (int m = 0; m < MB; ++m) {
@@ -899,7 +915,8 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
 #pragma unroll
         for (int cc = 0; cc <= m; ++cc) {
             const int kk = q + 8 * cc;
-            if (i < dy && kk <= i) a[(long)i * dy + kk] = v[m][cc];
+            // the lane's upper-triangle entries of a diagonal block pair are written as zeros
+            if (i < dy && kk < dy) a[(long)i * dy + kk] = (kk <= i) ? v[m][cc] : 0.0;
         }
     }
     chol_sync<true>();

@@ -276,7 +276,11 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
  *        1 the tiles of a 32-row block on one XCD;
  *   kind DINO_TUNE_HESS  (r, d_y, 0): the BF16/FP8 paths' Gauss-Newton kernel of the primal
  *        form, 0 one block per chain with B^T staged in LDS (where it fits), 1 one block per
- *        64 x 64 output tile streaming B (the only choice where B^T does not fit).
+ *        64 x 64 output tile streaming B (the only choice where B^T does not fit);
+ *   kind DINO_TUNE_FWDCHAIN (chains, layers, widest hidden layer): the mixed paths' FP32
+ *        forward, 0 one launch per layer (the default), 1 one launch for all layers (row
+ *        blocks hand layers on through device counters; taken only where all its blocks
+ *        are resident at once).
  * Every choice computes the same quantities (rounding order may differ between factor
  * kernels). n_entries (optional): table entries written. Releases the problem's launch
  * graphs (they hold the earlier choices). dino_tune_set sets or (choice < 0) erases an
@@ -285,6 +289,7 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
 #define DINO_TUNE_FWD64 1
 #define DINO_TUNE_FWD32 2
 #define DINO_TUNE_HESS 3
+#define DINO_TUNE_FWDCHAIN 4
 dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries);
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice);
 dino_status dino_tuning_table(char* buf, size_t cap, size_t* length);

@@ -311,6 +311,8 @@ struct dino_problem {
     int ldd32 = 0;            // row length of d32 (width rounded up to 32)
     float* xpf = nullptr;     // C x r reduced point in FP32
     float* h0f = nullptr;     // C x wmax FP32 activations
+    uint32_t* fsync = nullptr;  // row-block counters of the one-launch FP32 forward (zero between launches)
+    long fwd_chain_cap = 0;     // blocks of that kernel the device holds at once
     float* h1f = nullptr;
     float* f32 = nullptr;     // C x d_y FP32 network output
     float* d32 = nullptr;     // n_act x C x ldd32 gelu'(z), zero padded
@@ -371,7 +373,7 @@ namespace dino {
 
 // Tuning table (runtime.hip): the implementation chosen for a stage at a shape (a, b, c),
 // process-wide; -1 when the shape has no entry (the launcher's default then applies).
-enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3 };
+enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3, TUNE_FWDCHAIN = 4 };
 constexpr int CHOL_VARIANTS = 7;
 int tuned_choice(int kind, int a, int b, int c);
 void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms);
@@ -495,6 +497,8 @@ void pack_sweep_tiles(const std::vector<double>& W, int fan_out, int fan_in, int
                       int& nmb_out);
 // FP32 forward; the first layer reads x64 (FP64, rounded on load) if given, else xf.
 void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st);
+int fwd_chain_capacity(int device);
+bool fwd_chain_usable(const dino_problem* p, int n);
 void launch_sweep_bf16(dino_problem* p, int n, const float* d32, int ldd, __hip_bfloat16* Bout, hipStream_t st);
 // FP8 reverse sweep (kernels_fp8.hip): same output as launch_sweep_bf16, products in e4m3,
 // the left operand as one e4m3 term or two (terms = 1 or 2).

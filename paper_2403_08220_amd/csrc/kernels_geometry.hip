@@ -281,6 +281,161 @@ static inline dim3 grid2(int M, int N) { return dim3((N + 63) / 64, grid_y((M + 
 // 8 (q / 4) + 4 h + q % 4 and column j of the tile.
 typedef __attribute__((ext_vector_type(16))) float f32x16g;
 
+typedef __attribute__((ext_vector_type(4))) float f32x4g;
+
+// One 32 x 32 output tile (rows m0.., columns n0..) of an FP32 layer on the block's four
+// waves. red: the block's split-K reduction buffer. wait(): called by every thread once
+// the tile's weight loads are issued and before any input row is read (a no-op for a
+// layer launched on its own). COH: the input rows come from other blocks of the same
+// launch and are read with device-coherent loads (sc1: past any stale L1 / L2 copy);
+// coh_out: the outputs are written with device-coherent stores. poison: write NaN in
+// place of the outputs (a producer tile was not seen in time).
+template <bool COH, typename Wait>
+__device__ __forceinline__ void fwd_tile(int M, int K, int N, const float* __restrict__ in, int ldin,
+                                         const double* __restrict__ in64, const float* __restrict__ W,
+                                         const float* __restrict__ b, int kind, float* __restrict__ out, int ldout,
+                                         float* __restrict__ dprime, int ldd, int m0, int n0, float (*red)[64][17],
+                                         Wait&& wait, bool coh_out, const int& poison) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int arow = m0 + l32, wrow = n0 + l32;
+    const bool aok = arow < M, wok = wrow < N;
+    const float* ap = in64 ? nullptr : in + (long)(aok ? arow : 0) * ldin;
+    const double* ap64 = in64 ? in64 + (long)(aok ? arow : 0) * ldin : nullptr;
+    const float* wp = W + (long)(wok ? wrow : 0) * K;
+    const bool vec = ((ldin & 3) == 0) && ((K & 3) == 0);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)in, (short)0, COH ? M * ldin * 4 : 0, 0x00020000);
+    f32x16g acc;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
+    const int nchunk = (K + 7) / 8;
+    auto coh_ld = [&](int k) { return __hip_atomic_load(ap + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); };
+    auto load_a = [&](int t, float4& a4) {
+        const int k = 8 * t + 4 * h;
+        // whole chunks read rows past M as row 0 (their products only reach output rows
+        // that are never stored), so the loaded values need no select
+        if (vec && k + 3 < K) {
+            if (ap64) {
+                const double2 lo = *reinterpret_cast<const double2*>(ap64 + k);
+                const double2 hi = *reinterpret_cast<const double2*>(ap64 + k + 2);
+                a4 = make_float4((float)lo.x, (float)lo.y, (float)hi.x, (float)hi.y);
+            } else if constexpr (COH) {
+                // aux 16 = sc1: a device-scope load
+                // (the whole vector is reinterpreted: a bit cast of one element of it loses the others)
+                const f32x4g v = __builtin_bit_cast(
+                    f32x4g, __builtin_amdgcn_raw_buffer_load_b128(rs, ((aok ? arow : 0) * ldin + k) * 4, 0, 16));
+                a4 = make_float4(v[0], v[1], v[2], v[3]);
+            } else {
+                a4 = *reinterpret_cast<const float4*>(ap + k);
+            }
+        } else if (ap64) {
+            a4.x = (aok && k < K) ? (float)ap64[k] : 0.f;
+            a4.y = (aok && k + 1 < K) ? (float)ap64[k + 1] : 0.f;
+            a4.z = (aok && k + 2 < K) ? (float)ap64[k + 2] : 0.f;
+            a4.w = (aok && k + 3 < K) ? (float)ap64[k + 3] : 0.f;
+        } else if constexpr (COH) {
+            a4.x = (aok && k < K) ? coh_ld(k) : 0.f;
+            a4.y = (aok && k + 1 < K) ? coh_ld(k + 1) : 0.f;
+            a4.z = (aok && k + 2 < K) ? coh_ld(k + 2) : 0.f;
+            a4.w = (aok && k + 3 < K) ? coh_ld(k + 3) : 0.f;
+        } else {
+            a4.x = (aok && k < K) ? ap[k] : 0.f;
+            a4.y = (aok && k + 1 < K) ? ap[k + 1] : 0.f;
+            a4.z = (aok && k + 2 < K) ? ap[k + 2] : 0.f;
+            a4.w = (aok && k + 3 < K) ? ap[k + 3] : 0.f;
+        }
+    };
+    auto load_w = [&](int t, float4& w4) {
+        const int k = 8 * t + 4 * h;
+        if (vec && k + 3 < K) {
+            w4 = *reinterpret_cast<const float4*>(wp + k);  // rows past N: row 0, for unstored columns
+        } else {
+            w4.x = (wok && k < K) ? wp[k] : 0.f;
+            w4.y = (wok && k + 1 < K) ? wp[k + 1] : 0.f;
+            w4.z = (wok && k + 2 < K) ? wp[k + 2] : 0.f;
+            w4.w = (wok && k + 3 < K) ? wp[k + 3] : 0.f;
+        }
+    };
+    auto mfma4 = [&](const float4& a4, const float4& w4) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, w4.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, w4.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, w4.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, w4.w, acc, 0, 0, 0);
+    };
+    // the epilogue's operands are loaded ahead, their latency hidden behind the products:
+    // lane (j, h) of wave w finishes column n0 + j of rows m0 + 8 w + 4 h + 0..3
+    const int n = n0 + l32;
+    const bool nok = n < N;
+    const float bn = (b && nok) ? b[n] : 0.f;
+    float res[4] = {0.f, 0.f, 0.f, 0.f};
+    auto load_res = [&] {
+        if (kind != DINO_LAYER_RESID || !nok) return;
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int m = m0 + 8 * wave + 4 * h + qq;
+            if (m >= M) continue;
+            if (in64) res[qq] = (float)in64[(long)m * ldin + n];
+            else if constexpr (COH) res[qq] = __hip_atomic_load(in + (long)m * ldin + n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else res[qq] = in[(long)m * ldin + n];
+        }
+    };
+    constexpr int PRE = 16;  // chunks per wave with all loads issued before the products
+    if (nchunk <= 4 * PRE) {
+        // wave w takes a contiguous quarter of K: its lanes read whole cache lines of their rows
+        const int per = (nchunk + 3) / 4;
+        float4 a4[PRE], w4[PRE];
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int t = wave * per + u;
+            if (u < per && t < nchunk) load_w(t, w4[u]);
+        }
+        wait();
+#pragma unroll
+        for (int u = 0; u < PRE; ++u) {
+            const int t = wave * per + u;
+            if (u < per && t < nchunk) load_a(t, a4[u]);
+        }
+        load_res();
+#pragma unroll
+        for (int u = 0; u < PRE; ++u)
+            if (u < per && wave * per + u < nchunk) mfma4(a4[u], w4[u]);
+    } else {
+        wait();
+        load_res();
+        for (int t = wave; t < nchunk; t += 4) {
+            float4 a4, w4;
+            load_w(t, w4);
+            load_a(t, a4);
+            mfma4(a4, w4);
+        }
+    }
+    // split-K partial sums meet in LDS; wave w finishes registers 4w..4w+3 of the tile
+    // (rows m0 + 8w + 4h + 0..3), so the epilogue runs on all four waves
+#pragma unroll
+    for (int q = 0; q < 16; ++q) red[wave][lane][q] = acc[q];
+    __syncthreads();
+    if (!nok) return;
+    const float nan = __builtin_nanf("");
+    const bool bad = poison != 0;
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        const int q = 4 * wave + qq;
+        const int m = m0 + 8 * wave + 4 * h + qq;
+        if (m >= M) continue;
+        const float z = bad ? nan : red[0][lane][q] + red[1][lane][q] + red[2][lane][q] + red[3][lane][q] + bn;
+        float o;
+        if (kind == DINO_LAYER_LINEAR) {
+            o = z;
+        } else {
+            o = gelu_t<float>(z);
+            if (kind == DINO_LAYER_RESID) o += res[qq];
+            if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
+        }
+        if (coh_out) __hip_atomic_store(out + (long)m * ldout + n, o, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else out[(long)m * ldout + n] = o;
+    }
+}
+
 __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, const float* __restrict__ in, int ldin,
                                                        const double* __restrict__ in64,
                                                        const float* __restrict__ W, const float* __restrict__ b,
@@ -289,8 +444,6 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
                                                        int xcd_map) {
     // in64 (first layer): the FP64 states, rounded to FP32 as they are loaded
     __shared__ float red[4][64][17];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l32 = lane & 31, h = lane >> 5;
     // 1-D grid of nx * ny tiles. Blocks are dispatched round-robin over the 8 XCDs; when
     // ny is a multiple of 8, every tile of row block y goes to XCD y % 8, so that the next
     // layer's blocks of that row block read activations written through the same L2.
@@ -306,94 +459,98 @@ __global__ __launch_bounds__(256) void fwd_mfma_kernel(int M, int K, int N, cons
     }
     const int m0 = ty * 32, n0 = tx * 32;
     if (m_dev && m0 >= *m_dev) return;  // no input rows in this tile (uniform over the block)
-    const int arow = m0 + l32, wrow = n0 + l32;
-    const bool aok = arow < M, wok = wrow < N;
-    const float* ap = in64 ? nullptr : in + (long)(aok ? arow : 0) * ldin;
-    const double* ap64 = in64 ? in64 + (long)(aok ? arow : 0) * ldin : nullptr;
-    const float* wp = W + (long)(wok ? wrow : 0) * K;
-    const bool vec = ((ldin & 3) == 0) && ((K & 3) == 0);
-    f32x16g acc;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] = 0.f;
-    const int nchunk = (K + 7) / 8;
-    auto load = [&](int t, float4& a4, float4& w4) {
-        const int k = 8 * t + 4 * h;
-        if (vec && k + 3 < K) {
-            if (ap64) {
-                const double2 lo = aok ? *reinterpret_cast<const double2*>(ap64 + k) : make_double2(0.0, 0.0);
-                const double2 hi = aok ? *reinterpret_cast<const double2*>(ap64 + k + 2) : make_double2(0.0, 0.0);
-                a4 = make_float4((float)lo.x, (float)lo.y, (float)hi.x, (float)hi.y);
-            } else {
-                a4 = aok ? *reinterpret_cast<const float4*>(ap + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            w4 = wok ? *reinterpret_cast<const float4*>(wp + k) : make_float4(0.f, 0.f, 0.f, 0.f);
-        } else {
-            if (ap64) {
-                a4.x = (aok && k < K) ? (float)ap64[k] : 0.f;
-                a4.y = (aok && k + 1 < K) ? (float)ap64[k + 1] : 0.f;
-                a4.z = (aok && k + 2 < K) ? (float)ap64[k + 2] : 0.f;
-                a4.w = (aok && k + 3 < K) ? (float)ap64[k + 3] : 0.f;
-            } else {
-                a4.x = (aok && k < K) ? ap[k] : 0.f;
-                a4.y = (aok && k + 1 < K) ? ap[k + 1] : 0.f;
-                a4.z = (aok && k + 2 < K) ? ap[k + 2] : 0.f;
-                a4.w = (aok && k + 3 < K) ? ap[k + 3] : 0.f;
-            }
-            w4.x = (wok && k < K) ? wp[k] : 0.f;
-            w4.y = (wok && k + 1 < K) ? wp[k + 1] : 0.f;
-            w4.z = (wok && k + 2 < K) ? wp[k + 2] : 0.f;
-            w4.w = (wok && k + 3 < K) ? wp[k + 3] : 0.f;
-        }
-    };
-    auto mfma4 = [&](const float4& a4, const float4& w4) {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.x, w4.x, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.y, w4.y, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.z, w4.z, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a4.w, w4.w, acc, 0, 0, 0);
-    };
-    constexpr int PRE = 16;  // chunks per wave with all loads issued before the products
-    if (nchunk <= 4 * PRE) {
-        // wave w takes a contiguous quarter of K: its lanes read whole cache lines of their rows
-        const int per = (nchunk + 3) / 4;
-        float4 a4[PRE], w4[PRE];
-#pragma unroll
-        for (int u = 0; u < PRE; ++u) {
-            const int t = wave * per + u;
-            if (u < per && t < nchunk) load(t, a4[u], w4[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < PRE; ++u)
-            if (u < per && wave * per + u < nchunk) mfma4(a4[u], w4[u]);
+    const int no_poison = 0;
+    fwd_tile<false>(M, K, N, in, ldin, in64, W, b, kind, out, ldout, dprime, ldd, m0, n0, red, [] {}, false,
+                    no_poison);
+}
+
+// The whole FP32 forward in one launch. Block (ty, tx) owns output tile (ty, tx) of every
+// layer (tiles past a layer's width idle). Layer l of row block ty starts once every tile
+// of row block ty of layer l - 1 is written; counter (ty, l - 1) counts them. The hand-off
+// needs no cache write-back or invalidation: the hidden activations are written with
+// device-scope (sc1) stores, each wave waits for its stores to complete before thread 0
+// bumps the counter (an atomic, coherent across the XCDs), and the consumers read the
+// activations with device-scope loads after thread 0 has seen the count. The weight loads
+// of a tile are issued before its wait. Row blocks run through the layers independently:
+// no grid-wide barrier. Every block of the grid must be resident at once (the host checks
+// the occupancy before choosing this kernel). A poll that gives up after FWD_SPIN_LIMIT
+// rounds poisons the block's later outputs with NaN instead of waiting on, so the launch
+// always ends. The last block of a row block to finish clears its counters, which are
+// therefore zero between launches.
+constexpr int FWD_MAXL = 16;
+constexpr uint32_t FWD_SPIN_LIMIT = 1u << 20;
+struct FwdLayer32 {
+    const float* W;
+    const float* b;
+    float* out;
+    float* dprime;
+    int K, N, ldout, kind;
+};
+struct FwdChainArgs {
+    int M, L, nxmax, ldin0, ldd;
+    const float* in32;    // the first layer's input rows (FP32), or
+    const double* in64;   // the FP64 states, rounded to FP32 as they are loaded
+    uint32_t* sync;       // ceil(M / 32) x (L + 1) counters
+    FwdLayer32 layer[FWD_MAXL];
+};
+
+__global__ __launch_bounds__(256) void fwd_chain32_kernel(FwdChainArgs a) {
+    __shared__ float red[4][64][17];
+    __shared__ int poisoned;
+    const int tid = threadIdx.x;
+    const int nx = a.nxmax, ny = (a.M + 31) / 32;
+    int tx, ty;
+    if ((ny & 7) == 0) {  // every tile of row block y on XCD y % 8, as in fwd_mfma_kernel
+        const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+        ty = xcd + 8 * (slot / nx);
+        tx = slot % nx;
     } else {
-        for (int t = wave; t < nchunk; t += 4) {
-            float4 a4, w4;
-            load(t, a4, w4);
-            mfma4(a4, w4);
+        tx = blockIdx.x % nx;
+        ty = blockIdx.x / nx;
+    }
+    uint32_t* cnt = a.sync + (long)ty * (a.L + 1);
+    if (tid == 0) poisoned = 0;
+    __syncthreads();
+    for (int l = 0; l < a.L; ++l) {
+        const FwdLayer32& ly = a.layer[l];
+        const bool last = l + 1 == a.L;
+        // layer l of row block ty waits for every tile of layer l - 1 of that row block
+        auto wait = [&] {
+            if (l == 0) return;
+            if (tid == 0) {
+                const uint32_t want = (uint32_t)((a.layer[l - 1].N + 31) / 32);
+                uint32_t spins = 0;
+                while (__hip_atomic_load(cnt + l - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins >= FWD_SPIN_LIMIT) {
+                        poisoned = 1;
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+        };
+        if (tx < (ly.N + 31) / 32) {
+            if (l == 0)
+                fwd_tile<false>(a.M, ly.K, ly.N, a.in32, a.ldin0, a.in64, ly.W, ly.b, ly.kind, ly.out, ly.ldout,
+                                ly.dprime, a.ldd, ty * 32, tx * 32, red, wait, !last, poisoned);
+            else
+                fwd_tile<true>(a.M, ly.K, ly.N, a.layer[l - 1].out, a.layer[l - 1].ldout, nullptr, ly.W, ly.b,
+                               ly.kind, ly.out, ly.ldout, ly.dprime, a.ldd, ty * 32, tx * 32, red, wait, !last,
+                               poisoned);
+            if (!last) {
+                // the wave's device-scope stores are complete before the count moves
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+                if (tid == 0) __hip_atomic_fetch_add(cnt + l, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
-    // split-K partial sums meet in LDS; wave w finishes registers 4w..4w+3 of the tile
-    // (rows m0 + 8w + 4h + 0..3), so the epilogue runs on all four waves
-#pragma unroll
-    for (int q = 0; q < 16; ++q) red[wave][lane][q] = acc[q];
-    __syncthreads();
-    const int n = n0 + l32;
-    if (n >= N) return;
-    const float bn = b ? b[n] : 0.f;
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq) {
-        const int q = 4 * wave + qq;
-        const int m = m0 + 8 * wave + 4 * h + qq;
-        if (m >= M) continue;
-        const float z = red[0][lane][q] + red[1][lane][q] + red[2][lane][q] + red[3][lane][q] + bn;
-        float o;
-        if (kind == DINO_LAYER_LINEAR) {
-            o = z;
-        } else {
-            o = gelu_t<float>(z);
-            if (kind == DINO_LAYER_RESID) o += in64 ? (float)in64[(long)m * ldin + n] : in[(long)m * ldin + n];
-            if (dprime) dprime[(long)m * ldd + n] = gelu_prime_t<float>(z);
-        }
-        out[(long)m * ldout + n] = o;
+    if (tid == 0) {
+        // every block of this row block has passed its last poll once all nx have arrived
+        const uint32_t prev = __hip_atomic_fetch_add(cnt + a.L, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev + 1 == (uint32_t)nx)
+            for (int l = 0; l <= a.L; ++l) __hip_atomic_store(cnt + l, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -504,10 +661,68 @@ static int fwd32_xcd_map(int M, int K, int N) {
     return t == 0 ? 0 : 1;
 }
 
+// Blocks of fwd_chain32_kernel that one device holds at once (0 if the query fails).
+int fwd_chain_capacity(int device) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fwd_chain32_kernel, 256, 0) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+// Blocks of the one-launch forward of n rows (widest layer's tiles x row blocks).
+static long fwd_chain_blocks(const dino_problem* p, int n) {
+    const auto& ls = p->ctx->layers;
+    int nx = 0;
+    for (size_t l = 0; l < ls.size(); ++l) {
+        const int N = (l + 1 == ls.size()) ? p->d_y : ls[l].fan_out;
+        nx = std::max(nx, (N + 31) / 32);
+    }
+    return (long)nx * ((n + 31) / 32);
+}
+
+// The forward in one launch (fwd_chain32_kernel) where the tuning entry (chains, layers,
+// widest layer) asks for it and its blocks are all resident at once; one launch per layer
+// otherwise.
+bool fwd_chain_usable(const dino_problem* p, int n) {
+    if (!p->fsync || (int)p->ctx->layers.size() > FWD_MAXL) return false;
+    if (fwd_chain_blocks(p, n) > p->fwd_chain_cap) return false;
+    return tuned_choice(TUNE_FWDCHAIN, n, (int)p->ctx->layers.size(), p->wmax) == 1;
+}
+
 // FP32 forward of the mixed-precision path: gelu'(z) into d32 (row length ldd32).
 void launch_forward32(dino_problem* p, int n, const float* xf, const double* x64, float* f_out, hipStream_t st) {
     const dino_ctx* ctx = p->ctx;
     const int L = (int)ctx->layers.size();
+    if (fwd_chain_usable(p, n)) {
+        FwdChainArgs a{};
+        a.M = n;
+        a.L = L;
+        a.ldin0 = p->r;
+        a.ldd = p->ldd32;
+        a.in32 = x64 ? nullptr : xf;
+        a.in64 = x64;
+        a.sync = p->fsync;
+        int act = 0, nx = 0;
+        for (int l = 0; l < L; ++l) {
+            const Layer& ly = ctx->layers[l];
+            const bool last = (l == L - 1);
+            FwdLayer32& d = a.layer[l];
+            d.W = ly.W32;
+            d.b = ly.b32;
+            d.out = last ? f_out : ((l % 2 == 0) ? p->h0f : p->h1f);
+            d.ldout = last ? p->d_y : p->wmax;
+            d.N = last ? p->d_y : ly.fan_out;
+            d.K = ly.fan_in;
+            d.kind = ly.kind;
+            d.dprime = nullptr;
+            if (ly.kind != DINO_LAYER_LINEAR) d.dprime = p->d32 + (long)act++ * p->C * p->ldd32;
+            nx = std::max(nx, (d.N + 31) / 32);
+        }
+        a.nxmax = nx;
+        hipLaunchKernelGGL(fwd_chain32_kernel, dim3(nx * ((n + 31) / 32)), dim3(256), 0, st, a);
+        DINO_HIP(hipGetLastError());
+        return;
+    }
     const float* in = x64 ? nullptr : xf;
     int ldin = p->r;
     int act = 0;

@@ -236,6 +236,7 @@ static void layout(dino_problem* p, Carver& cv) {
         p->ldd32 = fp8 ? (w + 31) / 32 * 32 : 32 * sweep_nmb(p->ctx);
         p->xpf = cv.take<float>(C * r);
         p->h0f = cv.take<float>(C * w);
+        p->fsync = cv.take<uint32_t>((C + 31) / 32 * 17);
         p->h1f = cv.take<float>(C * w);
         p->f32 = cv.take<float>(C * dy);
         p->d32 = cv.take<float>((size_t)std::max(p->n_act, 1) * C * p->ldd32);
@@ -796,6 +797,10 @@ dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, co
             DINO_HIP(hipMemcpy(p->winv, winv.data(), sizeof(double) * desc->d_y, hipMemcpyHostToDevice));
             if (p->d32)  // the sweep reads gelu' rows up to a multiple of 32: the padding stays zero
                 DINO_HIP(hipMemset(p->d32, 0, sizeof(float) * std::max(p->n_act, 1) * p->C * p->ldd32));
+            if (p->fsync) {
+                DINO_HIP(hipMemset(p->fsync, 0, sizeof(uint32_t) * ((p->C + 31) / 32) * 17));
+                p->fwd_chain_cap = fwd_chain_capacity(ctx->device);
+            }
             reset_meta(p, nullptr);
             DINO_HIP(hipDeviceSynchronize());
         } catch (...) {
@@ -1171,6 +1176,11 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
                 if (!f64 && ((C + 31) / 32) % 8 != 0) continue;  // the block order only differs then
                 if (std::find(shapes.begin(), shapes.end(), sh) == shapes.end()) shapes.push_back(sh);
             }
+            // per-layer launches are timed with the one-launch forward switched off, then
+            // the one launch against the best of them
+            const int nl = (int)L.size();
+            const bool chain = !f64 && (p->ctx->layers.size() <= 16) && p->fsync;
+            if (chain) set_tuned_choice(TUNE_FWDCHAIN, C, nl, p->wmax, 0, {});
             for (const auto& sh : shapes) {
                 std::vector<double> ms(ncand, -1.0);
                 int best = -1;
@@ -1180,6 +1190,15 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
                     if (best < 0 || ms[cnd] < ms[best]) best = cnd;
                 }
                 set_tuned_choice(kind, sh[0], sh[1], sh[2], best, ms);
+                ++count;
+            }
+            if (chain) {
+                std::vector<double> ms(2, -1.0);
+                ms[0] = time_on_stream(st, e0, e1, 5, [&] { stage_forward(p, C, p->x, p->f, st); });
+                set_tuned_choice(TUNE_FWDCHAIN, C, nl, p->wmax, 1, {});
+                if (fwd_chain_usable(p, C))
+                    ms[1] = time_on_stream(st, e0, e1, 5, [&] { stage_forward(p, C, p->x, p->f, st); });
+                set_tuned_choice(TUNE_FWDCHAIN, C, nl, p->wmax, (ms[1] >= 0.0 && ms[1] < ms[0]) ? 1 : 0, ms);
                 ++count;
             }
         } catch (...) {
@@ -1197,7 +1216,7 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
 
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice) {
     return guarded([&] {
-        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_HESS, DINO_EINVAL, "unknown tuning kind");
+        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_FWDCHAIN, DINO_EINVAL, "unknown tuning kind");
         const int ncand = kind == TUNE_CHOL ? CHOL_VARIANTS : (kind == TUNE_FWD64 ? 3 : 2);
         DINO_REQUIRE(choice < ncand, DINO_EINVAL, "choice out of range for this kind");
         DINO_REQUIRE(kind != TUNE_CHOL || choice < 0 || cholesky_variant_max(choice) >= b, DINO_EINVAL,

@@ -112,3 +112,43 @@ def test_tune_set_rejects_a_variant_that_cannot_hold_the_order():
         tune_set("chol", (8, 100, 0), 0)
     with pytest.raises(DinoError, match="out of range"):
         tune_set("fwd32", (64, 40, 80), 2)
+
+
+@pytest.mark.parametrize("key", ["mid-512", "resnet-ragged"])
+def test_one_launch_forward_is_bit_identical_to_per_layer_launches(key):
+    """The mixed path's forward in one launch (row blocks handing layers on through device
+    counters) runs the same tile arithmetic as one launch per layer: f, g, the metric and B
+    agree bit for bit, on two evaluations in a row (the counters clear themselves), the
+    second with fewer chains."""
+    from paper_2403_08220_amd import clear_tuning, tune_set
+
+    if key == "mid-512":
+        case = make_case("mid", chains=512)
+        fact = "dual"
+    else:
+        case = make_case("tiny", chains=37, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
+                         bias_scale=0.3, noise_scale=0.2)
+        fact = "primal"
+    ctx, p = device_problem(case, precision="bf16", factorization=fact)
+    C, r = case["C"], case["w"].r
+    L = len(case["layers"])
+    wmax = max(W.shape[0] for _, W, _ in case["layers"][:-1])
+    x = 0.5 * np.random.default_rng(11).standard_normal((C, r))
+    try:
+        for n in (C, C - 13):
+            xd = torch.tensor(x[:n], dtype=torch.float64, device="cuda:0")
+            outs = []
+            for choice in (0, 1, 1):
+                tune_set("fwdchain", (n, L, wmax), choice)
+                got = {k: t.cpu().numpy() for k, t in p.eval_geometry(xd).items()}
+                got["B"] = p.eval_jacobian(xd).cpu().numpy()
+                outs.append(got)
+            print(f"one-launch forward {key}: n {n}, layers {L}, width {wmax}", flush=True)
+            for got in outs[1:]:
+                for k in ("f", "phi", "g", "H", "L", "B"):
+                    np.testing.assert_array_equal(got[k], outs[0][k], err_msg=k)
+            assert np.all(np.isfinite(outs[1]["f"]))
+    finally:
+        clear_tuning()
+        p.close()
+        ctx.close()

@@ -280,9 +280,15 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
  *   kind DINO_TUNE_FWDCHAIN (chains, layers, widest hidden layer): the mixed paths' FP32
  *        forward, 0 one launch per layer (the default), 1 one launch for all layers (row
  *        blocks hand layers on through device counters; taken only where all its blocks
- *        are resident at once).
+ *        are resident at once);
+ *   kind DINO_TUNE_DUALSOLVE (d_y, 0, 0): the triangular solves of the dual proposal and
+ *        acceptance on the mixed path, 1 (the default where the fused Gram + factor kernel
+ *        makes the factors) blocks of 32 rows through their inverted diagonal blocks,
+ *        which that kernel stores in the factor's unused upper triangle, 0 serial
+ *        substitution in every block. Not timed by dino_autotune (timing it would move the
+ *        chains); set by dino_tune_set.
  * Every choice computes the same quantities (rounding order may differ between factor
- * kernels). n_entries (optional): table entries written. Releases the problem's launch
+ * kernels and between the two solves). n_entries (optional): table entries written. Releases the problem's launch
  * graphs (they hold the earlier choices). dino_tune_set sets or (choice < 0) erases an
  * entry; dino_tuning_table writes the table as text lines "kind a b c choice ms...". */
 #define DINO_TUNE_CHOL 0
@@ -290,6 +296,7 @@ dino_status dino_set_launch_mode(dino_problem* p, int mode, int steps_per_graph)
 #define DINO_TUNE_FWD32 2
 #define DINO_TUNE_HESS 3
 #define DINO_TUNE_FWDCHAIN 4
+#define DINO_TUNE_DUALSOLVE 5
 dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries);
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice);
 dino_status dino_tuning_table(char* buf, size_t cap, size_t* length);

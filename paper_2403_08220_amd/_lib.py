@@ -14,7 +14,7 @@ STATUS_NAMES = {0: "DINO_OK", -1: "DINO_EINVAL", -2: "DINO_ENOMEM", -3: "DINO_ED
 LAYER_KINDS = {"linear": 0, "act": 1, "resid": 2}
 PRECISIONS = {"f64": 0, "bf16": 1, "fp8": 2, "fp8_single": 3}
 FACTORIZATIONS = {"primal": 0, "dual": 1, "auto": 2}
-TUNE_KINDS = {"chol": 0, "fwd64": 1, "fwd32": 2, "hess": 3, "fwdchain": 4}
+TUNE_KINDS = {"chol": 0, "fwd64": 1, "fwd32": 2, "hess": 3, "fwdchain": 4, "dualsolve": 5}
 LAUNCH_MODES = {"eager": 0, "graph": 1}
 METHODS = {"mmala": 0, "pcn": 1, "mala": 2, "lapcn": 3, "da_mmala": 4, "dis_mmala": 5}
 

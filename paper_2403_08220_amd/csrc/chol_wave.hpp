@@ -97,11 +97,19 @@ __device__ __forceinline__ void chol_wave_step(double (&v)[MB][MB], double* col,
     chol_sync<WS>();
 }
 
+// A phase hook that does nothing (hook.template done<PH>(v) runs after every phase that
+// completes all its eight columns, with those columns final in v).
+struct CholNoHook {
+    template <int PH, typename V>
+    __device__ __forceinline__ void done(V&) {}
+};
+
 template <int MB, int PH, bool WS = false>
 struct CholWavePhases {
     // pivot: a_jj of the first column of the phase, in every lane
+    template <typename Hook = CholNoHook>
     __device__ __forceinline__ static void run(double (&v)[MB][MB], double* col, double* pivs, int r, int g, int q,
-                                               bool& bad, double& pivot) {
+                                               bool& bad, double& pivot, Hook&& hook = Hook{}) {
 #pragma unroll 1
         for (int JJ = 0; JJ < 7; ++JJ) {
             if (8 * PH + JJ >= r) return;
@@ -109,7 +117,8 @@ struct CholWavePhases {
         }
         if (8 * PH + 7 >= r) return;
         chol_wave_step<MB, PH, true, WS>(v, col, pivs, r, g, q, bad, 7, pivot);
-        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1, WS>::run(v, col, pivs, r, g, q, bad, pivot);
+        hook.template done<PH>(v);
+        if constexpr (PH + 1 < MB) CholWavePhases<MB, PH + 1, WS>::run(v, col, pivs, r, g, q, bad, pivot, hook);
     }
 };
 

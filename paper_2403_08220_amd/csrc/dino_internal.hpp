@@ -313,6 +313,7 @@ struct dino_problem {
     float* h0f = nullptr;     // C x wmax FP32 activations
     uint32_t* fsync = nullptr;  // row-block counters of the one-launch FP32 forward (zero between launches)
     long fwd_chain_cap = 0;     // blocks of that kernel the device holds at once
+    bool dinv = false;          // the factors in Lbuf carry their inverted diagonal blocks
     float* h1f = nullptr;
     float* f32 = nullptr;     // C x d_y FP32 network output
     float* d32 = nullptr;     // n_act x C x ldd32 gelu'(z), zero padded
@@ -373,7 +374,7 @@ namespace dino {
 
 // Tuning table (runtime.hip): the implementation chosen for a stage at a shape (a, b, c),
 // process-wide; -1 when the shape has no entry (the launcher's default then applies).
-enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3, TUNE_FWDCHAIN = 4 };
+enum TuneKind : int { TUNE_CHOL = 0, TUNE_FWD64 = 1, TUNE_FWD32 = 2, TUNE_HESS = 3, TUNE_FWDCHAIN = 4, TUNE_DUALSOLVE = 5 };
 constexpr int CHOL_VARIANTS = 7;
 int tuned_choice(int kind, int a, int b, int c);
 void set_tuned_choice(int kind, int a, int b, int c, int choice, const std::vector<double>& ms);
@@ -456,7 +457,7 @@ void launch_true_misfit(dino_problem* p, int n, double* out, hipStream_t st);
 bool gram_chol_bf16_fits(int r, int dy);
 void launch_gram_chol_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                            long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g,
-                           double* logdet, int32_t* ok, hipStream_t st);
+                           double* logdet, int32_t* ok, int dinv, hipStream_t st);
 void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                       long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g, hipStream_t st);
 void launch_gram_f64(dino_problem* p, int n, const double* B, double* A, long strideA, const int32_t* slot,

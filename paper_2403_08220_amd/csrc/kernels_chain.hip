@@ -320,6 +320,155 @@ __device__ __forceinline__ void l_solve2(const double* __restrict__ L, const dou
     }
 }
 
+// Triangular solves with inverted diagonal blocks. The fused Gram + factor kernel also
+// stores D_b = L_bb^-1 for every diagonal block b of SB rows: the strictly lower entries
+// of D_b transposed in the strictly upper triangle of block (b, b) of the factor (entry
+// D_b[k][m], m < k, at row b0 + m, column b0 + k); the diagonal of D_b is invd. A block of
+// a solve is then w_b = D_b (b_b - the solved part), two parallel passes with the same
+// thread layout (32 rows x 8 threads), instead of a serial sweep over the block's
+// columns. The loads of D_b's entries go out with the partial sums' loads.
+
+// thread (il, sub)'s entries of row il of D_b, columns 4 sub + q (zero past the diagonal)
+__device__ __forceinline__ void dinv_row4(const double* __restrict__ L, int r, int b0, int nb, int il, int sub,
+                                          double dv[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = 4 * sub + q;
+        dv[q] = (il < nb && m < il) ? L[(long)(b0 + m) * r + b0 + il] : 0.0;
+    }
+}
+
+// sum_m D_b[il][m] a_m over the thread's four columns (a: the block's right-hand side in
+// LDS; the diagonal entry from invd), reduced over the row's 8 threads
+__device__ __forceinline__ double dinv_row_dot(const double dv[4], const double* invd, int b0, int nb, int il, int sub,
+                                               const double* a) {
+    double s = 0.0;
+    if (il < nb) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = 4 * sub + q;
+            if (m < il) s += dv[q] * a[m];
+            else if (m == il) s += invd[b0 + il] * a[m];
+        }
+    }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    return s;
+}
+
+// Partial sums of rows b0 + il over the solved columns j < b0 (8 threads per row), for
+// one or two right-hand sides (w2 may be null), as l_solve / l_solve2 form them.
+__device__ __forceinline__ void lower_partials(const double* __restrict__ L, int r, int b0, int nb, int il, int sub,
+                                               const double* w1, const double* w2, double& c1, double& c2) {
+    const int i = b0 + il;
+    c1 = 0.0;
+    c2 = 0.0;
+    constexpr int PB = 4;
+    if (il < nb)
+        for (int j0 = 4 * sub; j0 < b0; j0 += 32 * PB) {
+            double lv[PB][4];
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) lv[u][q] = (j0 + 32 * u < b0) ? L[(long)i * r + j0 + 32 * u + q] : 0.0;
+#pragma unroll
+            for (int u = 0; u < PB; ++u)
+                if (j0 + 32 * u < b0)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        c1 += lv[u][q] * w1[j0 + 32 * u + q];
+                        if (w2) c2 += lv[u][q] * w2[j0 + 32 * u + q];
+                    }
+        }
+#pragma unroll
+    for (int o = 4; o > 0; o >>= 1) {
+        c1 += __shfl_xor(c1, o);
+        if (w2) c2 += __shfl_xor(c2, o);
+    }
+}
+
+// L w1 = b1 and, if w2, L w2 = b2 (acc_s: 2 SB doubles).
+__device__ __forceinline__ void l_solve_dinv(const double* __restrict__ L, const double* invd, int r, const double* b1,
+                                             double* w1, const double* b2, double* w2, double* acc_s) {
+    const int tid = threadIdx.x, il = tid >> 3, sub = tid & 7;
+    for (int b0 = 0; b0 < r; b0 += SB) {
+        const int nb = min(SB, r - b0), i = b0 + il;
+        double dv[4];
+        dinv_row4(L, r, b0, nb, il, sub, dv);
+        double c1, c2;
+        lower_partials(L, r, b0, nb, il, sub, w1, w2, c1, c2);
+        if (il < nb && sub == 0) {
+            acc_s[il] = b1[i] - c1;
+            if (w2) acc_s[SB + il] = b2[i] - c2;
+        }
+        __syncthreads();
+        const double s1 = dinv_row_dot(dv, invd, b0, nb, il, sub, acc_s);
+        const double s2 = w2 ? dinv_row_dot(dv, invd, b0, nb, il, sub, acc_s + SB) : 0.0;
+        if (il < nb && sub == 0) {
+            w1[i] = s1;
+            if (w2) w2[i] = s2;
+        }
+        __syncthreads();
+    }
+}
+
+// L^T x = b, blocks from the bottom: x_b = D_b^T (b_b - sum over the solved rows below of
+// L_jb x_j). The partial sums as lt_solve forms them (part: 8 SB doubles), the block's
+// right-hand side into acc_s (SB doubles), then thread (il, sub) forms
+// sum_k D_b[k][il] a_k over k = 4 sub + q (D_b[k][il] at row b0 + il, column b0 + k).
+__device__ __forceinline__ void lt_solve_dinv(const double* __restrict__ L, const double* invd, int r, const double* b,
+                                              double* x, double* part, double* acc_s) {
+    const int tid = threadIdx.x;
+    const int nblk = (r + SB - 1) / SB;
+    for (int bi = nblk - 1; bi >= 0; --bi) {
+        const int b0 = bi * SB;
+        const int nb = min(SB, r - b0);
+        const int il2 = tid >> 3, sub = tid & 7;
+        double dv[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 4 * sub + q;
+            dv[q] = (il2 < nb && k > il2 && k < nb) ? L[(long)(b0 + il2) * r + b0 + k] : 0.0;
+        }
+        {
+            const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
+            double acc = 0.0;
+            constexpr int PB = 8;
+            if (il < nb)
+                for (int j0 = b0 + nb + grp; j0 < r; j0 += 8 * PB) {
+                    double lv[PB];
+#pragma unroll
+                    for (int u = 0; u < PB; ++u) lv[u] = (j0 + 8 * u < r) ? L[(long)(j0 + 8 * u) * r + b0 + il] : 0.0;
+#pragma unroll
+                    for (int u = 0; u < PB; ++u)
+                        if (j0 + 8 * u < r) acc += lv[u] * x[j0 + 8 * u];
+                }
+            part[grp * SB + il] = acc;
+        }
+        __syncthreads();
+        if (tid < nb) {
+            double s = 0.0;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) s += part[g * SB + tid];
+            acc_s[tid] = b[b0 + tid] - s;
+        }
+        __syncthreads();
+        double t = 0.0;
+        if (il2 < nb) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * sub + q;
+                if (k > il2 && k < nb) t += dv[q] * acc_s[k];
+                else if (k == il2) t += invd[b0 + il2] * acc_s[k];
+            }
+        }
+#pragma unroll
+        for (int o = 4; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (il2 < nb && sub == 0) x[b0 + il2] = t;
+        __syncthreads();
+    }
+}
+
 // Dynamic LDS of the per-chain transition kernels: CH_NV vectors of length r, the
 // triangular-solve scratch and the partial sums of the transposed products.
 constexpr int CH_NV = 10;
@@ -1557,7 +1706,7 @@ template <typename TB>
 __device__ __forceinline__ double dual_rho0(const TB* Ba, int ldb, const double* Ka, const double* invd, int r, int dy, double dt,
                             double s, double beta, const double* a, const double* b, const double* ga,
                             double logdet_a, double* v, double* mh, double* t1, double* t2, double* z,
-                            double* acc_s, double* red) {
+                            double* acc_s, double* red, int dinv) {
     const int tid = threadIdx.x;
     b_times(Ba, dy, r, ldb, a, t1);
     bt_times(Ba, dy, r, ldb, t1, v);
@@ -1567,7 +1716,8 @@ __device__ __forceinline__ double dual_rho0(const TB* Ba, int ldb, const double*
     }
     __syncthreads();
     b_times2(Ba, dy, r, ldb, v, t2, mh, t1);
-    l_solve(Ka, invd, dy, t2, z, acc_s);
+    if (dinv) l_solve_dinv(Ka, invd, dy, t2, z, nullptr, nullptr, acc_s);
+    else l_solve(Ka, invd, dy, t2, z, acc_s);
     double sums[4] = {0.0, 0.0, 0.0, 0.0};  // |v|^2, mh.v, |z|^2, |B mh|^2
     for (int j = tid; j < r; j += TPB) {
         sums[0] += v[j] * v[j];
@@ -1590,7 +1740,7 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
                          const double* __restrict__ x, const double* __restrict__ g, const TB* __restrict__ B,
                          const double* Kbuf, long strideK, const int32_t* slot, int slot_xor, long slot_stride,
                          const double* __restrict__ logdet, const double* __restrict__ xi_given,
-                         double* __restrict__ xp, double* __restrict__ lfwd) {
+                         double* __restrict__ xp, double* __restrict__ lfwd, int dinv) {
     extern __shared__ double dyn[];
     double* R = dyn;
     double *xs = R, *gs = R + r, *u = R + 2 * r, *w = R + 3 * r, *v = R + 4 * r, *mh = R + 5 * r,
@@ -1652,8 +1802,13 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     for (int i = tid; i < dy; i += TPB) t2[i] = bx[i] + bg[i];
     __syncthreads();
     // z1 = K^-1 B u and zs = K^-1 B (x + g) in one sweep
-    l_solve2(Kc, invd, dy, y, z1, t2, zs, part);
-    lt_solve(Kc, invd, dy, z1, t1, part);
+    if (dinv) {
+        l_solve_dinv(Kc, invd, dy, y, z1, t2, zs, part);
+        lt_solve_dinv(Kc, invd, dy, z1, t1, part, acc);
+    } else {
+        l_solve2(Kc, invd, dy, y, z1, t2, zs, part);
+        lt_solve(Kc, invd, dy, z1, t1, part);
+    }
     bt_times(Bc, dy, r, ldl, t1, w);
     for (int j = tid; j < r; j += TPB) {
         xn[j] = xs[j] + u[j] - w[j];
@@ -1697,7 +1852,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
                         double* phi, double* logdet, const double* Kbuf, long half, int32_t* cur, const double* xp,
                         const double* gp, const double* phip, const double* logdetp, const int32_t* okp,
                         const double* lfwd, const TB* __restrict__ Bp, TB* __restrict__ Bs, int64_t* accepts,
-                        int64_t* failures, int32_t* accflag, StepRecord rec, int da) {
+                        int64_t* failures, int32_t* accflag, StepRecord rec, int da, int dinv) {
     extern __shared__ double dyn[];
     double* R = dyn;
     double *xs = R, *ps = R + r, *ga = R + 2 * r, *v = R + 3 * r, *mh = R + 4 * r;
@@ -1743,7 +1898,7 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
         if (okc) {
             load_inv_diag(Kp, dy, invd);
             rev = dual_rho0(Bpc, ldl, Kp, invd, r, dy, dt, s, beta, ps, xs, ga, logdetp[c], v, mh, t1, t2, z, acc,
-                            red);
+                            red, dinv);
         }
         if (tid == 0) {
             const double lr = phi[c] - phip[c] + rev - lfwd[c];
@@ -1819,14 +1974,14 @@ void log_rho_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     const TB* B1 = stage_b(Bx + (long)c * dy * ldb, dy, ldb, red + DU_RED);
     load_inv_diag(Kx + c * kk, dy, invd);
     const double fwd = dual_rho0(B1, ldl, Kx + c * kk, invd, r, dy, dt, s, beta, xs, ps, ga, logdet_x[c], v, mh, t1,
-                                 t2, z, acc, red);
+                                 t2, z, acc, red, 0);
     __syncthreads();  // every thread is done with B1, invd and ga
     for (int j = tid; j < r; j += TPB) ga[j] = g_p[(long)c * r + j];
     __syncthreads();
     const TB* B2 = stage_b(Bp + (long)c * dy * ldb, dy, ldb, red + DU_RED);
     load_inv_diag(Kp + c * kk, dy, invd);
     const double rev = dual_rho0(B2, ldl, Kp + c * kk, invd, r, dy, dt, s, beta, ps, xs, ga, logdet_p[c], v, mh, t1,
-                                 t2, z, acc, red);
+                                 t2, z, acc, red, 0);
     if (tid == 0) out[c] = phi_x[c] - phi_p[c] + rev - fwd;
 }
 
@@ -2370,6 +2525,13 @@ void launch_log_rho(dino_problem* p, int n, const double* x, const double* phi_x
     DINO_HIP(hipGetLastError());
 }
 
+// The dual kernels of a step solve with the inverted diagonal blocks where the problem's
+// factors carry them (the fused Gram + factor kernel writes them) and the tuning entry
+// (d_y) does not ask for the substitution sweeps.
+static bool dual_solve_dinv(const dino_problem* p) {
+    return p->dinv && tuned_choice(TUNE_DUALSOLVE, p->d_y, 0, 0) != 0;
+}
+
 template <typename TB>
 static void propose_dual_t(dino_problem* p, int n, const TB* Bs, int ldb, hipStream_t st) {
     static bool attr = false;
@@ -2379,7 +2541,8 @@ static void propose_dual_t(dino_problem* p, int n, const TB* Bs, int ldb, hipStr
     hipLaunchKernelGGL(propose_dual_kernel<TB>, dim3(n), dim3(TPB),
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, Bs, p->Lbuf, kk,
-                       p->cur, 0, (long)p->C * kk, p->logdet, (const double*)nullptr, p->xp, p->lfwd);
+                       p->cur, 0, (long)p->C * kk, p->logdet, (const double*)nullptr, p->xp, p->lfwd,
+                       dual_solve_dinv(p) ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
 
@@ -2395,7 +2558,7 @@ static void eval_propose_dual_t(dino_problem* p, int n, const double* x, const d
     hipLaunchKernelGGL(propose_dual_kernel<TB>, dim3(n), dim3(TPB),
                        dual_lds_doubles(p->r, p->d_y, ldb, sizeof(TB) == 2) * sizeof(double), st, p->r, p->d_y, ldb,
                        p->desc.dt, p->s, p->beta, ChainMeta{}, x, g, B, K, kk, (const int32_t*)nullptr, 0, 0L, logdet,
-                       xi, xp, lfwd);
+                       xi, xp, lfwd, 0);
     DINO_HIP(hipGetLastError());
 }
 
@@ -2472,7 +2635,7 @@ static void accept_dual_t(dino_problem* p, int n, const TB* Bp, TB* Bs, int ldb,
                        dual_lds_doubles(p->r, p->d_y, ldb, bf) * sizeof(double),
                        st, p->r, p->d_y, ldb, p->desc.dt, p->s, p->beta, p->meta, p->x, p->g, p->phi, p->logdet,
                        p->Lbuf, half, p->cur, p->xp, p->gp, p->phip, p->logdetp, p->okp, p->lfwd, Bp, Bs,
-                       p->accepts, p->failures, p->acc, step_record(p), p->da ? 1 : 0);
+                       p->accepts, p->failures, p->acc, step_record(p), p->da ? 1 : 0, dual_solve_dinv(p) ? 1 : 0);
     DINO_HIP(hipGetLastError());
 }
 

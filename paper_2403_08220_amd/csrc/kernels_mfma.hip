@@ -786,6 +786,74 @@ void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
     DINO_HIP(hipGetLastError());
 }
 
+// Column `lane` of D = L_bb^-1 for one diagonal block of the factor (Lc: the block in
+// LDS, column-major with stride 32; entries at or past nb are padded with the identity
+// here, so that NS branch-free steps of right-looking substitution serve any nb <= NS),
+// written into the strictly upper triangle of the factor's block: D[k][lane] at row
+// b0 + lane, column b0 + k (row stride dy). Lane k holds 1 / L_kk. Column k + 1 is loaded
+// while column k is applied; after each step an empty asm statement takes the updated
+// entries as operands and clobbers memory, so that the compiler neither sinks a step's
+// products below later steps nor hoists later columns' loads above it.
+template <int NS>
+__device__ __forceinline__ void invert_diag_block(double* Lc, int nb, int lane, double* a, int dy, int b0) {
+    if (nb < NS) {
+        for (int e = lane; e < NS * NS; e += 64) {
+            const int k = e / NS, i = e - k * NS;
+            if (i >= nb || k >= nb) Lc[k * 32 + i] = (i == k) ? 1.0 : 0.0;
+        }
+    }
+    const double rl = 1.0 / Lc[(lane % NS) * 33];
+    double d[NS], col[2][NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) d[k] = (k == lane) ? 1.0 : 0.0;
+#pragma unroll
+    for (int i = 1; i < NS; ++i) col[0][i] = Lc[i];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+#pragma unroll
+        for (int i = k + 2; i < NS; ++i) col[(k + 1) & 1][i] = Lc[(k + 1) * 32 + i];
+        d[k] *= lane_value(rl, k);
+#pragma unroll
+        for (int i = k + 1; i < NS; ++i) d[i] -= col[k & 1][i] * d[k];
+#pragma unroll
+        for (int i = k; i < NS; ++i) asm volatile("" : "+v"(d[i]));
+        asm volatile("" ::: "memory");
+    }
+    if (lane < nb) {
+#pragma unroll
+        for (int k = 1; k < NS; ++k)
+            if (k > lane && k < nb) a[(long)(b0 + lane) * dy + b0 + k] = d[k];
+    }
+}
+
+// Phase hook of the fused kernel's factorisation: once the phase that completes diagonal
+// block b (columns 32 b .. 32 b + 31) is done, the first wave copies the block to LDS
+// (column-major) and raises ready[b]; another wave inverts it while the factorisation
+// goes on.
+template <int MB>
+struct DiagBlockPublish {
+    double* Ld;
+    int* ready;
+    int dy, g, q;
+    template <int PH>
+    __device__ __forceinline__ void done(double (&v)[MB][MB]) {
+        if constexpr ((PH & 3) == 3) {
+            constexpr int b = PH / 4;
+            if (32 * b + 32 <= dy) {
+#pragma unroll
+                for (int m = 4 * b; m < 4 * b + 4; ++m)
+#pragma unroll
+                    for (int cc = 4 * b; cc <= m; ++cc) {
+                        const int i = g + 8 * m, kk = q + 8 * cc;
+                        if (kk <= i) Ld[b * 1024 + (kk & 31) * 32 + (i & 31)] = v[m][cc];
+                    }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the block is in LDS first
+                if (g == 0 && q == 0) __hip_atomic_store(ready + b, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+};
+
 // Observation-space Gram matrix and its Cholesky factor in one launch, one block per
 // chain: the block stages the chain's B, forms the residual, the misfit and g = B^T e as
 // gram_bf16_kernel does, accumulates the lower 32 x 32 blocks of B B^T by MFMA in
@@ -793,19 +861,26 @@ void launch_gram_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const flo
 // wave factorises K = I + B B^T in FP64 registers (the identity added in FP64; the
 // single-wave column steps), so that K never leaves LDS and the factor equals that of the
 // separate Gram and factor kernels bit for bit. Writes the factor (lower triangle, row stride d_y), log det K / 2
-// and the pivot flag. d_y <= 8 MB.
+// and the pivot flag. d_y <= 8 MB. With dinv the kernel also inverts the diagonal blocks
+// of 32 rows (D_b = L_bb^-1, written into the strictly upper triangle of the factor's
+// block (b, b); the solves of the dual proposal and acceptance read it there and form
+// its diagonal, 1 / L_jj, themselves): wave b + 1 inverts full block b as soon as the
+// factorisation has passed it (d_y <= 104: at most three full blocks), the first wave
+// inverts a short last block after the factorisation.
 template <int MB>
 __global__ __launch_bounds__(HES_TPB) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ldt,
                            const __hip_bfloat16* __restrict__ B, const float* __restrict__ f, const double* y_rows,
                            const double* winv_rows, const int32_t* rows, double* __restrict__ phi, double* A,
                            long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* __restrict__ g,
-                           double* __restrict__ logdet, int32_t* __restrict__ ok) {
+                           double* __restrict__ logdet, int32_t* __restrict__ ok, int dinv) {
     extern __shared__ __hip_bfloat16 bs[];  // dy_pad x ldt B, then e (dy floats); K (FP32) over B afterwards
     __shared__ double red[HES_TPB / 64];
     __shared__ double col[8 * MB];
     __shared__ double pivs[8 * MB];
+    __shared__ int dready[4];
     const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 4) dready[tid] = 0;  // ordered before the flags by the barriers below
     const __hip_bfloat16* Bc = B + (long)c * dy * ldb;
     float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
     const int k8 = k_pad / 8;
@@ -885,48 +960,72 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
         }
     }
     __syncthreads();
-    if (wave != 0) return;  // the factorisation runs on the first wave alone (wavefront-scope steps)
-    const int gg = lane >> 3, q = lane & 7;
-    double v[MB][MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int i = gg + 8 * m;
-#pragma unroll
-        for (int cc = 0; cc < MB; ++cc) {
-            const int kk = q + 8 * cc;
-            // the identity is added in FP64, as the separate Gram kernel writes it; the read
-            // is unconditional (clamped index) so that the reads issue back to back
-            const float kv = K[min(i, dy - 1) * ldk + min(kk, dy - 1)];
-            v[m][cc] = (cc <= m && i < dy && kk <= i) ? (double)kv + (i == kk ? 1.0 : 0.0) : 0.0;
-        }
-    }
-    bool bad = false;
-    if (q == 0) {  // column 0
-#pragma unroll
-        for (int m = 0; m < MB; ++m) col[gg + 8 * m] = v[m][0];
-    }
-    chol_sync<true>();
-    double pivot = lane_value(v[0][0], 0);
-    CholWavePhases<MB, 0, true>::run(v, col, pivs, dy, gg, q, bad, pivot);
     double* a = A + (long)c * strideA + (slot ? (long)(slot[c] ^ slot_xor) * slot_stride : 0);
+    // with dinv: the diagonal blocks, 32 x 32 each, column-major, over K once the first wave
+    // has read K into registers
+    double* Ld = reinterpret_cast<double*>(bs);
+    const int nfull = dy / 32;
+    if (wave == 0) {  // the factorisation runs on the first wave alone (wavefront-scope steps)
+        const int gg = lane >> 3, q = lane & 7;
+        double v[MB][MB];
 #pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int i = gg + 8 * m;
+        for (int m = 0; m < MB; ++m) {
+            const int i = gg + 8 * m;
 #pragma unroll
-        for (int cc = 0; cc <= m; ++cc) {
-            const int kk = q + 8 * cc;
-            // the lane's upper-triangle entries of a diagonal block pair are written as zeros
-            if (i < dy && kk < dy) a[(long)i * dy + kk] = (kk <= i) ? v[m][cc] : 0.0;
+            for (int cc = 0; cc < MB; ++cc) {
+                const int kk = q + 8 * cc;
+                // the identity is added in FP64, as the separate Gram kernel writes it; the read
+                // is unconditional (clamped index) so that the reads issue back to back
+                const float kv = K[min(i, dy - 1) * ldk + min(kk, dy - 1)];
+                v[m][cc] = (cc <= m && i < dy && kk <= i) ? (double)kv + (i == kk ? 1.0 : 0.0) : 0.0;
+            }
         }
-    }
-    chol_sync<true>();
-    double ls = 0.0;
-    for (int j = lane; j < dy; j += 64) ls += log(pivs[j]);
-    for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o);
-    const bool any_bad = __any(bad);
-    if (lane == 0) {
-        if (logdet) logdet[c] = 0.5 * ls;
-        if (ok) ok[c] = any_bad ? 0 : 1;
+        bool bad = false;
+        if (q == 0) {  // column 0
+#pragma unroll
+            for (int m = 0; m < MB; ++m) col[gg + 8 * m] = v[m][0];
+        }
+        chol_sync<true>();
+        double pivot = lane_value(v[0][0], 0);
+        CholWavePhases<MB, 0, true>::run(v, col, pivs, dy, gg, q, bad, pivot,
+                                         DiagBlockPublish<MB>{Ld, dready, dinv ? dy : 0, gg, q});
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const int i = gg + 8 * m;
+#pragma unroll
+            for (int cc = 0; cc <= m; ++cc) {
+                const int kk = q + 8 * cc;
+                // the lane's upper-triangle entries of a diagonal block pair are written as
+                // zeros (with dinv they are left to the inverted blocks)
+                if (i < dy && kk < dy && (kk <= i || !dinv)) a[(long)i * dy + kk] = (kk <= i) ? v[m][cc] : 0.0;
+                if (dinv && nfull * 32 < dy && i < dy && kk <= i && (i >> 5) == nfull && (kk >> 5) == nfull)
+                    Ld[nfull * 1024 + (kk & 31) * 32 + (i & 31)] = v[m][cc];
+            }
+        }
+        chol_sync<true>();
+        double ls = 0.0;
+        for (int j = lane; j < dy; j += 64) ls += log(pivs[j]);
+        for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o);
+        const bool any_bad = __any(bad);
+        if (lane == 0) {
+            if (logdet) logdet[c] = 0.5 * ls;
+            if (ok) ok[c] = any_bad ? 0 : 1;
+        }
+        if (dinv && nfull * 32 < dy) {  // the short last block
+            const int nb = dy - 32 * nfull;
+            if (nb <= 8) invert_diag_block<8>(Ld + nfull * 1024, nb, lane, a, dy, 32 * nfull);
+            else invert_diag_block<32>(Ld + nfull * 1024, nb, lane, a, dy, 32 * nfull);
+        }
+    } else if (dinv && wave - 1 < nfull) {
+        const int b = wave - 1;
+        // wait for the first wave to publish block b (bounded: a lost flag cannot hang the
+        // launch; the factorisation always reaches it)
+        for (int spins = 0; spins < (1 << 22); ++spins) {
+            if (__hip_atomic_load(dready + b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) break;
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        invert_diag_block<32>(Ld + b * 1024, 32, lane, a, dy, 32 * b);
     }
 }
 
@@ -936,14 +1035,15 @@ static size_t gram_chol_lds(int r, int dy) {
     const size_t dy_pad = (dy + 31) / 32 * 32, k_pad = (r + 15) / 16 * 16, ldt = k_pad + 8;
     const size_t b = dy_pad * ldt * sizeof(__hip_bfloat16) + (size_t)dy * sizeof(float);
     const size_t k = (size_t)dy * (dy + 1) * sizeof(float);
-    return std::max(b, k);
+    const size_t d = (dy_pad / 32) * 1024 * sizeof(double);  // the diagonal blocks (dinv)
+    return std::max(std::max(b, k), d);
 }
 
 bool gram_chol_bf16_fits(int r, int dy) { return dy <= 104 && gram_chol_lds(r, dy) <= 160 * 1024 - 4096; }
 
 void launch_gram_chol_bf16(dino_problem* p, int n, const __hip_bfloat16* B, const float* f, double* phi, double* A,
                            long strideA, const int32_t* slot, int slot_xor, long slot_stride, double* g,
-                           double* logdet, int32_t* ok, hipStream_t st) {
+                           double* logdet, int32_t* ok, int dinv, hipStream_t st) {
     const int r = p->r, dy = p->d_y;
     DINO_REQUIRE(gram_chol_bf16_fits(r, dy), DINO_EINVAL, "d_y x r beyond the fused Gram + factor kernel");
     const int dy_pad = (dy + 31) / 32 * 32;
@@ -958,7 +1058,7 @@ void launch_gram_chol_bf16(dino_problem* p, int n, const __hip_bfloat16* B, cons
     }
     hipLaunchKernelGGL(gram_chol_bf16_kernel<13>, dim3(n), dim3(HES_TPB), lds, st, dy, r, (r + 31) / 32 * 32, dy_pad,
                        k_pad, ldt, B, f, p->y, p->winv, p->meta.row, phi, A, strideA, slot, slot_xor, slot_stride, g,
-                       logdet, ok);
+                       logdet, ok, dinv);
     DINO_HIP(hipGetLastError());
 }
 

@@ -379,7 +379,7 @@ static void stage_metric_factor(dino_problem* p, int n, double* phi, double* g, 
                                 const int32_t* slot, int slot_xor, long slot_stride, double* logdet, int32_t* ok,
                                 hipStream_t st) {
     if (fused_metric_factor(p)) {
-        launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, A, strideA, slot, slot_xor, slot_stride, g, logdet, ok, st);
+        launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, A, strideA, slot, slot_xor, slot_stride, g, logdet, ok, 1, st);
     } else {
         stage_hessian(p, n, phi, g, A, strideA, slot, slot_xor, slot_stride, st);
         launch_cholesky_slot(n, p->kdim, A, strideA, slot, slot_xor, slot_stride, logdet, ok, st);
@@ -721,8 +721,11 @@ dino_problem* create_problem(dino_ctx* ctx, const dino_problem_desc* desc, int n
         p->ws_bytes = need;
         Carver cv2{reinterpret_cast<char*>(p->ws)};
         layout(p, cv2);
-        // every slot starts idle with zero state; rows are written at admission
+        // every slot starts idle with zero state (the forward's counters too); rows are
+        // written at admission
         DINO_HIP(hipMemset(p->ws, 0, need));
+        if (p->fsync) p->fwd_chain_cap = fwd_chain_capacity(ctx->device);
+        p->dinv = fused_metric_factor(p);
         launch_meta_fill(p, 0, p->C, 0, 0, 0, 0, 0, CHAIN_IDLE, 0, nullptr);
         DINO_HIP(hipDeviceSynchronize());
         p->initialised = true;
@@ -801,6 +804,7 @@ dino_status dino_problem_create(dino_ctx* ctx, const dino_problem_desc* desc, co
                 DINO_HIP(hipMemset(p->fsync, 0, sizeof(uint32_t) * ((p->C + 31) / 32) * 17));
                 p->fwd_chain_cap = fwd_chain_capacity(ctx->device);
             }
+            p->dinv = fused_metric_factor(p);  // every factor of Lbuf then comes from the fused kernel
             reset_meta(p, nullptr);
             DINO_HIP(hipDeviceSynchronize());
         } catch (...) {
@@ -966,7 +970,7 @@ static void run_steps_eager(dino_problem* p, int n, int n_steps, hipStream_t st)
         if (fused) {
             // one kernel for both stages (profiled as the metric stage)
             launch_gram_chol_bf16(p, n, p->B16, p->f32, p->phip, p->Lbuf, rr, p->cur, 1, half, p->gp, p->logdetp,
-                                  p->okp, st);
+                                  p->okp, 1, st);
             mark(5);
         } else {
             stage_hessian(p, n, p->phip, p->gp, p->Lbuf, rr, p->cur, 1, half, st);
@@ -1216,7 +1220,7 @@ dino_status dino_autotune(dino_problem* p, void* stream, int32_t* n_entries) {
 
 dino_status dino_tune_set(int32_t kind, int32_t a, int32_t b, int32_t c, int32_t choice) {
     return guarded([&] {
-        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_FWDCHAIN, DINO_EINVAL, "unknown tuning kind");
+        DINO_REQUIRE(kind >= TUNE_CHOL && kind <= TUNE_DUALSOLVE, DINO_EINVAL, "unknown tuning kind");
         const int ncand = kind == TUNE_CHOL ? CHOL_VARIANTS : (kind == TUNE_FWD64 ? 3 : 2);
         DINO_REQUIRE(choice < ncand, DINO_EINVAL, "choice out of range for this kind");
         DINO_REQUIRE(kind != TUNE_CHOL || choice < 0 || cholesky_variant_max(choice) >= b, DINO_EINVAL,
@@ -1433,7 +1437,7 @@ dino_status dino_eval_geometry(dino_problem* p, int n, const double* x, double* 
         stage_jacobian(p, n, st);
         stage_misfit(p, n, f, phi, g, st);
         if (fused_metric_factor(p)) {
-            launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, L, rr, nullptr, 0, 0, g, logdet, ok, st);
+            launch_gram_chol_bf16(p, n, p->B16, p->f32, phi, L, rr, nullptr, 0, 0, g, logdet, ok, 0, st);
             if (p->desc.precision != DINO_PREC_F64) launch_to_double((long)n * p->d_y, p->f32, f, st);
             if (H) launch_btb(p, n, H, st);
         } else {

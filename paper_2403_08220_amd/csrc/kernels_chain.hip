@@ -119,9 +119,9 @@ __device__ __forceinline__ void lt_solve(const double* __restrict__ L, const dou
 }
 
 // 1 / L_jj for j < r into LDS (the solves multiply instead of dividing).
-__device__ __forceinline__ void load_inv_diag(const double* __restrict__ L, int r, double* invd) {
+__device__ __forceinline__ void load_inv_diag(const double* __restrict__ L, int r, double* invd, bool sync = true) {
     for (int j = threadIdx.x; j < r; j += TPB) invd[j] = 1.0 / L[(long)j * r + j];
-    __syncthreads();
+    if (sync) __syncthreads();
 }
 
 // out1_j = sum_{i >= j} L[i][j] v1_i (L^T v1) and, if v2, out2 = L^T v2, in one pass
@@ -1596,30 +1596,37 @@ __device__ __forceinline__ void b_times_lds(const __hip_bfloat16* B, int dy, int
     __syncthreads();
 }
 
-// w_j = sum_i B[i][j] z_i (j < r), B in LDS: a thread takes a column pair (4-byte reads,
-// consecutive across lanes) and every Q-th row; the Q row shares are added in turn.
-__device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
+// w_j = sum_i B[i][j] z_i (j < r) and, if w2, w2 = B^T z2 in the same pass, B in LDS: a
+// thread takes a column pair (4-byte reads, consecutive across lanes) and every Q-th
+// row; the Q row shares are added in turn.
+__device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w,
+                                             const double* z2 = nullptr, double* w2 = nullptr) {
     const int np = (r + 1) >> 1;
     const int Q = max(1, min(TPB / np, dy));
     const int tid = threadIdx.x, jp = tid % np, q = tid / np;
     const bool act = q < Q;
-    double a0 = 0.0, a1 = 0.0;
+    double a0 = 0.0, a1 = 0.0, c0 = 0.0, c1 = 0.0;
     if (act) {
         // U rows per batch: their LDS reads are issued before the products
         constexpr int U = 8;
         int i = q;
         for (; i + (U - 1) * Q < dy; i += U * Q) {
             uint32_t uu[U];
-            double zz[U];
+            double zz[U], zz2[U];
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 uu[k] = *reinterpret_cast<const uint32_t*>(B + (long)(i + k * Q) * ldl + 2 * jp);
                 zz[k] = z[i + k * Q];
+                if (z2) zz2[k] = z2[i + k * Q];
             }
 #pragma unroll
             for (int k = 0; k < U; ++k) {
                 a0 += bf_lo(uu[k]) * zz[k];
                 a1 += bf_hi(uu[k]) * zz[k];
+                if (z2) {
+                    c0 += bf_lo(uu[k]) * zz2[k];
+                    c1 += bf_hi(uu[k]) * zz2[k];
+                }
             }
         }
         for (; i < dy; i += Q) {
@@ -1627,6 +1634,11 @@ __device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, in
             const double zi = z[i];
             a0 += bf_lo(u) * zi;
             a1 += bf_hi(u) * zi;
+            if (z2) {
+                const double z2i = z2[i];
+                c0 += bf_lo(u) * z2i;
+                c1 += bf_hi(u) * z2i;
+            }
         }
     }
     const int j = 2 * jp;
@@ -1634,6 +1646,10 @@ __device__ __forceinline__ void bt_times_lds(const __hip_bfloat16* B, int dy, in
         if (act && q == qq) {
             w[j] = (qq == 0 ? 0.0 : w[j]) + a0;
             if (j + 1 < r) w[j + 1] = (qq == 0 ? 0.0 : w[j + 1]) + a1;
+            if (w2) {
+                w2[j] = (qq == 0 ? 0.0 : w2[j]) + c0;
+                if (j + 1 < r) w2[j + 1] = (qq == 0 ? 0.0 : w2[j + 1]) + c1;
+            }
         }
         __syncthreads();
     }
@@ -1647,6 +1663,16 @@ __device__ __forceinline__ void b_times(const __hip_bfloat16* B, int dy, int r, 
 }
 __device__ __forceinline__ void bt_times(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w) {
     bt_times_lds(B, dy, r, ldl, z, w);
+}
+// w = B^T z and w2 = B^T z2 in one pass over B
+__device__ __forceinline__ void bt_times2(const __hip_bfloat16* B, int dy, int r, int ldl, const double* z, double* w,
+                                          const double* z2, double* w2) {
+    bt_times_lds(B, dy, r, ldl, z, w, z2, w2);
+}
+__device__ __forceinline__ void bt_times2(const double* B, int dy, int r, int ldb, const double* z, double* w,
+                                          const double* z2, double* w2) {
+    bt_times(B, dy, r, ldb, z, w);
+    bt_times(B, dy, r, ldb, z2, w2);
 }
 // y = B v and y2 = B v2 in one pass over B
 __device__ __forceinline__ void b_times2(const __hip_bfloat16* B, int dy, int r, int ldl, const double* v, double* y,
@@ -1686,15 +1712,17 @@ __host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool 
 
 // BF16 B rows are copied to LDS (16-byte moves, row stride ldb + 8) and used from there;
 // FP64 B is read from global memory as it is.
-__device__ __forceinline__ const double* stage_b(const double* Bg, int, int, double*) { return Bg; }
-__device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* Bg, int dy, int ldb, double* lds) {
+// sync = false leaves the barrier to the caller (other loads can share its round trip).
+__device__ __forceinline__ const double* stage_b(const double* Bg, int, int, double*, bool = true) { return Bg; }
+__device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* Bg, int dy, int ldb, double* lds,
+                                                          bool sync = true) {
     __hip_bfloat16* Bl = reinterpret_cast<__hip_bfloat16*>(lds);
     const int c16 = ldb / 8, l16 = dual_ldl(ldb, true) / 8;  // 16-byte chunks per row (ldb: a multiple of 32)
     const long n16 = (long)dy * c16;
     const uint4* src = reinterpret_cast<const uint4*>(Bg);
     uint4* dst = reinterpret_cast<uint4*>(Bl);
     for (long e = threadIdx.x; e < n16; e += TPB) dst[(e / c16) * l16 + e % c16] = src[e];
-    __syncthreads();
+    if (sync) __syncthreads();
     return Bl;
 }
 
@@ -1764,10 +1792,11 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         if (lfwd && tid == 0) lfwd[c] = 0.0;
         return;
     }
-    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + DU_RED);
+    // B's staging, the pivots' reciprocals, the states and the draws share one barrier
+    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + DU_RED, false);
     const int ldl = dual_ldl(ldb, sizeof(TB) == 2);  // row stride of Bc
     const double* Kc = Kbuf + (long)c * strideK + slot_offset(slot, slot_xor, slot_stride, c);
-    load_inv_diag(Kc, dy, invd);
+    load_inv_diag(Kc, dy, invd, false);
     for (int j = tid; j < r; j += TPB) {
         xs[j] = x[(long)c * r + j];
         gs[j] = g[(long)c * r + j];
@@ -1809,22 +1838,22 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         l_solve2(Kc, invd, dy, y, z1, t2, zs, part);
         lt_solve(Kc, invd, dy, z1, t1, part);
     }
-    bt_times(Bc, dy, r, ldl, t1, w);
+    // w = B^T t1 and, for the forward term, v = B^T (B x) in the same pass over B
+    if (lfwd) bt_times2(Bc, dy, r, ldl, t1, w, bx, v);
+    else bt_times(Bc, dy, r, ldl, t1, w);
     for (int j = tid; j < r; j += TPB) {
         xn[j] = xs[j] + u[j] - w[j];
         xp[(long)c * r + j] = xn[j];
+        if (lfwd) {
+            v[j] -= gs[j];
+            mh[j] = (xn[j] - s * xs[j]) / beta;
+        }
     }
     __syncthreads();
     if (lfwd) {
         // log rho_0(x -> xn) with the cache of x (the reverse term of the dual form):
         // v = H x - g = B^T (B x) - g, and K^-1 B v = K^T (B x) - K^-1 B (x + g), since
         // B B^T = K K^T - I; the second term is zs from the sweep above.
-        bt_times(Bc, dy, r, ldl, bx, v);
-        for (int j = tid; j < r; j += TPB) {
-            v[j] -= gs[j];
-            mh[j] = (xn[j] - s * xs[j]) / beta;
-        }
-        __syncthreads();
         b_times(Bc, dy, r, ldl, mh, y);          // y = B mhat
         lt_matvec(Kc, dy, bx, z1, part);        // z1 = K^T (B x)
         double sums[4] = {0.0, 0.0, 0.0, 0.0};   // |v|^2, mhat.v, |K^-1 B v|^2, |B mhat|^2
@@ -1873,13 +1902,16 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
     const int other = cur[c] ^ 1;
     const double* Kp = Kbuf + (long)other * half + c * kk;
     const TB* Bpg = Bp + (long)c * dy * ldb;
-    const TB* Bpc = stage_b(Bpg, dy, ldb, red + DU_RED);
+    // B's staging, the states and the pivots' reciprocals share one barrier (the
+    // reciprocals are used only where the proposal's factor exists)
+    const TB* Bpc = stage_b(Bpg, dy, ldb, red + DU_RED, false);
     const int ldl = dual_ldl(ldb, sizeof(TB) == 2);  // row stride of Bpc
     for (int j = tid; j < r; j += TPB) {
         xs[j] = x[(long)c * r + j];
         ps[j] = xp[(long)c * r + j];
         ga[j] = gp[(long)c * r + j];
     }
+    load_inv_diag(Kp, dy, invd, false);
     __syncthreads();
     const int okc = okp[c];
     if (state == CHAIN_FRESH) {
@@ -1895,11 +1927,9 @@ void accept_dual_kernel(int r, int dy, int ldb, double dt, double s, double beta
         __syncthreads();
     } else {
         double rev = 0.0;
-        if (okc) {
-            load_inv_diag(Kp, dy, invd);
+        if (okc)
             rev = dual_rho0(Bpc, ldl, Kp, invd, r, dy, dt, s, beta, ps, xs, ga, logdetp[c], v, mh, t1, t2, z, acc,
                             red, dinv);
-        }
         if (tid == 0) {
             const double lr = phi[c] - phip[c] + rev - lfwd[c];
             const double u = philox_uniform(meta.key0[c], meta.key1[c], (uint64_t)step, (uint64_t)meta.index[c]);

@@ -416,8 +416,11 @@ __device__ __forceinline__ void l_solve_dinv(const double* __restrict__ L, const
 // L_jb x_j). The partial sums as lt_solve forms them (part: 8 SB doubles), the block's
 // right-hand side into acc_s (SB doubles), then thread (il, sub) forms
 // sum_k D_b[k][il] a_k over k = 4 sub + q (D_b[k][il] at row b0 + il, column b0 + k).
+// With v2, out2 = L^T v2 rides on the same loads of L's columns (the block's own lower
+// triangle loaded besides; partial sums in part2, 8 SB doubles, added in group order).
 __device__ __forceinline__ void lt_solve_dinv(const double* __restrict__ L, const double* invd, int r, const double* b,
-                                              double* x, double* part, double* acc_s) {
+                                              double* x, double* part, double* acc_s, const double* v2 = nullptr,
+                                              double* out2 = nullptr, double* part2 = nullptr) {
     const int tid = threadIdx.x;
     const int nblk = (r + SB - 1) / SB;
     for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -432,8 +435,22 @@ __device__ __forceinline__ void lt_solve_dinv(const double* __restrict__ L, cons
         }
         {
             const int il = tid & 31, grp = tid >> 5;  // 32 columns x 8 row groups
-            double acc = 0.0;
+            double acc = 0.0, acc2 = 0.0;
             constexpr int PB = 8;
+            if (v2 && il < nb) {
+                // L^T v2 over the block's own rows j >= b0 + il
+                double dl[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int jj = grp + 8 * t;
+                    dl[t] = (jj < nb && jj >= il) ? L[(long)(b0 + jj) * r + b0 + il] : 0.0;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int jj = grp + 8 * t;
+                    if (jj < nb && jj >= il) acc2 += dl[t] * v2[b0 + jj];
+                }
+            }
             if (il < nb)
                 for (int j0 = b0 + nb + grp; j0 < r; j0 += 8 * PB) {
                     double lv[PB];
@@ -441,9 +458,13 @@ __device__ __forceinline__ void lt_solve_dinv(const double* __restrict__ L, cons
                     for (int u = 0; u < PB; ++u) lv[u] = (j0 + 8 * u < r) ? L[(long)(j0 + 8 * u) * r + b0 + il] : 0.0;
 #pragma unroll
                     for (int u = 0; u < PB; ++u)
-                        if (j0 + 8 * u < r) acc += lv[u] * x[j0 + 8 * u];
+                        if (j0 + 8 * u < r) {
+                            acc += lv[u] * x[j0 + 8 * u];
+                            if (v2) acc2 += lv[u] * v2[j0 + 8 * u];
+                        }
                 }
             part[grp * SB + il] = acc;
+            if (v2) part2[grp * SB + il] = acc2;
         }
         __syncthreads();
         if (tid < nb) {
@@ -451,6 +472,12 @@ __device__ __forceinline__ void lt_solve_dinv(const double* __restrict__ L, cons
 #pragma unroll
             for (int g = 0; g < 8; ++g) s += part[g * SB + tid];
             acc_s[tid] = b[b0 + tid] - s;
+            if (v2) {
+                double s2 = 0.0;
+#pragma unroll
+                for (int g = 0; g < 8; ++g) s2 += part2[g * SB + tid];
+                out2[b0 + tid] = s2;
+            }
         }
         __syncthreads();
         double t = 0.0;
@@ -1707,7 +1734,7 @@ constexpr int DU_RED = 4 * (TPB / 64);  // block_sum4 scratch
 __host__ __device__ inline int dual_ldl(int ldb, bool stage_bf16) { return stage_bf16 ? ldb + 8 : ldb; }
 __host__ __device__ inline size_t dual_lds_doubles(int r, int dy, int ldb, bool stage_bf16) {
     const size_t b = stage_bf16 ? ((size_t)dy * dual_ldl(ldb, true) * sizeof(__hip_bfloat16) + 7) / 8 : 0;
-    return (size_t)DU_NR * r + (size_t)DU_NY * dy + SB + (size_t)8 * SB + DU_RED + b;
+    return (size_t)DU_NR * r + (size_t)DU_NY * dy + SB + (size_t)8 * SB + DU_RED + (size_t)8 * SB + b;
 }
 
 // BF16 B rows are copied to LDS (16-byte moves, row stride ldb + 8) and used from there;
@@ -1793,7 +1820,8 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         return;
     }
     // B's staging, the pivots' reciprocals, the states and the draws share one barrier
-    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, red + DU_RED, false);
+    double* part2 = red + DU_RED;  // 8 SB doubles: the partial sums of K^T (B x) in the back solve
+    const TB* Bc = stage_b(B + (long)c * dy * ldb, dy, ldb, part2 + 8 * SB, false);
     const int ldl = dual_ldl(ldb, sizeof(TB) == 2);  // row stride of Bc
     const double* Kc = Kbuf + (long)c * strideK + slot_offset(slot, slot_xor, slot_stride, c);
     load_inv_diag(Kc, dy, invd, false);
@@ -1831,9 +1859,12 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
     for (int i = tid; i < dy; i += TPB) t2[i] = bx[i] + bg[i];
     __syncthreads();
     // z1 = K^-1 B u and zs = K^-1 B (x + g) in one sweep
+    // with the inverted blocks the back solve also forms K^T (B x) (into bg: B g is spent),
+    // the forward term's product
+    double* kbx = bg;
     if (dinv) {
         l_solve_dinv(Kc, invd, dy, y, z1, t2, zs, part);
-        lt_solve_dinv(Kc, invd, dy, z1, t1, part, acc);
+        lt_solve_dinv(Kc, invd, dy, z1, t1, part, acc, lfwd ? bx : nullptr, kbx, part2);
     } else {
         l_solve2(Kc, invd, dy, y, z1, t2, zs, part);
         lt_solve(Kc, invd, dy, z1, t1, part);
@@ -1855,14 +1886,14 @@ void propose_dual_kernel(int r, int dy, int ldb, double dt, double s, double bet
         // v = H x - g = B^T (B x) - g, and K^-1 B v = K^T (B x) - K^-1 B (x + g), since
         // B B^T = K K^T - I; the second term is zs from the sweep above.
         b_times(Bc, dy, r, ldl, mh, y);          // y = B mhat
-        lt_matvec(Kc, dy, bx, z1, part);        // z1 = K^T (B x)
+        if (!dinv) lt_matvec(Kc, dy, bx, kbx, part);  // K^T (B x)
         double sums[4] = {0.0, 0.0, 0.0, 0.0};   // |v|^2, mhat.v, |K^-1 B v|^2, |B mhat|^2
         for (int j = tid; j < r; j += TPB) {
             sums[0] += v[j] * v[j];
             sums[1] += mh[j] * v[j];
         }
         for (int i = tid; i < dy; i += TPB) {
-            const double zr = z1[i] - zs[i];
+            const double zr = kbx[i] - zs[i];
             sums[2] += zr * zr;
             sums[3] += y[i] * y[i];
         }

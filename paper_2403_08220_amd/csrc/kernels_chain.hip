@@ -1745,10 +1745,26 @@ __device__ __forceinline__ const __hip_bfloat16* stage_b(const __hip_bfloat16* B
                                                           bool sync = true) {
     __hip_bfloat16* Bl = reinterpret_cast<__hip_bfloat16*>(lds);
     const int c16 = ldb / 8, l16 = dual_ldl(ldb, true) / 8;  // 16-byte chunks per row (ldb: a multiple of 32)
-    const long n16 = (long)dy * c16;
+    const int n16 = dy * c16;
     const uint4* src = reinterpret_cast<const uint4*>(Bg);
     uint4* dst = reinterpret_cast<uint4*>(Bl);
-    for (long e = threadIdx.x; e < n16; e += TPB) dst[(e / c16) * l16 + e % c16] = src[e];
+    // SBATCH chunks per thread in flight: the loads of a batch go out before its LDS stores
+    constexpr int SBATCH = 4;
+    for (int base = 0; base < n16; base += SBATCH * TPB) {
+        uint4 v[SBATCH];
+#pragma unroll
+        for (int u = 0; u < SBATCH; ++u) {
+            const int e = base + u * TPB + (int)threadIdx.x;
+            v[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < n16) v[u] = src[e];
+        }
+#pragma unroll
+        for (int u = 0; u < SBATCH; ++u) {
+            const int e = base + u * TPB + (int)threadIdx.x;
+            const int row = e / c16;
+            if (e < n16) dst[row * l16 + (e - row * c16)] = v[u];
+        }
+    }
     if (sync) __syncthreads();
     return Bl;
 }

@@ -4,7 +4,8 @@ The fused Gram + factor kernel stores D_b = L_bb^-1 for every diagonal block of 
 in the factor's unused upper triangle (D_b[k][m], m < k, at row b0 + m, column b0 + k),
 and the dual proposal and acceptance then solve block by block through D_b instead of a
 serial substitution. The stored blocks are checked against numpy's inverse of the
-factor's own diagonal blocks (FP64, 1e-12 relative per block, full and ragged blocks),
+factor's own diagonal blocks (FP64, 1e-12 relative per block, full and ragged blocks, d_y
+from 20 to 104),
 and chains stepped with these solves against the same chains stepped with the
 substitution (tuning kind dualsolve = 0): identical decisions and states to 1e-10, the
 solves differing only in FP64 rounding.
@@ -22,6 +23,10 @@ CASES = {
     "resnet-37": dict(name="tiny", chains=37, arch="resnet", r=40, width=80, depth=2, d_out=24, d_y=20,
                       bias_scale=0.3, noise_scale=0.2, dt=0.5),
 }
+# d_y at the edges of the inversion's split: three full blocks and no short one (96), a
+# short block of 8 rows (72, 104), one full block and a short one of 9 rows (41)
+EDGES = {f"resnet-dy{dy}": dict(name="tiny", chains=19, arch="resnet", r=128, width=80, depth=2, d_out=dy, d_y=dy,
+                                bias_scale=0.3, noise_scale=0.2, dt=0.05) for dy in (41, 72, 96, 104)}
 
 
 def stepped(case, n_steps, choice=None):
@@ -47,9 +52,9 @@ def stepped(case, n_steps, choice=None):
     return x, acc, fail, L
 
 
-@pytest.mark.parametrize("key", list(CASES))
+@pytest.mark.parametrize("key", list(CASES) + list(EDGES))
 def test_factor_carries_its_inverted_diagonal_blocks(key):
-    kw = dict(CASES[key])
+    kw = dict({**CASES, **EDGES}[key])
     case = make_case(kw.pop("name"), **kw)
     C, r, dy = case["C"], case["w"].r, case["prob"].d_y
     print(f"inverted diagonal blocks {key}: {C} chains, d_y {dy}", flush=True)

@@ -885,7 +885,10 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
     float* es = reinterpret_cast<float*>(bs + (long)dy_pad * ldt);
     const int k8 = k_pad / 8;
     const int n16 = dy_pad * k8;  // 16-byte chunks of the staged B
-    // eight chunks per thread in flight: all loads of a batch before its LDS stores
+    // eight chunks per thread in flight: all loads of a batch before its LDS stores. A
+    // chunk is read whole (j8 + 8 <= k_pad <= ldb: inside the padded row), so that no load
+    // waits for another; the entries of a row's last chunk past r are cleared on the store
+    // side.
     constexpr int SBATCH = 8;
     for (int base = 0; base < n16; base += SBATCH * HES_TPB) {
         uint4 v[SBATCH];
@@ -894,21 +897,21 @@ void gram_chol_bf16_kernel(int dy, int r, int ldb, int dy_pad, int k_pad, int ld
             const int e2 = base + u * HES_TPB + tid;
             v[u] = make_uint4(0u, 0u, 0u, 0u);
             const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
-            if (e2 < n16 && i < dy) {
-                if (j8 + 8 <= r) {
-                    v[u] = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
-                } else {
-                    __hip_bfloat16 t[8];
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) t[q] = (j8 + q < r) ? Bc[(long)i * ldb + j8 + q] : __float2bfloat16(0.f);
-                    v[u] = *reinterpret_cast<const uint4*>(t);
-                }
-            }
+            if (e2 < n16 && i < dy) v[u] = *reinterpret_cast<const uint4*>(Bc + (long)i * ldb + j8);
         }
 #pragma unroll
         for (int u = 0; u < SBATCH; ++u) {
             const int e2 = base + u * HES_TPB + tid;
             const int i = e2 / k8, j8 = 8 * (e2 - i * k8);
+            if (j8 + 8 > r) {
+                uint32_t w4[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (j8 + 2 * q >= r) w4[q] = 0u;
+                    else if (j8 + 2 * q + 1 >= r) w4[q] &= 0xFFFFu;  // the low half is entry j8 + 2q
+                }
+                v[u] = make_uint4(w4[0], w4[1], w4[2], w4[3]);
+            }
             if (e2 < n16) *reinterpret_cast<uint4*>(bs + (long)i * ldt + j8) = v[u];
         }
     }

@@ -658,9 +658,22 @@ __global__ __launch_bounds__(PTPB) void cholesky_panel_kernel(int r, double* A, 
     for (int j0 = 0; j0 < r; j0 += PNB) {
         const int jb = min(PNB, r - j0), rows = r - j0;
         __syncthreads();  // the previous panel's readers are done
-        for (int e = tid; e < rows * PNB; e += PTPB) {
-            const int i = e >> 5, jj = e & (PNB - 1);
-            if (jj < jb && jj <= i) Pt[jj * LD + i] = a[(long)(j0 + i) * r + j0 + jj];
+        // eight loads per thread in flight before their LDS stores (one load and its wait
+        // per element had made the staging a chain of memory round trips)
+        constexpr int PB8 = 8;
+        for (int e0 = tid; e0 < rows * PNB; e0 += PB8 * PTPB) {
+            double v[PB8];
+#pragma unroll
+            for (int u = 0; u < PB8; ++u) {
+                const int e = e0 + u * PTPB, i = e >> 5, jj = e & (PNB - 1);
+                v[u] = 0.0;
+                if (e < rows * PNB && jj < jb && jj <= i) v[u] = a[(long)(j0 + i) * r + j0 + jj];
+            }
+#pragma unroll
+            for (int u = 0; u < PB8; ++u) {
+                const int e = e0 + u * PTPB, i = e >> 5, jj = e & (PNB - 1);
+                if (e < rows * PNB && jj < jb && jj <= i) Pt[jj * LD + i] = v[u];
+            }
         }
         __syncthreads();
         if (wave == 0) {
